@@ -1,0 +1,152 @@
+"""Seeded synthetic inputs shared by the FP64 oracle and the HIP path.
+
+This module holds no arithmetic of the FR method, the linear solvers or the
+time integrators.  It only produces input data:
+
+* quad-mesh vertex arrays (uniform, or with interior nodes randomly moved),
+* closed-form flow states of the two test problems as functions of the
+  physical position (x, y) and time t,
+* seeded random vectors used as GMRES right-hand sides and Krylov vectors.
+
+Vertex array layout: ``nodes[j, i, c]`` with ``j = 0..ny``, ``i = 0..nx`` and
+``c`` in {x, y}.  Element (ex, ey) has corners (ex, ey), (ex+1, ey),
+(ex, ey+1), (ex+1, ey+1).  The domain is doubly periodic, so node (nx, j)
+is the copy of node (0, j) shifted by Lx (likewise in y); boundary nodes are
+never moved, which keeps that identification exact.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+GAMMA = 1.4
+
+
+def uniform_nodes(nx: int, ny: int, x0: float, y0: float, lx: float, ly: float) -> np.ndarray:
+    xs = x0 + lx * np.arange(nx + 1) / nx
+    ys = y0 + ly * np.arange(ny + 1) / ny
+    nodes = np.empty((ny + 1, nx + 1, 2))
+    nodes[:, :, 0] = xs[None, :]
+    nodes[:, :, 1] = ys[:, None]
+    # make the periodic copies exact: last column/row = first + L
+    nodes[:, nx, 0] = nodes[:, 0, 0] + lx
+    nodes[ny, :, 1] = nodes[0, :, 1] + ly
+    return nodes
+
+
+def perturbed_nodes(nx: int, ny: int, x0: float, y0: float, lx: float, ly: float,
+                    frac: float, seed: int) -> np.ndarray:
+    """Uniform grid whose interior nodes are moved by iid U(-frac*h, frac*h)
+    in x and in y (h = L/N per direction), drawn in (j, i, {x,y}) order."""
+    nodes = uniform_nodes(nx, ny, x0, y0, lx, ly)
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(-1.0, 1.0, size=(ny - 1, nx - 1, 2))
+    nodes[1:ny, 1:nx, 0] += frac * (lx / nx) * d[:, :, 0]
+    nodes[1:ny, 1:nx, 1] += frac * (ly / ny) * d[:, :, 1]
+    return nodes
+
+
+@dataclass(frozen=True)
+class Vortex:
+    """Isentropic vortex convected by a uniform stream (Section 5.1, eq. VP_Solution).
+
+    Defaults follow the 2D Euler workloads: free stream (rho,u,v,p)=(1,1,1,1),
+    R=1, strength alpha=5, phi=1/2, centre (0,0), periodic box [-5,5]^2.
+    """
+    rho_inf: float = 1.0
+    u_inf: float = 1.0
+    v_inf: float = 1.0
+    p_inf: float = 1.0
+    rgas: float = 1.0
+    gamma: float = GAMMA
+    alpha: float = 5.0
+    phi: float = 0.5
+    xc: float = 0.0
+    yc: float = 0.0
+    xlo: float = -5.0
+    ylo: float = -5.0
+    lx: float = 10.0
+    ly: float = 10.0
+
+    def primitive(self, x, y, t=0.0):
+        """(rho, u, v, p) of the exact solution at time t."""
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        # position relative to the convected centre, wrapped into the periodic box
+        xb = x - self.xc - self.u_inf * t
+        yb = y - self.yc - self.v_inf * t
+        xb = _wrap(xb, self.lx)
+        yb = _wrap(yb, self.ly)
+        r2 = xb * xb + yb * yb
+        ex = np.exp(self.phi * (1.0 - r2))
+        du = -self.alpha / (2.0 * math.pi) * yb * ex
+        dv = self.alpha / (2.0 * math.pi) * xb * ex
+        t_inf = self.p_inf / (self.rho_inf * self.rgas)
+        dT = -(self.alpha ** 2) * (self.gamma - 1.0) / (16.0 * self.phi * self.gamma * math.pi ** 2) * ex * ex
+        T = t_inf + dT
+        # isentropic: p/rho^gamma constant, p = rho R T
+        rho = self.rho_inf * (T / t_inf) ** (1.0 / (self.gamma - 1.0))
+        p = rho * self.rgas * T
+        return rho, self.u_inf + du, self.v_inf + dv, p
+
+    def conservative(self, x, y, t=0.0):
+        rho, u, v, p = self.primitive(x, y, t)
+        return np.stack([rho, rho * u, rho * v, p / (self.gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
+
+
+def _wrap(d, L):
+    """Map a displacement into [-L/2, L/2)."""
+    return d - L * np.floor(d / L + 0.5)
+
+
+@dataclass(frozen=True)
+class ShearLayer:
+    """Doubly periodic shear layer on [0,1]^2 (Navier-Stokes workload).
+
+    u = tanh(80(y-1/4)) for y <= 1/2 and tanh(80(3/4-y)) above; v = 0.05 sin(2 pi x);
+    rho = 1; p = 1/(gamma M^2) with M = 0.1.  mu = 1e-4 (Re = 1e4), Pr = 0.71.
+    """
+    gamma: float = GAMMA
+    rgas: float = 1.0
+    mach: float = 0.1
+    width: float = 80.0
+    amp: float = 0.05
+    mu: float = 1e-4
+    prandtl: float = 0.71
+
+    def primitive(self, x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        ym = y - np.floor(y)
+        u = np.where(ym <= 0.5, np.tanh(self.width * (ym - 0.25)), np.tanh(self.width * (0.75 - ym)))
+        v = self.amp * np.sin(2.0 * math.pi * x)
+        rho = np.ones_like(u)
+        p = np.full_like(u, 1.0 / (self.gamma * self.mach ** 2))
+        return rho, u, v, p
+
+    def conservative(self, x, y):
+        rho, u, v, p = self.primitive(x, y)
+        return np.stack([rho, rho * u, rho * v, p / (self.gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
+
+
+def random_vector(shape, seed: int, scale: float = 1.0) -> np.ndarray:
+    """Seeded standard-normal array (GMRES right-hand sides, Krylov test vectors)."""
+    return scale * np.random.default_rng(seed).standard_normal(size=shape)
+
+
+# Named workloads: mesh size, polynomial degree, domain and mesh seed.
+WORKLOADS = {
+    "vortex8_p2": dict(nx=8, ny=8, p=2, x0=-5.0, y0=-5.0, lx=10.0, ly=10.0, perturb=0.0, seed=None),
+    "vortex64_p3_perturbed": dict(nx=64, ny=64, p=3, x0=-5.0, y0=-5.0, lx=10.0, ly=10.0, perturb=0.1, seed=2),
+    "shear256_p3": dict(nx=256, ny=256, p=3, x0=0.0, y0=0.0, lx=1.0, ly=1.0, perturb=0.0, seed=None),
+    "vortex512_p4_perturbed": dict(nx=512, ny=512, p=4, x0=-5.0, y0=-5.0, lx=10.0, ly=10.0, perturb=0.1, seed=5),
+}
+
+
+def workload_nodes(name: str) -> np.ndarray:
+    w = WORKLOADS[name]
+    if w["perturb"] > 0.0:
+        return perturbed_nodes(w["nx"], w["ny"], w["x0"], w["y0"], w["lx"], w["ly"], w["perturb"], w["seed"])
+    return uniform_nodes(w["nx"], w["ny"], w["x0"], w["y0"], w["lx"], w["ly"])

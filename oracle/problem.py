@@ -1,0 +1,31 @@
+"""Oracle (test infrastructure only): set-up helpers tying a mesh, a basis and a
+residual operator together, plus the L2 error of Section 5.1."""
+from __future__ import annotations
+
+import numpy as np
+
+from .basis import Basis
+from .geometry import Geometry, Mesh
+from .euler import EulerFR
+
+
+def make_euler(nodes, P, gamma=1.4, flux="rusanov"):
+    geo = Geometry(Mesh(nodes), Basis(P))
+    return EulerFR(geo, gamma=gamma, flux=flux)
+
+
+def sample_state(op, fn):
+    """Evaluate a closed-form state fn(x, y) -> (4, ...) at all solution points, [v, e, k] layout."""
+    x, y = op.geo.points()
+    return np.asarray(fn(x, y), dtype=np.float64).reshape(4, op.nel, -1)
+
+
+def l2_error(op, s_num, s_exact):
+    """sqrt( int (s_exact - s_num)^2 dV / V ) (Section 5.1) with the tensor Gauss rule
+    of the solution points; s_* indexed [e, k]."""
+    w = op.b.w
+    wk = (w[:, None] * w[None, :]).reshape(-1)          # weight of point k = b*n + a
+    Jk = op.geo.J.reshape(op.nel, -1)
+    vol = np.sum(wk[None, :] * Jk)
+    d = np.asarray(s_num) - np.asarray(s_exact)
+    return float(np.sqrt(np.sum(wk[None, :] * Jk * d * d) / vol))
