@@ -1,0 +1,270 @@
+/*
+ * frjf.h -- C ABI of the MI355X (gfx950) Jacobian-free implicit solver for
+ * flux reconstruction (FR/CPR) discretisations of the 2D Euler and
+ * Navier-Stokes equations.
+ *
+ * Method: Wang & Yu, "A comparative study of implicit Jacobian-free
+ * Rosenbrock-Wanner, ESDIRK and BDF methods for unsteady flow simulation with
+ * high-order flux reconstruction formulations", arXiv:1904.04825.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Array arguments named d_* are DEVICE pointers (HBM of the current
+ *   HIP device); h_* are host pointers.  The caller allocates and owns every
+ *   buffer, including the workspace whose size fr_workspace_bytes() reports
+ *   and the element-Jacobi store.  The library never allocates device memory.
+ *   All device arrays must be 256-byte aligned (torch allocations are).
+ * State layout.  A solution-shaped vector holds 4 * nel * Np doubles as
+ *   U[v][e][k]: v in (rho, rho*u, rho*v, E); e = ey*nx + ex; k = b*(P+1) + a,
+ *   where a indexes the Gauss point along the element's xi (i) direction and
+ *   b along eta (j).  Np = (P+1)^2, ndof = 4 * nel * Np.
+ * Mesh.  Structured, doubly periodic, nx * ny bilinear quadrilaterals given
+ *   by a vertex array d_nodes[(ny+1)][(nx+1)][2] (x, y); element (ex, ey) has
+ *   corners (ex,ey), (ex+1,ey), (ex,ey+1), (ex+1,ey+1), counter-clockwise
+ *   orientation (positive |J|).  Column nx and row ny are the periodic copies
+ *   of column 0 and row 0 shifted by the period.  nx, ny >= 2.
+ * Streams.  fr_stream is a hipStream_t (NULL = the null stream).  Every call
+ *   enqueues its work on that stream.  Functions that return statistics
+ *   (fr_gmres_solve and the *_step functions) synchronise the stream before
+ *   returning; the others return as soon as the work is enqueued.
+ * Errors.  Negative status = caller or system error: nothing was enqueued and
+ *   outputs are untouched; fr_last_error() returns a message (thread-local).
+ *   Positive status = numerical outcome (statistics are filled).  The *_step
+ *   functions are transactional: on any status other than FR_OK the state
+ *   arrays they update are left unchanged.
+ * Threads.  A fr_disc may be used from one host thread at a time.
+ */
+#ifndef FRJF_H
+#define FRJF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void* fr_stream; /* hipStream_t */
+
+typedef enum {
+  FR_OK = 0,
+  FR_EINVAL = -1,  /* invalid argument (null pointer, bad size, bad enum) */
+  FR_EHIP = -2,    /* a HIP runtime call failed */
+  FR_ESIZE = -3,   /* workspace or store too small */
+  FR_NOTCONV = 1,  /* iteration limit reached before the tolerance */
+  FR_BREAKDOWN = 2,/* GMRES: zero Krylov direction with a nonzero residual */
+  FR_ENAN = 3,     /* a NaN or Inf appeared in a norm */
+  FR_REJECTED = 4  /* PTC: too many rejected pseudo-steps */
+} fr_status;
+
+enum { FR_EULER = 0, FR_NS_BR1 = 1 };            /* physics */
+enum { FR_RUSANOV = 0, FR_ROE = 1 };             /* inviscid common flux */
+enum { FR_F64 = 0, FR_F32 = 1 };                 /* element-Jacobi precision */
+enum { FR_EPS_ABS = 0, FR_EPS_RMS = 1 };         /* JF perturbation rule */
+enum { FR_ROW2 = 2, FR_ROW3 = 3, FR_ROW4 = 4 };  /* ROW schemes */
+enum { FR_ESDIRK2 = 2, FR_ESDIRK3 = 3, FR_ESDIRK4 = 4 };
+enum { FR_WS_RESIDUAL = 0, FR_WS_MATVEC = 1, FR_WS_GMRES = 2, FR_WS_STEP = 3 };
+
+typedef struct fr_disc fr_disc; /* opaque: host metadata + borrowed device pointers */
+
+typedef struct {
+  int nx, ny;       /* elements per direction, >= 2 */
+  int p;            /* polynomial degree: 2, 3 or 4 */
+  int physics;      /* FR_EULER or FR_NS_BR1 */
+  int flux;         /* FR_RUSANOV or FR_ROE */
+  double gamma;     /* ratio of specific heats (Section 2: 1.4) */
+  double rgas;      /* gas constant R, p = rho R T */
+  double mu;        /* dynamic viscosity (FR_NS_BR1), constant */
+  double prandtl;   /* Prandtl number (FR_NS_BR1), kappa = mu Cp / Pr */
+  const double* d_nodes; /* device vertex array, see above; borrowed, must outlive the disc */
+} fr_disc_desc;
+
+/* Create / destroy a discretisation handle.  Computes the Gauss points,
+ * Lagrange extrapolation rows, differentiation matrix and Radau correction
+ * derivatives of degree p (Section 3).  Returns FR_EINVAL for p outside 2..4,
+ * nx or ny < 2, physics/flux out of range or a null d_nodes. */
+fr_status fr_disc_create(const fr_disc_desc* desc, fr_disc** out);
+void fr_disc_destroy(fr_disc* disc);
+
+/* Number of doubles in a solution-shaped vector: 4 * nel * (p+1)^2. */
+size_t fr_ndof(const fr_disc* disc);
+
+/* Workspace bytes needed by the entry points of class `what` (FR_WS_*) with
+ * GMRES restart m (ignored for FR_WS_RESIDUAL / FR_WS_MATVEC) and
+ * element-Jacobi precision `precision` (FR_WS_STEP only: the step functions
+ * keep their own element-Jacobi store in the workspace). */
+size_t fr_workspace_bytes(const fr_disc* disc, int what, int m, int precision);
+
+/* Bytes of an element-Jacobi store of the given precision:
+ * nel * (4 Np)^2 * sizeof(double or float). */
+size_t fr_ejacobi_bytes(const fr_disc* disc, int precision);
+
+/* Physical coordinates of the solution points: d_xy[2][nel][Np] (x then y). */
+fr_status fr_solution_points(const fr_disc* disc, double* d_xy, fr_stream stream);
+
+/* Semi-discrete right-hand side R(q) of dq/dt = R(q) (Section 4, eq.
+ * simplified_ode): the FR residual of Section 3 -- interpolated transformed
+ * fluxes F = |J|(f xi_x + g xi_y), G = |J|(f eta_x + g eta_y) (eq.
+ * trans_detail), common interface fluxes scaled by |J||grad xi| (eq.
+ * norm_num_f; Rusanov or Roe, eq. invis_com), Radau correction and
+ * R = -(1/|J|)(dF~/dxi + dG~/deta) (eq. discrete_ns).  For FR_NS_BR1 the
+ * viscous flux of Section 2 with the BR1 common gradient is included.
+ * d_U, d_R: ndof doubles (may not alias).  d_work: fr_workspace_bytes(
+ * FR_WS_RESIDUAL) bytes (may be NULL when that is 0). */
+fr_status fr_residual(const fr_disc* disc, const double* d_U, double* d_R, void* d_work,
+                      fr_stream stream);
+
+/* Jacobian-free product (Section 4.5):
+ *   d_Av = shift * v - [R(U + e v) - R0] / e,
+ * e = eps for FR_EPS_ABS (the paper's rule, eps = 1e-8) or
+ * e = eps / rms(v), rms(v) = ||v||_2 / sqrt(ndof), for FR_EPS_RMS.
+ * v = 0 gives Av = 0.  d_R0 must be R(U).  d_work: FR_WS_MATVEC bytes. */
+fr_status fr_jf_matvec(const fr_disc* disc, const double* d_U, const double* d_R0,
+                       const double* d_v, double shift, double eps, int eps_mode,
+                       double* d_Av, void* d_work, fr_stream stream);
+
+/* Element-Jacobi preconditioner store (Section 4.5: the diagonal element
+ * blocks of the Jacobian).  d_factors: caller-allocated, fr_ejacobi_bytes(
+ * precision) bytes; after fr_ejacobi_factor it holds, per element, the
+ * explicit inverse of P_e = shift I - dR_e/dq_e, column-major, in
+ * `precision`. */
+typedef struct {
+  void* d_factors;
+  int precision; /* FR_F64 or FR_F32 */
+  double shift;  /* set by fr_ejacobi_factor */
+} fr_ejacobi;
+
+/* Assemble the raw blocks P_e = shift I - dR_e/dq_e by one-sided finite
+ * differences (column j = (v,k) perturbs q[v][e][k] by 1e-8 max(1,|q|) with
+ * every other entry of the state held fixed) into d_blocks: nel * Nb * Nb
+ * doubles, Nb = 4 Np, block e column-major: entry (row i, col j) at
+ * e*Nb*Nb + j*Nb + i, with row/col index v*Np + k. */
+fr_status fr_ejacobi_assemble(const fr_disc* disc, const double* d_U, double shift,
+                              double* d_blocks, fr_stream stream);
+
+/* Assemble the blocks at state d_U and replace each by its inverse (Gauss-
+ * Jordan elimination with partial pivoting), in pc->precision (FR_F32:
+ * assembled in FP64, rounded to FP32, inverted in FP32).  Sets pc->shift.
+ * A zero pivot gives Inf/NaN entries, which fr_gmres_solve reports as
+ * FR_ENAN. */
+fr_status fr_ejacobi_factor(const fr_disc* disc, const double* d_U, double shift, fr_ejacobi* pc,
+                            fr_stream stream);
+
+/* Invert caller-provided FP64 blocks (layout as fr_ejacobi_assemble) into pc
+ * (rounded to FP32 first when pc->precision == FR_F32). */
+fr_status fr_ejacobi_factor_blocks(const fr_disc* disc, const double* d_blocks, fr_ejacobi* pc,
+                                   fr_stream stream);
+
+/* z = P_e^{-1} r for every element (the preconditioner application).
+ * d_r, d_z: ndof doubles (may not alias).  FP32 stores convert r to FP32 and
+ * accumulate in FP32; z is returned in FP64. */
+fr_status fr_ejacobi_solve(const fr_disc* disc, const fr_ejacobi* pc, const double* d_r, double* d_z,
+                           fr_stream stream);
+
+/* GMRES options and statistics. */
+typedef struct {
+  int m;            /* restart length (Section 4.5; the paper uses 60) */
+  int max_iters;    /* total Arnoldi iterations; <= 0 means 50*m */
+  double rtol;      /* stop when ||b - A x|| <= rtol * r_ref */
+  double ref_norm;  /* r_ref; <= 0 means ||b - A x0|| (Section 5.1: relative to the first residual) */
+  double eps;       /* JF perturbation, default 1e-8 */
+  int eps_mode;     /* FR_EPS_RMS or FR_EPS_ABS */
+} fr_gmres_opts;
+
+typedef struct {
+  int iters;         /* Arnoldi iterations */
+  int restarts;      /* completed cycles that did not converge */
+  int converged;     /* 1 if ||r|| <= rtol * r_ref */
+  double r_ref;      /* reference norm used */
+  double r_final;    /* least-squares residual estimate (true residual after a restart) */
+  long residual_evals; /* residual evaluations (one per JF product) */
+} fr_gmres_stats;
+
+/* Solve (shift I - dR/dq(U)) x = b (Section 4.5, eq. for A = D - dR/dq with
+ * D = shift I) by restarted flexible GMRES(m), right-preconditioned by the
+ * element-Jacobi store pc (which must have been factored with the same
+ * shift), with the Jacobian-free product about (U, R0 = R(U)).
+ * d_x: in = initial guess x0, out = solution.  d_work: FR_WS_GMRES bytes for
+ * opts->m.  Returns FR_OK, FR_NOTCONV, FR_BREAKDOWN or FR_ENAN (x holds the
+ * last iterate in all three numerical cases). */
+fr_status fr_gmres_solve(const fr_disc* disc, const fr_ejacobi* pc, const double* d_U,
+                         const double* d_R0, double shift, const double* d_b, double* d_x,
+                         const fr_gmres_opts* opts, fr_gmres_stats* stats, void* d_work,
+                         fr_stream stream);
+
+/* Options and statistics of one time step. */
+typedef struct {
+  fr_gmres_opts lin;     /* linear solver (ROW: every stage; ESDIRK/BDF2: every PTC iteration) */
+  double tol_nl;         /* PTC: stop when ||F|| <= tol_nl ||F(q0)|| */
+  double dtau_init;      /* PTC initial pseudo-step; <= 0 means dt (Section 4.4) */
+  double dtau_max;       /* PTC cap (Section 4.4: 1e20); halved on each rejection */
+  int max_ptc;           /* PTC iterations per stage; <= 0 means 200 */
+  int max_reject;        /* PTC rejections per stage; <= 0 means 30 */
+  int precond_precision; /* FR_F64 or FR_F32 element-Jacobi */
+  int commit_unconverged;/* 1: apply the update even if a linear/nonlinear solve did not converge */
+} fr_solver_opts;
+
+typedef struct {
+  int gmres_iters;     /* all Arnoldi iterations of the step */
+  int ptc_iters;       /* accepted PTC iterations (ESDIRK, BDF2) */
+  int rejections;      /* rejected PTC iterations */
+  int linear_solves;   /* GMRES calls */
+  int unconverged;     /* GMRES calls that ended above tolerance */
+  long residual_evals; /* residual evaluations incl. JF products */
+  double wall_s;       /* host wall time of the call */
+} fr_step_stats;
+
+/* One step of a linearly implicit ROW scheme (Section 4.3, eq.
+ * Rosenbrock_General) in transformed form, Jacobian and preconditioner frozen
+ * at q^n, shift 1/(gamma dt):
+ *   (I/(gamma dt) - dR/dq)^n Y_i = R(q^n + sum_{j<i} a_ij Y_j) + (1/dt) sum_{j<i} c_ij Y_j,
+ *   q^{n+1} = q^n + sum_j m_j Y_j.
+ * scheme: FR_ROW2 (3-stage order-2 stiffly accurate scheme with gamma = 1/4),
+ * FR_ROW3 (ROS34PW2), FR_ROW4 (RODASP).  Stage solves start from zero.
+ * d_U: in q^n, out q^{n+1}.  d_work: FR_WS_STEP bytes. */
+fr_status fr_row_step(const fr_disc* disc, int scheme, double dt, double* d_U,
+                      const fr_solver_opts* opts, fr_step_stats* stats, void* d_work,
+                      fr_stream stream);
+
+/* One ESDIRK step (Section 4.2, eq. ESDIRK2): explicit first stage; stage
+ * i >= 2 solves F(q_i) = (q_i - q^n - dt sum_{j<i} a_ij R(q_j))/(omega dt)
+ * - R(q_i) = 0 (eq. SDIRK_newton) by pseudo-transient continuation (Section
+ * 4.4: eq. linearized_pseudo_transient_final, SER pseudo-step, rejection and
+ * halving of dtau_max when GMRES does not gain one order of magnitude),
+ * starting from q_{i-1}; q^{n+1} = q^n + dt sum_i b_i R(q_i).
+ * scheme: FR_ESDIRK2/3/4.  d_U in/out.  d_work: FR_WS_STEP bytes. */
+fr_status fr_esdirk_step(const fr_disc* disc, int scheme, double dt, double* d_U,
+                         const fr_solver_opts* opts, fr_step_stats* stats, void* d_work,
+                         fr_stream stream);
+
+/* One BDF2 step (Section 4.1, eq. BDF: omega = 2/3, a_1 = 4/3, a_2 = -1/3),
+ * F from eq. BDF_newton solved by the same PTC starting from q^n.  With
+ * d_Unm1 == NULL a BDF1 step (omega = 1, a_1 = 1) is taken (start-up).
+ * d_Unp1 receives q^{n+1} and may alias neither input. */
+fr_status fr_bdf2_step(const fr_disc* disc, double dt, const double* d_Unm1, const double* d_Un,
+                       double* d_Unp1, const fr_solver_opts* opts, fr_step_stats* stats,
+                       void* d_work, fr_stream stream);
+
+/* Vector helpers used around the solver (device arrays of ndof doubles). */
+/* L2 error of Section 5.1 for variable `var` (0 = rho, 1 = u velocity) of
+ * d_U against the exact isentropic vortex (eq. VP_Solution) at time t:
+ * sqrt(sum_e sum_k w_k |J|_k (s_exact - s_num)^2 / V), Gauss quadrature at
+ * the solution points.  Vortex parameters in h_params[14]: rho_inf, u_inf,
+ * v_inf, p_inf, R, gamma, alpha, phi, xc, yc, xlo, ylo, Lx, Ly.
+ * Synchronises; result in *h_err. */
+fr_status fr_l2_error_vortex(const fr_disc* disc, const double* d_U, int var, double t,
+                             const double* h_params, double* h_err, void* d_work, fr_stream stream);
+
+/* Coefficients of the built-in schemes, for inspection: kind 0 = ROW
+ * (transformed a_ij, c_ij, m_j, gamma), kind 1 = ESDIRK (a_ij, b_i).
+ * h_a and h_c: s*s row-major (c unused for ESDIRK), h_b: s.  Returns the
+ * number of stages s, or a negative status. */
+int fr_scheme_table(int kind, int scheme, double* h_a, double* h_c, double* h_b, double* h_gamma);
+
+/* Last error message of this thread ("" if none). */
+const char* fr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FRJF_H */

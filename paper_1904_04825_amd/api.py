@@ -1,0 +1,278 @@
+"""Torch-facing binding of the frjf C ABI: argument checks and marshalling only.
+
+Every computation runs in the HIP library; tensors supply device memory and
+the current torch stream supplies the HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+EULER, NS_BR1 = 0, 1
+RUSANOV, ROE = 0, 1
+F64, F32 = 0, 1
+EPS_ABS, EPS_RMS = 0, 1
+_PHYS = {"euler": EULER, "ns": NS_BR1, "ns_br1": NS_BR1}
+_FLUX = {"rusanov": RUSANOV, "roe": ROE}
+_PREC = {"f64": F64, "fp64": F64, "f32": F32, "fp32": F32}
+
+
+class FrError(RuntimeError):
+    def __init__(self, fn, status):
+        msg = L.lib().fr_last_error().decode()
+        super().__init__(f"{fn} -> {L.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(fn, st, allow_numerical=False):
+    if st < 0 or (st > 0 and not allow_numerical):
+        raise FrError(fn, st)
+    return st
+
+
+@dataclass
+class GmresOpts:
+    m: int = 20
+    max_iters: int = 0
+    rtol: float = 1e-8
+    ref_norm: float = 0.0
+    eps: float = 1e-8
+    eps_mode: int = EPS_RMS
+
+    def c(self):
+        return L.GmresOptsC(self.m, self.max_iters, self.rtol, self.ref_norm, self.eps, self.eps_mode)
+
+
+@dataclass
+class SolverOpts:
+    lin: GmresOpts = None
+    tol_nl: float = 1e-8
+    dtau_init: float = 0.0
+    dtau_max: float = 1e20
+    max_ptc: int = 0
+    max_reject: int = 0
+    precond_precision: int = F64
+    commit_unconverged: int = 0
+
+    def c(self):
+        lin = self.lin or GmresOpts()
+        return L.SolverOptsC(lin.c(), self.tol_nl, self.dtau_init, self.dtau_max, self.max_ptc, self.max_reject,
+                             self.precond_precision, self.commit_unconverged)
+
+
+def _stats(s):
+    return {k: getattr(s, k) for k, _ in s._fields_}
+
+
+class Ejacobi:
+    """Element-Jacobi store (torch-owned) of one discretisation."""
+
+    def __init__(self, disc, precision=F64):
+        self.disc = disc
+        self.precision = _PREC.get(precision, precision)
+        nbytes = L.lib().fr_ejacobi_bytes(disc.handle, self.precision)
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=disc.device)
+        self.c = L.EjacobiC(self.buf.data_ptr(), self.precision, 0.0)
+
+    def inverse_blocks(self):
+        dt = torch.float32 if self.precision == F32 else torch.float64
+        nb = self.disc.nb
+        # column-major per element: [e][col][row] -> return [e][row][col]
+        return self.buf.view(dt).view(self.disc.nel, nb, nb).transpose(1, 2)
+
+
+class Disc:
+    """A periodic structured quad mesh with FR degree p, bound to one GPU."""
+
+    def __init__(self, nodes, p, physics="euler", flux="rusanov", gamma=1.4, rgas=1.0, mu=0.0, prandtl=0.71,
+                 device="cuda"):
+        self.lib = L.lib()
+        self.device = torch.device(device)
+        self.nodes = torch.as_tensor(nodes, dtype=torch.float64).to(self.device).contiguous()
+        self.ny, self.nx = self.nodes.shape[0] - 1, self.nodes.shape[1] - 1
+        self.p = p
+        self.n = p + 1
+        self.np_ = self.n * self.n
+        self.nb = 4 * self.np_
+        self.nel = self.nx * self.ny
+        self.physics = _PHYS.get(physics, physics)
+        self.flux = _FLUX.get(flux, flux)
+        self.gamma, self.rgas, self.mu, self.prandtl = gamma, rgas, mu, prandtl
+        desc = L.DiscDesc(self.nx, self.ny, p, self.physics, self.flux, gamma, rgas, mu, prandtl,
+                          self.nodes.data_ptr())
+        h = ctypes.c_void_p()
+        _check("fr_disc_create", self.lib.fr_disc_create(ctypes.byref(desc), ctypes.byref(h)))
+        self.handle = h
+        self.ndof = int(self.lib.fr_ndof(h))
+        self.shape = (4, self.nel, self.np_)
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.fr_disc_destroy(h)
+            self.handle = None
+
+    # ------------------------------------------------------------ helpers
+    def _vec(self, t, name):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_contiguous() \
+                or t.device != self.nodes.device or t.numel() != self.ndof:
+            raise ValueError(f"{name}: expected a contiguous float64 {self.device} tensor with {self.ndof} entries")
+        return t
+
+    def empty(self):
+        return torch.empty(self.shape, dtype=torch.float64, device=self.device)
+
+    def zeros(self):
+        return torch.zeros(self.shape, dtype=torch.float64, device=self.device)
+
+    def workspace(self, what, m=20, precision=F64):
+        nbytes = int(self.lib.fr_workspace_bytes(self.handle, what, m, precision))
+        key = (what, m, precision)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
+
+    # ------------------------------------------------------------ entry points
+    def solution_points(self):
+        xy = torch.empty((2, self.nel, self.np_), dtype=torch.float64, device=self.device)
+        _check("fr_solution_points", self.lib.fr_solution_points(self.handle, _ptr(xy), _stream()))
+        return xy
+
+    def residual(self, U, R=None):
+        self._vec(U, "U")
+        R = self.empty() if R is None else self._vec(R, "R")
+        ws = self.workspace(L.WS_RESIDUAL)
+        _check("fr_residual", self.lib.fr_residual(self.handle, _ptr(U), _ptr(R), _ptr(ws), _stream()))
+        return R
+
+    def jf_matvec(self, U, R0, v, shift, eps=1e-8, eps_mode=EPS_RMS, out=None):
+        for t, nm in ((U, "U"), (R0, "R0"), (v, "v")):
+            self._vec(t, nm)
+        out = self.empty() if out is None else self._vec(out, "out")
+        ws = self.workspace(L.WS_MATVEC)
+        _check("fr_jf_matvec", self.lib.fr_jf_matvec(self.handle, _ptr(U), _ptr(R0), _ptr(v), shift, eps, eps_mode,
+                                                     _ptr(out), _ptr(ws), _stream()))
+        return out
+
+    def ejacobi_assemble(self, U, shift):
+        """Raw FP64 blocks P_e = shift I - dR_e/dq_e as a [nel, Nb, Nb] (row, col) tensor."""
+        self._vec(U, "U")
+        blocks = torch.empty((self.nel, self.nb, self.nb), dtype=torch.float64, device=self.device)
+        _check("fr_ejacobi_assemble", self.lib.fr_ejacobi_assemble(self.handle, _ptr(U), shift, _ptr(blocks),
+                                                                   _stream()))
+        return blocks.transpose(1, 2)   # stored column-major
+
+    def ejacobi_factor(self, U, shift, precision=F64, pc=None):
+        self._vec(U, "U")
+        pc = Ejacobi(self, precision) if pc is None else pc
+        _check("fr_ejacobi_factor", self.lib.fr_ejacobi_factor(self.handle, _ptr(U), shift, ctypes.byref(pc.c),
+                                                               _stream()))
+        return pc
+
+    def ejacobi_factor_blocks(self, blocks_rowcol, precision=F64):
+        """Invert caller-given blocks [nel, Nb, Nb] (row, col)."""
+        colmajor = blocks_rowcol.to(self.device, torch.float64).transpose(1, 2).contiguous()
+        pc = Ejacobi(self, precision)
+        _check("fr_ejacobi_factor_blocks", self.lib.fr_ejacobi_factor_blocks(self.handle, _ptr(colmajor),
+                                                                             ctypes.byref(pc.c), _stream()))
+        torch.cuda.current_stream().synchronize()
+        return pc
+
+    def ejacobi_solve(self, pc, r, z=None):
+        self._vec(r, "r")
+        z = self.empty() if z is None else self._vec(z, "z")
+        _check("fr_ejacobi_solve", self.lib.fr_ejacobi_solve(self.handle, ctypes.byref(pc.c), _ptr(r), _ptr(z),
+                                                             _stream()))
+        return z
+
+    def gmres_solve(self, pc, U, R0, shift, b, x=None, opts=None):
+        opts = opts or GmresOpts()
+        for t, nm in ((U, "U"), (R0, "R0"), (b, "b")):
+            self._vec(t, nm)
+        x = self.zeros() if x is None else self._vec(x, "x")
+        ws = self.workspace(L.WS_GMRES, opts.m)
+        st = L.GmresStatsC()
+        oc = opts.c()
+        status = self.lib.fr_gmres_solve(self.handle, ctypes.byref(pc.c), _ptr(U), _ptr(R0), shift, _ptr(b), _ptr(x),
+                                         ctypes.byref(oc), ctypes.byref(st), _ptr(ws), _stream())
+        _check("fr_gmres_solve", status, allow_numerical=True)
+        return x, dict(_stats(st), status=status)
+
+    def _step_ws(self, opts):
+        lin = opts.lin or GmresOpts()
+        return self.workspace(L.WS_STEP, lin.m, opts.precond_precision)
+
+    def row_step(self, U, scheme, dt, opts=None):
+        opts = opts or SolverOpts(lin=GmresOpts())
+        self._vec(U, "U")
+        st = L.StepStatsC()
+        oc = opts.c()
+        status = self.lib.fr_row_step(self.handle, int(scheme), dt, _ptr(U), ctypes.byref(oc), ctypes.byref(st),
+                                      _ptr(self._step_ws(opts)), _stream())
+        _check("fr_row_step", status, allow_numerical=True)
+        return dict(_stats(st), status=status)
+
+    def esdirk_step(self, U, scheme, dt, opts=None):
+        opts = opts or SolverOpts(lin=GmresOpts(rtol=1e-1))
+        self._vec(U, "U")
+        st = L.StepStatsC()
+        oc = opts.c()
+        status = self.lib.fr_esdirk_step(self.handle, int(scheme), dt, _ptr(U), ctypes.byref(oc), ctypes.byref(st),
+                                         _ptr(self._step_ws(opts)), _stream())
+        _check("fr_esdirk_step", status, allow_numerical=True)
+        return dict(_stats(st), status=status)
+
+    def bdf2_step(self, Unm1, Un, dt, opts=None, out=None):
+        opts = opts or SolverOpts(lin=GmresOpts(rtol=1e-1))
+        self._vec(Un, "Un")
+        if Unm1 is not None:
+            self._vec(Unm1, "Unm1")
+        out = self.empty() if out is None else self._vec(out, "out")
+        st = L.StepStatsC()
+        oc = opts.c()
+        status = self.lib.fr_bdf2_step(self.handle, dt, _ptr(Unm1), _ptr(Un), _ptr(out), ctypes.byref(oc),
+                                       ctypes.byref(st), _ptr(self._step_ws(opts)), _stream())
+        _check("fr_bdf2_step", status, allow_numerical=True)
+        return out, dict(_stats(st), status=status)
+
+    def l2_error_vortex(self, U, var, t, vortex):
+        """vortex: object with the fields of fr_inputs.Vortex."""
+        self._vec(U, "U")
+        prm = (ctypes.c_double * 14)(vortex.rho_inf, vortex.u_inf, vortex.v_inf, vortex.p_inf, vortex.rgas,
+                                     vortex.gamma, vortex.alpha, vortex.phi, vortex.xc, vortex.yc, vortex.xlo,
+                                     vortex.ylo, vortex.lx, vortex.ly)
+        err = ctypes.c_double()
+        ws = self.workspace(L.WS_MATVEC)
+        _check("fr_l2_error_vortex", self.lib.fr_l2_error_vortex(self.handle, _ptr(U), var, t, prm,
+                                                                 ctypes.byref(err), _ptr(ws), _stream()))
+        return err.value
+
+
+def scheme_table(kind, scheme):
+    """Coefficients compiled into the library: kind 0 = ROW (a, c, m, gamma), 1 = ESDIRK (a, b, gamma)."""
+    a = (ctypes.c_double * 36)()
+    c = (ctypes.c_double * 36)()
+    b = (ctypes.c_double * 6)()
+    g = ctypes.c_double()
+    s = L.lib().fr_scheme_table(kind, scheme, a, c, b, ctypes.byref(g))
+    if s < 0:
+        raise ValueError("unknown scheme")
+    import numpy as np
+    A = np.array(a[:s * s]).reshape(s, s)
+    C = np.array(c[:s * s]).reshape(s, s)
+    return A, C, np.array(b[:s]), g.value

@@ -1,0 +1,305 @@
+// C ABI entry points (include/frjf.h): argument checks, workspace carving and
+// dispatch to the kernels and host drivers.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+#include "solvers.h"
+
+namespace frjf {
+
+static thread_local std::string g_err;
+
+fr_status set_error(fr_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+void clear_error() { g_err.clear(); }
+
+}  // namespace frjf
+
+using namespace frjf;
+
+#define CHECK(cond, msg)                                   \
+  do {                                                     \
+    if (!(cond)) return set_error(FR_EINVAL, msg);         \
+  } while (0)
+
+static inline hipStream_t S(fr_stream s) { return (hipStream_t)s; }
+
+extern "C" {
+
+const char* fr_last_error(void) { return g_err.c_str(); }
+
+fr_status fr_disc_create(const fr_disc_desc* desc, fr_disc** out) {
+  clear_error();
+  CHECK(desc != nullptr && out != nullptr, "fr_disc_create: null argument");
+  CHECK(desc->p >= 2 && desc->p <= 4, "fr_disc_create: p must be 2, 3 or 4");
+  CHECK(desc->nx >= 2 && desc->ny >= 2, "fr_disc_create: nx and ny must be >= 2");
+  CHECK(desc->physics == FR_EULER || desc->physics == FR_NS_BR1, "fr_disc_create: bad physics");
+  CHECK(desc->flux == FR_RUSANOV || desc->flux == FR_ROE, "fr_disc_create: bad flux");
+  CHECK(desc->d_nodes != nullptr, "fr_disc_create: d_nodes is null");
+  CHECK(desc->gamma > 1.0 && desc->rgas > 0.0, "fr_disc_create: gamma must exceed 1 and R be positive");
+  CHECK((size_t)desc->nx * desc->ny < (1u << 30), "fr_disc_create: mesh too large");
+  if (desc->physics == FR_NS_BR1) {
+    CHECK(desc->mu >= 0.0 && desc->prandtl > 0.0, "fr_disc_create: mu >= 0 and Pr > 0 required");
+  }
+  fr_disc* d = new fr_disc{};
+  d->nx = desc->nx;
+  d->ny = desc->ny;
+  d->p = desc->p;
+  d->n = desc->p + 1;
+  d->np = d->n * d->n;
+  d->nb = 4 * d->np;
+  d->nel = desc->nx * desc->ny;
+  d->physics = desc->physics;
+  d->flux = desc->flux;
+  d->ndof = (size_t)4 * d->nel * d->np;
+  d->phys.gamma = desc->gamma;
+  d->phys.rgas = desc->rgas;
+  d->phys.mu = desc->mu;
+  d->phys.prandtl = desc->prandtl;
+  d->phys.cp_over_pr = desc->physics == FR_NS_BR1 ? desc->gamma * desc->rgas / (desc->gamma - 1.0) / desc->prandtl : 0.0;
+  d->basis = make_basis(desc->p);
+  d->nodes = desc->d_nodes;
+  hipError_t e = hipGetDevice(&d->device);
+  if (e == hipSuccess) e = hipHostMalloc(&d->h_pinned, 4096, hipHostMallocMapped | hipHostMallocCoherent);
+  if (e == hipSuccess) e = hipHostGetDevicePointer(&d->d_pinned, d->h_pinned, 0);
+  for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&d->ev[i], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    delete d;
+    return set_error(FR_EHIP, std::string("fr_disc_create: ") + hipGetErrorString(e));
+  }
+  *out = d;
+  return FR_OK;
+}
+
+void fr_disc_destroy(fr_disc* d) {
+  if (d == nullptr) return;
+  for (int i = 0; i < 4; ++i)
+    if (d->ev[i]) (void)hipEventDestroy(d->ev[i]);
+  if (d->h_pinned) (void)hipHostFree(d->h_pinned);
+  delete d;
+}
+
+size_t fr_ndof(const fr_disc* d) { return d ? d->ndof : 0; }
+
+size_t fr_ejacobi_bytes(const fr_disc* d, int precision) {
+  if (d == nullptr) return 0;
+  const size_t es = precision == FR_F32 ? sizeof(float) : sizeof(double);
+  return (size_t)d->nel * d->nb * d->nb * es;
+}
+
+size_t fr_workspace_bytes(const fr_disc* d, int what, int m, int precision) {
+  if (d == nullptr) return 0;
+  const size_t vec = ((sizeof(double) * d->ndof) + 255) & ~(size_t)255;
+  const size_t tr = (ns_trace_bytes(d) + 255) & ~(size_t)255;
+  switch (what) {
+    case FR_WS_RESIDUAL: return tr;
+    case FR_WS_MATVEC: return tr + small_bytes(d);
+    case FR_WS_GMRES: return gmres_bytes(d, m < 1 ? 1 : m);
+    case FR_WS_STEP:
+      return gmres_bytes(d, m < 1 ? 1 : m) + ((fr_ejacobi_bytes(d, precision) + 255) & ~(size_t)255) + 12 * vec;
+  }
+  return 0;
+}
+
+fr_status fr_solution_points(const fr_disc* d, double* xy, fr_stream s) {
+  clear_error();
+  CHECK(d && xy, "fr_solution_points: null argument");
+  FR_HIP(launch_solution_points(d, xy, S(s)));
+  return FR_OK;
+}
+
+static double* ns_traces(const fr_disc* d, void* work) { return d->physics == FR_NS_BR1 ? (double*)work : nullptr; }
+
+fr_status fr_residual(const fr_disc* d, const double* U, double* R, void* work, fr_stream s) {
+  clear_error();
+  CHECK(d && U && R, "fr_residual: null argument");
+  CHECK(U != R, "fr_residual: U and R alias");
+  CHECK(d->physics == FR_EULER || work != nullptr, "fr_residual: Navier-Stokes needs a workspace");
+  ResArgs a{};
+  a.U = U;
+  a.out = R;
+  a.grad = ns_traces(d, work);
+  FR_HIP(launch_residual(d, 0, a, S(s)));
+  return FR_OK;
+}
+
+fr_status fr_jf_matvec(const fr_disc* d, const double* U, const double* R0, const double* v, double shift, double eps,
+                       int eps_mode, double* Av, void* work, fr_stream s) {
+  clear_error();
+  CHECK(d && U && R0 && v && Av && work, "fr_jf_matvec: null argument");
+  CHECK(Av != U && Av != R0 && Av != v, "fr_jf_matvec: output aliases an input");
+  CHECK(eps_mode == FR_EPS_ABS || eps_mode == FR_EPS_RMS, "fr_jf_matvec: bad eps_mode");
+  CHECK(eps > 0.0, "fr_jf_matvec: eps must be positive");
+  Carver c(work);
+  double* tr = (double*)c.take(ns_trace_bytes(d));
+  double* scal = (double*)c.take(256);
+  unsigned* counter = (unsigned*)c.take(256);
+  double* partials = (double*)c.take(sizeof(double) * partials_count(d));
+  FR_HIP(zero_counters(counter, S(s)));
+  if (eps_mode == FR_EPS_RMS) FR_HIP(launch_norm2(v, d->ndof, partials, counter, scal, nullptr, S(s)));
+  ResArgs a{};
+  a.U = U;
+  a.V = v;
+  a.R0 = R0;
+  a.out = Av;
+  a.nrm2 = scal;
+  a.eps = eps;
+  a.eps_mode = eps_mode;
+  a.shift = shift;
+  a.grad = d->physics == FR_NS_BR1 ? tr : nullptr;
+  FR_HIP(launch_residual(d, 1, a, S(s)));
+  return FR_OK;
+}
+
+fr_status fr_ejacobi_assemble(const fr_disc* d, const double* U, double shift, double* blocks, fr_stream s) {
+  clear_error();
+  CHECK(d && U && blocks, "fr_ejacobi_assemble: null argument");
+  FR_HIP(launch_ejacobi_assemble(d, U, shift, blocks, FR_F64, 0, S(s)));
+  return FR_OK;
+}
+
+fr_status fr_ejacobi_factor(const fr_disc* d, const double* U, double shift, fr_ejacobi* pc, fr_stream s) {
+  clear_error();
+  CHECK(d && U && pc && pc->d_factors, "fr_ejacobi_factor: null argument");
+  CHECK(pc->precision == FR_F64 || pc->precision == FR_F32, "fr_ejacobi_factor: bad precision");
+  FR_HIP(launch_ejacobi_assemble(d, U, shift, pc->d_factors, pc->precision, 1, S(s)));
+  pc->shift = shift;
+  return FR_OK;
+}
+
+fr_status fr_ejacobi_factor_blocks(const fr_disc* d, const double* blocks, fr_ejacobi* pc, fr_stream s) {
+  clear_error();
+  CHECK(d && blocks && pc && pc->d_factors, "fr_ejacobi_factor_blocks: null argument");
+  CHECK(pc->precision == FR_F64 || pc->precision == FR_F32, "fr_ejacobi_factor_blocks: bad precision");
+  CHECK((const void*)blocks != pc->d_factors || pc->precision == FR_F64,
+        "fr_ejacobi_factor_blocks: in-place inversion needs FR_F64");
+  FR_HIP(launch_ejacobi_invert_blocks(d, blocks, pc->d_factors, pc->precision, S(s)));
+  return FR_OK;
+}
+
+fr_status fr_ejacobi_solve(const fr_disc* d, const fr_ejacobi* pc, const double* r, double* z, fr_stream s) {
+  clear_error();
+  CHECK(d && pc && pc->d_factors && r && z, "fr_ejacobi_solve: null argument");
+  CHECK(r != z, "fr_ejacobi_solve: r and z alias");
+  CHECK(pc->precision == FR_F64 || pc->precision == FR_F32, "fr_ejacobi_solve: bad precision");
+  FR_HIP(launch_ejacobi_solve(d, pc->d_factors, pc->precision, r, nullptr, nullptr, z, nullptr, nullptr, nullptr,
+                              nullptr, S(s)));
+  return FR_OK;
+}
+
+static fr_status check_gmres_opts(const fr_gmres_opts* o) {
+  CHECK(o != nullptr, "null GMRES options");
+  CHECK(o->m >= 1 && o->m <= kMaxM, "GMRES restart m must be in 1..64");
+  CHECK(o->rtol >= 0.0, "GMRES rtol must be >= 0");
+  CHECK(o->eps_mode == FR_EPS_ABS || o->eps_mode == FR_EPS_RMS, "bad eps_mode");
+  return FR_OK;
+}
+
+fr_status fr_gmres_solve(const fr_disc* d, const fr_ejacobi* pc, const double* U, const double* R0, double shift,
+                         const double* b, double* x, const fr_gmres_opts* opts, fr_gmres_stats* stats, void* work,
+                         fr_stream s) {
+  clear_error();
+  CHECK(d && pc && pc->d_factors && U && R0 && b && x && stats && work, "fr_gmres_solve: null argument");
+  fr_status c = check_gmres_opts(opts);
+  if (c != FR_OK) return c;
+  CHECK(x != b && x != U && x != R0, "fr_gmres_solve: x aliases an input");
+  Carver cv(work);
+  GmWork W = carve_gmres(cv, d, opts->m);
+  return gmres_core(d, pc->d_factors, pc->precision, U, R0, shift, b, x, false, *opts, stats, W, S(s));
+}
+
+static fr_status check_step(const fr_disc* d, const fr_solver_opts* o, fr_step_stats* st, void* work) {
+  CHECK(d && o && st && work, "step: null argument");
+  fr_status c = check_gmres_opts(&o->lin);
+  if (c != FR_OK) return c;
+  CHECK(o->precond_precision == FR_F64 || o->precond_precision == FR_F32, "step: bad precond_precision");
+  return FR_OK;
+}
+
+fr_status fr_row_step(const fr_disc* d, int scheme, double dt, double* U, const fr_solver_opts* o,
+                      fr_step_stats* st, void* work, fr_stream s) {
+  clear_error();
+  fr_status c = check_step(d, o, st, work);
+  if (c != FR_OK) return c;
+  CHECK(U != nullptr && dt > 0.0, "fr_row_step: null state or dt <= 0");
+  CHECK(row_scheme(scheme) != nullptr, "fr_row_step: scheme must be FR_ROW2/3/4");
+  *st = fr_step_stats{};
+  return row_step_impl(d, scheme, dt, U, *o, st, work, S(s));
+}
+
+fr_status fr_esdirk_step(const fr_disc* d, int scheme, double dt, double* U, const fr_solver_opts* o,
+                         fr_step_stats* st, void* work, fr_stream s) {
+  clear_error();
+  fr_status c = check_step(d, o, st, work);
+  if (c != FR_OK) return c;
+  CHECK(U != nullptr && dt > 0.0, "fr_esdirk_step: null state or dt <= 0");
+  CHECK(esdirk_scheme(scheme) != nullptr, "fr_esdirk_step: scheme must be FR_ESDIRK2/3/4");
+  *st = fr_step_stats{};
+  return esdirk_step_impl(d, scheme, dt, U, *o, st, work, S(s));
+}
+
+fr_status fr_bdf2_step(const fr_disc* d, double dt, const double* Unm1, const double* Un, double* Unp1,
+                       const fr_solver_opts* o, fr_step_stats* st, void* work, fr_stream s) {
+  clear_error();
+  fr_status c = check_step(d, o, st, work);
+  if (c != FR_OK) return c;
+  CHECK(Un != nullptr && Unp1 != nullptr && dt > 0.0, "fr_bdf2_step: null state or dt <= 0");
+  CHECK(Unp1 != Un && Unp1 != Unm1, "fr_bdf2_step: output aliases an input");
+  *st = fr_step_stats{};
+  return bdf2_step_impl(d, dt, Unm1, Un, Unp1, *o, st, work, S(s));
+}
+
+fr_status fr_l2_error_vortex(const fr_disc* d, const double* U, int var, double t, const double* h_params,
+                             double* h_err, void* work, fr_stream s) {
+  clear_error();
+  CHECK(d && U && h_params && h_err && work, "fr_l2_error_vortex: null argument");
+  CHECK(var == 0 || var == 1, "fr_l2_error_vortex: var must be 0 (rho) or 1 (u)");
+  Carver c(work);
+  double* scal = (double*)c.take(256);
+  unsigned* counter = (unsigned*)c.take(256);
+  double* partials = (double*)c.take(sizeof(double) * partials_count(d));
+  FR_HIP(zero_counters(counter, S(s)));
+  FR_HIP(launch_l2_vortex(d, U, var, t, h_params, partials, counter, scal, S(s)));
+  double host[2];
+  char* slot = (char*)d->h_pinned + 1024;
+  FR_HIP(hipMemcpyAsync(slot, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, S(s)));
+  FR_HIP(hipStreamSynchronize(S(s)));
+  std::memcpy(host, slot, sizeof(host));
+  *h_err = std::sqrt(host[0] / host[1]);
+  return FR_OK;
+}
+
+int fr_scheme_table(int kind, int scheme, double* a, double* c, double* b, double* gamma) {
+  if (!a || !b || !gamma) return FR_EINVAL;
+  if (kind == 0) {
+    const RowScheme* r = row_scheme(scheme);
+    if (!r || !c) return FR_EINVAL;
+    for (int i = 0; i < r->s; ++i) {
+      for (int j = 0; j < r->s; ++j) {
+        a[i * r->s + j] = r->a[i][j];
+        c[i * r->s + j] = r->c[i][j];
+      }
+      b[i] = r->m[i];
+    }
+    *gamma = r->gamma;
+    return r->s;
+  }
+  if (kind == 1) {
+    const EsdirkScheme* e = esdirk_scheme(scheme);
+    if (!e) return FR_EINVAL;
+    for (int i = 0; i < e->s; ++i) {
+      for (int j = 0; j < e->s; ++j) a[i * e->s + j] = e->a[i][j];
+      b[i] = e->b[i];
+    }
+    *gamma = e->gamma;
+    return e->s;
+  }
+  return FR_EINVAL;
+}
+
+}  // extern "C"

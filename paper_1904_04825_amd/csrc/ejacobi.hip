@@ -1,0 +1,446 @@
+// Element-Jacobi preconditioner (Section 4.5): the diagonal element blocks
+// P_e = shift I - dR_e/dq_e of the linear system, assembled by one-sided
+// finite differences, inverted per element, and applied as z = P_e^{-1} r.
+//
+// Assembly.  Moving one state entry (v, k) of element e changes only the
+// transformed fluxes at point k, the element's traces on the two xi-faces of
+// k's eta-row and the two eta-faces of k's xi-column, and therefore the
+// residual only along that row and column.  The kernel forms the finite
+// difference of exactly those terms (flux at k, four common fluxes with the
+// neighbours' traces held fixed), which equals [R_e(q + d e_j) - R_e(q)]
+// up to rounding without re-evaluating the whole element.
+// Inversion.  Gauss-Jordan elimination with partial pivoting in LDS, one
+// workgroup per element; FP64, or FP32 after rounding the FP64 block.
+// Application.  One 64-lane group per block row set: z_i = sum_j Pinv(i,j) r_j
+// with the inverse stored column-major, so each step of the j loop is a
+// coalesced load of one column.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+#include "physics.h"
+
+namespace frjf {
+
+template <int P>
+struct EJ {
+  static constexpr int n = P + 1, Np = n * n, Nb = 4 * Np;
+  static constexpr int NT = ((Nb + 63) / 64) * 64;
+  static constexpr int LD = Nb + 1;  // padded LDS leading dimension
+};
+
+struct AsmArgs {
+  const double* U;
+  const double* nodes;
+  int nx, ny, nel;
+  double gam, shift;
+  void* out;
+};
+
+// Gauss-Jordan inversion with partial pivoting of the LDS block A (column-major, leading dim LD).
+template <typename T, int N, int LD, int NT>
+__device__ void gj_invert(T* A, T* sf, int* piv_row, int* perm) {
+  const int tid = threadIdx.x;
+  __shared__ T red_v[NT / 64];
+  __shared__ int red_i[NT / 64];
+  for (int k = 0; k < N; ++k) {
+    // pivot search over rows k..N-1 of column k
+    T best = (T)-1;
+    int bi = k;
+    for (int i = k + tid; i < N; i += NT) {
+      const T a = fabs(A[k * LD + i]);
+      if (a > best) {
+        best = a;
+        bi = i;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const T ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if ((tid & 63) == 0) {
+      red_v[tid >> 6] = best;
+      red_i[tid >> 6] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      T b = red_v[0];
+      int ii = red_i[0];
+      for (int w = 1; w < NT / 64; ++w)
+        if (red_v[w] > b || (red_v[w] == b && red_i[w] < ii)) {
+          b = red_v[w];
+          ii = red_i[w];
+        }
+      *piv_row = ii;
+      perm[k] = ii;
+    }
+    __syncthreads();
+    const int p = *piv_row;
+    if (p != k)
+      for (int j = tid; j < N; j += NT) {
+        const T t = A[j * LD + k];
+        A[j * LD + k] = A[j * LD + p];
+        A[j * LD + p] = t;
+      }
+    __syncthreads();
+    const T pv = A[k * LD + k];
+    for (int i = tid; i < N; i += NT) sf[i] = A[k * LD + i];
+    __syncthreads();
+    const T ipv = (T)1 / pv;
+    for (int j = tid; j < N; j += NT) A[j * LD + k] = (j == k ? (T)1 : A[j * LD + k]) * ipv;
+    __syncthreads();
+    for (int i = tid; i < N; i += NT) {
+      if (i == k) continue;
+      const T fi = sf[i];
+      for (int j = 0; j < N; ++j) {
+        const T akj = A[j * LD + k];
+        const T aij = (j == k) ? (T)0 : A[j * LD + i];
+        A[j * LD + i] = aij - fi * akj;
+      }
+    }
+    __syncthreads();
+  }
+  // undo the row interchanges as column interchanges, last first
+  for (int k = N - 1; k >= 0; --k) {
+    const int p = perm[k];
+    if (p != k)
+      for (int i = tid; i < N; i += NT) {
+        const T t = A[k * LD + i];
+        A[k * LD + i] = A[p * LD + i];
+        A[p * LD + i] = t;
+      }
+    __syncthreads();
+  }
+}
+
+template <int P, int FLUX, typename T, bool INVERT>
+__global__ void __launch_bounds__(EJ<P>::NT) k_ejacobi_assemble(const AsmArgs a, const Basis B) {
+  using C = EJ<P>;
+  constexpr int n = C::n, Np = C::Np, Nb = C::Nb, NT = C::NT, LD = C::LD;
+  __shared__ T A[Nb * LD];
+  __shared__ T sf[Nb];
+  __shared__ int piv_row, perm[Nb];
+  __shared__ double sq[4][Np], sF[4][Np], sG[4][Np], sIJ[Np];
+  __shared__ double sqo[4][4][n], sqn[4][4][n], sFn[4][4][n];  // [face][var][j]
+  __shared__ double sS[4][2];
+  __shared__ double sMet[Np][4];  // xxi, xeta, yxi, yeta
+  const int tid = threadIdx.x;
+  const int el = blockIdx.x;
+  const int ex = el % a.nx, ey = el / a.nx;
+  const size_t nel = (size_t)a.nel;
+
+  // base state, fluxes and metrics at the solution points
+  for (int k = tid; k < Np; k += NT) {
+    double q[4], c[8], f[4], g[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) q[v] = a.U[((size_t)v * nel + el) * Np + k];
+    load_corners(a.nodes, a.nx, ex, ey, c);
+    const Metric m = bilinear_metric(c, B.x[k % n], B.x[k / n]);
+    euler_fluxes(q, a.gam, f, g);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      sq[v][k] = q[v];
+      sF[v][k] = m.yeta * f[v] - m.xeta * g[v];
+      sG[v][k] = -m.yxi * f[v] + m.xxi * g[v];
+    }
+    sIJ[k] = 1.0 / m.J;
+    sMet[k][0] = m.xxi;
+    sMet[k][1] = m.xeta;
+    sMet[k][2] = m.yxi;
+    sMet[k][3] = m.yeta;
+  }
+  if (tid < 4) {
+    double Sx, Sy;
+    if (tid == 0) xi_face_normal(a.nodes, a.nx, ex, ey, &Sx, &Sy);
+    else if (tid == 1) xi_face_normal(a.nodes, a.nx, (ex + 1 == a.nx) ? 0 : ex + 1, ey, &Sx, &Sy);
+    else if (tid == 2) eta_face_normal(a.nodes, a.nx, ex, ey, &Sx, &Sy);
+    else eta_face_normal(a.nodes, a.nx, ex, (ey + 1 == a.ny) ? 0 : ey + 1, &Sx, &Sy);
+    sS[tid][0] = Sx;
+    sS[tid][1] = Sy;
+  }
+  __syncthreads();
+  // traces and base common fluxes on the four faces
+  for (int t = tid; t < 4 * n; t += NT) {
+    const int f = t / n, j = t % n;
+    const bool xi_face = f < 2;
+    const double* lw = (f == 0 || f == 2) ? B.lm : B.lp;
+    const double* lo = (f == 0 || f == 2) ? B.lp : B.lm;
+    int nex = ex, ney = ey;
+    if (f == 0) nex = (ex == 0) ? a.nx - 1 : ex - 1;
+    if (f == 1) nex = (ex + 1 == a.nx) ? 0 : ex + 1;
+    if (f == 2) ney = (ey == 0) ? a.ny - 1 : ey - 1;
+    if (f == 3) ney = (ey + 1 == a.ny) ? 0 : ey + 1;
+    const size_t ne = (size_t)ney * a.nx + nex;
+    double qo[4] = {0, 0, 0, 0}, qn[4] = {0, 0, 0, 0};
+    for (int c = 0; c < n; ++c) {
+      const int kk = xi_face ? j * n + c : c * n + j;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        qo[v] = fma(lw[c], sq[v][kk], qo[v]);
+        qn[v] = fma(lo[c], a.U[((size_t)v * nel + ne) * Np + kk], qn[v]);
+      }
+    }
+    double Fn[4];
+    if (f == 0 || f == 2)
+      common_flux<FLUX>(qn, qo, sS[f][0], sS[f][1], a.gam, Fn);
+    else
+      common_flux<FLUX>(qo, qn, sS[f][0], sS[f][1], a.gam, Fn);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      sqo[f][v][j] = qo[v];
+      sqn[f][v][j] = qn[v];
+      sFn[f][v][j] = Fn[v];
+    }
+  }
+  __syncthreads();
+
+  // one finite-difference column per thread
+  for (int jc = tid; jc < Nb; jc += NT) {
+    const int vv = jc / Np, k = jc % Np, ak = k % n, bk = k / n;
+    T* col = A + jc * LD;
+    for (int i = 0; i < Nb; ++i) col[i] = (T)0;
+    double q[4], f[4], g[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) q[v] = sq[v][k];
+    const double delta = 1e-8 * fmax(1.0, fabs(q[vv]));
+    q[vv] += delta;
+    euler_fluxes(q, a.gam, f, g);
+    double dF[4], dG[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      dF[v] = (sMet[k][3] * f[v] - sMet[k][1] * g[v]) - sF[v][k];
+      dG[v] = (-sMet[k][2] * f[v] + sMet[k][0] * g[v]) - sG[v][k];
+    }
+    // change of (common flux - own flux trace) on the faces W, E (face point bk) and S, N (face point ak)
+    double dJW[4], dJE[4], dJS[4], dJN[4];
+    {
+      double qL[4], qR[4], Fn[4];
+      // W face: neighbour (left) fixed, own trace moved
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        qL[v] = sqn[0][v][bk];
+        qR[v] = sqo[0][v][bk] + (v == vv ? B.lm[ak] * delta : 0.0);
+      }
+      common_flux<FLUX>(qL, qR, sS[0][0], sS[0][1], a.gam, Fn);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dJW[v] = (Fn[v] - sFn[0][v][bk]) - B.lm[ak] * dF[v];
+      // E face: own (left) moved, neighbour fixed
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        qL[v] = sqo[1][v][bk] + (v == vv ? B.lp[ak] * delta : 0.0);
+        qR[v] = sqn[1][v][bk];
+      }
+      common_flux<FLUX>(qL, qR, sS[1][0], sS[1][1], a.gam, Fn);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dJE[v] = (Fn[v] - sFn[1][v][bk]) - B.lp[ak] * dF[v];
+      // S face at face point ak
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        qL[v] = sqn[2][v][ak];
+        qR[v] = sqo[2][v][ak] + (v == vv ? B.lm[bk] * delta : 0.0);
+      }
+      common_flux<FLUX>(qL, qR, sS[2][0], sS[2][1], a.gam, Fn);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dJS[v] = (Fn[v] - sFn[2][v][ak]) - B.lm[bk] * dG[v];
+      // N face
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        qL[v] = sqo[3][v][ak] + (v == vv ? B.lp[bk] * delta : 0.0);
+        qR[v] = sqn[3][v][ak];
+      }
+      common_flux<FLUX>(qL, qR, sS[3][0], sS[3][1], a.gam, Fn);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dJN[v] = (Fn[v] - sFn[3][v][ak]) - B.lp[bk] * dG[v];
+    }
+    const double s = -1.0 / delta;  // column of -dR/dq: -(dR)/delta, with dR = -invJ * (...)
+    // points of k's eta-row (a, bk): D[a][ak] dF + dJW gL[a] + dJE gR[a]
+    for (int ia = 0; ia < n; ++ia) {
+      const int kk = bk * n + ia;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double t = B.D[ia][ak] * dF[v] + dJW[v] * B.gL[ia] + dJE[v] * B.gR[ia];
+        if (ia == ak) t += B.D[bk][bk] * dG[v] + dJS[v] * B.gL[bk] + dJN[v] * B.gR[bk];
+        col[v * Np + kk] = (T)(s * (-sIJ[kk] * t));
+      }
+    }
+    // points of k's xi-column (ak, b), b != bk
+    for (int ib = 0; ib < n; ++ib) {
+      if (ib == bk) continue;
+      const int kk = ib * n + ak;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double t = B.D[ib][bk] * dG[v] + dJS[v] * B.gL[ib] + dJN[v] * B.gR[ib];
+        col[v * Np + kk] = (T)(s * (-sIJ[kk] * t));
+      }
+    }
+    col[jc] = (T)((double)col[jc] + a.shift);
+  }
+  __syncthreads();
+  if constexpr (INVERT) gj_invert<T, Nb, LD, NT>(A, sf, &piv_row, perm);
+  T* out = reinterpret_cast<T*>(a.out) + (size_t)el * Nb * Nb;
+  for (int idx = tid; idx < Nb * Nb; idx += NT) out[idx] = A[(idx / Nb) * LD + idx % Nb];
+}
+
+// Invert caller-provided FP64 blocks.
+template <int P, typename T>
+__global__ void __launch_bounds__(EJ<P>::NT) k_ejacobi_invert(const double* __restrict__ blocks, void* outp) {
+  using C = EJ<P>;
+  constexpr int Nb = C::Nb, NT = C::NT, LD = C::LD;
+  __shared__ T A[Nb * LD];
+  __shared__ T sf[Nb];
+  __shared__ int piv_row, perm[Nb];
+  const size_t el = blockIdx.x;
+  const double* src = blocks + el * Nb * Nb;
+  for (int idx = threadIdx.x; idx < Nb * Nb; idx += NT) A[(idx / Nb) * LD + idx % Nb] = (T)src[idx];
+  __syncthreads();
+  gj_invert<T, Nb, LD, NT>(A, sf, &piv_row, perm);
+  T* out = reinterpret_cast<T*>(outp) + el * Nb * Nb;
+  for (int idx = threadIdx.x; idx < Nb * Nb; idx += NT) out[idx] = A[(idx / Nb) * LD + idx % Nb];
+}
+
+// z = Pinv r per element (+ per-workgroup partial sums of ||z||^2), r optionally
+// scaled by 1/(*r_scale) on load and stored back to r_store (fused normalisation of
+// the Arnoldi vector).  Workgroups stride over groups of NBLK elements.
+template <int P, typename T>
+__global__ void __launch_bounds__(256) k_ejacobi_solve(const T* __restrict__ inv, const double* __restrict__ r,
+                                                        const double* r_scale, double* r_store, double* __restrict__ z,
+                                                        int nel, double* partials, const int* skip) {
+  using C = EJ<P>;
+  constexpr int Np = C::Np, Nb = C::Nb, TPB = C::NT, NBLK = 256 / TPB;
+  if (skip != nullptr && *skip) return;
+  __shared__ T sr[NBLK][Nb];
+  const int tid = threadIdx.x;
+  const int blk = tid / TPB, i = tid % TPB;
+  const double sc = (r_scale != nullptr) ? 1.0 / *r_scale : 1.0;
+  const int ngroups = (nel + NBLK - 1) / NBLK;
+  double zz = 0.0;
+  for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int el = grp * NBLK + blk;
+    __syncthreads();
+    if (el < nel)
+      for (int jj = i; jj < Nb; jj += TPB) {
+        const int v = jj / Np, k = jj % Np;
+        const size_t gi = ((size_t)v * nel + el) * Np + k;
+        double rv = r[gi];
+        if (r_scale != nullptr) {
+          rv *= sc;
+          if (r_store != nullptr) r_store[gi] = rv;
+        }
+        sr[blk][jj] = (T)rv;
+      }
+    __syncthreads();
+    if (el < nel && i < Nb) {
+      const T* col = inv + (size_t)el * Nb * Nb + i;
+      T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+      int j = 0;
+      for (; j + 4 <= Nb; j += 4) {
+        acc0 = fma(col[(size_t)(j + 0) * Nb], sr[blk][j + 0], acc0);
+        acc1 = fma(col[(size_t)(j + 1) * Nb], sr[blk][j + 1], acc1);
+        acc2 = fma(col[(size_t)(j + 2) * Nb], sr[blk][j + 2], acc2);
+        acc3 = fma(col[(size_t)(j + 3) * Nb], sr[blk][j + 3], acc3);
+      }
+      for (; j < Nb; ++j) acc0 = fma(col[(size_t)j * Nb], sr[blk][j], acc0);
+      const double zi = (double)((acc0 + acc1) + (acc2 + acc3));
+      const int v = i / Np, k = i % Np;
+      z[((size_t)v * nel + el) * Np + k] = zi;
+      zz = fma(zi, zi, zz);
+    }
+  }
+  if (partials == nullptr) return;
+  __shared__ double red[4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) zz += __shfl_xor(zz, off, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = zz;
+  __syncthreads();
+  if (tid == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+template <int P, int FLUX>
+static hipError_t asm_pf(const fr_disc* d, const AsmArgs& a, int precision, int invert, hipStream_t s) {
+  dim3 grid(d->nel), block(EJ<P>::NT);
+  if (precision == FR_F32) {
+    if (!invert) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_ejacobi_assemble<P, FLUX, float, true>), grid, block, 0, s, a, d->basis);
+  } else if (invert) {
+    hipLaunchKernelGGL((k_ejacobi_assemble<P, FLUX, double, true>), grid, block, 0, s, a, d->basis);
+  } else {
+    hipLaunchKernelGGL((k_ejacobi_assemble<P, FLUX, double, false>), grid, block, 0, s, a, d->basis);
+  }
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t asm_p(const fr_disc* d, const AsmArgs& a, int precision, int invert, hipStream_t s) {
+  return d->flux == FR_ROE ? asm_pf<P, 1>(d, a, precision, invert, s) : asm_pf<P, 0>(d, a, precision, invert, s);
+}
+
+hipError_t launch_ns_ejacobi_assemble(const fr_disc* d, const double* U, double shift, void* out, int precision,
+                                      int invert, hipStream_t s);
+
+hipError_t launch_ejacobi_assemble(const fr_disc* d, const double* U, double shift, void* out, int precision,
+                                   int invert, hipStream_t s) {
+  if (d->physics == FR_NS_BR1) return launch_ns_ejacobi_assemble(d, U, shift, out, precision, invert, s);
+  const AsmArgs a{U, d->nodes, d->nx, d->ny, d->nel, d->phys.gamma, shift, out};
+  switch (d->p) {
+    case 2: return asm_p<2>(d, a, precision, invert, s);
+    case 3: return asm_p<3>(d, a, precision, invert, s);
+    case 4: return asm_p<4>(d, a, precision, invert, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int P>
+static hipError_t inv_p(const fr_disc* d, const double* blocks, void* out, int precision, hipStream_t s) {
+  dim3 grid(d->nel), block(EJ<P>::NT);
+  if (precision == FR_F32)
+    hipLaunchKernelGGL((k_ejacobi_invert<P, float>), grid, block, 0, s, blocks, out);
+  else
+    hipLaunchKernelGGL((k_ejacobi_invert<P, double>), grid, block, 0, s, blocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ejacobi_invert_blocks(const fr_disc* d, const double* blocks, void* out, int precision,
+                                        hipStream_t s) {
+  switch (d->p) {
+    case 2: return inv_p<2>(d, blocks, out, precision, s);
+    case 3: return inv_p<3>(d, blocks, out, precision, s);
+    case 4: return inv_p<4>(d, blocks, out, precision, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int P>
+static hipError_t solve_p(const fr_disc* d, const void* f, int precision, const double* r, const double* r_scale,
+                          double* r_store, double* z, double* partials, double* nrm2, const int* skip, hipStream_t s) {
+  constexpr int NBLK = 256 / EJ<P>::NT;
+  const int ngroups = (d->nel + NBLK - 1) / NBLK;
+  const int nb = std::min(ngroups, kRedBlocks);
+  double* part = nrm2 != nullptr ? partials : nullptr;
+  if (precision == FR_F32)
+    hipLaunchKernelGGL((k_ejacobi_solve<P, float>), dim3(nb), dim3(256), 0, s, (const float*)f, r, r_scale, r_store, z,
+                       d->nel, part, skip);
+  else
+    hipLaunchKernelGGL((k_ejacobi_solve<P, double>), dim3(nb), dim3(256), 0, s, (const double*)f, r, r_scale, r_store,
+                       z, d->nel, part, skip);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || nrm2 == nullptr) return e;
+  return launch_finalize(partials, nb, 1, 1, nrm2, skip, s);
+}
+
+hipError_t launch_ejacobi_solve(const fr_disc* d, const void* factors, int precision, const double* r,
+                                const double* r_scale, double* r_store, double* z, double* partials,
+                                unsigned*, double* nrm2, const int* skip, hipStream_t s) {
+  switch (d->p) {
+    case 2: return solve_p<2>(d, factors, precision, r, r_scale, r_store, z, partials, nrm2, skip, s);
+    case 3: return solve_p<3>(d, factors, precision, r, r_scale, r_store, z, partials, nrm2, skip, s);
+    case 4: return solve_p<4>(d, factors, precision, r, r_scale, r_store, z, partials, nrm2, skip, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace frjf

@@ -1,0 +1,155 @@
+// Internal declarations of the frjf library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/frjf.h"
+
+namespace frjf {
+
+constexpr int kMaxN = 5;  // P <= 4
+
+// 1D reference-element tables of degree P, passed to kernels by value.
+struct Basis {
+  int n;                   // P + 1
+  double x[kMaxN];         // Gauss-Legendre points
+  double w[kMaxN];         // Gauss weights
+  double D[kMaxN][kMaxN];  // D[a][b] = l_b'(x_a)
+  double lm[kMaxN];        // l_b(-1)
+  double lp[kMaxN];        // l_b(+1)
+  double gL[kMaxN];        // g_L'(x_a), left Radau correction derivative
+  double gR[kMaxN];        // g_R'(x_a), right Radau correction derivative
+  double kLL, kLR, kRL, kRR;  // sum_a l_a(s) g_t'(x_a): trace of a lifted face jump (BR1)
+};
+
+Basis make_basis(int P);
+
+struct Phys {
+  double gamma, rgas, mu, prandtl;
+  double cp_over_pr;  // kappa / mu = Cp / Pr
+};
+
+}  // namespace frjf
+
+struct fr_disc {
+  int nx, ny, p, n, np, nb, nel;
+  int physics, flux;
+  size_t ndof;
+  frjf::Phys phys;
+  frjf::Basis basis;
+  const double* nodes;
+  int device;
+  // pinned, mapped host scratch: [0, 1 KiB) GMRES status written by the device,
+  // [1 KiB, 4 KiB) staging of synchronous device-to-host reads
+  void* h_pinned;
+  void* d_pinned;  // device-side address of h_pinned
+  hipEvent_t ev[4];
+};
+
+namespace frjf {
+
+// error reporting (thread-local message)
+fr_status set_error(fr_status st, const std::string& msg);
+void clear_error();
+
+#define FR_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return ::frjf::set_error(FR_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------- launchers
+// Residual family.  mode 0: out = R(U);  mode 1: out = shift v - (R(U + e v) - R0)/e;
+// mode 2: out = b - [shift v - (R(U + e v) - R0)/e].  e from *nrm2 (rms) or eps (abs).
+struct ResArgs {
+  const double* U;
+  const double* V;
+  const double* R0;
+  const double* B;
+  double* out;
+  const double* nrm2;   // device scalar ||v||^2 (rms mode)
+  const int* skip;      // optional device flag: nonzero -> kernel returns at once
+  double eps;
+  int eps_mode;
+  double shift;
+  double* grad;         // BR1 face-gradient traces (workspace)
+};
+hipError_t launch_residual(const fr_disc* d, int mode, const ResArgs& a, hipStream_t s);
+
+// Vector operations (flat arrays of n doubles).
+// Sum of squares with a deterministic two-level reduction; result in *out (device).
+hipError_t launch_norm2(const double* x, size_t n, double* partials, unsigned* counter, double* out,
+                        const int* skip, hipStream_t s);
+// y = sum_i c[i] * x[i] (k <= 8); pointers and coefficients passed by value
+hipError_t launch_lincomb(double* y, int k, const double* const* x, const double* c, size_t n,
+                          hipStream_t s);
+// y = alpha_dev[0] * x  (alpha read on device; inv=1: y = x / alpha)
+hipError_t launch_scale_dev(double* y, const double* x, const double* alpha, int inv, size_t n,
+                            const int* skip, hipStream_t s);
+
+// element-Jacobi
+hipError_t launch_ejacobi_assemble(const fr_disc* d, const double* U, double shift, void* out,
+                                   int precision, int invert, hipStream_t s);
+hipError_t launch_ejacobi_invert_blocks(const fr_disc* d, const double* blocks, void* out,
+                                        int precision, hipStream_t s);
+hipError_t launch_ejacobi_solve(const fr_disc* d, const void* factors, int precision,
+                                const double* r, const double* r_scale, double* r_store,
+                                double* z, double* partials, unsigned* counter, double* nrm2,
+                                const int* skip, hipStream_t s);
+
+hipError_t launch_solution_points(const fr_disc* d, double* xy, hipStream_t s);
+hipError_t launch_l2_vortex(const fr_disc* d, const double* U, int var, double t, const double* prm,
+                            double* partials, unsigned* counter, double* out, hipStream_t s);
+
+// Arnoldi (CGS2) device state, one per GMRES solve, in the workspace.
+constexpr int kMaxM = 64;
+struct GmState {
+  double H[(kMaxM + 1) * kMaxM];  // column-major: H[j*(M+1) + i]
+  double cs[kMaxM], sn[kMaxM];
+  double g[kMaxM + 1];
+  double h1[kMaxM + 1];
+  double h2[kMaxM + 1];
+  double y[kMaxM];
+  double target;       // rtol * r_ref
+  double hn;           // ||w|| after orthogonalisation
+  double w0;           // ||w|| before
+  // status block copied to the host after every Arnoldi step
+  double rest;         // |g_{j+1}|, the least-squares residual
+  double beta;
+  int j;               // Arnoldi steps done in this cycle
+  int stop;            // 1: converged / breakdown / nan -> the rest of the cycle is skipped
+  int why;             // 1 converged, 2 breakdown, 3 nan
+  int pad;
+  struct GmStatus* hslot;  // mapped host memory receiving the status after every step
+};
+struct GmStatus {
+  double rest, beta;
+  int j, stop, why, pad;
+};
+// V: nv vectors of n doubles stored back to back (vector i at V + i*n).
+hipError_t launch_cgs_dots(const double* V, int nv, const double* w, double* partials,
+                           unsigned* counter, double* out, const int* skip, size_t n, hipStream_t s);
+hipError_t launch_cgs_update_dots(const double* V, int nv, double* w, const double* h,
+                                  double* partials, unsigned* counter, double* out, const int* skip,
+                                  size_t n, hipStream_t s);
+hipError_t launch_cgs_update_norm(const double* V, int nv, double* w, const double* h2,
+                                  double* partials, unsigned* counter, GmState* st, int M,
+                                  size_t n, hipStream_t s);
+hipError_t launch_gm_init(GmState* st, const double* beta2, double target, int M, GmStatus* hslot, hipStream_t s);
+// Sum partials[b*stride + i] over b < nblocks into out[i], i < nv (one workgroup).
+hipError_t launch_finalize(const double* partials, int nblocks, int stride, int nv, double* out, const int* skip,
+                           hipStream_t s);
+// Number of workgroups of the grid-stride reductions over n entries (<= kRedBlocks).
+int red_blocks(size_t n);
+hipError_t launch_gm_solve_y(GmState* st, int k, int M, hipStream_t s);
+hipError_t launch_gm_update_x(double* x, const double* Z, int k, const GmState* st, size_t n,
+                              hipStream_t s);
+
+constexpr int kRedBlocks = 1024;  // blocks of the grid-stride vector kernels
+constexpr int kRedThreads = 256;
+
+}  // namespace frjf

@@ -1,0 +1,57 @@
+// Internal interfaces of the host drivers.
+#pragma once
+#include "internal.h"
+
+namespace frjf {
+
+struct RowScheme {
+  int s;
+  double gamma;
+  double a[6][6], c[6][6], m[6];
+};
+struct EsdirkScheme {
+  int s;
+  double gamma;
+  double a[6][6], b[6];
+};
+const RowScheme* row_scheme(int id);
+const EsdirkScheme* esdirk_scheme(int id);
+
+struct GmWork {
+  double* grad;  // BR1 gradient traces (Navier-Stokes only)
+  GmState* st;
+  double* scal;
+  unsigned* counter;
+  double* partials;
+  double* V;
+  double* Z;
+  double* w;
+  double* r;
+};
+
+struct Carver {
+  char* p;
+  explicit Carver(void* base);
+  void* take(size_t bytes);
+};
+
+size_t gmres_bytes(const fr_disc* d, int m);
+size_t ns_trace_bytes(const fr_disc* d);
+size_t small_bytes(const fr_disc* d);
+size_t partials_count(const fr_disc* d);
+GmWork carve_gmres(Carver& c, const fr_disc* d, int m);
+hipError_t zero_counters(unsigned* c, hipStream_t s);
+fr_status device_norm(const fr_disc* d, const double* x, double* partials, unsigned* counter, double* dev_out,
+                      double* host_out, hipStream_t s);
+
+fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const double* U, const double* R0,
+                     double shift, const double* b, double* x, bool x_is_zero, const fr_gmres_opts& o,
+                     fr_gmres_stats* stats, GmWork& W, hipStream_t s);
+fr_status row_step_impl(const fr_disc* d, int scheme, double dt, double* U, const fr_solver_opts& o,
+                        fr_step_stats* st, void* work, hipStream_t s);
+fr_status esdirk_step_impl(const fr_disc* d, int scheme, double dt, double* U, const fr_solver_opts& o,
+                           fr_step_stats* st, void* work, hipStream_t s);
+fr_status bdf2_step_impl(const fr_disc* d, double dt, const double* Unm1, const double* Un, double* Unp1,
+                         const fr_solver_opts& o, fr_step_stats* st, void* work, hipStream_t s);
+
+}  // namespace frjf

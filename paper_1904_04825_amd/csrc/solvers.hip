@@ -1,0 +1,679 @@
+// Host drivers of the implicit solver (Section 4): restarted flexible GMRES
+// with the Jacobian-free product and the element-Jacobi preconditioner, the
+// ROW, ESDIRK and BDF2 time steps, and pseudo-transient continuation (PTC)
+// with SER pseudo-time stepping and rejection.  Every vector operation runs
+// on the device; the host only sequences kernels and reads scalar norms.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+#include "solvers.h"
+
+namespace frjf {
+
+// ---------------------------------------------------------------- coefficient tables
+// ROW schemes in the transformed form of eq. Rosenbrock_General.
+// ROW2: 3-stage, order 2, stiffly accurate, L-stable, gamma = 1/4 (standard form:
+//   beta_21 = 1/2, b = (5/8, 1/8, 1/4), alpha_21 = alpha_31 = alpha_32 = 1/2),
+//   used because the ROS2PR coefficients are not available.
+// ROW3: ROS34PW2 (Rang & Angermann 2005), converted from the published standard form.
+// ROW4: RODASP (Steinebach 1995), transformed form as published.
+namespace {
+
+void to_transformed(int s, const double* alpha, const double* gam, const double* b, RowScheme* out) {
+  // Gamma lower triangular: invert by forward substitution, then
+  // A = alpha Gamma^{-1}, C = diag(1/gamma) - Gamma^{-1}, m = b Gamma^{-1}.
+  double Gi[36] = {0};
+  for (int c = 0; c < s; ++c) {
+    for (int r = 0; r < s; ++r) {
+      double v = (r == c) ? 1.0 : 0.0;
+      for (int k = 0; k < r; ++k) v -= gam[r * s + k] * Gi[k * s + c];
+      Gi[r * s + c] = v / gam[r * s + r];
+    }
+  }
+  out->s = s;
+  out->gamma = gam[0];
+  for (int r = 0; r < s; ++r)
+    for (int c = 0; c < s; ++c) {
+      double a = 0.0;
+      for (int k = 0; k < s; ++k) a += alpha[r * s + k] * Gi[k * s + c];
+      out->a[r][c] = (c < r) ? a : 0.0;
+      out->c[r][c] = (c < r) ? -Gi[r * s + c] : 0.0;
+    }
+  for (int c = 0; c < s; ++c) {
+    double m = 0.0;
+    for (int k = 0; k < s; ++k) m += b[k] * Gi[k * s + c];
+    out->m[c] = m;
+  }
+}
+
+RowScheme make_row2() {
+  const double g = 0.25;
+  const double alpha[9] = {0, 0, 0, 0.5, 0, 0, 0.5, 0.5, 0};
+  const double b[3] = {5.0 / 8.0, 1.0 / 8.0, 0.25};
+  // Gamma = beta - alpha with beta_21 = 1/2 and the last row of beta equal to b
+  const double gam[9] = {g, 0, 0, 0.5 - 0.5, g, 0, b[0] - 0.5, b[1] - 0.5, g};
+  RowScheme r{};
+  to_transformed(3, alpha, gam, b, &r);
+  return r;
+}
+
+RowScheme make_ros34pw2() {
+  const double g = 0.4358665215084590;
+  double alpha[16] = {0}, gam[16] = {0};
+  alpha[1 * 4 + 0] = 0.87173304301691801;
+  alpha[2 * 4 + 0] = 0.84457060015369423;
+  alpha[2 * 4 + 1] = -0.11299064236484185;
+  alpha[3 * 4 + 2] = 1.0;
+  gam[1 * 4 + 0] = -0.87173304301691801;
+  gam[2 * 4 + 0] = -0.90338057013044082;
+  gam[2 * 4 + 1] = 0.054180672388095326;
+  gam[3 * 4 + 0] = 0.24212380706095346;
+  gam[3 * 4 + 1] = -1.2232505839045147;
+  gam[3 * 4 + 2] = 0.54526025533510214;
+  for (int i = 0; i < 4; ++i) gam[i * 4 + i] = g;
+  const double b[4] = {0.24212380706095346, -1.2232505839045147, 1.5452602553351020, 0.43586652150845900};
+  RowScheme r{};
+  to_transformed(4, alpha, gam, b, &r);
+  return r;
+}
+
+RowScheme make_rodasp() {
+  RowScheme r{};
+  r.s = 6;
+  r.gamma = 0.25;
+  const double A[6][5] = {{0, 0, 0, 0, 0},
+                          {3.0, 0, 0, 0, 0},
+                          {1.831036793486759, 0.4955183967433795, 0, 0, 0},
+                          {2.304376582692669, -0.05249275245743001, -1.176798761832782, 0, 0},
+                          {-7.170454962423024, -4.741636671481785, -16.31002631330971, -1.062004044111401, 0},
+                          {-7.170454962423024, -4.741636671481785, -16.31002631330971, -1.062004044111401, 1.0}};
+  const double C[6][5] = {{0, 0, 0, 0, 0},
+                          {-12.0, 0, 0, 0, 0},
+                          {-8.791795173947035, -2.207865586973518, 0, 0, 0},
+                          {10.81793056857153, 6.780270611428266, 19.53485944642410, 0, 0},
+                          {34.19095006749676, 15.49671153725963, 54.74760875964130, 14.16005392148534, 0},
+                          {34.62605830930532, 15.30084976114473, 56.99955578662667, 18.40807009793095,
+                           -5.714285714285717}};
+  const double m[6] = {-7.170454962423024, -4.741636671481785, -16.31002631330971, -1.062004044111401, 1.0, 1.0};
+  for (int i = 0; i < 6; ++i) {
+    for (int j = 0; j < 5; ++j) {
+      r.a[i][j] = A[i][j];
+      r.c[i][j] = C[i][j];
+    }
+    r.m[i] = m[i];
+  }
+  return r;
+}
+
+// ESDIRK Butcher tables (eq. ESDIRK2 form: explicit first stage, a_ii = omega).
+EsdirkScheme make_esdirk2() {
+  EsdirkScheme e{};
+  const double g = 1.0 - 1.0 / std::sqrt(2.0);
+  e.s = 3;
+  e.gamma = g;
+  e.a[1][0] = g;
+  e.a[1][1] = g;
+  e.a[2][0] = 0.5 * (1.0 - g);
+  e.a[2][1] = 0.5 * (1.0 - g);
+  e.a[2][2] = g;
+  for (int i = 0; i < 3; ++i) e.b[i] = e.a[2][i];
+  return e;
+}
+
+// Kennedy & Carpenter ARK3(2)4L[2]SA, implicit part (the ESDIRK3 of Bijl et al. 2002).
+EsdirkScheme make_esdirk3() {
+  EsdirkScheme e{};
+  const double g = 1767732205903.0 / 4055673282236.0;
+  e.s = 4;
+  e.gamma = g;
+  e.a[1][0] = g;
+  e.a[1][1] = g;
+  e.a[2][0] = 2746238789719.0 / 10658868560708.0;
+  e.a[2][1] = -640167445237.0 / 6845629431997.0;
+  e.a[2][2] = g;
+  e.a[3][0] = 1471266399579.0 / 7840856788654.0;
+  e.a[3][1] = -4482444167858.0 / 7529755066697.0;
+  e.a[3][2] = 11266239266428.0 / 11593286722821.0;
+  e.a[3][3] = g;
+  for (int i = 0; i < 4; ++i) e.b[i] = e.a[3][i];
+  return e;
+}
+
+// Kennedy & Carpenter ARK4(3)6L[2]SA, implicit part (the ESDIRK4 of Bijl et al. 2002).
+EsdirkScheme make_esdirk4() {
+  EsdirkScheme e{};
+  const double g = 0.25;
+  e.s = 6;
+  e.gamma = g;
+  e.a[1][0] = g;
+  e.a[1][1] = g;
+  e.a[2][0] = 8611.0 / 62500.0;
+  e.a[2][1] = -1743.0 / 31250.0;
+  e.a[2][2] = g;
+  e.a[3][0] = 5012029.0 / 34652500.0;
+  e.a[3][1] = -654441.0 / 2922500.0;
+  e.a[3][2] = 174375.0 / 388108.0;
+  e.a[3][3] = g;
+  e.a[4][0] = 15267082809.0 / 155376265600.0;
+  e.a[4][1] = -71443401.0 / 120774400.0;
+  e.a[4][2] = 730878875.0 / 902184768.0;
+  e.a[4][3] = 2285395.0 / 8070912.0;
+  e.a[4][4] = g;
+  e.a[5][0] = 82889.0 / 524892.0;
+  e.a[5][1] = 0.0;
+  e.a[5][2] = 15625.0 / 83664.0;
+  e.a[5][3] = 69875.0 / 102672.0;
+  e.a[5][4] = -2260.0 / 8211.0;
+  e.a[5][5] = g;
+  for (int i = 0; i < 6; ++i) e.b[i] = e.a[5][i];
+  return e;
+}
+
+}  // namespace
+
+const RowScheme* row_scheme(int id) {
+  static const RowScheme r2 = make_row2(), r3 = make_ros34pw2(), r4 = make_rodasp();
+  switch (id) {
+    case FR_ROW2: return &r2;
+    case FR_ROW3: return &r3;
+    case FR_ROW4: return &r4;
+  }
+  return nullptr;
+}
+
+const EsdirkScheme* esdirk_scheme(int id) {
+  static const EsdirkScheme e2 = make_esdirk2(), e3 = make_esdirk3(), e4 = make_esdirk4();
+  switch (id) {
+    case FR_ESDIRK2: return &e2;
+    case FR_ESDIRK3: return &e3;
+    case FR_ESDIRK4: return &e4;
+  }
+  return nullptr;
+}
+
+// ---------------------------------------------------------------- workspace
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t ns_trace_bytes(const fr_disc* d) {
+  // BR1: corrected-gradient traces on 4 faces x (P+1) points x 4 variables x 2 components
+  return d->physics == FR_NS_BR1 ? (size_t)d->nel * 4 * d->n * 4 * 2 * sizeof(double) : 0;
+}
+
+// Partial sums: the grid-stride reductions use kRedBlocks x (kMaxM + 2) slots, the
+// preconditioner application one slot per workgroup (at most one per element).
+size_t partials_count(const fr_disc* d) {
+  return std::max<size_t>((size_t)kRedBlocks * (kMaxM + 2), (size_t)d->nel);
+}
+
+size_t gmres_bytes(const fr_disc* d, int m) {
+  return align256(ns_trace_bytes(d)) + align256(sizeof(GmState)) + 256 + 256 +
+         align256(sizeof(double) * partials_count(d)) + align256(sizeof(double) * d->ndof) * (size_t)(2 * m + 3);
+}
+
+size_t small_bytes(const fr_disc* d) { return 256 + 256 + align256(sizeof(double) * partials_count(d)); }
+
+Carver::Carver(void* base) : p((char*)base) {}
+void* Carver::take(size_t bytes) {
+  void* r = p;
+  p += align256(bytes);
+  return r;
+}
+
+GmWork carve_gmres(Carver& c, const fr_disc* d, int m) {
+  GmWork w{};
+  w.grad = d->physics == FR_NS_BR1 ? (double*)c.take(ns_trace_bytes(d)) : nullptr;
+  w.st = (GmState*)c.take(sizeof(GmState));
+  w.scal = (double*)c.take(256);
+  w.counter = (unsigned*)c.take(256);
+  w.partials = (double*)c.take(sizeof(double) * partials_count(d));
+  w.V = (double*)c.take(sizeof(double) * d->ndof * (size_t)(m + 1));
+  w.Z = (double*)c.take(sizeof(double) * d->ndof * (size_t)m);
+  w.w = (double*)c.take(sizeof(double) * d->ndof);
+  w.r = (double*)c.take(sizeof(double) * d->ndof);
+  return w;
+}
+
+__global__ void k_zero_u32(unsigned* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+hipError_t zero_counters(unsigned* c, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, c, 64);
+  return hipGetLastError();
+}
+
+// Read `bytes` from device into the pinned host scratch and wait.
+static fr_status read_sync(const fr_disc* d, void* dst, const void* dev, size_t bytes, hipStream_t s) {
+  char* slot = (char*)d->h_pinned + 1024;  // the first KiB holds the Arnoldi status slots
+  FR_HIP(hipMemcpyAsync(slot, dev, bytes, hipMemcpyDeviceToHost, s));
+  FR_HIP(hipStreamSynchronize(s));
+  std::memcpy(dst, slot, bytes);
+  return FR_OK;
+}
+
+fr_status device_norm(const fr_disc* d, const double* x, double* partials, unsigned* counter, double* dev_out,
+                      double* host_out, hipStream_t s) {
+  FR_HIP(launch_norm2(x, d->ndof, partials, counter, dev_out, nullptr, s));
+  double v = 0.0;
+  fr_status st = read_sync(d, &v, dev_out, sizeof(double), s);
+  if (st != FR_OK) return st;
+  *host_out = std::sqrt(v);
+  return FR_OK;
+}
+
+// ---------------------------------------------------------------- FGMRES
+fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const double* U, const double* R0,
+                     double shift, const double* b, double* x, bool x_is_zero, const fr_gmres_opts& o,
+                     fr_gmres_stats* stats, GmWork& W, hipStream_t s) {
+  const size_t n = d->ndof;
+  const int m = o.m;
+  const int max_iters = o.max_iters > 0 ? o.max_iters : 50 * m;
+  fr_gmres_stats S{};
+  double* nz = W.scal + 0;     // ||z||^2 or ||x||^2 for the JF epsilon
+  double* beta2 = W.scal + 1;  // ||r||^2
+  FR_HIP(zero_counters(W.counter, s));
+
+  ResArgs ra{};
+  ra.U = U;
+  ra.R0 = R0;
+  ra.eps = o.eps > 0 ? o.eps : 1e-8;
+  ra.eps_mode = o.eps_mode;
+  ra.shift = shift;
+  ra.nrm2 = nz;
+  ra.grad = W.grad;
+
+  const double* rsrc = b;
+  if (!x_is_zero) {
+    FR_HIP(launch_norm2(x, n, W.partials, W.counter, nz, nullptr, s));
+    ResArgs a2 = ra;
+    a2.V = x;
+    a2.B = b;
+    a2.out = W.r;
+    FR_HIP(launch_residual(d, 2, a2, s));
+    S.residual_evals++;
+    rsrc = W.r;
+  }
+  FR_HIP(launch_norm2(rsrc, n, W.partials, W.counter, beta2, nullptr, s));
+  double b2 = 0.0;
+  fr_status rs = read_sync(d, &b2, beta2, sizeof(double), s);
+  if (rs != FR_OK) return rs;
+  double beta = std::sqrt(b2);
+  S.r_ref = o.ref_norm > 0 ? o.ref_norm : beta;
+  const double target = o.rtol * S.r_ref;
+  S.r_final = beta;
+  if (!std::isfinite(beta)) {
+    *stats = S;
+    return FR_ENAN;
+  }
+  if (beta <= target) {
+    S.converged = 1;
+    *stats = S;
+    return FR_OK;
+  }
+  // mapped host status written by the Givens kernel after every Arnoldi step
+  volatile GmStatus* hstat = (volatile GmStatus*)d->h_pinned;
+  GmStatus* dstat = (GmStatus*)d->d_pinned;
+  const size_t status_off = offsetof(GmState, rest);
+  fr_status result = FR_NOTCONV;
+  for (;;) {
+    hstat->stop = 0;
+    FR_HIP(launch_gm_init(W.st, beta2, target, m, dstat, s));
+    FR_HIP(launch_scale_dev(W.V, rsrc, &W.st->beta, 1, n, nullptr, s));
+    const int budget = std::min(m, max_iters - S.iters);
+    for (int j = 0; j < budget; ++j) {
+      double* vj = W.V + (size_t)j * n;
+      double* zj = W.Z + (size_t)j * n;
+      const int* skip = &W.st->stop;
+      // z_j = M^{-1} v_j; for j >= 1, v_j = w / h_{j,j-1} is formed on the fly and stored
+      if (j == 0)
+        FR_HIP(launch_ejacobi_solve(d, factors, prec, vj, nullptr, nullptr, zj, W.partials, nullptr, nz, skip, s));
+      else
+        FR_HIP(launch_ejacobi_solve(d, factors, prec, W.w, &W.st->hn, vj, zj, W.partials, nullptr, nz, skip, s));
+      ResArgs a1 = ra;
+      a1.V = zj;
+      a1.out = W.w;
+      a1.skip = skip;
+      FR_HIP(launch_residual(d, 1, a1, s));
+      FR_HIP(launch_cgs_dots(W.V, j + 1, W.w, W.partials, nullptr, W.st->h1, skip, n, s));
+      FR_HIP(launch_cgs_update_dots(W.V, j + 1, W.w, W.st->h1, W.partials, nullptr, W.st->h2, skip, n, s));
+      FR_HIP(launch_cgs_update_norm(W.V, j + 1, W.w, W.st->h2, W.partials, nullptr, W.st, m, n, s));
+      FR_HIP(hipEventRecord(d->ev[j & 1], s));
+      // wait for step j-1 while step j runs
+      if (j >= 1) {
+        FR_HIP(hipEventSynchronize(d->ev[(j - 1) & 1]));
+        if (hstat->stop) break;
+      }
+    }
+    FR_HIP(hipStreamSynchronize(s));
+    GmStatus fin;
+    rs = read_sync(d, &fin, (const char*)W.st + status_off, sizeof(GmStatus), s);
+    if (rs != FR_OK) return rs;
+    const int k = fin.j;
+    S.iters += k;
+    S.residual_evals += k;
+    S.r_final = fin.rest;
+    if (fin.why == 3) {
+      result = FR_ENAN;
+      break;
+    }
+    if (k > 0) {
+      FR_HIP(launch_gm_solve_y(W.st, k, m, s));
+      FR_HIP(launch_gm_update_x(x, W.Z, k, W.st, n, s));
+    }
+    if (fin.why == 1) {
+      S.converged = 1;
+      result = FR_OK;
+      break;
+    }
+    // cycle exhausted (or breakdown): true residual r = b - A x
+    FR_HIP(launch_norm2(x, n, W.partials, W.counter, nz, nullptr, s));
+    ResArgs a2 = ra;
+    a2.V = x;
+    a2.B = b;
+    a2.out = W.r;
+    FR_HIP(launch_residual(d, 2, a2, s));
+    S.residual_evals++;
+    FR_HIP(launch_norm2(W.r, n, W.partials, W.counter, beta2, nullptr, s));
+    rs = read_sync(d, &b2, beta2, sizeof(double), s);
+    if (rs != FR_OK) return rs;
+    beta = std::sqrt(b2);
+    S.r_final = beta;
+    rsrc = W.r;
+    if (!std::isfinite(beta)) {
+      result = FR_ENAN;
+      break;
+    }
+    if (beta <= target) {
+      S.converged = 1;
+      result = FR_OK;
+      break;
+    }
+    if (fin.why == 2) {
+      result = FR_BREAKDOWN;
+      break;
+    }
+    if (S.iters >= max_iters) {
+      result = FR_NOTCONV;
+      break;
+    }
+    S.restarts++;
+  }
+  FR_HIP(hipStreamSynchronize(s));
+  *stats = S;
+  return result;
+}
+
+// ---------------------------------------------------------------- time steps
+namespace {
+
+struct StepBufs {
+  GmWork gw;
+  void* pc;
+  double* vec[12];
+};
+
+StepBufs carve_step(const fr_disc* d, void* work, int m, int precision) {
+  Carver c(work);
+  StepBufs b{};
+  b.gw = carve_gmres(c, d, m);
+  b.pc = c.take(fr_ejacobi_bytes(d, precision));
+  for (int i = 0; i < 12; ++i) b.vec[i] = (double*)c.take(sizeof(double) * d->ndof);
+  return b;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+fr_status residual_into(const fr_disc* d, const double* U, double* R, double* grad, hipStream_t s) {
+  ResArgs a{};
+  a.U = U;
+  a.out = R;
+  a.grad = grad;
+  FR_HIP(launch_residual(d, 0, a, s));
+  return FR_OK;
+}
+
+fr_status lincomb(double* y, std::initializer_list<std::pair<const double*, double>> terms, size_t n,
+                  hipStream_t s) {
+  const double* xs[8];
+  double cs[8];
+  int k = 0;
+  for (auto& t : terms) {
+    xs[k] = t.first;
+    cs[k] = t.second;
+    ++k;
+  }
+  FR_HIP(launch_lincomb(y, k, xs, cs, n, s));
+  return FR_OK;
+}
+
+fr_status lincomb_v(double* y, int k, const double* const* xs, const double* cs, size_t n, hipStream_t s) {
+  FR_HIP(launch_lincomb(y, k, xs, cs, n, s));
+  return FR_OK;
+}
+
+#define FR_TRY(expr)                 \
+  do {                               \
+    fr_status st_ = (expr);          \
+    if (st_ < 0) return st_;         \
+  } while (0)
+
+// PTC for F(q) = (q - cst)/(omega dt) - R(q) = 0, in place on q; Rq holds R(q) on entry
+// (if rq_valid) and on exit.
+fr_status ptc_solve(const fr_disc* d, const double* cst, double omega_dt, double dt, double* q, double* Rq,
+                    bool rq_valid, const fr_solver_opts& o, StepBufs& B, fr_step_stats* st, hipStream_t s) {
+  const size_t n = d->ndof;
+  double* negF = B.vec[9];
+  double* dq = B.vec[10];
+  if (!rq_valid) {
+    FR_TRY(residual_into(d, q, Rq, B.gw.grad, s));
+    st->residual_evals++;
+  }
+  const double iw = 1.0 / omega_dt;
+  FR_TRY(lincomb(negF, {{cst, iw}, {q, -iw}, {Rq, 1.0}}, n, s));
+  double nF = 0.0;
+  FR_TRY(device_norm(d, negF, B.gw.partials, B.gw.counter, B.gw.scal + 2, &nF, s));
+  const double nF0 = nF;
+  double dtau = o.dtau_init > 0 ? o.dtau_init : dt;
+  double dtau_max = o.dtau_max > 0 ? o.dtau_max : 1e20;
+  const int max_ptc = o.max_ptc > 0 ? o.max_ptc : 200;
+  const int max_rej = o.max_reject > 0 ? o.max_reject : 30;
+  int k = 0, rejects = 0;
+  fr_ejacobi pc{B.pc, o.precond_precision, 0.0};
+  while (nF > o.tol_nl * nF0) {
+    if (!std::isfinite(nF)) return FR_ENAN;
+    if (k >= max_ptc) return FR_NOTCONV;
+    if (rejects > max_rej) return FR_REJECTED;
+    const double shift = 1.0 / dtau + iw;
+    FR_HIP(launch_ejacobi_assemble(d, q, shift, pc.d_factors, pc.precision, 1, s));
+    FR_TRY(lincomb(dq, {}, n, s));
+    fr_gmres_stats gs{};
+    fr_status g = gmres_core(d, pc.d_factors, pc.precision, q, Rq, shift, negF, dq, true, o.lin, &gs, B.gw, s);
+    if (g < 0) return g;
+    st->gmres_iters += gs.iters;
+    st->linear_solves++;
+    st->residual_evals += gs.residual_evals;
+    if (!gs.converged) st->unconverged++;
+    if (g == FR_ENAN) return FR_ENAN;
+    if (!(gs.r_final <= 0.1 * gs.r_ref)) {
+      // the linear solve did not gain one order of magnitude: reject, halve dtau_max
+      st->rejections++;
+      rejects++;
+      dtau_max *= 0.5;
+      dtau = std::min(dtau, dtau_max);
+      continue;
+    }
+    FR_TRY(lincomb(q, {{q, 1.0}, {dq, 1.0}}, n, s));
+    FR_TRY(residual_into(d, q, Rq, B.gw.grad, s));
+    st->residual_evals++;
+    FR_TRY(lincomb(negF, {{cst, iw}, {q, -iw}, {Rq, 1.0}}, n, s));
+    double nFn = 0.0;
+    FR_TRY(device_norm(d, negF, B.gw.partials, B.gw.counter, B.gw.scal + 2, &nFn, s));
+    dtau = (nFn > 0.0) ? std::min(dtau * nF / nFn, dtau_max) : dtau_max;
+    nF = nFn;
+    ++k;
+    st->ptc_iters++;
+  }
+  return FR_OK;
+}
+
+}  // namespace
+
+fr_status row_step_impl(const fr_disc* d, int scheme, double dt, double* U, const fr_solver_opts& o,
+                        fr_step_stats* st, void* work, hipStream_t s) {
+  const RowScheme* T = row_scheme(scheme);
+  const size_t n = d->ndof;
+  const double t0 = now_s();
+  StepBufs B = carve_step(d, work, o.lin.m, o.precond_precision);
+  FR_HIP(zero_counters(B.gw.counter, s));
+  double* R0 = B.vec[0];
+  double* Ui = B.vec[1];
+  double* rhs = B.vec[2];
+  double** Y = B.vec + 3;  // up to 6 stage vectors: vec[3..8]
+  FR_TRY(residual_into(d, U, R0, B.gw.grad, s));
+  st->residual_evals++;
+  const double shift = 1.0 / (T->gamma * dt);
+  FR_HIP(launch_ejacobi_assemble(d, U, shift, B.pc, o.precond_precision, 1, s));
+  fr_status worst = FR_OK;
+  for (int i = 0; i < T->s; ++i) {
+    if (i == 0) {
+      FR_TRY(lincomb(rhs, {{R0, 1.0}}, n, s));
+    } else {
+      const double* xs[8];
+      double cs[8];
+      int k = 0;
+      xs[k] = U;
+      cs[k++] = 1.0;
+      bool any = false;
+      for (int j = 0; j < i; ++j)
+        if (T->a[i][j] != 0.0) {
+          xs[k] = Y[j];
+          cs[k++] = T->a[i][j];
+          any = true;
+        }
+      if (any) {
+        FR_TRY(lincomb_v(Ui, k, xs, cs, n, s));
+        FR_TRY(residual_into(d, Ui, rhs, B.gw.grad, s));
+        st->residual_evals++;
+      } else {
+        FR_TRY(lincomb(rhs, {{R0, 1.0}}, n, s));
+      }
+      k = 0;
+      xs[k] = rhs;
+      cs[k++] = 1.0;
+      for (int j = 0; j < i; ++j)
+        if (T->c[i][j] != 0.0) {
+          xs[k] = Y[j];
+          cs[k++] = T->c[i][j] / dt;
+        }
+      if (k > 1) FR_TRY(lincomb_v(rhs, k, xs, cs, n, s));
+    }
+    FR_TRY(lincomb(Y[i], {}, n, s));
+    fr_gmres_stats gs{};
+    fr_status g = gmres_core(d, B.pc, o.precond_precision, U, R0, shift, rhs, Y[i], true, o.lin, &gs, B.gw, s);
+    if (g < 0) return g;
+    st->gmres_iters += gs.iters;
+    st->linear_solves++;
+    st->residual_evals += gs.residual_evals;
+    if (g != FR_OK) {
+      st->unconverged++;
+      if (worst == FR_OK || g == FR_ENAN) worst = g;
+    }
+  }
+  if (worst == FR_OK || (o.commit_unconverged && worst != FR_ENAN)) {
+    const double* xs[8];
+    double cs[8];
+    int k = 0;
+    xs[k] = U;
+    cs[k++] = 1.0;
+    for (int j = 0; j < T->s; ++j) {
+      xs[k] = Y[j];
+      cs[k++] = T->m[j];
+    }
+    FR_TRY(lincomb_v(U, k, xs, cs, n, s));
+  }
+  FR_HIP(hipStreamSynchronize(s));
+  st->wall_s = now_s() - t0;
+  return worst;
+}
+
+fr_status esdirk_step_impl(const fr_disc* d, int scheme, double dt, double* U, const fr_solver_opts& o,
+                           fr_step_stats* st, void* work, hipStream_t s) {
+  const EsdirkScheme* T = esdirk_scheme(scheme);
+  const size_t n = d->ndof;
+  const double t0 = now_s();
+  StepBufs B = carve_step(d, work, o.lin.m, o.precond_precision);
+  FR_HIP(zero_counters(B.gw.counter, s));
+  double** Rj = B.vec;      // vec[0..5]
+  double* q = B.vec[6];
+  double* cst = B.vec[7];
+  FR_TRY(residual_into(d, U, Rj[0], B.gw.grad, s));
+  st->residual_evals++;
+  FR_TRY(lincomb(q, {{U, 1.0}}, n, s));
+  fr_status worst = FR_OK;
+  for (int i = 1; i < T->s; ++i) {
+    const double* xs[8];
+    double cs[8];
+    int k = 0;
+    xs[k] = U;
+    cs[k++] = 1.0;
+    for (int j = 0; j < i; ++j)
+      if (T->a[i][j] != 0.0) {
+        xs[k] = Rj[j];
+        cs[k++] = dt * T->a[i][j];
+      }
+    FR_TRY(lincomb_v(cst, k, xs, cs, n, s));
+    FR_TRY(lincomb(Rj[i], {{Rj[i - 1], 1.0}}, n, s));  // R(q) at the stage's starting guess q_{i-1}
+    fr_status p = ptc_solve(d, cst, T->gamma * dt, dt, q, Rj[i], true, o, B, st, s);
+    if (p < 0) return p;
+    if (p != FR_OK && worst == FR_OK) worst = p;
+    if (p == FR_ENAN || (p != FR_OK && !o.commit_unconverged)) break;  // the step will not be committed
+  }
+  if (worst == FR_OK || (o.commit_unconverged && worst != FR_ENAN)) {
+    const double* xs[8];
+    double cs[8];
+    int k = 0;
+    xs[k] = U;
+    cs[k++] = 1.0;
+    for (int i = 0; i < T->s; ++i)
+      if (T->b[i] != 0.0) {
+        xs[k] = Rj[i];
+        cs[k++] = dt * T->b[i];
+      }
+    FR_TRY(lincomb_v(U, k, xs, cs, n, s));
+  }
+  FR_HIP(hipStreamSynchronize(s));
+  st->wall_s = now_s() - t0;
+  return worst;
+}
+
+fr_status bdf2_step_impl(const fr_disc* d, double dt, const double* Unm1, const double* Un, double* Unp1,
+                         const fr_solver_opts& o, fr_step_stats* st, void* work, hipStream_t s) {
+  const size_t n = d->ndof;
+  const double t0 = now_s();
+  StepBufs B = carve_step(d, work, o.lin.m, o.precond_precision);
+  FR_HIP(zero_counters(B.gw.counter, s));
+  double* q = B.vec[0];
+  double* Rq = B.vec[1];
+  double* cst = B.vec[2];
+  double omega;
+  if (Unm1 == nullptr) {
+    omega = 1.0;
+    FR_TRY(lincomb(cst, {{Un, 1.0}}, n, s));
+  } else {
+    omega = 2.0 / 3.0;
+    FR_TRY(lincomb(cst, {{Un, 4.0 / 3.0}, {Unm1, -1.0 / 3.0}}, n, s));
+  }
+  FR_TRY(lincomb(q, {{Un, 1.0}}, n, s));
+  fr_status p = ptc_solve(d, cst, omega * dt, dt, q, Rq, false, o, B, st, s);
+  if (p < 0) return p;
+  if (p == FR_OK || (o.commit_unconverged && p != FR_ENAN)) FR_TRY(lincomb(Unp1, {{q, 1.0}}, n, s));
+  FR_HIP(hipStreamSynchronize(s));
+  st->wall_s = now_s() - t0;
+  return p;
+}
+
+}  // namespace frjf

@@ -1,0 +1,63 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/frjf.h declares, and its compiled-in coefficient tables equal the
+oracle's (independently typed) tables."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "frjf.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fr_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    from paper_1904_04825_amd import _lib
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding declares signatures for all of them
+    assert set(names) <= set(_lib._SIGS), set(names) - set(_lib._SIGS)
+
+
+def test_binding_struct_sizes_match_header_layout():
+    from paper_1904_04825_amd import _lib
+    assert ctypes.sizeof(_lib.DiscDesc) == 5 * 4 + 4 + 4 * 8 + 8
+    assert ctypes.sizeof(_lib.GmresOptsC) == 2 * 4 + 3 * 8 + 8
+    assert ctypes.sizeof(_lib.SolverOptsC) == ctypes.sizeof(_lib.GmresOptsC) + 3 * 8 + 4 * 4
+
+
+@pytest.mark.parametrize("scheme", [2, 3, 4])
+def test_row_tables_match_oracle(scheme):
+    from paper_1904_04825_amd.api import scheme_table
+    from oracle.tableaux import ROW
+    A, C, m, g = scheme_table(0, scheme)
+    t = ROW[f"ROW{scheme}"]
+    assert g == pytest.approx(t.gamma, abs=1e-15)
+    assert np.allclose(A, t.A, atol=1e-13) and np.allclose(C, t.C, atol=1e-12) and np.allclose(m, t.m, atol=1e-13)
+
+
+@pytest.mark.parametrize("scheme", [2, 3, 4])
+def test_esdirk_tables_match_oracle(scheme):
+    from paper_1904_04825_amd.api import scheme_table
+    from oracle.tableaux import ESDIRK
+    A, _, b, g = scheme_table(1, scheme)
+    t = ESDIRK[f"ESDIRK{scheme}"]
+    assert np.allclose(A, t.A, atol=1e-15) and np.allclose(b, t.b, atol=1e-15) and g == t.gamma
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    from paper_1904_04825_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.lib()

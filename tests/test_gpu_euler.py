@@ -1,0 +1,126 @@
+"""GPU parity of the Euler path (residual, JF product, element-Jacobi) against
+the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import fr_inputs as fi
+from oracle import linear
+from oracle.problem import l2_error, sample_state
+from tests.gpu_common import rel, residual_parity, setup, to_gpu, to_np, vortex_state
+
+pytestmark = pytest.mark.gpu
+
+# meshes span several tiles with a ragged tail for every tile shape (P2: 8x4, P3: 4x4, P4: 5x2)
+MESHES = {2: (19, 9), 3: (13, 11), 4: (13, 7)}
+
+
+@pytest.mark.parametrize("P", [2, 3, 4])
+@pytest.mark.parametrize("flux", ["rusanov", "roe"])
+def test_residual_parity(P, flux):
+    nx, ny = MESHES[P]
+    print(f"residual parity P={P} flux={flux} mesh={nx}x{ny}", flush=True)
+    _, op, disc = setup(nx, ny, P, flux)
+    U = vortex_state(op)
+    Rg = to_np(disc.residual(to_gpu(U)))
+    Ro = op.residual(U)
+    print(f"  rel err {rel(Rg, Ro):.3e}  budget measure {residual_parity(Rg, Ro, op, U):.3e}", flush=True)
+    assert residual_parity(Rg, Ro, op, U) <= 1e-12
+
+
+@pytest.mark.parametrize("P", [2, 3, 4])
+def test_residual_freestream_and_conservation(P):
+    nx, ny = MESHES[P]
+    _, op, disc = setup(nx, ny, P, "roe", seed=8)
+    one = np.ones((op.nel, (P + 1) ** 2))
+    Uf = np.stack([1.2 * one, 0.84 * one, -0.48 * one, (0.9 / 0.4 + 0.5 * 1.2 * (0.49 + 0.16)) * one])
+    assert np.abs(to_np(disc.residual(to_gpu(Uf)))).max() < 1e-12
+    U = vortex_state(op, 1.1)
+    R = to_np(disc.residual(to_gpu(U))).reshape(4, op.nel, -1)
+    w = op.b.w
+    wk = (w[:, None] * w[None, :]).reshape(-1)
+    J = op.geo.J.reshape(op.nel, -1)
+    for v in range(4):
+        assert abs(np.sum(wk * J * R[v])) < 1e-11
+
+
+def test_residual_minimum_mesh_and_full_workload_mesh():
+    for (nx, ny, P, seed) in ((2, 2, 3, 1), (2, 5, 2, 4), (64, 64, 3, 2)):
+        _, op, disc = setup(nx, ny, P, "rusanov", seed=seed)
+        U = vortex_state(op, 0.7)
+        Rg, Ro = to_np(disc.residual(to_gpu(U))), op.residual(U)
+        print(f"  {nx}x{ny} P{P}: rel err {rel(Rg, Ro):.3e}  budget measure {residual_parity(Rg, Ro, op, U):.3e}",
+              flush=True)
+        assert residual_parity(Rg, Ro, op, U) <= 1e-12
+
+
+def test_solution_points():
+    _, op, disc = setup(13, 11, 3)
+    xy = to_np(disc.solution_points())
+    x, y = op.geo.points()
+    assert np.abs(xy[0] - x).max() < 1e-13 and np.abs(xy[1] - y).max() < 1e-13
+
+
+@pytest.mark.parametrize("P", [2, 3, 4])
+@pytest.mark.parametrize("mode", ["rms", "abs"])
+def test_jf_matvec_parity(P, mode):
+    from paper_1904_04825_amd import EPS_ABS, EPS_RMS
+    nx, ny = MESHES[P]
+    _, op, disc = setup(nx, ny, P, "roe" if P == 3 else "rusanov")
+    U = vortex_state(op)
+    R0 = op.residual(U)
+    v = fi.random_vector(U.shape, seed=5 + P, scale=1.0 if mode == "abs" else 1e-3)
+    shift = 4.0
+    Ao = linear.jf_matvec(op.residual, U, R0, v, shift, mode=mode)
+    Ag = to_np(disc.jf_matvec(to_gpu(U), to_gpu(R0), to_gpu(v), shift, 1e-8, EPS_RMS if mode == "rms" else EPS_ABS))
+    assert rel(Ag, Ao) <= 1e-6
+    # v = 0 gives exactly zero
+    z = disc.jf_matvec(to_gpu(U), to_gpu(R0), to_gpu(np.zeros_like(v)), shift)
+    assert float(torch.abs(z).max()) == 0.0
+
+
+@pytest.mark.parametrize("P", [2, 3, 4])
+@pytest.mark.parametrize("flux", ["rusanov", "roe"])
+def test_ejacobi_assemble_parity(P, flux):
+    nx, ny = (5, 4) if P < 4 else (5, 3)
+    _, op, disc = setup(nx, ny, P, flux, seed=6)
+    U = vortex_state(op)
+    shift = 3.0
+    Bo = linear.ejacobi_blocks(op, U, shift)
+    Bg = to_np(disc.ejacobi_assemble(to_gpu(U), shift))
+    for e in range(op.nel):
+        assert np.linalg.norm(Bg[e] - Bo[e]) <= 1e-6 * np.linalg.norm(Bo[e])
+
+
+@pytest.mark.parametrize("P", [2, 3, 4])
+def test_ejacobi_inverse_and_solve_parity(P):
+    from paper_1904_04825_amd import F32, F64
+    nx, ny = (6, 5) if P < 4 else (5, 3)
+    _, op, disc = setup(nx, ny, P, "roe", seed=7)
+    U = vortex_state(op)
+    Bo = linear.ejacobi_blocks(op, U, 2.0)
+    r = fi.random_vector(U.shape, seed=11)
+    zo = linear.ejacobi_apply(op, Bo, r)
+    pc = disc.ejacobi_factor_blocks(torch.as_tensor(Bo), F64)
+    zg = to_np(disc.ejacobi_solve(pc, to_gpu(r)))
+    kappa = max(np.linalg.cond(b) for b in Bo)
+    assert rel(zg, zo) <= 1e-14 * kappa * 10
+    pc32 = disc.ejacobi_factor_blocks(torch.as_tensor(Bo), F32)
+    z32 = to_np(disc.ejacobi_solve(pc32, to_gpu(r)))
+    assert rel(z32, zo) <= kappa * 6e-8 * 10
+    # assembled + inverted on the GPU in one call, FP64
+    pcg = disc.ejacobi_factor(to_gpu(U), 2.0, F64)
+    zf = to_np(disc.ejacobi_solve(pcg, to_gpu(r)))
+    assert rel(zf, zo) <= 1e-6
+
+
+def test_l2_error_parity():
+    _, op, disc = setup(13, 11, 3)
+    v = fi.Vortex()
+    U = vortex_state(op, 0.0) * (1.0 + 1e-3 * fi.random_vector((4, op.nel, 16), seed=3))
+    x, y = op.geo.points()
+    ex = v.conservative(x, y, 0.0)
+    for var, (num, exact) in enumerate(((U[0], ex[0]), (U[1] / U[0], ex[1] / ex[0]))):
+        eo = l2_error(op, num, exact)
+        eg = disc.l2_error_vortex(to_gpu(U), var, 0.0, v)
+        assert abs(eg - eo) <= 1e-10 * eo

@@ -1,0 +1,147 @@
+"""GPU parity of FGMRES and the ROW / ESDIRK / BDF2 steps against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import fr_inputs as fi
+from oracle import integrators as I
+from oracle import linear
+from oracle.tableaux import ESDIRK, ROW
+from tests.gpu_common import rel, setup, to_gpu, to_np, vortex_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("P,m", [(2, 20), (3, 8)])
+def test_gmres_parity(P, m):
+    from paper_1904_04825_amd import F64, GmresOpts
+    _, op, disc = setup(9, 7, P, "roe", seed=12)
+    U = vortex_state(op)
+    R0 = op.residual(U)
+    shift = 1.0 / (0.25 * 0.2)
+    b = fi.random_vector(U.shape, seed=21)
+    rtol = 1e-10
+    pc_o = linear.ElementJacobi(op, U, shift)
+    xo, so = linear.fgmres(lambda v: linear.jf_matvec(op.residual, U, R0, v, shift), pc_o.apply, b, m=m, rtol=rtol)
+    Ug, R0g = to_gpu(U), to_gpu(R0)
+    pc = disc.ejacobi_factor(Ug, shift, F64)
+    xg, sg = disc.gmres_solve(pc, Ug, R0g, shift, to_gpu(b), opts=GmresOpts(m=m, rtol=rtol))
+    print("oracle", so, "gpu", sg, flush=True)
+    assert sg["status"] == 0 and sg["converged"] == 1
+    assert abs(sg["iters"] - so.iters) <= 1
+    assert rel(to_np(xg), xo) <= 10 * rtol * 100
+
+
+def test_gmres_nonzero_initial_guess_and_restart():
+    from paper_1904_04825_amd import F64, GmresOpts
+    _, op, disc = setup(6, 6, 2, "rusanov", seed=13)
+    U = vortex_state(op)
+    R0 = op.residual(U)
+    shift = 2.0
+    b = fi.random_vector(U.shape, seed=22)
+    x0 = fi.random_vector(U.shape, seed=23, scale=0.1)
+    pc_o = linear.ElementJacobi(op, U, shift)
+    Ug = to_gpu(U)
+    pc = disc.ejacobi_factor(Ug, shift, F64)
+    # m = 10 converges after several restarts; m = 3 does not within 50 m iterations (oracle alike)
+    for m, conv in ((10, True), (3, False)):
+        xo, so = linear.fgmres(lambda v: linear.jf_matvec(op.residual, U, R0, v, shift), pc_o.apply, b, x0=x0, m=m,
+                               rtol=1e-9)
+        xg, sg = disc.gmres_solve(pc, Ug, to_gpu(R0), shift, to_gpu(b), x=to_gpu(x0), opts=GmresOpts(m=m, rtol=1e-9))
+        print(m, "oracle", so, "gpu", sg, flush=True)
+        assert so.converged == conv and bool(sg["converged"]) == conv
+        assert sg["status"] == (0 if conv else 1)
+        # restarted cycles diverge slowly (CGS2 vs MGS rounding, FD product): counts agree within 25 %
+        assert abs(sg["iters"] - so.iters) <= 0.25 * so.iters
+        if conv:
+            assert sg["restarts"] >= 1 and rel(to_np(xg), xo) <= 1e-7
+
+
+def test_gmres_reports_nan():
+    from paper_1904_04825_amd import F64, GmresOpts
+    _, op, disc = setup(4, 4, 2, "rusanov", seed=14)
+    U = vortex_state(op)
+    R0 = op.residual(U)
+    b = fi.random_vector(U.shape, seed=1)
+    b[0, 0, 0] = np.nan
+    Ug = to_gpu(U)
+    pc = disc.ejacobi_factor(Ug, 5.0, F64)
+    xg, sg = disc.gmres_solve(pc, Ug, to_gpu(R0), 5.0, to_gpu(b), opts=GmresOpts(m=5, rtol=1e-8))
+    assert sg["status"] == 3   # FR_ENAN
+
+
+def test_row2_vortex_8x8_p2_twenty_steps():
+    """The 8x8 P=2 vortex workload: ROW2, dt = 0.05, 20 steps, GMRES(20) rtol 1e-8."""
+    from paper_1904_04825_amd import GmresOpts, SolverOpts
+    _, op, disc = setup(8, 8, 2, "rusanov", perturb=0.0)
+    U = vortex_state(op, 0.0)
+    Ug = to_gpu(U)
+    Uo = U.copy()
+    opts = SolverOpts(lin=GmresOpts(m=20, rtol=1e-8))
+    iters_g, iters_o = [], []
+    for n in range(20):
+        st = disc.row_step(Ug, 2, 0.05, opts)
+        assert st["status"] == 0
+        Uo, so = I.row_step(op, ROW["ROW2"], 0.05, Uo, I.LinOpts(m=20, rtol=1e-8))
+        iters_g.append(st["gmres_iters"])
+        iters_o.append(so.gmres_iters)
+    print("gmres iters gpu", iters_g, "oracle", iters_o, flush=True)
+    assert rel(to_np(Ug), Uo) <= 1e-8
+
+
+@pytest.mark.parametrize("scheme", [3, 4])
+def test_row_steps_perturbed_p3(scheme):
+    from paper_1904_04825_amd import GmresOpts, SolverOpts
+    _, op, disc = setup(7, 6, 3, "roe", seed=2)
+    U = vortex_state(op, 0.0)
+    Ug = to_gpu(U)
+    opts = SolverOpts(lin=GmresOpts(m=20, rtol=1e-10))
+    Uo = U.copy()
+    for n in range(2):
+        st = disc.row_step(Ug, scheme, 0.1, opts)
+        assert st["status"] == 0
+        Uo, _ = I.row_step(op, ROW[f"ROW{scheme}"], 0.1, Uo, I.LinOpts(m=20, rtol=1e-10))
+    assert rel(to_np(Ug), Uo) <= 1e-8
+
+
+@pytest.mark.parametrize("scheme", [2, 3, 4])
+def test_esdirk_step_parity(scheme):
+    from paper_1904_04825_amd import GmresOpts, SolverOpts
+    _, op, disc = setup(6, 5, 2, "rusanov", seed=4)
+    U = vortex_state(op, 0.0)
+    Ug = to_gpu(U)
+    opts = SolverOpts(lin=GmresOpts(m=20, rtol=1e-10), tol_nl=1e-10)
+    st = disc.esdirk_step(Ug, scheme, 0.2, opts)
+    Uo, so = I.esdirk_step(op, ESDIRK[f"ESDIRK{scheme}"], 0.2, U, I.LinOpts(m=20, rtol=1e-10), I.NlOpts(tol_nl=1e-10))
+    print("gpu", st, "oracle ptc", so.ptc_iters, so.gmres_iters, flush=True)
+    assert st["status"] == 0
+    assert rel(to_np(Ug), Uo) <= 1e-8
+
+
+def test_bdf2_parity():
+    from paper_1904_04825_amd import GmresOpts, SolverOpts
+    _, op, disc = setup(6, 5, 2, "roe", seed=5)
+    U0 = vortex_state(op, 0.0)
+    opts = SolverOpts(lin=GmresOpts(m=20, rtol=1e-10), tol_nl=1e-10)
+    lin, nl = I.LinOpts(m=20, rtol=1e-10), I.NlOpts(tol_nl=1e-10)
+    U1o, _ = I.bdf2_step(op, 0.2, None, U0, lin, nl)
+    U2o, _ = I.bdf2_step(op, 0.2, U0, U1o, lin, nl)
+    U0g = to_gpu(U0)
+    U1g, s1 = disc.bdf2_step(None, U0g, 0.2, opts)
+    U2g, s2 = disc.bdf2_step(U0g, U1g, 0.2, opts)
+    assert s1["status"] == 0 and s2["status"] == 0
+    assert rel(to_np(U1g), U1o) <= 1e-8 and rel(to_np(U2g), U2o) <= 1e-8
+
+
+def test_ptc_rejection_leaves_state_unchanged():
+    """A single GMRES iteration cannot gain an order of magnitude: every PTC attempt is
+    rejected, dtau_max halves, and the step reports FR_REJECTED without touching U."""
+    from paper_1904_04825_amd import GmresOpts, SolverOpts
+    _, op, disc = setup(4, 4, 2, "rusanov", seed=6)
+    U = vortex_state(op, 0.0)
+    Ug = to_gpu(U)
+    before = Ug.clone()
+    opts = SolverOpts(lin=GmresOpts(m=1, max_iters=1, rtol=1e-3), tol_nl=1e-8, max_reject=3, dtau_init=1e3)
+    st = disc.esdirk_step(Ug, 3, 1.0, opts)
+    assert st["status"] == 4 and st["rejections"] == 4
+    assert torch.equal(Ug, before)
