@@ -38,16 +38,16 @@ def parse():
     ap.add_argument("--precond", default="f64", choices=["f64", "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernels", action="store_true", help="skip the per-kernel timing block")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 1 GiB device-to-device copy (counter calibration for rocprofv3 --pmc runs)")
     return ap.parse_args()
 
 
-def kernel_source_sha():
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_1904_04825_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
-    return h.hexdigest()[:16]
+def source_sha(rel):
+    """Hash of the source file of a kernel: counter-derived traffic is reported only while
+    the kernel is unchanged since the counters were taken."""
+    with open(os.path.join(ROOT, rel), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
 def time_kernel(fn, reps=50, warm=5):
@@ -175,12 +175,21 @@ def main():
         if os.path.exists(tp):
             with open(tp) as fh:
                 tj = json.load(fh)
-            if tj.get("source_sha") == kernel_source_sha() and tj.get("kernel") == dom:
+            if tj.get("kernel") == dom and tj.get("source_sha") == source_sha(tj["source"]) \
+                    and prec == F64 and WORKLOAD == "vortex64_p3_perturbed":
                 traffic = tj.get("bytes_per_launch")
         ach = kernels[dom]["GBs"]
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
                            "alg_bytes_per_launch": solve_bytes}
+
+    if args.calib_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["extra"]["calib_copy_bytes"] = src.numel() * 8
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nodes, U0_np.reshape(4, disc.nel, -1), args.dt)

@@ -35,25 +35,38 @@ __device__ __forceinline__ double block_sum(double v) {
 }
 
 int red_blocks(size_t n) {
-  const size_t b = (n + (size_t)kRedThreads * 4 - 1) / ((size_t)kRedThreads * 4);
+  const size_t b = (n + (size_t)kRedThreads - 1) / (size_t)kRedThreads;
   return (int)std::max<size_t>(1, std::min<size_t>(b, kRedBlocks));
 }
 
-// One workgroup: out[i] = sum_b partials[b*stride + i] in block order, i < nv.
+// out[i] = sum_b partials[b*stride + i], i < nv: one wavefront per output value, its
+// lanes striding over the blocks, then a fixed-order wavefront tree (deterministic).
 __global__ void __launch_bounds__(kRedThreads) k_finalize(const double* __restrict__ partials, int nblocks, int stride,
                                                           int nv, double* out, const int* skip) {
   if (skip != nullptr && *skip) return;
-  for (int i = 0; i < nv; ++i) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kRedThreads) s += partials[(size_t)b * stride + i];
-    s = block_sum(s);
-    if (threadIdx.x == 0) out[i] = s;
+  const int i = blockIdx.x * (kRedThreads / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= nv) return;
+  // all loads of a lane issued together (up to 16 per lane, kRedBlocks = 1024)
+  double a[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int b = lane + 64 * q;
+    a[q] = (b < nblocks) ? partials[(size_t)b * stride + i] : 0.0;
   }
+  double s = 0.0;
+  for (int b = lane + 64 * 16; b < nblocks; b += 64) s += partials[(size_t)b * stride + i];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) s += a[q];
+  s = wave_sum(s);
+  if (lane == 0) out[i] = s;
 }
 
 hipError_t launch_finalize(const double* partials, int nblocks, int stride, int nv, double* out, const int* skip,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedThreads), 0, s, partials, nblocks, stride, nv, out, skip);
+  const int waves = kRedThreads / 64;
+  hipLaunchKernelGGL(k_finalize, dim3((nv + waves - 1) / waves), dim3(kRedThreads), 0, s, partials, nblocks, stride,
+                     nv, out, skip);
   return hipGetLastError();
 }
 
@@ -150,14 +163,12 @@ __global__ void __launch_bounds__(kRedThreads) k_cgs_dots(const double* __restri
   }
 }
 
+static hipError_t cgs_pass(const double* V, int nv, double* w, const double* h, double* partials, double* out,
+                           const int* skip, size_t n, hipStream_t s);
+
 hipError_t launch_cgs_dots(const double* V, int nv, const double* w, double* partials, unsigned*, double* out,
                            const int* skip, size_t n, hipStream_t s) {
-  const int nb = red_blocks(n);
-  dim3 grid(nb, (nv + kChunk - 1) / kChunk);
-  hipLaunchKernelGGL(k_cgs_dots, grid, dim3(kRedThreads), 0, s, V, nv, w, partials, skip, n);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_finalize(partials, nb, kMaxM + 2, nv, out, skip, s);
+  return cgs_pass(V, nv, const_cast<double*>(w), nullptr, partials, out, skip, n, s);
 }
 
 // w -= sum_t h[t] V_t (t < nv)
@@ -174,12 +185,72 @@ __global__ void __launch_bounds__(256) k_cgs_update(const double* __restrict__ V
   }
 }
 
-hipError_t launch_cgs_update_dots(const double* V, int nv, double* w, const double* h, double* partials,
-                                  unsigned* counter, double* out, const int* skip, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_cgs_update, dim3(red_blocks(n)), dim3(256), 0, s, V, nv, w, h, skip, n);
+// Fused CGS pass: w -= sum_t h[t] V_t (if h) and partial sums of <w, V_t>, reading each
+// V_t once; V_t(i) held in registers (NV >= nv, compile-time).
+template <int NV>
+__global__ void __launch_bounds__(kRedThreads) k_cgs_pass(const double* __restrict__ V, int nv, double* __restrict__ w,
+                                                          const double* __restrict__ h, double* partials,
+                                                          const int* skip, size_t n) {
+  if (skip != nullptr && *skip) return;
+  __shared__ double sh[NV];
+  if (threadIdx.x < NV) sh[threadIdx.x] = (h != nullptr && threadIdx.x < nv) ? h[threadIdx.x] : 0.0;
+  __syncthreads();
+  double acc[NV];
+#pragma unroll
+  for (int t = 0; t < NV; ++t) acc[t] = 0.0;
+  for (size_t i = blockIdx.x * (size_t)kRedThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kRedThreads) {
+    double vr[NV];
+#pragma unroll
+    for (int t = 0; t < NV; ++t) vr[t] = (t < nv) ? V[(size_t)t * n + i] : 0.0;
+    double s = w[i];
+    if (h != nullptr) {
+#pragma unroll
+      for (int t = 0; t < NV; ++t) s = fma(-sh[t], vr[t], s);
+      w[i] = s;
+    }
+#pragma unroll
+    for (int t = 0; t < NV; ++t) acc[t] = fma(s, vr[t], acc[t]);
+  }
+  __shared__ double red[kRedThreads / 64][NV];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < NV; ++t) {
+    const double r = wave_sum(acc[t]);
+    if (lane == 0) red[wv][t] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < nv) {
+    double r = 0.0;
+    for (int q = 0; q < kRedThreads / 64; ++q) r += red[q][threadIdx.x];
+    partials[(size_t)blockIdx.x * (kMaxM + 2) + threadIdx.x] = r;
+  }
+}
+
+static hipError_t cgs_pass(const double* V, int nv, double* w, const double* h, double* partials, double* out,
+                           const int* skip, size_t n, hipStream_t s) {
+  const int nb = red_blocks(n);
+  if (nv <= 8)
+    hipLaunchKernelGGL(k_cgs_pass<8>, dim3(nb), dim3(kRedThreads), 0, s, V, nv, w, h, partials, skip, n);
+  else if (nv <= 16)
+    hipLaunchKernelGGL(k_cgs_pass<16>, dim3(nb), dim3(kRedThreads), 0, s, V, nv, w, h, partials, skip, n);
+  else if (nv <= 24)
+    hipLaunchKernelGGL(k_cgs_pass<24>, dim3(nb), dim3(kRedThreads), 0, s, V, nv, w, h, partials, skip, n);
+  else if (nv <= 32)
+    hipLaunchKernelGGL(k_cgs_pass<32>, dim3(nb), dim3(kRedThreads), 0, s, V, nv, w, h, partials, skip, n);
+  else {
+    // long restarts: plain update, then the chunked dot kernel
+    if (h != nullptr) hipLaunchKernelGGL(k_cgs_update, dim3(nb), dim3(256), 0, s, V, nv, w, h, skip, n);
+    hipLaunchKernelGGL(k_cgs_dots, dim3(nb, (nv + kChunk - 1) / kChunk), dim3(kRedThreads), 0, s, V, nv, w, partials,
+                       skip, n);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_cgs_dots(V, nv, w, partials, counter, out, skip, n, s);
+  return launch_finalize(partials, nb, kMaxM + 2, nv, out, skip, s);
+}
+
+hipError_t launch_cgs_update_dots(const double* V, int nv, double* w, const double* h, double* partials,
+                                  unsigned*, double* out, const int* skip, size_t n, hipStream_t s) {
+  return cgs_pass(V, nv, w, h, partials, out, skip, n, s);
 }
 
 // Second update fused with the partial sums of ||w||^2.
@@ -206,54 +277,62 @@ __global__ void __launch_bounds__(kRedThreads) k_cgs_update_norm(const double* _
 // also written to mapped host memory for the host's poll.
 __global__ void __launch_bounds__(kRedThreads) k_givens(GmState* st, const double* __restrict__ partials, int nblocks,
                                                         int M) {
-  GmStatus* host_status = st->hslot;
   if (st->stop) return;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += kRedThreads) s += partials[b];
-  const double hn2 = block_sum(s);
-  if (threadIdx.x != 0) return;
+  __shared__ double col[kMaxM + 2], cs[kMaxM], sn[kMaxM];
+  const int tid = threadIdx.x;
   const int j = st->j;
   const int ld = M + 1;
-  double* col = st->H + (size_t)j * ld;
-  for (int i = 0; i <= j; ++i) col[i] = st->h1[i] + st->h2[i];
-  const double hn = sqrt(hn2);
-  double w02 = hn2;  // ||w||^2 before orthogonalisation (Pythagoras)
-  for (int i = 0; i <= j; ++i) w02 += col[i] * col[i];
-  st->w0 = sqrt(w02);
-  col[j + 1] = hn;
-  for (int i = 0; i < j; ++i) {
-    const double t = st->cs[i] * col[i] + st->sn[i] * col[i + 1];
-    col[i + 1] = -st->sn[i] * col[i] + st->cs[i] * col[i + 1];
-    col[i] = t;
+  if (tid <= j) col[tid] = st->h1[tid] + st->h2[tid];
+  if (tid < j) {
+    cs[tid] = st->cs[tid];
+    sn[tid] = st->sn[tid];
   }
-  const double den = hypot(col[j], col[j + 1]);
-  st->cs[j] = col[j] / den;
-  st->sn[j] = col[j + 1] / den;
-  col[j] = den;
-  col[j + 1] = 0.0;
-  st->g[j + 1] = -st->sn[j] * st->g[j];
-  st->g[j] = st->cs[j] * st->g[j];
-  const double rest = fabs(st->g[j + 1]);
-  st->rest = rest;
-  st->hn = hn;
-  st->j = j + 1;
-  if (!(rest == rest) || !(den == den) || isinf(rest) || den == 0.0) {
-    st->stop = 1;
-    st->why = 3;
-  } else if (rest <= st->target) {
-    st->stop = 1;
-    st->why = 1;
-  } else if (hn <= 1e-14 * st->w0) {
-    st->stop = 1;
-    st->why = 2;
+  double s = 0.0;
+  for (int b = tid; b < nblocks; b += kRedThreads) s += partials[b];
+  const double hn2 = block_sum(s);  // (contains barriers: the staged column is visible below)
+  if (tid == 0) {
+    const double hn = sqrt(hn2);
+    double w02 = hn2;  // ||w||^2 before orthogonalisation (Pythagoras)
+    for (int i = 0; i <= j; ++i) w02 += col[i] * col[i];
+    st->w0 = sqrt(w02);
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+      col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+      col[i] = t;
+    }
+    const double den = hypot(col[j], col[j + 1]);
+    st->cs[j] = col[j] / den;
+    st->sn[j] = col[j + 1] / den;
+    col[j] = den;
+    col[j + 1] = 0.0;
+    st->g[j + 1] = -st->sn[j] * st->g[j];
+    st->g[j] = st->cs[j] * st->g[j];
+    const double rest = fabs(st->g[j + 1]);
+    st->rest = rest;
+    st->hn = hn;
+    st->j = j + 1;
+    if (!(rest == rest) || !(den == den) || isinf(rest) || den == 0.0) {
+      st->stop = 1;
+      st->why = 3;
+    } else if (rest <= st->target) {
+      st->stop = 1;
+      st->why = 1;
+    } else if (hn <= 1e-14 * st->w0) {
+      st->stop = 1;
+      st->why = 2;
+    }
+    GmStatus* hs = st->hslot;
+    if (hs != nullptr) {
+      hs->rest = st->rest;
+      hs->beta = st->beta;
+      hs->j = st->j;
+      hs->stop = st->stop;
+      hs->why = st->why;
+    }
   }
-  if (host_status != nullptr) {
-    host_status->rest = st->rest;
-    host_status->beta = st->beta;
-    host_status->j = st->j;
-    host_status->stop = st->stop;
-    host_status->why = st->why;
-  }
+  __syncthreads();
+  if (tid <= j + 1) st->H[(size_t)j * ld + tid] = col[tid];
 }
 
 hipError_t launch_cgs_update_norm(const double* V, int nv, double* w, const double* h2, double* partials,
