@@ -166,6 +166,12 @@ class EulerFR:
                + (GnN - GN)[:, :, None, :] * b.gRp[None, None, :, None])
         return -div / geo.J[None]
 
+    def local_residual_factory(self, U):
+        """R_e as a function of the element's own state, the neighbours held at U: for the
+        Euler residual they enter only through their solution traces on the shared faces."""
+        nbr = self.neighbour_traces(self.traces(self.shape(U)))
+        return lambda q: self.residual_given_neighbours(q, nbr)
+
     def residual(self, U):
         """R(q) for the whole mesh; U and the result in [v, e, k] layout (flattened)."""
         q = self.shape(U)

@@ -43,9 +43,9 @@ def ejacobi_blocks(op, U, shift):
     Column j = (v, k) of block e is a one-sided difference of the element's
     residual when only entry (v, e, k) of the state moves by
     delta = BLOCK_FD_REL * max(1, |q|), with every other entry, in particular
-    the neighbours' states, held fixed.  For the Euler residual an element's
-    residual depends on its neighbours only through their face traces, so the
-    neighbours' traces of the unperturbed state are passed in unchanged.
+    the neighbours' states, held fixed.  The operator supplies the element-local
+    residual (own state in, neighbours frozen at U), so all elements' column j is
+    formed in one vectorised evaluation.
 
     Returns blocks[e, row, col] with row/col index j = v * Np + k.
     """
@@ -53,8 +53,8 @@ def ejacobi_blocks(op, U, shift):
     nel, n = op.nel, op.n
     Np = n * n
     Nb = 4 * Np
-    nbr = op.neighbour_traces(op.traces(q))
-    R0 = op.residual_given_neighbours(q, nbr).reshape(4, nel, Np)
+    local = op.local_residual_factory(U)
+    R0 = local(q).reshape(4, nel, Np)
     qf = q.reshape(4, nel, Np)
     blocks = np.zeros((nel, Nb, Nb))
     for v in range(4):
@@ -62,7 +62,7 @@ def ejacobi_blocks(op, U, shift):
             delta = BLOCK_FD_REL * np.maximum(1.0, np.abs(qf[v, :, k]))
             qp = qf.copy()
             qp[v, :, k] += delta
-            Rp = op.residual_given_neighbours(qp.reshape(q.shape), nbr).reshape(4, nel, Np)
+            Rp = local(qp.reshape(q.shape)).reshape(4, nel, Np)
             col = -(Rp - R0) / delta[None, :, None]          # -dR/dq_j, [v', e, k']
             blocks[:, :, v * Np + k] = col.transpose(1, 0, 2).reshape(nel, Nb)
     blocks += shift * np.eye(Nb)[None]

@@ -7,11 +7,17 @@ import numpy as np
 from .basis import Basis
 from .geometry import Geometry, Mesh
 from .euler import EulerFR
+from .ns import NavierStokesFR
 
 
 def make_euler(nodes, P, gamma=1.4, flux="rusanov"):
     geo = Geometry(Mesh(nodes), Basis(P))
     return EulerFR(geo, gamma=gamma, flux=flux)
+
+
+def make_ns(nodes, P, gamma=1.4, flux="rusanov", rgas=1.0, mu=1e-4, prandtl=0.71):
+    geo = Geometry(Mesh(nodes), Basis(P))
+    return NavierStokesFR(geo, gamma=gamma, flux=flux, rgas=rgas, mu=mu, prandtl=prandtl)
 
 
 def sample_state(op, fn):
