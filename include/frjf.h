@@ -138,17 +138,20 @@ typedef struct {
  * differences (column j = (v,k) perturbs q[v][e][k] by 1e-8 max(1,|q|) with
  * every other entry of the state held fixed) into d_blocks: nel * Nb * Nb
  * doubles, Nb = 4 Np, block e column-major: entry (row i, col j) at
- * e*Nb*Nb + j*Nb + i, with row/col index v*Np + k. */
+ * e*Nb*Nb + j*Nb + i, with row/col index v*Np + k.
+ * d_work: FR_WS_RESIDUAL bytes (needed for FR_NS_BR1: the neighbours' corrected
+ * gradients enter each block through the shared faces' common state; may be
+ * NULL for FR_EULER). */
 fr_status fr_ejacobi_assemble(const fr_disc* disc, const double* d_U, double shift,
-                              double* d_blocks, fr_stream stream);
+                              double* d_blocks, void* d_work, fr_stream stream);
 
 /* Assemble the blocks at state d_U and replace each by its inverse (Gauss-
  * Jordan elimination with partial pivoting), in pc->precision (FR_F32:
  * assembled in FP64, rounded to FP32, inverted in FP32).  Sets pc->shift.
  * A zero pivot gives Inf/NaN entries, which fr_gmres_solve reports as
- * FR_ENAN. */
+ * FR_ENAN.  d_work as for fr_ejacobi_assemble. */
 fr_status fr_ejacobi_factor(const fr_disc* disc, const double* d_U, double shift, fr_ejacobi* pc,
-                            fr_stream stream);
+                            void* d_work, fr_stream stream);
 
 /* Invert caller-provided FP64 blocks (layout as fr_ejacobi_assemble) into pc
  * (rounded to FP32 first when pc->precision == FR_F32). */

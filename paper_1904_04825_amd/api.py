@@ -173,15 +173,17 @@ class Disc:
         """Raw FP64 blocks P_e = shift I - dR_e/dq_e as a [nel, Nb, Nb] (row, col) tensor."""
         self._vec(U, "U")
         blocks = torch.empty((self.nel, self.nb, self.nb), dtype=torch.float64, device=self.device)
+        ws = self.workspace(L.WS_RESIDUAL)
         _check("fr_ejacobi_assemble", self.lib.fr_ejacobi_assemble(self.handle, _ptr(U), shift, _ptr(blocks),
-                                                                   _stream()))
+                                                                   _ptr(ws), _stream()))
         return blocks.transpose(1, 2)   # stored column-major
 
     def ejacobi_factor(self, U, shift, precision=F64, pc=None):
         self._vec(U, "U")
         pc = Ejacobi(self, precision) if pc is None else pc
+        ws = self.workspace(L.WS_RESIDUAL)
         _check("fr_ejacobi_factor", self.lib.fr_ejacobi_factor(self.handle, _ptr(U), shift, ctypes.byref(pc.c),
-                                                               _stream()))
+                                                               _ptr(ws), _stream()))
         return pc
 
     def ejacobi_factor_blocks(self, blocks_rowcol, precision=F64):

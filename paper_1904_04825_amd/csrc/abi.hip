@@ -106,14 +106,14 @@ size_t fr_workspace_bytes(const fr_disc* d, int what, int m, int precision) {
   return 0;
 }
 
+static double* ns_traces(const fr_disc* d, void* work) { return d->physics == FR_NS_BR1 ? (double*)work : nullptr; }
+
 fr_status fr_solution_points(const fr_disc* d, double* xy, fr_stream s) {
   clear_error();
   CHECK(d && xy, "fr_solution_points: null argument");
   FR_HIP(launch_solution_points(d, xy, S(s)));
   return FR_OK;
 }
-
-static double* ns_traces(const fr_disc* d, void* work) { return d->physics == FR_NS_BR1 ? (double*)work : nullptr; }
 
 fr_status fr_residual(const fr_disc* d, const double* U, double* R, void* work, fr_stream s) {
   clear_error();
@@ -156,18 +156,22 @@ fr_status fr_jf_matvec(const fr_disc* d, const double* U, const double* R0, cons
   return FR_OK;
 }
 
-fr_status fr_ejacobi_assemble(const fr_disc* d, const double* U, double shift, double* blocks, fr_stream s) {
+fr_status fr_ejacobi_assemble(const fr_disc* d, const double* U, double shift, double* blocks, void* work,
+                              fr_stream s) {
   clear_error();
   CHECK(d && U && blocks, "fr_ejacobi_assemble: null argument");
-  FR_HIP(launch_ejacobi_assemble(d, U, shift, blocks, FR_F64, 0, S(s)));
+  CHECK(d->physics == FR_EULER || work != nullptr, "fr_ejacobi_assemble: Navier-Stokes needs a workspace");
+  FR_HIP(launch_ejacobi_assemble(d, U, shift, blocks, FR_F64, 0, ns_traces(d, work), S(s)));
   return FR_OK;
 }
 
-fr_status fr_ejacobi_factor(const fr_disc* d, const double* U, double shift, fr_ejacobi* pc, fr_stream s) {
+fr_status fr_ejacobi_factor(const fr_disc* d, const double* U, double shift, fr_ejacobi* pc, void* work,
+                            fr_stream s) {
   clear_error();
   CHECK(d && U && pc && pc->d_factors, "fr_ejacobi_factor: null argument");
   CHECK(pc->precision == FR_F64 || pc->precision == FR_F32, "fr_ejacobi_factor: bad precision");
-  FR_HIP(launch_ejacobi_assemble(d, U, shift, pc->d_factors, pc->precision, 1, S(s)));
+  CHECK(d->physics == FR_EULER || work != nullptr, "fr_ejacobi_factor: Navier-Stokes needs a workspace");
+  FR_HIP(launch_ejacobi_assemble(d, U, shift, pc->d_factors, pc->precision, 1, ns_traces(d, work), S(s)));
   pc->shift = shift;
   return FR_OK;
 }

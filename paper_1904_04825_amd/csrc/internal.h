@@ -92,8 +92,9 @@ hipError_t launch_scale_dev(double* y, const double* x, const double* alpha, int
                             const int* skip, hipStream_t s);
 
 // element-Jacobi
+// grad: BR1 gradient-trace workspace (Navier-Stokes only, else unused)
 hipError_t launch_ejacobi_assemble(const fr_disc* d, const double* U, double shift, void* out,
-                                   int precision, int invert, hipStream_t s);
+                                   int precision, int invert, double* grad, hipStream_t s);
 hipError_t launch_ejacobi_invert_blocks(const fr_disc* d, const double* blocks, void* out,
                                         int precision, hipStream_t s);
 hipError_t launch_ejacobi_solve(const fr_disc* d, const void* factors, int precision,

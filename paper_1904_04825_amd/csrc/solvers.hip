@@ -488,7 +488,7 @@ fr_status ptc_solve(const fr_disc* d, const double* cst, double omega_dt, double
     if (k >= max_ptc) return FR_NOTCONV;
     if (rejects > max_rej) return FR_REJECTED;
     const double shift = 1.0 / dtau + iw;
-    FR_HIP(launch_ejacobi_assemble(d, q, shift, pc.d_factors, pc.precision, 1, s));
+    FR_HIP(launch_ejacobi_assemble(d, q, shift, pc.d_factors, pc.precision, 1, B.gw.grad, s));
     FR_TRY(lincomb(dq, {}, n, s));
     fr_gmres_stats gs{};
     fr_status g = gmres_core(d, pc.d_factors, pc.precision, q, Rq, shift, negF, dq, true, o.lin, &gs, B.gw, s);
@@ -536,7 +536,7 @@ fr_status row_step_impl(const fr_disc* d, int scheme, double dt, double* U, cons
   FR_TRY(residual_into(d, U, R0, B.gw.grad, s));
   st->residual_evals++;
   const double shift = 1.0 / (T->gamma * dt);
-  FR_HIP(launch_ejacobi_assemble(d, U, shift, B.pc, o.precond_precision, 1, s));
+  FR_HIP(launch_ejacobi_assemble(d, U, shift, B.pc, o.precond_precision, 1, B.gw.grad, s));
   fr_status worst = FR_OK;
   for (int i = 0; i < T->s; ++i) {
     if (i == 0) {
