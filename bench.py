@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--precond", default="f64", choices=["f64", "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernels", action="store_true", help="skip the per-kernel timing block")
+    ap.add_argument("--no-fp32-leg", action="store_true", help="skip the FP32-preconditioner comparison")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy (counter calibration for rocprofv3 --pmc runs)")
     return ap.parse_args()
@@ -182,6 +183,40 @@ def main():
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
                            "alg_bytes_per_launch": solve_bytes}
+
+    if args.precond == "f64" and not args.no_fp32_leg:
+        # the same steps with the FP32 element-Jacobi factored on MFMA
+        opts32 = SolverOpts(lin=GmresOpts(m=20, rtol=1e-8), precond_precision=F32)
+        U32 = U0.clone()
+        disc.row_step(U32, args.scheme, args.dt, opts32)
+        U32.copy_(U0)
+        torch.cuda.synchronize()
+        ev32 = it32 = 0
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            st = disc.row_step(U32, args.scheme, args.dt, opts32)
+            ev32 += st["residual_evals"]
+            it32 += st["gmres_iters"]
+        torch.cuda.synchronize()
+        w32 = time.perf_counter() - t1
+        out["extra"]["fp32_precond"] = {
+            "ms_per_step": w32 / args.steps * 1e3, "wall_s_per_time_unit": w32 / t_phys,
+            "gmres_iters_per_step": it32 / args.steps, "dof_res_per_s": ndof * ev32 / w32,
+            "l2_err_rho": disc.l2_error_vortex(U32, 0, t_phys, vortex),
+            "rel_diff_vs_fp64_state": float(torch.linalg.norm(U32 - U) / torch.linalg.norm(U))}
+        pc32 = disc.ejacobi_factor(U0, 1.0 / (0.4358665215084590 * args.dt), F32)
+        z = disc.empty()
+        v = torch.randn_like(U0)
+        t_s32 = time_kernel(lambda: disc.ejacobi_solve(pc32, v, z))
+        t_f32 = time_kernel(lambda: disc.ejacobi_factor(U0, 1.0 / (0.4358665215084590 * args.dt), F32, pc32),
+                            reps=10, warm=2)
+        nb = disc.nb
+        b32 = disc.nel * nb * nb * 4 + 16 * ndof
+        out["extra"]["kernels"]["ejacobi_solve_fp32"] = {"us": t_s32 * 1e6, "alg_bytes": b32,
+                                                         "GBs": b32 / t_s32 / 1e9}
+        fl = disc.nel * 2.0 * nb ** 3   # Gauss-Jordan inversion flops
+        out["extra"]["kernels"]["ejacobi_factor_fp32_mfma(assemble+invert)"] = {
+            "us": t_f32 * 1e6, "inversion_TFLOPs": fl / t_f32 / 1e12}
 
     if args.calib_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)

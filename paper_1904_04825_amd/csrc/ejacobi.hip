@@ -15,6 +15,7 @@
 // with the inverse stored column-major, so each step of the j loop is a
 // coalesced load of one column.
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 
 #include "internal.h"
@@ -41,10 +42,12 @@ struct AsmArgs {
 template <int P, int FLUX, typename T, bool INVERT>
 __global__ void __launch_bounds__(EJ<P>::NT) k_ejacobi_assemble(const AsmArgs a, const Basis B) {
   using C = EJ<P>;
-  constexpr int n = C::n, Np = C::Np, Nb = C::Nb, NT = C::NT, LD = C::LD;
-  __shared__ T A[Nb * LD];
-  __shared__ T sf[Nb];
-  __shared__ int piv_row, perm[Nb];
+  using L = BlockLds<C::Nb, T>;
+  constexpr int n = C::n, Np = C::Np, Nb = C::Nb, NT = C::NT, LD = L::LD;
+  __shared__ T A[L::NP * LD];
+  __shared__ T sf[L::NP];
+  __shared__ int piv_row, perm[L::NP];
+  __shared__ float Xs[L::mfma ? 16 * L::NP : 1], rowc[16];
   __shared__ double sq[4][Np], sF[4][Np], sG[4][Np], sIJ[Np];
   __shared__ double sqo[4][4][n], sqn[4][4][n], sFn[4][4][n];  // [face][var][j]
   __shared__ double sS[4][2];
@@ -201,7 +204,7 @@ __global__ void __launch_bounds__(EJ<P>::NT) k_ejacobi_assemble(const AsmArgs a,
     col[jc] = (T)((double)col[jc] + a.shift);
   }
   __syncthreads();
-  if constexpr (INVERT) gj_invert<T, Nb, LD, NT>(A, sf, &piv_row, perm);
+  if constexpr (INVERT) invert_lds<T, Nb, NT>(A, sf, &piv_row, perm, Xs, rowc);
   T* out = reinterpret_cast<T*>(a.out) + (size_t)el * Nb * Nb;
   for (int idx = tid; idx < Nb * Nb; idx += NT) out[idx] = A[(idx / Nb) * LD + idx % Nb];
 }
@@ -210,15 +213,17 @@ __global__ void __launch_bounds__(EJ<P>::NT) k_ejacobi_assemble(const AsmArgs a,
 template <int P, typename T>
 __global__ void __launch_bounds__(EJ<P>::NT) k_ejacobi_invert(const double* __restrict__ blocks, void* outp) {
   using C = EJ<P>;
-  constexpr int Nb = C::Nb, NT = C::NT, LD = C::LD;
-  __shared__ T A[Nb * LD];
-  __shared__ T sf[Nb];
-  __shared__ int piv_row, perm[Nb];
+  using L = BlockLds<C::Nb, T>;
+  constexpr int Nb = C::Nb, NT = C::NT, LD = L::LD;
+  __shared__ T A[L::NP * LD];
+  __shared__ T sf[L::NP];
+  __shared__ int piv_row, perm[L::NP];
+  __shared__ float Xs[L::mfma ? 16 * L::NP : 1], rowc[16];
   const size_t el = blockIdx.x;
   const double* src = blocks + el * Nb * Nb;
   for (int idx = threadIdx.x; idx < Nb * Nb; idx += NT) A[(idx / Nb) * LD + idx % Nb] = (T)src[idx];
   __syncthreads();
-  gj_invert<T, Nb, LD, NT>(A, sf, &piv_row, perm);
+  invert_lds<T, Nb, NT>(A, sf, &piv_row, perm, Xs, rowc);
   T* out = reinterpret_cast<T*>(outp) + el * Nb * Nb;
   for (int idx = threadIdx.x; idx < Nb * Nb; idx += NT) out[idx] = A[(idx / Nb) * LD + idx % Nb];
 }

@@ -423,13 +423,15 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_res(const NSArgs a, const Basi
 template <int P, int FLUX, typename T, bool INVERT>
 __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const Basis B, void* outp) {
   using C = NS<P>;
-  constexpr int n = C::n, Np = C::Np, Nb = C::Nb, ST = C::ST, SL = C::SLOTS, NT = C::NT, LD = C::LD;
+  using L = BlockLds<C::Nb, T>;
+  constexpr int n = C::n, Np = C::Np, Nb = C::Nb, ST = C::ST, SL = C::SLOTS, NT = C::NT, LD = L::LD;
   __shared__ Slot<P> S[SL];
   __shared__ ElemGeo<P> Gm;
   __shared__ double q0[4][Np], R0[4][Np], qc0[4][4][n], cg[4][n][2];
-  __shared__ T A[Nb * LD];
-  __shared__ T sf[Nb];
-  __shared__ int piv_row, perm[Nb];
+  __shared__ T A[L::NP * LD];
+  __shared__ T sf[L::NP];
+  __shared__ int piv_row, perm[L::NP];
+  __shared__ float Xs[L::mfma ? 16 * L::NP : 1], rowc[16];
   const int tid = threadIdx.x;
   const int sl = tid / ST, t = tid % ST;
   const int el = blockIdx.x;
@@ -534,7 +536,7 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const 
         }
     __syncthreads();
   }
-  if constexpr (INVERT) gj_invert<T, Nb, LD, NT>(A, sf, &piv_row, perm);
+  if constexpr (INVERT) invert_lds<T, Nb, NT>(A, sf, &piv_row, perm, Xs, rowc);
   T* out = reinterpret_cast<T*>(outp) + (size_t)el * Nb * Nb;
   for (int idx = tid; idx < Nb * Nb; idx += NT) out[idx] = A[(idx / Nb) * LD + idx % Nb];
 }
