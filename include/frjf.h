@@ -195,6 +195,41 @@ fr_status fr_gmres_solve(const fr_disc* disc, const fr_ejacobi* pc, const double
                          const fr_gmres_opts* opts, fr_gmres_stats* stats, void* d_work,
                          fr_stream stream);
 
+/* ---- learned warm start (an addition to the paper's method) --------------
+ * A per-element MLP predicts a stage increment Y_i from the element's entries of
+ * [U, R(U), Y_{i-1}/dt, Y_{i-2}/dt]: n_in = 16 Np inputs (field, variable, point),
+ * standardised per (field, variable); two GELU hidden layers of n_hidden;
+ * n_out = 4 Np outputs = Y_i/dt standardised per variable.  BF16 weights and layer
+ * inputs, FP32 accumulation (MFMA), FP32 biases. */
+typedef struct fr_mlp {
+  int n_in, n_hidden, n_out;
+  void* d_w;      /* bf16: W1[h][in], W2[h][h], W3[out][h], then W1^T, W2^T, W3^T (fr_mlp_weight_bytes) */
+  float* d_b;     /* b1[h], b2[h], b3[out] */
+  float* d_norm;  /* (mean, std) of the 16 input groups [field][var], then of the 4 output variables: 40 floats */
+} fr_mlp;
+
+/* Training state: FP32 master parameters W1, b1, W2, b2, W3, b3 (fr_mlp_param_count
+ * floats each for master, gradient, and Adam's first and second moments). */
+typedef struct {
+  fr_mlp net;
+  float* d_master;
+  float* d_grad;
+  float* d_m;
+  float* d_v;
+  int t;           /* Adam step counter */
+  float lr, beta1, beta2, eps;  /* lr <= 0: compute gradients only */
+} fr_mlp_trainer;
+
+/* Samples logged by the ROW step for one stage: per sample 20 Np floats, the
+ * unnormalised inputs (16 Np) followed by the converged Y_i/dt (4 Np). */
+typedef struct {
+  float* d_samples;      /* capacity x 20 Np floats */
+  const int* d_elems;    /* per_stage element indices logged after each solve of this stage */
+  int per_stage;
+  int capacity;          /* samples */
+  int count;             /* samples stored so far (advanced by the step) */
+} fr_stage_log;
+
 /* Options and statistics of one time step. */
 typedef struct {
   fr_gmres_opts lin;     /* linear solver (ROW: every stage; ESDIRK/BDF2: every PTC iteration) */
@@ -205,6 +240,15 @@ typedef struct {
   int max_reject;        /* PTC rejections per stage; <= 0 means 30 */
   int precond_precision; /* FR_F64 or FR_F32 element-Jacobi */
   int commit_unconverged;/* 1: apply the update even if a linear/nonlinear solve did not converge */
+  /* ROW only: */
+  const fr_mlp* warm;    /* NULL, or one network per stage: stage i starts GMRES from its
+                            prediction; if that guess's residual is not below ||b|| (the zero
+                            guess's), GMRES starts from zero instead.  The tolerance stays
+                            relative to ||b|| in both cases. */
+  fr_stage_log* log;     /* NULL, or one log per stage (training data) */
+  double* d_yhist;       /* NULL, or 2 x ndof: in, the previous step's last two stage
+                            increments (Y_{s-2}, Y_{s-1}); out, this step's.  NULL = zeros. */
+  void* d_mlp_work;      /* fr_mlp_work_bytes bytes when warm != NULL */
 } fr_solver_opts;
 
 typedef struct {
@@ -213,6 +257,8 @@ typedef struct {
   int rejections;      /* rejected PTC iterations */
   int linear_solves;   /* GMRES calls */
   int unconverged;     /* GMRES calls that ended above tolerance */
+  int warm_used;       /* stages whose GMRES started from the learned guess */
+  int warm_rejected;   /* stages whose learned guess lost to the zero guess */
   long residual_evals; /* residual evaluations incl. JF products */
   double wall_s;       /* host wall time of the call */
 } fr_step_stats;
@@ -257,6 +303,35 @@ fr_status fr_bdf2_step(const fr_disc* disc, double dt, const double* d_Unm1, con
  * Synchronises; result in *h_err. */
 fr_status fr_l2_error_vortex(const fr_disc* disc, const double* d_U, int var, double t,
                              const double* h_params, double* h_err, void* d_work, fr_stream stream);
+
+/* Sizes: bf16 weight bytes (with the transposed copies), FP32 parameter count,
+ * and workspace bytes for inference on the disc's mesh and training batches of
+ * `batch` samples. */
+size_t fr_mlp_weight_bytes(int n_in, int n_hidden, int n_out);
+size_t fr_mlp_param_count(int n_in, int n_hidden, int n_out);
+size_t fr_mlp_work_bytes(const fr_disc* disc, int n_hidden, int batch);
+
+/* Stage-increment guess x0 (ndof doubles) of every element from U, R = R(U) and the
+ * two previous increments (NULL = zero). */
+fr_status fr_mlp_infer(const fr_disc* disc, const fr_mlp* net, const double* d_U, const double* d_R,
+                       const double* d_Y1, const double* d_Y2, double dt, double* d_x0, void* d_work,
+                       fr_stream stream);
+
+/* Raw forward pass on standardised bf16 features d_x[batch][n_in] -> d_y[batch][n_out] (FP32). */
+fr_status fr_mlp_forward(const fr_mlp* net, const uint16_t* d_x, int batch, float* d_y, void* d_work,
+                         fr_stream stream);
+
+/* Standardisation statistics of net->d_norm from the logged samples of `log`. */
+fr_status fr_mlp_fit_stats(const fr_disc* disc, const fr_stage_log* log, fr_mlp* net, fr_stream stream);
+
+/* Write the bf16 weights and FP32 biases of tr->net from the master copy. */
+fr_status fr_mlp_sync(fr_mlp_trainer* tr, fr_stream stream);
+
+/* One training step on the logged samples d_idx[0..batch): forward, mean-squared-error
+ * gradients (tr->d_grad), and an Adam update of the master copy followed by fr_mlp_sync
+ * (skipped when tr->lr <= 0).  Synchronises; *h_loss = batch MSE before the update. */
+fr_status fr_mlp_train_step(const fr_disc* disc, fr_mlp_trainer* tr, const fr_stage_log* log, const int* d_idx,
+                            int batch, double* h_loss, void* d_work, fr_stream stream);
 
 /* Coefficients of the built-in schemes, for inspection: kind 0 = ROW
  * (transformed a_ij, c_ij, m_j, gamma), kind 1 = ESDIRK (a_ij, b_i).

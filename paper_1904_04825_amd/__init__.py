@@ -4,8 +4,9 @@ The compute path is the HIP library libfrjf.so behind the C ABI in
 include/frjf.h; this package is a thin binding that marshals torch tensors
 (device memory, streams) into those calls.
 """
-from .api import (Disc, Ejacobi, GmresOpts, SolverOpts, FrError, EULER, NS_BR1, RUSANOV, ROE,
-                  F64, F32, EPS_ABS, EPS_RMS)
+from .api import (Disc, Ejacobi, GmresOpts, SolverOpts, FrError, Mlp, MlpTrainer, StageLog, StageLogs, WarmStart,
+                  EULER, NS_BR1, RUSANOV, ROE, F64, F32, EPS_ABS, EPS_RMS)
 
-__all__ = ["Disc", "Ejacobi", "GmresOpts", "SolverOpts", "FrError", "EULER", "NS_BR1", "RUSANOV", "ROE",
+__all__ = ["Disc", "Ejacobi", "GmresOpts", "SolverOpts", "FrError", "Mlp", "MlpTrainer", "StageLog", "StageLogs",
+           "WarmStart", "EULER", "NS_BR1", "RUSANOV", "ROE",
            "F64", "F32", "EPS_ABS", "EPS_RMS"]

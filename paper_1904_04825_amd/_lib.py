@@ -34,15 +34,33 @@ class GmresStatsC(Structure):
                 ("r_final", c_double), ("residual_evals", c_long)]
 
 
+class MlpC(Structure):
+    _fields_ = [("n_in", c_int), ("n_hidden", c_int), ("n_out", c_int), ("d_w", c_void_p), ("d_b", c_void_p),
+                ("d_norm", c_void_p)]
+
+
+class MlpTrainerC(Structure):
+    _fields_ = [("net", MlpC), ("d_master", c_void_p), ("d_grad", c_void_p), ("d_m", c_void_p), ("d_v", c_void_p),
+                ("t", c_int), ("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float)]
+
+
+class StageLogC(Structure):
+    _fields_ = [("d_samples", c_void_p), ("d_elems", c_void_p), ("per_stage", c_int), ("capacity", c_int),
+                ("count", c_int)]
+
+
 class SolverOptsC(Structure):
     _fields_ = [("lin", GmresOptsC), ("tol_nl", c_double), ("dtau_init", c_double), ("dtau_max", c_double),
                 ("max_ptc", c_int), ("max_reject", c_int), ("precond_precision", c_int),
-                ("commit_unconverged", c_int)]
+                ("commit_unconverged", c_int), ("warm", c_void_p), ("log", c_void_p), ("d_yhist", c_void_p),
+                ("d_mlp_work", c_void_p)]
 
 
 class StepStatsC(Structure):
     _fields_ = [("gmres_iters", c_int), ("ptc_iters", c_int), ("rejections", c_int), ("linear_solves", c_int),
-                ("unconverged", c_int), ("residual_evals", c_long), ("wall_s", c_double)]
+                ("unconverged", c_int), ("warm_used", c_int), ("warm_rejected", c_int), ("residual_evals", c_long),
+                ("wall_s", c_double)]
 
 
 _SIGS = {
@@ -71,6 +89,16 @@ _SIGS = {
                                    c_void_p, c_void_p]),
     "fr_scheme_table": (c_int, [c_int, c_int, POINTER(c_double), POINTER(c_double), POINTER(c_double),
                                 POINTER(c_double)]),
+    "fr_mlp_weight_bytes": (c_size_t, [c_int, c_int, c_int]),
+    "fr_mlp_param_count": (c_size_t, [c_int, c_int, c_int]),
+    "fr_mlp_work_bytes": (c_size_t, [c_void_p, c_int, c_int]),
+    "fr_mlp_infer": (c_int, [c_void_p, POINTER(MlpC), c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
+                             c_void_p, c_void_p]),
+    "fr_mlp_forward": (c_int, [POINTER(MlpC), c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
+    "fr_mlp_fit_stats": (c_int, [c_void_p, POINTER(StageLogC), POINTER(MlpC), c_void_p]),
+    "fr_mlp_sync": (c_int, [POINTER(MlpTrainerC), c_void_p]),
+    "fr_mlp_train_step": (c_int, [c_void_p, POINTER(MlpTrainerC), POINTER(StageLogC), c_void_p, c_int,
+                                  POINTER(c_double), c_void_p, c_void_p]),
     "fr_last_error": (ctypes.c_char_p, []),
 }
 

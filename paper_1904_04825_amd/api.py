@@ -65,11 +65,22 @@ class SolverOpts:
     max_reject: int = 0
     precond_precision: int = F64
     commit_unconverged: int = 0
+    warm: "WarmStart" = None          # ROW: learned initial guesses, one network per stage
+    log: "StageLogs" = None           # ROW: log training samples after each stage solve
+    yhist: torch.Tensor = None        # ROW: (2, ndof) previous step's last two increments (in/out)
 
     def c(self):
         lin = self.lin or GmresOpts()
-        return L.SolverOptsC(lin.c(), self.tol_nl, self.dtau_init, self.dtau_max, self.max_ptc, self.max_reject,
-                             self.precond_precision, self.commit_unconverged)
+        o = L.SolverOptsC(lin.c(), self.tol_nl, self.dtau_init, self.dtau_max, self.max_ptc, self.max_reject,
+                          self.precond_precision, self.commit_unconverged)
+        if self.warm is not None:
+            o.warm = ctypes.cast(self.warm.array, ctypes.c_void_p)
+            o.d_mlp_work = self.warm.work.data_ptr()
+        if self.log is not None:
+            o.log = ctypes.cast(self.log.array, ctypes.c_void_p)
+        if self.yhist is not None:
+            o.d_yhist = self.yhist.data_ptr()
+        return o
 
 
 def _stats(s):
@@ -137,6 +148,15 @@ class Disc:
 
     def zeros(self):
         return torch.zeros(self.shape, dtype=torch.float64, device=self.device)
+
+    def workspace_mlp(self, n_hidden, batch):
+        nbytes = int(self.lib.fr_mlp_work_bytes(self.handle, n_hidden, batch))
+        key = ("mlp", n_hidden)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
 
     def workspace(self, what, m=20, precision=F64):
         nbytes = int(self.lib.fr_workspace_bytes(self.handle, what, m, precision))
@@ -224,9 +244,15 @@ class Disc:
         self._vec(U, "U")
         st = L.StepStatsC()
         oc = opts.c()
+        if opts.yhist is not None:
+            self._vec(opts.yhist.view(-1)[: self.ndof], "yhist")
+            if opts.yhist.numel() != 2 * self.ndof or not opts.yhist.is_contiguous():
+                raise ValueError("yhist: expected a contiguous (2, ndof) float64 tensor")
         status = self.lib.fr_row_step(self.handle, int(scheme), dt, _ptr(U), ctypes.byref(oc), ctypes.byref(st),
                                       _ptr(self._step_ws(opts)), _stream())
         _check("fr_row_step", status, allow_numerical=True)
+        if opts.log is not None:
+            opts.log.pull()
         return dict(_stats(st), status=status)
 
     def esdirk_step(self, U, scheme, dt, opts=None):
@@ -263,6 +289,124 @@ class Disc:
         _check("fr_l2_error_vortex", self.lib.fr_l2_error_vortex(self.handle, _ptr(U), var, t, prm,
                                                                  ctypes.byref(err), _ptr(ws), _stream()))
         return err.value
+
+
+# ---------------------------------------------------------------- learned warm start
+class Mlp:
+    """Per-element MLP (BF16 weights) on the device; sizes fixed by the disc's degree."""
+
+    def __init__(self, disc, n_hidden=256):
+        lib = L.lib()
+        self.disc = disc
+        self.n_in, self.n_hidden, self.n_out = 16 * disc.np_, n_hidden, 4 * disc.np_
+        nw = lib.fr_mlp_weight_bytes(self.n_in, n_hidden, self.n_out) // 2
+        self.w = torch.zeros(nw, dtype=torch.bfloat16, device=disc.device)
+        self.b = torch.zeros(2 * n_hidden + self.n_out, dtype=torch.float32, device=disc.device)
+        self.norm = torch.tensor([0.0, 1.0] * 20, dtype=torch.float32, device=disc.device)
+        self.c = L.MlpC(self.n_in, n_hidden, self.n_out, self.w.data_ptr(), self.b.data_ptr(), self.norm.data_ptr())
+
+    def forward(self, x_bf16, y=None):
+        """Raw forward pass on standardised bf16 features [batch, n_in] -> [batch, n_out] float32."""
+        B = x_bf16.shape[0]
+        y = torch.empty((B, self.n_out), dtype=torch.float32, device=self.disc.device) if y is None else y
+        ws = self.disc.workspace_mlp(self.n_hidden, B)
+        _check("fr_mlp_forward", L.lib().fr_mlp_forward(ctypes.byref(self.c), _ptr(x_bf16.contiguous()), B, _ptr(y),
+                                                        _ptr(ws), _stream()))
+        return y
+
+    def infer(self, U, R, Y1, Y2, dt, out=None):
+        d = self.disc
+        out = d.empty() if out is None else out
+        ws = d.workspace_mlp(self.n_hidden, 1)
+        _check("fr_mlp_infer", L.lib().fr_mlp_infer(d.handle, ctypes.byref(self.c), _ptr(U), _ptr(R), _ptr(Y1),
+                                                    _ptr(Y2), dt, _ptr(out), _ptr(ws), _stream()))
+        return out
+
+
+class MlpTrainer:
+    """FP32 master parameters + Adam state of one network; initial weights uniform in
+    +-1/sqrt(fan_in) from a seeded generator, biases zero."""
+
+    def __init__(self, disc, n_hidden=256, seed=4, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        import numpy as np
+        self.net = Mlp(disc, n_hidden)
+        n = L.lib().fr_mlp_param_count(self.net.n_in, n_hidden, self.net.n_out)
+        rng = np.random.default_rng(seed)
+        parts = []
+        for o, i in ((n_hidden, self.net.n_in), (n_hidden, n_hidden), (self.net.n_out, n_hidden)):
+            lim = 1.0 / np.sqrt(i)
+            parts += [rng.uniform(-lim, lim, size=o * i), np.zeros(o)]
+        init = np.concatenate(parts).astype(np.float32)
+        assert init.size == n
+        dev = disc.device
+        self.master = torch.as_tensor(init, device=dev)
+        self.grad = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.m = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.v = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.c = L.MlpTrainerC(self.net.c, self.master.data_ptr(), self.grad.data_ptr(), self.m.data_ptr(),
+                               self.v.data_ptr(), 0, lr, beta1, beta2, eps)
+        self.sync()
+
+    def set_master(self, flat):
+        self.master.copy_(torch.as_tensor(flat, dtype=torch.float32))
+        self.sync()
+
+    def sync(self):
+        _check("fr_mlp_sync", L.lib().fr_mlp_sync(ctypes.byref(self.c), _stream()))
+
+    def fit_stats(self, log):
+        _check("fr_mlp_fit_stats", L.lib().fr_mlp_fit_stats(self.net.disc.handle, ctypes.byref(log.c),
+                                                            ctypes.byref(self.c.net), _stream()))
+
+    def step(self, log, idx, lr=None):
+        if lr is not None:
+            self.c.lr = lr
+        loss = ctypes.c_double()
+        ws = self.net.disc.workspace_mlp(self.net.n_hidden, idx.numel())
+        _check("fr_mlp_train_step", L.lib().fr_mlp_train_step(self.net.disc.handle, ctypes.byref(self.c),
+                                                              ctypes.byref(log.c), _ptr(idx), idx.numel(),
+                                                              ctypes.byref(loss), _ptr(ws), _stream()))
+        return loss.value
+
+
+class StageLog:
+    """Device buffer of logged (inputs, converged increment) samples of one stage."""
+
+    def __init__(self, disc, capacity, elems):
+        self.disc = disc
+        self.stride = 20 * disc.np_
+        self.samples = torch.zeros((capacity, self.stride), dtype=torch.float32, device=disc.device)
+        self.elems = torch.as_tensor(elems, dtype=torch.int32, device=disc.device).contiguous()
+        self.c = L.StageLogC(self.samples.data_ptr(), self.elems.data_ptr(), self.elems.numel(), capacity, 0)
+
+    @property
+    def count(self):
+        return self.c.count
+
+    def set_elems(self, elems):
+        self.elems.copy_(torch.as_tensor(elems, dtype=torch.int32))
+
+
+class StageLogs:
+    """One StageLog per stage of a scheme, as the C ABI expects (contiguous array)."""
+
+    def __init__(self, logs):
+        self.logs = logs
+        self.array = (L.StageLogC * len(logs))(*[lg.c for lg in logs])
+
+    def pull(self):
+        for i, lg in enumerate(self.logs):
+            lg.c.count = self.array[i].count
+
+
+class WarmStart:
+    """One network per stage, contiguous for the C ABI, plus the inference workspace."""
+
+    def __init__(self, nets):
+        self.nets = nets
+        self.array = (L.MlpC * len(nets))(*[n.c for n in nets])
+        d = nets[0].disc
+        self.work = d.workspace_mlp(nets[0].n_hidden, 1)
 
 
 def scheme_table(kind, scheme):

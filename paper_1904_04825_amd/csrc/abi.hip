@@ -4,6 +4,8 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <vector>
+#include <algorithm>
 
 #include "internal.h"
 #include "solvers.h"
@@ -275,6 +277,83 @@ fr_status fr_l2_error_vortex(const fr_disc* d, const double* U, int var, double 
   FR_HIP(hipStreamSynchronize(S(s)));
   std::memcpy(host, slot, sizeof(host));
   *h_err = std::sqrt(host[0] / host[1]);
+  return FR_OK;
+}
+
+size_t fr_mlp_weight_bytes(int n_in, int n_hidden, int n_out) {
+  return mlp_weight_elems(n_in, n_hidden, n_out) * sizeof(uint16_t);
+}
+size_t fr_mlp_param_count(int n_in, int n_hidden, int n_out) { return mlp_param_elems(n_in, n_hidden, n_out); }
+size_t fr_mlp_work_bytes(const fr_disc* d, int n_hidden, int batch) {
+  if (d == nullptr) return 0;
+  const int In = 16 * d->np, Out = 4 * d->np;
+  return std::max(mlp_infer_bytes(d->nel, In, n_hidden, Out), mlp_train_bytes(std::max(batch, 1), In, n_hidden, Out));
+}
+
+static fr_status check_mlp(const fr_disc* d, const fr_mlp* net) {
+  CHECK(net && net->d_w && net->d_b && net->d_norm, "null network buffers");
+  CHECK(net->n_hidden >= 16 && net->n_hidden <= 4096, "n_hidden must be in 16..4096");
+  if (d != nullptr) CHECK(net->n_in == 16 * d->np && net->n_out == 4 * d->np, "network sizes do not match the disc");
+  return FR_OK;
+}
+
+fr_status fr_mlp_infer(const fr_disc* d, const fr_mlp* net, const double* U, const double* R, const double* Y1,
+                       const double* Y2, double dt, double* x0, void* work, fr_stream s) {
+  clear_error();
+  CHECK(d && U && R && x0 && work && dt > 0.0, "fr_mlp_infer: null argument or dt <= 0");
+  fr_status c = check_mlp(d, net);
+  if (c != FR_OK) return c;
+  FR_HIP(mlp_infer(d, net, U, R, Y1, Y2, dt, x0, work, S(s)));
+  return FR_OK;
+}
+
+fr_status fr_mlp_forward(const fr_mlp* net, const uint16_t* x, int batch, float* y, void* work, fr_stream s) {
+  clear_error();
+  CHECK(x && y && work && batch > 0, "fr_mlp_forward: null argument or empty batch");
+  fr_status c = check_mlp(nullptr, net);
+  if (c != FR_OK) return c;
+  char* p = (char*)work;
+  uint16_t* H1 = (uint16_t*)p;
+  uint16_t* H2 = (uint16_t*)(p + (((size_t)batch * net->n_hidden * 2 + 255) / 256) * 256);
+  FR_HIP(mlp_forward(net, x, batch, y, nullptr, H1, nullptr, nullptr, H2, nullptr, S(s)));
+  return FR_OK;
+}
+
+fr_status fr_mlp_fit_stats(const fr_disc* d, const fr_stage_log* log, fr_mlp* net, fr_stream s) {
+  clear_error();
+  CHECK(d && log && log->d_samples && log->count > 0, "fr_mlp_fit_stats: empty log");
+  fr_status c = check_mlp(d, net);
+  if (c != FR_OK) return c;
+  FR_HIP(mlp_stats(log->d_samples, log->count, d->np, net->d_norm, S(s)));
+  return FR_OK;
+}
+
+fr_status fr_mlp_sync(fr_mlp_trainer* tr, fr_stream s) {
+  clear_error();
+  CHECK(tr && tr->d_master, "fr_mlp_sync: null argument");
+  fr_status c = check_mlp(nullptr, &tr->net);
+  if (c != FR_OK) return c;
+  FR_HIP(mlp_sync_weights(tr, S(s)));
+  return FR_OK;
+}
+
+fr_status fr_mlp_train_step(const fr_disc* d, fr_mlp_trainer* tr, const fr_stage_log* log, const int* idx, int batch,
+                            double* h_loss, void* work, fr_stream s) {
+  clear_error();
+  CHECK(d && tr && log && idx && h_loss && work && batch > 0, "fr_mlp_train_step: null argument");
+  CHECK(tr->d_master && tr->d_grad && tr->d_m && tr->d_v, "fr_mlp_train_step: null trainer buffers");
+  fr_status c = check_mlp(d, &tr->net);
+  if (c != FR_OK) return c;
+  const size_t tb = mlp_train_bytes(batch, tr->net.n_in, tr->net.n_hidden, tr->net.n_out);
+  double* partials = (double*)((char*)work + tb - sizeof(double) * 4096);
+  int np = 0;
+  FR_HIP(mlp_train_step(tr, log->d_samples, idx, batch, d->np, partials, &np, work, S(s)));
+  std::vector<double> h(np);
+  FR_HIP(hipMemcpyAsync(h.data(), partials, sizeof(double) * np, hipMemcpyDeviceToHost, S(s)));
+  FR_HIP(hipStreamSynchronize(S(s)));
+  double sum = 0.0;
+  for (double v : h) sum += v;
+  *h_loss = sum / ((double)batch * tr->net.n_out);
   return FR_OK;
 }
 

@@ -150,6 +150,22 @@ hipError_t launch_gm_solve_y(GmState* st, int k, int M, hipStream_t s);
 hipError_t launch_gm_update_x(double* x, const double* Z, int k, const GmState* st, size_t n,
                               hipStream_t s);
 
+// learned warm start (mlp.hip)
+size_t mlp_weight_elems(int In, int H, int Out);
+size_t mlp_param_elems(int In, int H, int Out);
+size_t mlp_infer_bytes(int nel, int In, int H, int Out);
+size_t mlp_train_bytes(int B, int In, int H, int Out);
+hipError_t mlp_forward(const fr_mlp* net, const uint16_t* X, int B, float* Y, float* Z1, uint16_t* H1, uint16_t* H1t,
+                       float* Z2, uint16_t* H2, uint16_t* H2t, hipStream_t s);
+hipError_t mlp_infer(const fr_disc* d, const fr_mlp* net, const double* U, const double* R, const double* Y1,
+                     const double* Y2, double dt, double* x0, void* work, hipStream_t s);
+hipError_t mlp_log(const fr_disc* d, fr_stage_log* log, const double* U, const double* R, const double* Y1,
+                   const double* Y2, const double* Y, double dt, hipStream_t s);
+hipError_t mlp_stats(const float* raw, int count, int Np, float* norm, hipStream_t s);
+hipError_t mlp_train_step(fr_mlp_trainer* tr, const float* raw, const int* idx, int B, int Np, double* loss_partials,
+                          int* nparts, void* work, hipStream_t s);
+hipError_t mlp_sync_weights(fr_mlp_trainer* tr, hipStream_t s);
+
 constexpr int kRedBlocks = 1024;  // blocks of the grid-stride vector kernels
 constexpr int kRedThreads = 256;
 

@@ -46,7 +46,8 @@ fr_status device_norm(const fr_disc* d, const double* x, double* partials, unsig
 
 fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const double* U, const double* R0,
                      double shift, const double* b, double* x, bool x_is_zero, const fr_gmres_opts& o,
-                     fr_gmres_stats* stats, GmWork& W, hipStream_t s);
+                     fr_gmres_stats* stats, GmWork& W, hipStream_t s, bool plain_fallback = false,
+                     int* fell_back = nullptr);
 fr_status row_step_impl(const fr_disc* d, int scheme, double dt, double* U, const fr_solver_opts& o,
                         fr_step_stats* st, void* work, hipStream_t s);
 fr_status esdirk_step_impl(const fr_disc* d, int scheme, double dt, double* U, const fr_solver_opts& o,

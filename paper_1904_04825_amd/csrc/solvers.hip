@@ -266,7 +266,7 @@ fr_status device_norm(const fr_disc* d, const double* x, double* partials, unsig
 // ---------------------------------------------------------------- FGMRES
 fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const double* U, const double* R0,
                      double shift, const double* b, double* x, bool x_is_zero, const fr_gmres_opts& o,
-                     fr_gmres_stats* stats, GmWork& W, hipStream_t s) {
+                     fr_gmres_stats* stats, GmWork& W, hipStream_t s, bool plain_fallback, int* fell_back) {
   const size_t n = d->ndof;
   const int m = o.m;
   const int max_iters = o.max_iters > 0 ? o.max_iters : 50 * m;
@@ -285,6 +285,15 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
   ra.grad = W.grad;
 
   const double* rsrc = b;
+  double bnorm = -1.0;  // ||b||, the residual of the zero (plain) guess
+  if (fell_back != nullptr) *fell_back = 0;
+  if (!x_is_zero && plain_fallback) {
+    double bb = 0.0;
+    FR_HIP(launch_norm2(b, n, W.partials, W.counter, beta2, nullptr, s));
+    fr_status r0 = read_sync(d, &bb, beta2, sizeof(double), s);
+    if (r0 != FR_OK) return r0;
+    bnorm = std::sqrt(bb);
+  }
   if (!x_is_zero) {
     FR_HIP(launch_norm2(x, n, W.partials, W.counter, nz, nullptr, s));
     ResArgs a2 = ra;
@@ -300,7 +309,17 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
   fr_status rs = read_sync(d, &b2, beta2, sizeof(double), s);
   if (rs != FR_OK) return rs;
   double beta = std::sqrt(b2);
-  S.r_ref = o.ref_norm > 0 ? o.ref_norm : beta;
+  if (bnorm >= 0.0 && !(beta < bnorm)) {
+    // the supplied guess is no better than zero: start from zero
+    const double* none[1];
+    double zc[1];
+    FR_HIP(launch_lincomb(x, 0, none, zc, n, s));
+    FR_HIP(launch_norm2(b, n, W.partials, W.counter, beta2, nullptr, s));
+    rsrc = b;
+    beta = bnorm;
+    if (fell_back != nullptr) *fell_back = 1;
+  }
+  S.r_ref = o.ref_norm > 0 ? o.ref_norm : (bnorm >= 0.0 ? bnorm : beta);
   const double target = o.rtol * S.r_ref;
   S.r_final = beta;
   if (!std::isfinite(beta)) {
@@ -491,7 +510,8 @@ fr_status ptc_solve(const fr_disc* d, const double* cst, double omega_dt, double
     FR_HIP(launch_ejacobi_assemble(d, q, shift, pc.d_factors, pc.precision, 1, B.gw.grad, s));
     FR_TRY(lincomb(dq, {}, n, s));
     fr_gmres_stats gs{};
-    fr_status g = gmres_core(d, pc.d_factors, pc.precision, q, Rq, shift, negF, dq, true, o.lin, &gs, B.gw, s);
+    fr_status g = gmres_core(d, pc.d_factors, pc.precision, q, Rq, shift, negF, dq, true, o.lin, &gs, B.gw, s, false,
+                             nullptr);
     if (g < 0) return g;
     st->gmres_iters += gs.iters;
     st->linear_solves++;
@@ -571,10 +591,28 @@ fr_status row_step_impl(const fr_disc* d, int scheme, double dt, double* U, cons
         }
       if (k > 1) FR_TRY(lincomb_v(rhs, k, xs, cs, n, s));
     }
-    FR_TRY(lincomb(Y[i], {}, n, s));
+    // previous increments seen by stage i: (Y_{i-1}, Y_{i-2}), reaching back into the
+    // previous step's last two increments for i < 2
+    const double* hist_last = o.d_yhist ? o.d_yhist + n : nullptr;
+    const double* hist_prev = o.d_yhist ? o.d_yhist : nullptr;
+    const double* Y1 = i >= 1 ? Y[i - 1] : hist_last;
+    const double* Y2 = i >= 2 ? Y[i - 2] : (i == 1 ? hist_last : hist_prev);
+    bool warm = false;
+    if (o.warm != nullptr) {
+      FR_HIP(mlp_infer(d, &o.warm[i], U, R0, Y1, Y2, dt, Y[i], o.d_mlp_work, s));
+      warm = true;
+    } else {
+      FR_TRY(lincomb(Y[i], {}, n, s));
+    }
     fr_gmres_stats gs{};
-    fr_status g = gmres_core(d, B.pc, o.precond_precision, U, R0, shift, rhs, Y[i], true, o.lin, &gs, B.gw, s);
+    int fell = 0;
+    fr_status g = gmres_core(d, B.pc, o.precond_precision, U, R0, shift, rhs, Y[i], !warm, o.lin, &gs, B.gw, s,
+                             warm, &fell);
     if (g < 0) return g;
+    if (warm) {
+      st->warm_used += fell ? 0 : 1;
+      st->warm_rejected += fell;
+    }
     st->gmres_iters += gs.iters;
     st->linear_solves++;
     st->residual_evals += gs.residual_evals;
@@ -582,6 +620,7 @@ fr_status row_step_impl(const fr_disc* d, int scheme, double dt, double* U, cons
       st->unconverged++;
       if (worst == FR_OK || g == FR_ENAN) worst = g;
     }
+    if (o.log != nullptr && g == FR_OK) FR_HIP(mlp_log(d, &o.log[i], U, R0, Y1, Y2, Y[i], dt, s));
   }
   if (worst == FR_OK || (o.commit_unconverged && worst != FR_ENAN)) {
     const double* xs[8];
@@ -594,6 +633,10 @@ fr_status row_step_impl(const fr_disc* d, int scheme, double dt, double* U, cons
       cs[k++] = T->m[j];
     }
     FR_TRY(lincomb_v(U, k, xs, cs, n, s));
+    if (o.d_yhist != nullptr) {
+      FR_TRY(lincomb(o.d_yhist, {{Y[T->s - 2], 1.0}}, n, s));
+      FR_TRY(lincomb(o.d_yhist + n, {{Y[T->s - 1], 1.0}}, n, s));
+    }
   }
   FR_HIP(hipStreamSynchronize(s));
   st->wall_s = now_s() - t0;

@@ -33,7 +33,10 @@ def test_binding_struct_sizes_match_header_layout():
     from paper_1904_04825_amd import _lib
     assert ctypes.sizeof(_lib.DiscDesc) == 5 * 4 + 4 + 4 * 8 + 8
     assert ctypes.sizeof(_lib.GmresOptsC) == 2 * 4 + 3 * 8 + 8
-    assert ctypes.sizeof(_lib.SolverOptsC) == ctypes.sizeof(_lib.GmresOptsC) + 3 * 8 + 4 * 4
+    assert ctypes.sizeof(_lib.SolverOptsC) == ctypes.sizeof(_lib.GmresOptsC) + 3 * 8 + 4 * 4 + 4 * 8
+    assert ctypes.sizeof(_lib.StepStatsC) == 7 * 4 + 4 + 8 + 8
+    assert ctypes.sizeof(_lib.MlpC) == 3 * 4 + 4 + 3 * 8
+    assert ctypes.sizeof(_lib.StageLogC) == 2 * 8 + 3 * 4 + 4
 
 
 @pytest.mark.parametrize("scheme", [2, 3, 4])
@@ -61,3 +64,24 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+def test_ctypes_layouts_match_the_c_compiler(tmp_path):
+    """Compile the header with gcc and compare every struct the binding declares."""
+    import shutil
+    import subprocess
+    from paper_1904_04825_amd import _lib
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include "frjf.h"\nint main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+                   'sizeof(fr_disc_desc),sizeof(fr_ejacobi),sizeof(fr_gmres_opts),sizeof(fr_gmres_stats),'
+                   'sizeof(fr_solver_opts),sizeof(fr_step_stats),sizeof(fr_mlp),sizeof(fr_mlp_trainer),'
+                   'sizeof(fr_stage_log));}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [ctypes.sizeof(t) for t in (_lib.DiscDesc, _lib.EjacobiC, _lib.GmresOptsC, _lib.GmresStatsC,
+                                       _lib.SolverOptsC, _lib.StepStatsC, _lib.MlpC, _lib.MlpTrainerC,
+                                       _lib.StageLogC)]
+    assert got == want
