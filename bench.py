@@ -1,22 +1,28 @@
-"""Benchmark: Jacobian-free implicit time steps of the FR/CPR vortex on one MI355X.
+"""Benchmark: Jacobian-free implicit time steps of FR/CPR flows on one MI355X.
 
-A step is one ROW3 (ROS34PW2) time step of the isentropic vortex on the
-64x64 perturbed quad mesh at P = 3 (262,144 DOFs), dt = 0.1, GMRES(20) with
-rtol 1e-8 and the FP64 element-Jacobi preconditioner, Rusanov flux: residual
-evaluations, Jacobian-free products, element-Jacobi assembly, inversion and
-application, and the Arnoldi/Givens loop all run in the HIP library.  Inputs
-(mesh, state) are synthetic and resident in HBM before timing.
+Default workload (64x64 perturbed quads, P = 3, 262,144 DOFs, the isentropic
+vortex): a step is one ROW3 (ROS34PW2) time step with dt = 0.1, FGMRES(20) at
+rtol 1e-8, Rusanov flux.  Residual evaluations, Jacobian-free products,
+element-Jacobi assembly/inversion/application, the Arnoldi/Givens loop and the
+learned warm start all run in the HIP library; inputs are synthetic and resident
+in HBM before timing.
 
-value = DOF-residuals/s = ndof x (residual evaluations incl. JF products) / wall time.
-The JSON line also carries the roofline of the dominant kernel (live HIP-event
-timing on the launch stream) and the FP64 oracle's rate on the host cores.
+Phases: (1) untimed warm-up: `--warmup` plain steps from t = 0 that also log the
+stage solves (training data); (2) one network per ROW stage trained on the GPU
+from those logs; (3) timed: `--steps` steps from the warm-up's end state with the
+FP64 element-Jacobi (the headline `value`), then the same steps with the FP32
+MFMA element-Jacobi, then FP32 + learned warm start.
+
+value = DOF-residuals/s = ndof x (residual evaluations incl. JF products) / wall time
+of the FP64 leg.  The JSON line also carries the dominant kernel's roofline (live
+HIP-event timing on the launch stream), wall-seconds per unit physical time and the
+L2 error of every leg, and the FP64 oracle's rate on one host core.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -25,20 +31,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = "vortex64_p3_perturbed"
+WORKLOADS = {
+    "vortex64_p3": dict(nodes="vortex64_p3_perturbed", p=3, physics="euler", scheme=3, dt=0.1, state="vortex",
+                        label="isentropic vortex, 64x64 perturbed quads (seed 2), P3, 262144 DOFs"),
+    "shear256_p3_ns": dict(nodes="shear256_p3", p=3, physics="ns", scheme=4, dt=1e-3, state="shear",
+                           label="Navier-Stokes shear layer (Re 1e4, M 0.1), 256x256 quads, P3, BR1, 4194304 DOFs"),
+    "vortex512_p4": dict(nodes="vortex512_p4_perturbed", p=4, physics="euler", scheme=4, dt=0.0125, state="vortex",
+                         label="isentropic vortex, 512x512 perturbed quads (seed 5), P4, 26214400 DOFs"),
+}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--dt", type=float, default=0.1)
-    ap.add_argument("--scheme", type=int, default=3)
-    ap.add_argument("--precond", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--warmup", type=int, default=24, help="untimed logging steps (training data for the warm start)")
+    ap.add_argument("--workload", default="vortex64_p3", choices=sorted(WORKLOADS))
+    ap.add_argument("--dt", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernels", action="store_true", help="skip the per-kernel timing block")
-    ap.add_argument("--no-fp32-leg", action="store_true", help="skip the FP32-preconditioner comparison")
+    ap.add_argument("--no-learned", action="store_true", help="skip logging, training and the learned leg")
+    ap.add_argument("--no-fp32-leg", action="store_true", help="skip the FP32-preconditioner legs")
+    ap.add_argument("--allow-unconverged", action="store_true",
+                    help="count GMRES solves that reach the iteration cap instead of stopping")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy (counter calibration for rocprofv3 --pmc runs)")
     return ap.parse_args()
@@ -67,29 +82,49 @@ def time_kernel(fn, reps=50, warm=5):
     return s.elapsed_time(e) / reps * 1e-3
 
 
-def cpu_baseline(nodes, U0, dt):
+def cpu_baseline(nodes, U0, dt, p, scheme):
     """The FP64 oracle on the host: R(U), the element-Jacobi blocks at q^n and the
-    first 30 FGMRES iterations of ROW3 stage 1 of the same workload (single thread)."""
+    first 30 FGMRES iterations of the first ROW stage of the same workload (one thread)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import integrators as I
     from oracle import linear
     from oracle.problem import make_euler
     from oracle.tableaux import ROW
-    op = make_euler(nodes, 3, flux="rusanov")
+    op = make_euler(nodes, p, flux="rusanov")
     with threadpool_limits(1):
         t0 = time.perf_counter()
         R = I.Counted(op)
         R0 = R(U0)
-        shift = 1.0 / (ROW["ROW3"].gamma * dt)
+        shift = 1.0 / (ROW[f"ROW{scheme}"].gamma * dt)
         pc = linear.ElementJacobi(op, U0, shift)
         x, st = linear.fgmres(lambda v: linear.jf_matvec(R, U0, R0, v, shift), pc.apply, R0, m=20, rtol=1e-8,
                               max_iters=30)
         wall = time.perf_counter() - t0
     evals = R.count
     return {"value": op.ndof * evals / wall, "unit": "DOF-residuals/s", "cores": 1, "kind": "oracle",
-            "sample": f"R(U) + element-Jacobi assembly + {st.iters} FGMRES(20) iterations of ROW3 stage 1 on the "
-                      f"same 64x64 P3 mesh: {evals} residual evaluations in {wall:.1f} s, numpy, 1 thread"}
+            "sample": f"R(U) + element-Jacobi assembly + {st.iters} FGMRES(20) iterations of ROW{scheme} stage 1 on "
+                      f"the same mesh and state: {evals} residual evaluations in {wall:.1f} s, numpy, 1 thread"}
+
+
+def run_leg(disc, U, steps, scheme, dt, opts, allow_unconverged=False):
+    import torch
+    evals = iters = 0
+    extra = {"warm_used": 0, "warm_rejected": 0, "unconverged_solves": 0}
+    opts.commit_unconverged = 1 if allow_unconverged else 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = disc.row_step(U, scheme, dt, opts)
+        if st["status"] != 0 and not (allow_unconverged and st["status"] == 1):
+            raise RuntimeError(f"row_step status {st['status']}")
+        extra["unconverged_solves"] += st["unconverged"]
+        evals += st["residual_evals"]
+        iters += st["gmres_iters"]
+        extra["warm_used"] += st["warm_used"]
+        extra["warm_rejected"] += st["warm_rejected"]
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, evals, iters, extra
 
 
 def main():
@@ -101,122 +136,155 @@ def main():
     import torch
 
     import fr_inputs as fi
-    from paper_1904_04825_amd import F32, F64, Disc, GmresOpts, SolverOpts
+    from paper_1904_04825_amd import (F32, F64, Disc, GmresOpts, MlpTrainer, SolverOpts, StageLog, StageLogs,
+                                      WarmStart)
 
+    W = WORKLOADS[args.workload]
+    dt = args.dt if args.dt is not None else W["dt"]
+    scheme = W["scheme"]
+    nstage = {2: 3, 3: 4, 4: 6}[scheme]
     dev = torch.device("cuda:0")
-    nodes = fi.workload_nodes(WORKLOAD)
-    disc = Disc(nodes, 3, flux="rusanov", device=dev)
-    vortex = fi.Vortex()
+    nodes = fi.workload_nodes(W["nodes"])
+    if W["physics"] == "ns":
+        sl = fi.ShearLayer()
+        disc = Disc(nodes, W["p"], physics="ns", mu=sl.mu, prandtl=sl.prandtl, device=dev)
+        fn = lambda x, y: sl.conservative(x, y)  # noqa: E731
+        vortex = None
+    else:
+        disc = Disc(nodes, W["p"], device=dev)
+        vortex = fi.Vortex()
+        fn = lambda x, y: vortex.conservative(x, y, 0.0)  # noqa: E731
     xy = disc.solution_points().cpu().numpy()
-    U0_np = vortex.conservative(xy[0], xy[1], 0.0)
+    U0_np = fn(xy[0], xy[1])
     U0 = torch.as_tensor(U0_np, device=dev).contiguous()
-    prec = F64 if args.precond == "f64" else F32
-    opts = SolverOpts(lin=GmresOpts(m=20, rtol=1e-8), precond_precision=prec)
-    U = U0.clone()
-    for _ in range(args.warmup):
-        disc.row_step(U, args.scheme, args.dt, opts)
-    U.copy_(U0)
-    torch.cuda.synchronize()
-    evals = iters = 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st = disc.row_step(U, args.scheme, args.dt, opts)
-        if st["status"] != 0:
-            raise RuntimeError(f"row_step status {st['status']}")
-        evals += st["residual_evals"]
-        iters += st["gmres_iters"]
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     ndof = disc.ndof
-    value = ndof * evals / wall
-    t_phys = args.steps * args.dt
-    err_rho = disc.l2_error_vortex(U, 0, t_phys, vortex)
+    lin = GmresOpts(m=20, rtol=1e-8)
+    out = {"metric": "DOF-residuals/s", "unit": "DOF-residuals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"{W['label']}; ROW{scheme} dt={dt}, FGMRES(20) rtol 1e-8, element-Jacobi FP64, "
+                                  f"Rusanov, eps_rms 1e-8; timed steps start after {args.warmup} untimed steps",
+                      "ndof": ndof, "dt": dt},
+           "extra": {}}
 
-    out = {
-        "metric": "DOF-residuals/s", "value": value, "unit": "DOF-residuals/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"isentropic vortex, 64x64 perturbed quads (seed 2), P3, 262144 DOFs, "
-                               f"ROW{args.scheme} dt={args.dt}, FGMRES(20) rtol 1e-8, element-Jacobi "
-                               f"{args.precond.upper()}, Rusanov, eps_rms 1e-8",
-                   "ndof": ndof, "dt": args.dt},
-        "extra": {"wall_s_per_time_unit": wall / t_phys, "gmres_iters_per_step": iters / args.steps,
-                  "residual_evals_per_step": evals / args.steps, "l2_err_rho": err_rho, "t_end": t_phys},
-    }
+    # ---- (1) warm-up steps, logging the stage solves
+    rng = np.random.default_rng(40)
+    learned = not args.no_learned and W["physics"] == "euler"
+    per_stage = min(256, disc.nel)
+    logs = StageLogs([StageLog(disc, max(args.warmup, 1) * per_stage, rng.choice(disc.nel, per_stage, replace=False))
+                      for _ in range(nstage)]) if learned else None
+    yhist = torch.zeros((2, ndof), dtype=torch.float64, device=dev)
+    U = U0.clone()
+    t_w = time.perf_counter()
+    for _ in range(args.warmup):
+        if logs is not None:
+            for lg in logs.logs:
+                lg.set_elems(rng.choice(disc.nel, per_stage, replace=False))
+        st = disc.row_step(U, scheme, dt, SolverOpts(lin=lin, log=logs, yhist=yhist,
+                                                     commit_unconverged=int(args.allow_unconverged)))
+        if st["status"] != 0 and not (args.allow_unconverged and st["status"] == 1):
+            raise RuntimeError(f"warm-up row_step status {st['status']}")
+    torch.cuda.synchronize()
+    out["extra"]["warmup_s"] = time.perf_counter() - t_w
+    t_start = args.warmup * dt
+    Ustart, hstart = U.clone(), yhist.clone()
+
+    # ---- (2) train one network per stage on the GPU
+    warm = None
+    if learned and args.warmup > 0:
+        t_tr = time.perf_counter()
+        trainers, final_loss = [], []
+        for i, lg in enumerate(logs.logs):
+            tr = MlpTrainer(disc, n_hidden=256, seed=4 + i, lr=1e-3)
+            tr.fit_stats(lg)
+            ls = []
+            for it in range(400):
+                idx = torch.as_tensor(rng.choice(lg.count, min(512, lg.count), replace=False), dtype=torch.int32,
+                                      device=dev)
+                ls.append(tr.step(lg, idx, lr=1e-3 * 0.5 * (1 + np.cos(np.pi * it / 400))))
+            trainers.append(tr)
+            final_loss.append(float(np.mean(ls[-20:])))
+        torch.cuda.synchronize()
+        warm = WarmStart([t.net for t in trainers])
+        out["extra"]["learned_training"] = {"samples_per_stage": logs.logs[0].count, "adam_steps_per_stage": 400,
+                                            "batch": 512, "final_mse_normalised": final_loss,
+                                            "train_s": time.perf_counter() - t_tr}
+
+    # ---- (3) timed legs from the same state
+    t_phys = args.steps * dt
+
+    def err(Ux):
+        return disc.l2_error_vortex(Ux, 0, t_start + t_phys, vortex) if vortex is not None else None
+
+    U = Ustart.clone()
+    wall, evals, iters, x1 = run_leg(disc, U, args.steps, scheme, dt, SolverOpts(lin=lin, yhist=hstart.clone()),
+                                     args.allow_unconverged)
+    U_fp64 = U
+    out["value"] = ndof * evals / wall
+    out["ms_per_step"] = wall / args.steps * 1e3
+    out["extra"].update({"wall_s_per_time_unit": wall / t_phys, "gmres_iters_per_step": iters / args.steps,
+                         "residual_evals_per_step": evals / args.steps, "l2_err_rho": err(U_fp64),
+                         "t_start": t_start, "t_end": t_start + t_phys,
+                         "unconverged_solves": x1["unconverged_solves"]})
+    legs = {}
+    if not args.no_fp32_leg:
+        U = Ustart.clone()
+        w2, e2, i2, _ = run_leg(disc, U, args.steps, scheme, dt,
+                                SolverOpts(lin=lin, precond_precision=F32, yhist=hstart.clone()), args.allow_unconverged)
+        legs["fp32_precond"] = {"wall_s_per_time_unit": w2 / t_phys, "ms_per_step": w2 / args.steps * 1e3,
+                                "gmres_iters_per_step": i2 / args.steps, "l2_err_rho": err(U),
+                                "rel_diff_vs_fp64": float(torch.linalg.norm(U - U_fp64) / torch.linalg.norm(U_fp64))}
+        if warm is not None:
+            U = Ustart.clone()
+            w3, e3, i3, x3 = run_leg(disc, U, args.steps, scheme, dt,
+                                     SolverOpts(lin=lin, precond_precision=F32, warm=warm, yhist=hstart.clone()))
+            legs["fp32_precond_learned"] = {
+                "wall_s_per_time_unit": w3 / t_phys, "ms_per_step": w3 / args.steps * 1e3,
+                "gmres_iters_per_step": i3 / args.steps, "l2_err_rho": err(U), **x3,
+                "rel_diff_vs_fp64": float(torch.linalg.norm(U - U_fp64) / torch.linalg.norm(U_fp64)),
+                "speedup_vs_plain_fp64": wall / w3}
+    out["extra"]["legs"] = legs
 
     if not args.no_kernels:
         # live per-kernel timing on the launch stream (torch's current stream)
-        R0 = disc.residual(U0)
-        v = torch.randn_like(U0) * 1e-3
-        shift = 1.0 / (0.4358665215084590 * args.dt)
-        pc = disc.ejacobi_factor(U0, shift, prec)
-        z = disc.empty()
-        t_res = time_kernel(lambda: disc.residual(U0, R0))
-        Av = disc.empty()
-        t_mv = time_kernel(lambda: disc.jf_matvec(U0, R0, v, shift, out=Av))
-        t_sol = time_kernel(lambda: disc.ejacobi_solve(pc, v, z))
-        t_fac = time_kernel(lambda: disc.ejacobi_factor(U0, shift, prec, pc), reps=10, warm=2)
+        R0 = disc.residual(Ustart)
+        v = torch.randn_like(Ustart) * 1e-3
+        gam = {2: 0.25, 3: 0.4358665215084590, 4: 0.25}[scheme]
+        shift = 1.0 / (gam * dt)
         nb = disc.nb
-        es = 8 if prec == F64 else 4
-        solve_bytes = disc.nel * nb * nb * es + 16 * ndof          # block inverse + r in + z out
-        res_bytes = 16 * ndof                                        # U in, R out
-        kernels = {
-            "fr_residual": {"us": t_res * 1e6, "alg_bytes": res_bytes, "GBs": res_bytes / t_res / 1e9,
-                            "dof_res_per_s": ndof / t_res},
-            "jf_matvec(norm+fused residual)": {"us": t_mv * 1e6, "alg_bytes": 40 * ndof,
-                                               "GBs": 40 * ndof / t_mv / 1e9},
-            "ejacobi_solve": {"us": t_sol * 1e6, "alg_bytes": solve_bytes, "GBs": solve_bytes / t_sol / 1e9},
-            "ejacobi_factor(assemble+invert)": {"us": t_fac * 1e6, "alg_bytes": disc.nel * nb * nb * es,
-                                                "GBs": disc.nel * nb * nb * es / t_fac / 1e9},
-        }
+        kernels = {}
+        t_res = time_kernel(lambda: disc.residual(Ustart, R0))
+        res_bytes = 16 * ndof
+        kernels["fr_residual"] = {"us": t_res * 1e6, "alg_bytes": res_bytes, "GBs": res_bytes / t_res / 1e9,
+                                  "dof_res_per_s": ndof / t_res}
+        Av = disc.empty()
+        t_mv = time_kernel(lambda: disc.jf_matvec(Ustart, R0, v, shift, out=Av))
+        kernels["jf_matvec(norm+fused residual)"] = {"us": t_mv * 1e6, "alg_bytes": 40 * ndof,
+                                                     "GBs": 40 * ndof / t_mv / 1e9}
+        z = disc.empty()
+        for prec, name, es in ((F64, "fp64", 8), (F32, "fp32", 4)):
+            pc = disc.ejacobi_factor(Ustart, shift, prec)
+            t_sol = time_kernel(lambda: disc.ejacobi_solve(pc, v, z))
+            sb = disc.nel * nb * nb * es + 16 * ndof       # block inverse + r in + z out
+            kernels[f"ejacobi_solve_{name}"] = {"us": t_sol * 1e6, "alg_bytes": sb, "GBs": sb / t_sol / 1e9}
+            t_fac = time_kernel(lambda: disc.ejacobi_factor(Ustart, shift, prec, pc), reps=5, warm=1)
+            kernels[f"ejacobi_factor_{name}(assemble+invert)"] = {
+                "us": t_fac * 1e6, "inversion_TFLOPs": disc.nel * 2.0 * nb ** 3 / t_fac / 1e12}
+            del pc
         out["extra"]["kernels"] = kernels
-        dom = "ejacobi_solve"
+        dom = "ejacobi_solve_fp64"
         traffic = None
         tp = os.path.join(ROOT, "profiles", "traffic.json")
         if os.path.exists(tp):
             with open(tp) as fh:
                 tj = json.load(fh)
-            if tj.get("kernel") == dom and tj.get("source_sha") == source_sha(tj["source"]) \
-                    and prec == F64 and WORKLOAD == "vortex64_p3_perturbed":
+            if tj.get("kernel") == dom and tj.get("workload") == args.workload \
+                    and tj.get("source_sha") == source_sha(tj["source"]):
                 traffic = tj.get("bytes_per_launch")
         ach = kernels[dom]["GBs"]
         out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
-                           "alg_bytes_per_launch": solve_bytes}
-
-    if args.precond == "f64" and not args.no_fp32_leg:
-        # the same steps with the FP32 element-Jacobi factored on MFMA
-        opts32 = SolverOpts(lin=GmresOpts(m=20, rtol=1e-8), precond_precision=F32)
-        U32 = U0.clone()
-        disc.row_step(U32, args.scheme, args.dt, opts32)
-        U32.copy_(U0)
-        torch.cuda.synchronize()
-        ev32 = it32 = 0
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            st = disc.row_step(U32, args.scheme, args.dt, opts32)
-            ev32 += st["residual_evals"]
-            it32 += st["gmres_iters"]
-        torch.cuda.synchronize()
-        w32 = time.perf_counter() - t1
-        out["extra"]["fp32_precond"] = {
-            "ms_per_step": w32 / args.steps * 1e3, "wall_s_per_time_unit": w32 / t_phys,
-            "gmres_iters_per_step": it32 / args.steps, "dof_res_per_s": ndof * ev32 / w32,
-            "l2_err_rho": disc.l2_error_vortex(U32, 0, t_phys, vortex),
-            "rel_diff_vs_fp64_state": float(torch.linalg.norm(U32 - U) / torch.linalg.norm(U))}
-        pc32 = disc.ejacobi_factor(U0, 1.0 / (0.4358665215084590 * args.dt), F32)
-        z = disc.empty()
-        v = torch.randn_like(U0)
-        t_s32 = time_kernel(lambda: disc.ejacobi_solve(pc32, v, z))
-        t_f32 = time_kernel(lambda: disc.ejacobi_factor(U0, 1.0 / (0.4358665215084590 * args.dt), F32, pc32),
-                            reps=10, warm=2)
-        nb = disc.nb
-        b32 = disc.nel * nb * nb * 4 + 16 * ndof
-        out["extra"]["kernels"]["ejacobi_solve_fp32"] = {"us": t_s32 * 1e6, "alg_bytes": b32,
-                                                         "GBs": b32 / t_s32 / 1e9}
-        fl = disc.nel * 2.0 * nb ** 3   # Gauss-Jordan inversion flops
-        out["extra"]["kernels"]["ejacobi_factor_fp32_mfma(assemble+invert)"] = {
-            "us": t_f32 * 1e6, "inversion_TFLOPs": fl / t_f32 / 1e12}
+                           "alg_bytes_per_launch": kernels[dom]["alg_bytes"]}
 
     if args.calib_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
@@ -226,8 +294,8 @@ def main():
         torch.cuda.synchronize()
         out["extra"]["calib_copy_bytes"] = src.numel() * 8
 
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(nodes, U0_np.reshape(4, disc.nel, -1), args.dt)
+    if not args.no_cpu_baseline and W["physics"] == "euler":
+        out["cpu_baseline"] = cpu_baseline(nodes, Ustart.cpu().numpy().reshape(4, disc.nel, -1), dt, W["p"], scheme)
     print(json.dumps(out), flush=True)
 
 
