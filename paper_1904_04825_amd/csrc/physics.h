@@ -91,6 +91,30 @@ __device__ __forceinline__ void roe_flux(const double qL[4], const double qR[4],
   for (int k = 0; k < 4; ++k) out[k] = mag * (0.5 * (fL[k] + fR[k]) - 0.5 * d[k]);
 }
 
+// Rusanov flux with the area-weighted normal S directly: |S| f^com =
+// (f_S(qL) + f_S(qR))/2 - Lambda (qR - qL)/2, f_S = f S_x + g S_y,
+// Lambda = max(|u.S| + c|S|) of the two sides (no normalisation of S needed).
+__device__ __forceinline__ void rusanov_flux_S(const double qL[4], const double qR[4], double Sx, double Sy,
+                                               double magS, double gam, double out[4]) {
+  double lam = 0.0;
+  double fs[2][4];
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const double* q = side ? qR : qL;
+    const double ir = 1.0 / q[0];
+    const double u = q[1] * ir, v = q[2] * ir;
+    const double p = (gam - 1.0) * (q[3] - 0.5 * (q[1] * u + q[2] * v));
+    const double uS = u * Sx + v * Sy;
+    fs[side][0] = q[0] * uS;
+    fs[side][1] = q[1] * uS + p * Sx;
+    fs[side][2] = q[2] * uS + p * Sy;
+    fs[side][3] = (q[3] + p) * uS;
+    lam = fmax(lam, fabs(uS) + sqrt(gam * p * ir) * magS);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) out[v] = 0.5 * (fs[0][v] + fs[1][v]) - 0.5 * lam * (qR[v] - qL[v]);
+}
+
 template <int FLUX>
 __device__ __forceinline__ void common_flux(const double qL[4], const double qR[4], double Sx, double Sy,
                                             double gam, double out[4]) {

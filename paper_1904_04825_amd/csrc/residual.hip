@@ -19,20 +19,28 @@
 
 namespace frjf {
 
+#ifndef FRJF_TILE_P2
+#define FRJF_TILE_P2 8, 4, 320
+#endif
+#ifndef FRJF_TILE_P3
+#define FRJF_TILE_P3 4, 4, 256
+#endif
+#ifndef FRJF_TILE_P4
+#define FRJF_TILE_P4 5, 2, 256
+#endif
+
+template <int TX_, int TY_, int NT_>
+struct TileShape {
+  static constexpr int TX = TX_, TY = TY_, NT = NT_;
+};
 template <int P>
 struct EulerTile;
 template <>
-struct EulerTile<2> {
-  static constexpr int TX = 8, TY = 4, NT = 320;
-};
+struct EulerTile<2> : TileShape<FRJF_TILE_P2> {};
 template <>
-struct EulerTile<3> {
-  static constexpr int TX = 4, TY = 4, NT = 256;
-};
+struct EulerTile<3> : TileShape<FRJF_TILE_P3> {};
 template <>
-struct EulerTile<4> {
-  static constexpr int TX = 5, TY = 2, NT = 256;
-};
+struct EulerTile<4> : TileShape<FRJF_TILE_P4> {};
 
 // Tiles handed to the 8 XCDs in contiguous ranges (workgroup i runs on XCD i % 8),
 // so neighbouring tiles share an L2.
@@ -56,15 +64,26 @@ __device__ __forceinline__ double state_at(const ResArgs& a, size_t gi, double e
     return fma(e, a.V[gi], a.U[gi]);
 }
 
+template <int FLUX>
+__device__ __forceinline__ void face_common_flux(const double qL[4], const double qR[4], double Sx, double Sy,
+                                                 double gam, double out[4]) {
+  if constexpr (FLUX == 0)
+    rusanov_flux_S(qL, qR, Sx, Sy, sqrt(Sx * Sx + Sy * Sy), gam, out);
+  else
+    roe_flux(qL, qR, Sx, Sy, gam, out);
+}
+
 template <int P, int FLUX, int MODE>
 __global__ void __launch_bounds__(EulerTile<P>::NT) k_euler(const ResArgs a, const MeshArgs g, const Basis B) {
   constexpr int n = P + 1, Np = n * n;
   constexpr int TX = EulerTile<P>::TX, TY = EulerTile<P>::TY, NE = TX * TY, NT = EulerTile<P>::NT;
+  constexpr int NFV = (TX + 1) * TY, NFH = TX * (TY + 1);  // xi-faces and eta-faces of the tile
   __shared__ double sQ[4][NE * Np];
   __shared__ double sF[4][NE * Np];
   __shared__ double sG[4][NE * Np];
-  __shared__ double sJmp[4][4][NE * n];
   __shared__ double sIJ[NE * Np];
+  __shared__ double sFv[4][NFV * n], sFh[4][NFH * n];   // common fluxes |S| f^com on the tile's faces
+  __shared__ double sJmp[4][4][NE * n];                  // F^num - F^l on each element face
   __shared__ double sX[n], sD[n * n], sLm[n], sLp[n], sGL[n], sGR[n];
 
   if (MODE != 0 && a.skip != nullptr && *a.skip) return;
@@ -120,61 +139,103 @@ __global__ void __launch_bounds__(EulerTile<P>::NT) k_euler(const ResArgs a, con
   }
   __syncthreads();
 
-  // ---- phase 2: common fluxes and jumps on the four faces of every element
+  // ---- phase 2a: one common flux per face point of the tile (the -xi / -eta side first)
+  for (int idx = tid; idx < (NFV + NFH) * n; idx += NT) {
+    const bool vert = idx < NFV * n;
+    const int f = vert ? idx / n : (idx - NFV * n) / n;
+    const int j = idx % n;
+    int fx, fy, exA, eyA, exB, eyB;  // A: -side element, B: +side element (tile coordinates)
+    if (vert) {
+      fx = f % (TX + 1);
+      fy = f / (TX + 1);
+      exA = fx - 1;
+      eyA = fy;
+      exB = fx;
+      eyB = fy;
+    } else {
+      fx = f % TX;
+      fy = f / TX;
+      exA = fx;
+      eyA = fy - 1;
+      exB = fx;
+      eyB = fy;
+    }
+    // the face is needed if one of its elements belongs to the tile and the mesh
+    const bool okA = exA >= 0 && exA < TX && eyA >= 0 && eyA < TY && ex0 + exA < g.nx && ey0 + eyA < g.ny;
+    const bool okB = exB < TX && eyB < TY && ex0 + exB < g.nx && ey0 + eyB < g.ny;
+    if (!okA && !okB) continue;
+    double qs[2][4];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      int gx = ex0 + (side ? exB : exA), gy = ey0 + (side ? eyB : eyA);
+      gx = (gx < 0) ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
+      gy = (gy < 0) ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
+      const double* lw = side ? sLm : sLp;  // the -side element's +face, the +side element's -face
+      double qv[4] = {0, 0, 0, 0};
+      if (gx >= ex0 && gx < ex0 + TX && gy >= ey0 && gy < ey0 + TY) {
+        const int le = (gy - ey0) * TX + (gx - ex0);
+#pragma unroll
+        for (int c = 0; c < n; ++c) {
+          const int kk = le * Np + (vert ? j * n + c : c * n + j);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) qv[v] = fma(lw[c], sQ[v][kk], qv[v]);
+        }
+      } else {
+        const size_t el = (size_t)gy * g.nx + gx;
+#pragma unroll
+        for (int c = 0; c < n; ++c) {
+          const int kk = vert ? j * n + c : c * n + j;
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            qv[v] = fma(lw[c], state_at<MODE>(a, ((size_t)v * nel + el) * Np + kk, e), qv[v]);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) qs[side][v] = qv[v];
+    }
+    double Sx, Sy;
+    if (vert) {
+      const int ix = ex0 + fx;
+      xi_face_normal(g.nodes, g.nx, ix >= g.nx ? ix - g.nx : ix, ey0 + fy, &Sx, &Sy);
+    } else {
+      const int iy = ey0 + fy;
+      eta_face_normal(g.nodes, g.nx, ex0 + fx, iy >= g.ny ? iy - g.ny : iy, &Sx, &Sy);
+    }
+    double Fn[4];
+    face_common_flux<FLUX>(qs[0], qs[1], Sx, Sy, g.gam, Fn);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (vert)
+        sFv[v][f * n + j] = Fn[v];
+      else
+        sFh[v][f * n + j] = Fn[v];
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 2b: jumps F^num - F^l on the four faces of every element
   for (int idx = tid; idx < NE * 4 * n; idx += NT) {
     const int le = idx / (4 * n);
     const int r = idx - le * 4 * n;
-    const int f = r / n, j = r - f * n;
-    const int ex = ex0 + le % TX, ey = ey0 + le / TX;
-    if (ex >= g.nx || ey >= g.ny) continue;
-    const bool xi_face = f < 2;
-    const double* lw = (f == 0 || f == 2) ? sLm : sLp;
-    const double* lo = (f == 0 || f == 2) ? sLp : sLm;  // neighbour's opposite face
-    double qo[4] = {0, 0, 0, 0}, Fl[4] = {0, 0, 0, 0}, qn[4] = {0, 0, 0, 0};
+    const int fc = r / n, j = r - fc * n;
+    const int lx = le % TX, ly = le / TX;
+    if (ex0 + lx >= g.nx || ey0 + ly >= g.ny) continue;
+    const bool xi_face = fc < 2;
+    const double* lw = (fc == 0 || fc == 2) ? sLm : sLp;
+    double Fl[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int c = 0; c < n; ++c) {
       const int kk = le * Np + (xi_face ? j * n + c : c * n + j);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        qo[v] = fma(lw[c], sQ[v][kk], qo[v]);
-        Fl[v] = fma(lw[c], xi_face ? sF[v][kk] : sG[v][kk], Fl[v]);
-      }
+      for (int v = 0; v < 4; ++v) Fl[v] = fma(lw[c], xi_face ? sF[v][kk] : sG[v][kk], Fl[v]);
     }
-    int nex = ex, ney = ey;
-    if (f == 0) nex = (ex == 0) ? g.nx - 1 : ex - 1;
-    if (f == 1) nex = (ex + 1 == g.nx) ? 0 : ex + 1;
-    if (f == 2) ney = (ey == 0) ? g.ny - 1 : ey - 1;
-    if (f == 3) ney = (ey + 1 == g.ny) ? 0 : ey + 1;
-    if (nex >= ex0 && nex < ex0 + TX && ney >= ey0 && ney < ey0 + TY) {
-      const int nle = (ney - ey0) * TX + (nex - ex0);
+    int fi;
+    if (fc == 0) fi = ly * (TX + 1) + lx;
+    else if (fc == 1) fi = ly * (TX + 1) + lx + 1;
+    else if (fc == 2) fi = ly * TX + lx;
+    else fi = (ly + 1) * TX + lx;
 #pragma unroll
-      for (int c = 0; c < n; ++c) {
-        const int kk = nle * Np + (xi_face ? j * n + c : c * n + j);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) qn[v] = fma(lo[c], sQ[v][kk], qn[v]);
-      }
-    } else {
-      const size_t nel_idx = (size_t)ney * g.nx + nex;
-#pragma unroll
-      for (int c = 0; c < n; ++c) {
-        const int kk = xi_face ? j * n + c : c * n + j;
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          qn[v] = fma(lo[c], state_at<MODE>(a, ((size_t)v * nel + nel_idx) * Np + kk, e), qn[v]);
-      }
-    }
-    double Sx, Sy;
-    if (f == 0) xi_face_normal(g.nodes, g.nx, ex, ey, &Sx, &Sy);
-    else if (f == 1) xi_face_normal(g.nodes, g.nx, (ex + 1 == g.nx) ? 0 : ex + 1, ey, &Sx, &Sy);
-    else if (f == 2) eta_face_normal(g.nodes, g.nx, ex, ey, &Sx, &Sy);
-    else eta_face_normal(g.nodes, g.nx, ex, (ey + 1 == g.ny) ? 0 : ey + 1, &Sx, &Sy);
-    double Fn[4];
-    if (f == 0 || f == 2)
-      common_flux<FLUX>(qn, qo, Sx, Sy, g.gam, Fn);
-    else
-      common_flux<FLUX>(qo, qn, Sx, Sy, g.gam, Fn);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) sJmp[f][v][le * n + j] = Fn[v] - Fl[v];
+    for (int v = 0; v < 4; ++v) sJmp[fc][v][le * n + j] = (xi_face ? sFv[v][fi * n + j] : sFh[v][fi * n + j]) - Fl[v];
   }
   __syncthreads();
 
