@@ -67,6 +67,7 @@ fr_status fr_disc_create(const fr_disc_desc* desc, fr_disc** out) {
   d->basis = make_basis(desc->p);
   d->nodes = desc->d_nodes;
   hipError_t e = hipGetDevice(&d->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&d->ncu, hipDeviceAttributeMultiprocessorCount, d->device);
   if (e == hipSuccess) e = hipHostMalloc(&d->h_pinned, 4096, hipHostMallocMapped | hipHostMallocCoherent);
   if (e == hipSuccess) e = hipHostGetDevicePointer(&d->d_pinned, d->h_pinned, 0);
   for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&d->ev[i], hipEventDisableTiming);

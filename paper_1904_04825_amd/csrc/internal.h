@@ -42,6 +42,7 @@ struct fr_disc {
   frjf::Basis basis;
   const double* nodes;
   int device;
+  int ncu;  // compute units of the device (persistent-grid sizing)
   // pinned, mapped host scratch: [0, 1 KiB) GMRES status written by the device,
   // [1 KiB, 4 KiB) staging of synchronous device-to-host reads
   void* h_pinned;

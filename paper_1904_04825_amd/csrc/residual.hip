@@ -4,47 +4,74 @@
 //   MODE 1: out = shift v - [R(U + e v) - R0] / e
 //   MODE 2: out = b - (shift v - [R(U + e v) - R0] / e)      (GMRES true residual)
 //
-// A workgroup owns a TX x TY tile of elements.  Phase 1 evaluates the
-// transformed fluxes F = y_eta f - x_eta g, G = -y_xi f + x_xi g at every
-// solution point into LDS.  Phase 2 forms, for every face point of every
-// element, the element's own solution/flux traces, the neighbour's solution
-// trace (from LDS inside the tile, from global memory for the halo), and the
-// common flux |S| f^com with the state on the -xi / -eta side first; each
-// element recomputes its four faces with identical arguments to its
-// neighbours, so both sides of a face see the same numerical flux and the
-// scheme stays conservative without atomics.  Phase 3 applies the derivative
-// matrix and the Radau correction derivatives.
+// A workgroup owns a TX x TY tile of elements and gives one thread to every
+// element line.  The operators are tensor products of 1D ones, so the work
+// splits into line passes whose basis coefficients are compile-time indexed
+// (scalar registers) and whose derivatives stay in vector registers:
+//   halo   the solution traces of the elements around the tile on the faces
+//          they share with it, straight from global memory;
+//   rows   thread (e, j) takes row j (constant eta) of element e: the state
+//          goes to LDS, F = y_eta f - x_eta g, D_xi F, and the W/E traces of
+//          q and of F;
+//   cols   the same thread takes column j (constant xi) from LDS:
+//          G = -y_xi f + x_xi g, D_eta G, and the S/N traces of q and of G;
+//   faces  one common flux |S| f^com per face point of the tile, the state
+//          on the -xi / -eta side first; a face on the tile border is also
+//          computed by the neighbouring tile from bit-identical traces, so
+//          both sides see the same flux and the scheme stays conservative;
+//   out    jumps F^num - F^l times the Radau correction derivatives, the
+//          column results handed to the row threads through LDS, R = -div/J.
+#include <algorithm>
+
 #include "internal.h"
 #include "physics.h"
 
 namespace frjf {
 
+// Tiles: a large one for big meshes, a small one so that small meshes still
+// spread over every compute unit.
+template <int P, bool BIG>
+struct LineTile;
 #ifndef FRJF_TILE_P2
-#define FRJF_TILE_P2 8, 4, 320
+#define FRJF_TILE_P2 16, 5, 7, 3
 #endif
 #ifndef FRJF_TILE_P3
-#define FRJF_TILE_P3 4, 4, 256
+#define FRJF_TILE_P3 8, 8, 4, 4
 #endif
 #ifndef FRJF_TILE_P4
-#define FRJF_TILE_P4 5, 2, 256
+#define FRJF_TILE_P4 10, 5, 5, 2
 #endif
-
-template <int TX_, int TY_, int NT_>
-struct TileShape {
-  static constexpr int TX = TX_, TY = TY_, NT = NT_;
+template <bool BIG, int TXB, int TYB, int TXS, int TYS>
+struct TilePick {
+  static constexpr int TX = BIG ? TXB : TXS, TY = BIG ? TYB : TYS;
 };
-template <int P>
-struct EulerTile;
-template <>
-struct EulerTile<2> : TileShape<FRJF_TILE_P2> {};
-template <>
-struct EulerTile<3> : TileShape<FRJF_TILE_P3> {};
-template <>
-struct EulerTile<4> : TileShape<FRJF_TILE_P4> {};
+template <bool BIG> struct LineTile<2, BIG> : TilePick<BIG, FRJF_TILE_P2> {};
+template <bool BIG> struct LineTile<3, BIG> : TilePick<BIG, FRJF_TILE_P3> {};
+template <bool BIG> struct LineTile<4, BIG> : TilePick<BIG, FRJF_TILE_P4> {};
 
-// Tiles handed to the 8 XCDs in contiguous ranges (workgroup i runs on XCD i % 8),
-// so neighbouring tiles share an L2.
+template <int P, bool BIG>
+struct LineCfg {
+  static constexpr int n = P + 1, Np = n * n;
+  // element stride of the LDS state: row writes and column reads without bank conflicts
+  static constexpr int ES = (n == 4) ? Np + 3 : Np;
+  static constexpr int TX = LineTile<P, BIG>::TX, TY = LineTile<P, BIG>::TY, NE = TX * TY;
+  static constexpr int NL = NE * n;                 // element lines = working threads
+  static constexpr int NT = (NL + 63) / 64 * 64;
+  static constexpr int NFX = TY * (TX + 1) * n;     // xi-face points
+  static constexpr int NFE = (TY + 1) * TX * n;     // eta-face points
+  static constexpr int NF = NFX + NFE;
+  static constexpr int NH = 2 * (TX + TY) * n;      // halo lines
+  // trace slots: W, E, S, N faces of the tile's elements, then the halo's W, E, S, N sides
+  static constexpr int SW = 0, SE = NE * n, SS = 2 * NE * n, SN = 3 * NE * n;
+  static constexpr int SHW = 4 * NE * n, SHE = SHW + TY * n, SHS = SHE + TY * n, SHN = SHS + TX * n;
+  static constexpr int NS = SHN + TX * n;
+  static constexpr int QS = NE * ES;                // variable stride of the LDS state
+  static constexpr int A = (4 * QS > 4 * NF) ? 4 * QS : 4 * NF;
+};
+
 __device__ __forceinline__ int xcd_remap(int i, int T) {
+  // tiles handed to the 8 XCDs in contiguous ranges (workgroup i runs on XCD i % 8),
+  // so neighbouring tiles share an L2
   const int q = T >> 3, r = T & 7;
   const int x = i & 7, l = i >> 3;
   return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
@@ -64,43 +91,116 @@ __device__ __forceinline__ double state_at(const ResArgs& a, size_t gi, double e
     return fma(e, a.V[gi], a.U[gi]);
 }
 
+// arr[t] for a per-thread t < n, by selects over compile-time indexed entries
+template <int n>
+__device__ __forceinline__ double pick(const double (&arr)[kMaxN], int t) {
+  double r = arr[0];
+#pragma unroll
+  for (int c = 1; c < n; ++c) r = (t == c) ? arr[c] : r;
+  return r;
+}
+
+// 1/a to full double precision: hardware estimate and two Newton steps
+__device__ __forceinline__ double rcp64(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  double e = fma(-a, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-a, r, 1.0);
+  return fma(r, e, r);
+}
+
+// sqrt(a) for positive normal a: hardware 1/sqrt(a) estimate refined by
+// Goldschmidt's coupled iteration for sqrt(a) and 1/(2 sqrt(a)).
+__device__ __forceinline__ double sqrt64(double a) {
+  const double y = __builtin_amdgcn_rsq(a);
+  double g = a * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, a);
+  g = fma(d, h, g);
+  d = fma(-g, g, a);
+  return fma(d, h, g);
+}
+
+// Rusanov flux with the area-weighted normal S: |S| f^com =
+// (f_S(qL) + f_S(qR))/2 - Lambda (qR - qL)/2, f_S = f S_x + g S_y,
+// Lambda = max over both sides of |u.S| + c|S|.
+__device__ __forceinline__ void rusanov_face(const double qL[4], const double qR[4], double Sx, double Sy,
+                                             double gam, double out[4]) {
+  const double magS = sqrt64(Sx * Sx + Sy * Sy);
+  double lam = 0.0;
+  double fs[2][4];
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const double* q = side ? qR : qL;
+    const double ir = rcp64(q[0]);
+    const double u = q[1] * ir, v = q[2] * ir;
+    const double p = (gam - 1.0) * (q[3] - 0.5 * (q[1] * u + q[2] * v));
+    const double uS = u * Sx + v * Sy;
+    fs[side][0] = q[0] * uS;
+    fs[side][1] = q[1] * uS + p * Sx;
+    fs[side][2] = q[2] * uS + p * Sy;
+    fs[side][3] = (q[3] + p) * uS;
+    lam = fmax(lam, fabs(uS) + sqrt64(gam * p * ir) * magS);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) out[v] = 0.5 * (fs[0][v] + fs[1][v]) - 0.5 * lam * (qR[v] - qL[v]);
+}
+
 template <int FLUX>
-__device__ __forceinline__ void face_common_flux(const double qL[4], const double qR[4], double Sx, double Sy,
-                                                 double gam, double out[4]) {
+__device__ __forceinline__ void face_flux(const double qL[4], const double qR[4], double Sx, double Sy,
+                                          double gam, double out[4]) {
   if constexpr (FLUX == 0)
-    rusanov_flux_S(qL, qR, Sx, Sy, sqrt(Sx * Sx + Sy * Sy), gam, out);
+    rusanov_face(qL, qR, Sx, Sy, gam, out);
   else
     roe_flux(qL, qR, Sx, Sy, gam, out);
 }
 
-template <int P, int FLUX, int MODE>
-__global__ void __launch_bounds__(EulerTile<P>::NT) k_euler(const ResArgs a, const MeshArgs g, const Basis B) {
-  constexpr int n = P + 1, Np = n * n;
-  constexpr int TX = EulerTile<P>::TX, TY = EulerTile<P>::TY, NE = TX * TY, NT = EulerTile<P>::NT;
-  constexpr int NFV = (TX + 1) * TY, NFH = TX * (TY + 1);  // xi-faces and eta-faces of the tile
-  __shared__ double sQ[4][NE * Np];
-  __shared__ double sF[4][NE * Np];
-  __shared__ double sG[4][NE * Np];
-  __shared__ double sIJ[NE * Np];
-  __shared__ double sFv[4][NFV * n], sFh[4][NFH * n];   // common fluxes |S| f^com on the tile's faces
-  __shared__ double sJmp[4][4][NE * n];                  // F^num - F^l on each element face
-  __shared__ double sX[n], sD[n * n], sLm[n], sLp[n], sGL[n], sGR[n];
+// f and g of q = (rho, rho u, rho v, E) combined into a transformed flux
+// alpha f + beta g.
+__device__ __forceinline__ void transformed_flux(const double q[4], double gam, double alpha, double beta,
+                                                 double out[4]) {
+  const double ir = rcp64(q[0]);
+  const double u = q[1] * ir, v = q[2] * ir;
+  const double p = (gam - 1.0) * (q[3] - 0.5 * (q[1] * u + q[2] * v));
+  const double un = alpha * u + beta * v;  // contravariant velocity
+  out[0] = q[0] * un;
+  out[1] = fma(q[1], un, alpha * p);
+  out[2] = fma(q[2], un, beta * p);
+  out[3] = (q[3] + p) * un;
+}
+
+// Tile of the linear sequence number k: first element column / row and the
+// live element counts (the last tile row / column may be ragged).
+template <int TX, int TY>
+struct TileIdx {
+  int ex0, ey0, mX, mY;
+  __device__ __forceinline__ TileIdx(int k, int T, int ntx, int nx, int ny) {
+    const int tile = xcd_remap(k, T);
+    ex0 = (tile % ntx) * TX;
+    ey0 = (tile / ntx) * TY;
+    mX = min(TX, nx - ex0);
+    mY = min(TY, ny - ey0);
+  }
+};
+
+template <int P, int FLUX, int MODE, bool BIG>
+__global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a, const MeshArgs g, const Basis B) {
+  using C = LineCfg<P, BIG>;
+  constexpr int n = C::n, Np = C::Np, ES = C::ES, TX = C::TX, TY = C::TY, NT = C::NT;
+  constexpr int QS = C::QS, NS = C::NS, NF = C::NF;
+  constexpr int RUN = TX * Np, NIT = (TY * RUN + NT - 1) / NT, NHI = (C::NH + NT - 1) / NT;
+  __shared__ double sA[C::A];        // state, then common face fluxes, then column results
+  __shared__ double sT[4 * C::NS];   // solution traces
 
   if (MODE != 0 && a.skip != nullptr && *a.skip) return;
   const int tid = threadIdx.x;
-  if (tid < n * n) sD[tid] = B.D[tid / n][tid % n];
-  if (tid < n) {
-    sX[tid] = B.x[tid];
-    sLm[tid] = B.lm[tid];
-    sLp[tid] = B.lp[tid];
-    sGL[tid] = B.gL[tid];
-    sGR[tid] = B.gR[tid];
-  }
   const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY;
-  const int tile = xcd_remap(blockIdx.x, ntx * nty);
-  const int ex0 = (tile % ntx) * TX, ey0 = (tile / ntx) * TY;
-  const size_t nel = (size_t)g.nel;
-  double e = 0.0;
+  const TileIdx<TX, TY> ti(blockIdx.x, ntx * nty, ntx, g.nx, g.ny);
+  const int ex0 = ti.ex0, ey0 = ti.ey0, mX = ti.mX, mY = ti.mY;
+  const size_t nel = (size_t)g.nel, vstride = nel * Np;
+  double e = 0.0, ie = 0.0;
   bool zero_v = false;
   if constexpr (MODE != 0) {
     if (a.eps_mode == FR_EPS_RMS) {
@@ -112,181 +212,368 @@ __global__ void __launch_bounds__(EulerTile<P>::NT) k_euler(const ResArgs a, con
     } else {
       e = a.eps;
     }
+    ie = zero_v ? 0.0 : 1.0 / e;
   }
-  __syncthreads();
 
-  // ---- phase 1: transformed fluxes at the solution points
-  for (int idx = tid; idx < NE * Np; idx += NT) {
-    const int le = idx / Np, k = idx - le * Np;
-    const int ex = ex0 + le % TX, ey = ey0 + le / TX;
-    if (ex >= g.nx || ey >= g.ny) continue;
-    const size_t el = (size_t)ey * g.nx + ex;
-    double q[4];
+  // ---- the tile's state and the halo lines.  Every global load of the phase is
+  // issued before the first use, so the tile and halo reads overlap.  Each tile row
+  // of a variable is one contiguous run of mX * Np doubles, read with consecutive
+  // lanes; U (and v) are combined when the state is written to LDS.
+  double pu[NIT][4], pv[MODE ? NIT : 1][4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) q[v] = state_at<MODE>(a, ((size_t)v * nel + el) * Np + k, e);
-    double c[8];
-    load_corners(g.nodes, g.nx, ex, ey, c);
-    const Metric m = bilinear_metric(c, sX[k % n], sX[k / n]);
-    double f[4], gg[4];
-    euler_fluxes(q, g.gam, f, gg);
+  for (int it = 0; it < NIT; ++it) {
+    const int idx = tid + it * NT, ry = idx / RUN, kk = idx - ry * RUN;
+    if (idx < TY * RUN && ry < mY && kk < mX * Np) {
+      const size_t base = ((size_t)(ey0 + ry) * g.nx + ex0) * Np + kk;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      sQ[v][idx] = q[v];
-      sF[v][idx] = m.yeta * f[v] - m.xeta * gg[v];
-      sG[v][idx] = -m.yxi * f[v] + m.xxi * gg[v];
+      for (int v = 0; v < 4; ++v) {
+        pu[it][v] = a.U[v * vstride + base];
+        if constexpr (MODE != 0) pv[MODE ? it : 0][v] = a.V[v * vstride + base];
+      }
     }
-    sIJ[idx] = 1.0 / m.J;
   }
-  __syncthreads();
-
-  // ---- phase 2a: one common flux per face point of the tile (the -xi / -eta side first)
-  for (int idx = tid; idx < (NFV + NFH) * n; idx += NT) {
-    const bool vert = idx < NFV * n;
-    const int f = vert ? idx / n : (idx - NFV * n) / n;
-    const int j = idx % n;
-    int fx, fy, exA, eyA, exB, eyB;  // A: -side element, B: +side element (tile coordinates)
-    if (vert) {
-      fx = f % (TX + 1);
-      fy = f / (TX + 1);
-      exA = fx - 1;
-      eyA = fy;
-      exB = fx;
-      eyB = fy;
-    } else {
-      fx = f % TX;
-      fy = f / TX;
-      exA = fx;
-      eyA = fy - 1;
-      exB = fx;
-      eyB = fy;
-    }
-    // the face is needed if one of its elements belongs to the tile and the mesh
-    const bool okA = exA >= 0 && exA < TX && eyA >= 0 && eyA < TY && ex0 + exA < g.nx && ey0 + eyA < g.ny;
-    const bool okB = exB < TX && eyB < TY && ex0 + exB < g.nx && ey0 + eyB < g.ny;
-    if (!okA && !okB) continue;
-    double qs[2][4];
+  {
+    // ---- halo lines: the row (west / east neighbour) or column (south / north
+    // neighbour) of the element across a border face, loaded before the state lands
+    double hq[NHI][n][4];
+    int hslot[NHI];
+    bool hplus[NHI];
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      int gx = ex0 + (side ? exB : exA), gy = ey0 + (side ? eyB : eyA);
-      gx = (gx < 0) ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
-      gy = (gy < 0) ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
-      const double* lw = side ? sLm : sLp;  // the -side element's +face, the +side element's -face
-      double qv[4] = {0, 0, 0, 0};
-      if (gx >= ex0 && gx < ex0 + TX && gy >= ey0 && gy < ey0 + TY) {
-        const int le = (gy - ey0) * TX + (gx - ex0);
-#pragma unroll
-        for (int c = 0; c < n; ++c) {
-          const int kk = le * Np + (vert ? j * n + c : c * n + j);
-#pragma unroll
-          for (int v = 0; v < 4; ++v) qv[v] = fma(lw[c], sQ[v][kk], qv[v]);
+    for (int it = 0; it < NHI; ++it) {
+      const int h = tid + it * NT;
+      hslot[it] = -1;
+      hplus[it] = false;
+      size_t base = 0;
+      int stride = 1;
+      if (h < 2 * TY * n) {  // rows of the west / east neighbours
+        const int side = h / (TY * n), r = h - side * (TY * n), ly = r / n, j = r - ly * n;
+        if (ly < mY) {
+          int hx = side ? ex0 + mX : ex0 - 1;
+          hx = hx < 0 ? hx + g.nx : (hx >= g.nx ? hx - g.nx : hx);
+          base = ((size_t)(ey0 + ly) * g.nx + hx) * Np + j * n;
+          hslot[it] = (side ? C::SHE : C::SHW) + ly * n + j;
+          hplus[it] = side == 0;  // the west neighbour's east face, the east neighbour's west face
         }
-      } else {
-        const size_t el = (size_t)gy * g.nx + gx;
+      } else if (h < C::NH) {  // columns of the south / north neighbours
+        const int h2 = h - 2 * TY * n;
+        const int side = h2 / (TX * n), r = h2 - side * (TX * n), lx = r / n, i = r - lx * n;
+        if (lx < mX) {
+          int hy = side ? ey0 + mY : ey0 - 1;
+          hy = hy < 0 ? hy + g.ny : (hy >= g.ny ? hy - g.ny : hy);
+          base = ((size_t)hy * g.nx + ex0 + lx) * Np + i;
+          stride = n;
+          hslot[it] = (side ? C::SHN : C::SHS) + lx * n + i;
+          hplus[it] = side == 0;  // the south neighbour's north face
+        }
+      }
+      if (hslot[it] >= 0) {
 #pragma unroll
-        for (int c = 0; c < n; ++c) {
-          const int kk = vert ? j * n + c : c * n + j;
+        for (int c = 0; c < n; ++c)
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            qv[v] = fma(lw[c], state_at<MODE>(a, ((size_t)v * nel + el) * Np + kk, e), qv[v]);
+            hq[it][c][v] = state_at<MODE>(a, v * vstride + base + c * stride, e);
+      }
+    }
+
+    // ---- the state into LDS
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int idx = tid + it * NT, ry = idx / RUN, kk = idx - ry * RUN;
+      if (idx < TY * RUN && ry < mY && kk < mX * Np) {
+        const int dst = (ry * TX + kk / Np) * ES + kk % Np;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sA[v * QS + dst] = MODE ? fma(e, pv[MODE ? it : 0][v], pu[it][v]) : pu[it][v];
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < NHI; ++it) {
+      if (hslot[it] < 0) continue;
+      double tr[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int c = 0; c < n; ++c) {
+        const double w = hplus[it] ? B.lp[c] : B.lm[c];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) tr[v] = fma(w, hq[it][c][v], tr[v]);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sT[v * NS + hslot[it]] = tr[v];
+    }
+    __syncthreads();
+
+    // ---- rows
+    const int le = tid / n, t = tid - le * n;
+    const int lx = le % TX, ly = le / TX;
+    const bool live = tid < C::NL && lx < mX && ly < mY;
+    const double tp = pick<n>(B.x, t);  // eta of row t, xi of column t
+    // bilinear map: x_xi = ax + bx eta, x_eta = cx + dx xi (and the same for y)
+    double ax = 0, bx = 0, ay = 0, by = 0, cx = 0, dx = 0, cy = 0, dy = 0;
+    double nW[2] = {0, 0}, nS[2] = {0, 0};  // normals of the west and south faces
+    double dF[n][4], FlW[4], FlE[4];
+    if (live) {
+      double c[8];
+      load_corners(g.nodes, g.nx, ex0 + lx, ey0 + ly, c);
+      ax = 0.25 * ((c[2] - c[0]) + (c[6] - c[4]));
+      bx = 0.25 * ((c[6] - c[4]) - (c[2] - c[0]));
+      ay = 0.25 * ((c[3] - c[1]) + (c[7] - c[5]));
+      by = 0.25 * ((c[7] - c[5]) - (c[3] - c[1]));
+      cx = 0.25 * ((c[4] - c[0]) + (c[6] - c[2]));
+      dx = 0.25 * ((c[6] - c[2]) - (c[4] - c[0]));
+      cy = 0.25 * ((c[5] - c[1]) + (c[7] - c[3]));
+      dy = 0.25 * ((c[7] - c[3]) - (c[5] - c[1]));
+      // xi-faces S = (y_eta, -x_eta), eta-faces S = (-y_xi, x_xi), from the edge's end nodes;
+      // the node pair of an edge is the same for both tiles sharing it
+      nW[0] = 0.5 * (c[5] - c[1]);
+      nW[1] = -0.5 * (c[4] - c[0]);
+      nS[0] = -0.5 * (c[3] - c[1]);
+      nS[1] = 0.5 * (c[2] - c[0]);
+      double q[n][4];
+#pragma unroll
+      for (int cc = 0; cc < n; ++cc)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) q[cc][v] = sA[v * QS + le * ES + t * n + cc];
+      double qW[4] = {0, 0, 0, 0}, qE[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        FlW[v] = 0.0;
+        FlE[v] = 0.0;
+#pragma unroll
+        for (int i = 0; i < n; ++i) dF[i][v] = 0.0;
+      }
+#pragma unroll
+      for (int cc = 0; cc < n; ++cc) {
+        const double xeta = fma(dx, B.x[cc], cx), yeta = fma(dy, B.x[cc], cy);
+        double F[4];
+        transformed_flux(q[cc], g.gam, yeta, -xeta, F);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+#pragma unroll
+          for (int i = 0; i < n; ++i) dF[i][v] = fma(B.D[i][cc], F[v], dF[i][v]);
+          qW[v] = fma(B.lm[cc], q[cc][v], qW[v]);
+          qE[v] = fma(B.lp[cc], q[cc][v], qE[v]);
+          FlW[v] = fma(B.lm[cc], F[v], FlW[v]);
+          FlE[v] = fma(B.lp[cc], F[v], FlE[v]);
         }
       }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) qs[side][v] = qv[v];
-    }
-    double Sx, Sy;
-    if (vert) {
-      const int ix = ex0 + fx;
-      xi_face_normal(g.nodes, g.nx, ix >= g.nx ? ix - g.nx : ix, ey0 + fy, &Sx, &Sy);
-    } else {
-      const int iy = ey0 + fy;
-      eta_face_normal(g.nodes, g.nx, ex0 + fx, iy >= g.ny ? iy - g.ny : iy, &Sx, &Sy);
-    }
-    double Fn[4];
-    face_common_flux<FLUX>(qs[0], qs[1], Sx, Sy, g.gam, Fn);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      if (vert)
-        sFv[v][f * n + j] = Fn[v];
-      else
-        sFh[v][f * n + j] = Fn[v];
-    }
-  }
-  __syncthreads();
-
-  // ---- phase 2b: jumps F^num - F^l on the four faces of every element
-  for (int idx = tid; idx < NE * 4 * n; idx += NT) {
-    const int le = idx / (4 * n);
-    const int r = idx - le * 4 * n;
-    const int fc = r / n, j = r - fc * n;
-    const int lx = le % TX, ly = le / TX;
-    if (ex0 + lx >= g.nx || ey0 + ly >= g.ny) continue;
-    const bool xi_face = fc < 2;
-    const double* lw = (fc == 0 || fc == 2) ? sLm : sLp;
-    double Fl[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int c = 0; c < n; ++c) {
-      const int kk = le * Np + (xi_face ? j * n + c : c * n + j);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Fl[v] = fma(lw[c], xi_face ? sF[v][kk] : sG[v][kk], Fl[v]);
-    }
-    int fi;
-    if (fc == 0) fi = ly * (TX + 1) + lx;
-    else if (fc == 1) fi = ly * (TX + 1) + lx + 1;
-    else if (fc == 2) fi = ly * TX + lx;
-    else fi = (ly + 1) * TX + lx;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) sJmp[fc][v][le * n + j] = (xi_face ? sFv[v][fi * n + j] : sFh[v][fi * n + j]) - Fl[v];
-  }
-  __syncthreads();
-
-  // ---- phase 3: divergence of the corrected flux
-  for (int idx = tid; idx < NE * Np; idx += NT) {
-    const int le = idx / Np, k = idx - le * Np;
-    const int ex = ex0 + le % TX, ey = ey0 + le / TX;
-    if (ex >= g.nx || ey >= g.ny) continue;
-    const int ia = k % n, ib = k / n;
-    const size_t el = (size_t)ey * g.nx + ex;
-    const int rowb = le * Np + ib * n, cola = le * Np + ia;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      double div = 0.0;
-#pragma unroll
-      for (int c = 0; c < n; ++c) {
-        div = fma(sD[ia * n + c], sF[v][rowb + c], div);
-        div = fma(sD[ib * n + c], sG[v][cola + c * n], div);
+      for (int v = 0; v < 4; ++v) {
+        sT[v * NS + C::SW + le * n + t] = qW[v];
+        sT[v * NS + C::SE + le * n + t] = qE[v];
       }
-      div = fma(sJmp[0][v][le * n + ib], sGL[ia], div);
-      div = fma(sJmp[1][v][le * n + ib], sGR[ia], div);
-      div = fma(sJmp[2][v][le * n + ia], sGL[ib], div);
-      div = fma(sJmp[3][v][le * n + ia], sGR[ib], div);
-      const double R = -div * sIJ[idx];
-      const size_t gi = ((size_t)v * nel + el) * Np + k;
-      if constexpr (MODE == 0) {
-        a.out[gi] = R;
+    }
+    __syncthreads();
+
+    // ---- columns
+    double dG[n][4], GlS[4], GlN[4];
+    if (live) {
+      const double xeta = fma(dx, tp, cx), yeta = fma(dy, tp, cy);
+      double qS[4] = {0, 0, 0, 0}, qN[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        GlS[v] = 0.0;
+        GlN[v] = 0.0;
+#pragma unroll
+        for (int j = 0; j < n; ++j) dG[j][v] = 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < n; ++r) {
+        double q[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) q[v] = sA[v * QS + le * ES + r * n + t];
+        const double xxi = fma(bx, B.x[r], ax), yxi = fma(by, B.x[r], ay);
+        double G[4];
+        transformed_flux(q, g.gam, -yxi, xxi, G);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+#pragma unroll
+          for (int j = 0; j < n; ++j) dG[j][v] = fma(B.D[j][r], G[v], dG[j][v]);
+          qS[v] = fma(B.lm[r], q[v], qS[v]);
+          qN[v] = fma(B.lp[r], q[v], qN[v]);
+          GlS[v] = fma(B.lm[r], G[v], GlS[v]);
+          GlN[v] = fma(B.lp[r], G[v], GlN[v]);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        sT[v * NS + C::SS + le * n + t] = qS[v];
+        sT[v * NS + C::SN + le * n + t] = qN[v];
+      }
+    }
+    __syncthreads();
+
+    // ---- faces: one common flux per face point, the state on the -xi / -eta side first.
+    // Slots: xi-face point j of face f in tile row fy at (fy (TX+1) + f) n + j, then
+    // eta-face point i of face row fy, column fx at NFX + (fy TX + fx) n + i.
+    const int nstride = g.nx + 1;
+    if (live) {  // the west face point t and the south face point t of the thread's element
+      double qL[4], qR[4], Fn[4];
+      int sL = (lx == 0) ? C::SHW + ly * n + t : C::SE + (le - 1) * n + t;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        qL[v] = sT[v * NS + sL];
+        qR[v] = sT[v * NS + C::SW + le * n + t];
+      }
+      face_flux<FLUX>(qL, qR, nW[0], nW[1], g.gam, Fn);
+      const int fW = (ly * (TX + 1) + lx) * n + t;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sA[v * NF + fW] = Fn[v];
+      sL = (ly == 0) ? C::SHS + lx * n + t : C::SN + (le - TX) * n + t;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        qL[v] = sT[v * NS + sL];
+        qR[v] = sT[v * NS + C::SS + le * n + t];
+      }
+      face_flux<FLUX>(qL, qR, nS[0], nS[1], g.gam, Fn);
+      const int fS = C::NFX + (ly * TX + lx) * n + t;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sA[v * NF + fS] = Fn[v];
+    }
+    for (int b = tid; b < (TY + TX) * n; b += NT) {  // the tile's east and north border faces
+      int sL, sR, slot;
+      double Sx, Sy;
+      if (b < TY * n) {
+        const int fy = b / n, j = b - fy * n;
+        if (fy >= mY) continue;
+        int ix = ex0 + mX;
+        if (ix >= g.nx) ix -= g.nx;
+        const double* pA = g.nodes + 2 * ((ey0 + fy) * nstride + ix);
+        const double* pB = pA + 2 * nstride;
+        Sx = 0.5 * (pB[1] - pA[1]);
+        Sy = -0.5 * (pB[0] - pA[0]);
+        sL = C::SE + (fy * TX + mX - 1) * n + j;
+        sR = C::SHE + fy * n + j;
+        slot = (fy * (TX + 1) + mX) * n + j;
       } else {
-        const double av = zero_v ? 0.0 : a.shift * a.V[gi] - (R - a.R0[gi]) / e;
-        if constexpr (MODE == 1)
-          a.out[gi] = av;
-        else
-          a.out[gi] = a.B[gi] - av;
+        const int b2 = b - TY * n, fx = b2 / n, i = b2 - fx * n;
+        if (fx >= mX) continue;
+        int iy = ey0 + mY;
+        if (iy >= g.ny) iy -= g.ny;
+        const double* pA = g.nodes + 2 * (iy * nstride + ex0 + fx);
+        Sx = -0.5 * (pA[3] - pA[1]);
+        Sy = 0.5 * (pA[2] - pA[0]);
+        sL = C::SN + ((mY - 1) * TX + fx) * n + i;
+        sR = C::SHN + fx * n + i;
+        slot = C::NFX + (mY * TX + fx) * n + i;
+      }
+      double qL[4], qR[4], Fn[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        qL[v] = sT[v * NS + sL];
+        qR[v] = sT[v * NS + sR];
+      }
+      face_flux<FLUX>(qL, qR, Sx, Sy, g.gam, Fn);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sA[v * NF + slot] = Fn[v];
+    }
+    __syncthreads();
+
+    // ---- corrections: rows take the W/E jumps, columns the S/N jumps
+    if (live) {
+      const int fW = (ly * (TX + 1) + lx) * n + t, fS = C::NFX + (ly * TX + lx) * n + t;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double jW = sA[v * NF + fW] - FlW[v], jE = sA[v * NF + fW + n] - FlE[v];
+        const double jS = sA[v * NF + fS] - GlS[v], jN = sA[v * NF + fS + TX * n] - GlN[v];
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+          dF[i][v] = fma(B.gL[i], jW, fma(B.gR[i], jE, dF[i][v]));
+          dG[i][v] = fma(B.gL[i], jS, fma(B.gR[i], jN, dG[i][v]));
+        }
+      }
+    }
+    // v and R0 of the write-out positions, on their way during the last passes
+    double ov[MODE ? NIT : 1][4], orr[MODE ? NIT : 1][4];
+    if constexpr (MODE != 0) {
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        const int idx = tid + it * NT, ry = idx / RUN, kk = idx - ry * RUN;
+        if (idx < TY * RUN && ry < mY && kk < mX * Np) {
+          const size_t base = ((size_t)(ey0 + ry) * g.nx + ex0) * Np + kk;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            ov[MODE ? it : 0][v] = a.V[v * vstride + base];
+            orr[MODE ? it : 0][v] = a.R0[v * vstride + base];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (live) {
+#pragma unroll
+      for (int r = 0; r < n; ++r)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sA[v * QS + le * ES + r * n + t] = dG[r][v];
+    }
+    __syncthreads();
+
+    // ---- R = -(D_xi F + D_eta G + corrections) / J on row t, back into LDS
+    if (live) {
+      const double xxi = fma(bx, tp, ax), yxi = fma(by, tp, ay);
+#pragma unroll
+      for (int i = 0; i < n; ++i) {
+        const double xeta = fma(dx, B.x[i], cx), yeta = fma(dy, B.x[i], cy);
+        const double iJ = rcp64(xxi * yeta - xeta * yxi);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double* o = &sA[v * QS + le * ES + t * n + i];
+          *o = -(dF[i][v] + *o) * iJ;
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- coalesced write-out, the matrix-free combinations on the fly
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int idx = tid + it * NT, ry = idx / RUN, kk = idx - ry * RUN;
+      if (idx < TY * RUN && ry < mY && kk < mX * Np) {
+        const size_t base = ((size_t)(ey0 + ry) * g.nx + ex0) * Np + kk;
+        const int src = (ry * TX + kk / Np) * ES + kk % Np;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const size_t gi = v * vstride + base;
+          const double R = sA[v * QS + src];
+          if constexpr (MODE == 0) {
+            a.out[gi] = R;
+          } else {
+            const double av = zero_v ? 0.0 : a.shift * ov[MODE ? it : 0][v] - (R - orr[MODE ? it : 0][v]) * ie;
+            if constexpr (MODE == 1)
+              a.out[gi] = av;
+            else
+              a.out[gi] = a.B[gi] - av;
+          }
+        }
       }
     }
   }
 }
 
+// Large tiles once the mesh gives every compute unit several of them.
+#ifndef FRJF_BIG_TILE_MIN_BLOCKS
+#define FRJF_BIG_TILE_MIN_BLOCKS 2048
+#endif
+constexpr int kBigTileMinBlocks = FRJF_BIG_TILE_MIN_BLOCKS;
+
+template <int P, int FLUX, bool BIG>
+static hipError_t launch_euler_tile(const fr_disc* d, int mode, const ResArgs& a, hipStream_t s) {
+  using C = LineCfg<P, BIG>;
+  const int ntx = (d->nx + C::TX - 1) / C::TX, nty = (d->ny + C::TY - 1) / C::TY;
+  const MeshArgs g{d->nodes, d->nx, d->ny, d->nel, d->phys.gamma};
+  dim3 grid(ntx * nty), block(C::NT);
+  if (mode == 0)
+    hipLaunchKernelGGL((k_euler<P, FLUX, 0, BIG>), grid, block, 0, s, a, g, d->basis);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_euler<P, FLUX, 1, BIG>), grid, block, 0, s, a, g, d->basis);
+  else
+    hipLaunchKernelGGL((k_euler<P, FLUX, 2, BIG>), grid, block, 0, s, a, g, d->basis);
+  return hipGetLastError();
+}
+
 template <int P, int FLUX>
 static hipError_t launch_euler_pf(const fr_disc* d, int mode, const ResArgs& a, hipStream_t s) {
-  using T = EulerTile<P>;
-  const int ntx = (d->nx + T::TX - 1) / T::TX, nty = (d->ny + T::TY - 1) / T::TY;
-  const MeshArgs g{d->nodes, d->nx, d->ny, d->nel, d->phys.gamma};
-  dim3 grid(ntx * nty), block(T::NT);
-  if (mode == 0)
-    hipLaunchKernelGGL((k_euler<P, FLUX, 0>), grid, block, 0, s, a, g, d->basis);
-  else if (mode == 1)
-    hipLaunchKernelGGL((k_euler<P, FLUX, 1>), grid, block, 0, s, a, g, d->basis);
-  else
-    hipLaunchKernelGGL((k_euler<P, FLUX, 2>), grid, block, 0, s, a, g, d->basis);
-  return hipGetLastError();
+  using C = LineCfg<P, true>;
+  const long big_blocks = (long)((d->nx + C::TX - 1) / C::TX) * ((d->ny + C::TY - 1) / C::TY);
+  return big_blocks >= kBigTileMinBlocks ? launch_euler_tile<P, FLUX, true>(d, mode, a, s)
+                                         : launch_euler_tile<P, FLUX, false>(d, mode, a, s);
 }
 
 template <int P>
