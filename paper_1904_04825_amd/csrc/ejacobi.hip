@@ -9,8 +9,9 @@
 // difference of exactly those terms (flux at k, four common fluxes with the
 // neighbours' traces held fixed), which equals [R_e(q + d e_j) - R_e(q)]
 // up to rounding without re-evaluating the whole element.
-// Inversion.  Gauss-Jordan elimination with partial pivoting in LDS, one
-// workgroup per element; FP64, or FP32 after rounding the FP64 block.
+// Inversion.  FP64: the raw blocks are written out and inverted in place with
+// the block rows in registers (gj_rows.hip).  FP32: the FP64 block is rounded
+// and inverted in LDS by blocked Gauss-Jordan with MFMA panel updates.
 // Application.  One 64-lane group per block row set: z_i = sum_j Pinv(i,j) r_j
 // with the inverse stored column-major, so each step of the j loop is a
 // coalesced load of one column.
@@ -291,10 +292,14 @@ static hipError_t asm_pf(const fr_disc* d, const AsmArgs& a, int precision, int 
   if (precision == FR_F32) {
     if (!invert) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_ejacobi_assemble<P, FLUX, float, true>), grid, block, 0, s, a, d->basis);
-  } else if (invert) {
-    hipLaunchKernelGGL((k_ejacobi_assemble<P, FLUX, double, true>), grid, block, 0, s, a, d->basis);
   } else {
+    // FP64: the raw blocks, then their inverses in place
     hipLaunchKernelGGL((k_ejacobi_assemble<P, FLUX, double, false>), grid, block, 0, s, a, d->basis);
+    if (invert) {
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      return launch_gj_rows_f64(EJ<P>::Nb, static_cast<double*>(a.out), d->nel, s);
+    }
   }
   return hipGetLastError();
 }
@@ -322,11 +327,15 @@ hipError_t launch_ejacobi_assemble(const fr_disc* d, const double* U, double shi
 template <int P>
 static hipError_t inv_p(const fr_disc* d, const double* blocks, void* out, int precision, hipStream_t s) {
   dim3 grid(d->nel), block(EJ<P>::NT);
-  if (precision == FR_F32)
+  if (precision == FR_F32) {
     hipLaunchKernelGGL((k_ejacobi_invert<P, float>), grid, block, 0, s, blocks, out);
-  else
-    hipLaunchKernelGGL((k_ejacobi_invert<P, double>), grid, block, 0, s, blocks, out);
-  return hipGetLastError();
+    return hipGetLastError();
+  }
+  constexpr int Nb = EJ<P>::Nb;
+  const hipError_t e = hipMemcpyAsync(out, blocks, (size_t)d->nel * Nb * Nb * sizeof(double),
+                                      hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  return launch_gj_rows_f64(Nb, static_cast<double*>(out), d->nel, s);
 }
 
 hipError_t launch_ejacobi_invert_blocks(const fr_disc* d, const double* blocks, void* out, int precision,

@@ -96,6 +96,8 @@ hipError_t launch_scale_dev(double* y, const double* x, const double* alpha, int
 // grad: BR1 gradient-trace workspace (Navier-Stokes only, else unused)
 hipError_t launch_ejacobi_assemble(const fr_disc* d, const double* U, double shift, void* out,
                                    int precision, int invert, double* grad, hipStream_t s);
+// In-place inversion of nblk FP64 blocks of order nb (36, 64 or 100), column-major.
+hipError_t launch_gj_rows_f64(int nb, double* blocks, int nblk, hipStream_t s);
 hipError_t launch_ejacobi_invert_blocks(const fr_disc* d, const double* blocks, void* out,
                                         int precision, hipStream_t s);
 hipError_t launch_ejacobi_solve(const fr_disc* d, const void* factors, int precision,

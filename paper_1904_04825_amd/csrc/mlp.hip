@@ -226,14 +226,28 @@ __global__ void __launch_bounds__(256) k_mse_grad(const float* __restrict__ Y, c
   if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// g[n] = sum_m D[m][n] (bf16 or fp32 source)
-__global__ void k_colsum(const uint16_t* __restrict__ Db, const float* __restrict__ Df, int M, int N,
-                         float* __restrict__ g) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+// g[n] = sum_m D[m][n] (bf16 or fp32 source).  A workgroup takes 64 columns;
+// its 16 row groups each sum every 16th row (coalesced along n), then LDS adds
+// the 16 partial sums in a fixed order.
+constexpr int kColsumCols = 64, kColsumRows = 16;
+__global__ void __launch_bounds__(kColsumCols* kColsumRows)
+    k_colsum(const uint16_t* __restrict__ Db, const float* __restrict__ Df, int M, int N, float* __restrict__ g) {
+  __shared__ double part[kColsumRows][kColsumCols];
+  const int c = threadIdx.x % kColsumCols, r = threadIdx.x / kColsumCols;
+  const int n = blockIdx.x * kColsumCols + c;
   double s = 0.0;
-  for (int m = 0; m < M; ++m) s += Db != nullptr ? (double)bf2f(Db[(size_t)m * N + n]) : (double)Df[(size_t)m * N + n];
-  g[n] = (float)s;
+  if (n < N) {
+    for (int m = r; m < M; m += kColsumRows)
+      s += Db != nullptr ? (double)bf2f(Db[(size_t)m * N + n]) : (double)Df[(size_t)m * N + n];
+  }
+  part[r][c] = s;
+  __syncthreads();
+  if (r == 0 && n < N) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kColsumRows; ++q) t += part[q][c];
+    g[n] = (float)t;
+  }
 }
 
 // Adam on the FP32 master parameters.
@@ -397,19 +411,19 @@ hipError_t mlp_train_step(fr_mlp_trainer* tr, const float* raw, const int* idx, 
   // weight and bias gradients, layer by layer
   if (e == hipSuccess) e = gemm<EPI_F32>(dyt, H2t, Out, H, B, nullptr, g + L.pW3, nullptr, nullptr, nullptr, nullptr, s);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_colsum, dim3((Out + 255) / 256), dim3(256), 0, s, nullptr, dy32, B, Out, g + L.pb3);
+    hipLaunchKernelGGL(k_colsum, dim3((Out + kColsumCols - 1) / kColsumCols), dim3(kColsumCols * kColsumRows), 0, s, nullptr, dy32, B, Out, g + L.pb3);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = gemm<EPI_GELU_GRAD>(dyr, W + L.w3t, B, H, Out, nullptr, nullptr, Z2, nullptr, dz2, dz2t, s);
   if (e == hipSuccess) e = gemm<EPI_F32>(dz2t, H1t, H, H, B, nullptr, g + L.pW2, nullptr, nullptr, nullptr, nullptr, s);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, s, dz2, nullptr, B, H, g + L.pb2);
+    hipLaunchKernelGGL(k_colsum, dim3((H + kColsumCols - 1) / kColsumCols), dim3(kColsumCols * kColsumRows), 0, s, dz2, nullptr, B, H, g + L.pb2);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = gemm<EPI_GELU_GRAD>(dz2, W + L.w2t, B, H, H, nullptr, nullptr, Z1, nullptr, dz1, dz1t, s);
   if (e == hipSuccess) e = gemm<EPI_F32>(dz1t, Xt, H, In, B, nullptr, g + L.pW1, nullptr, nullptr, nullptr, nullptr, s);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, s, dz1, nullptr, B, H, g + L.pb1);
+    hipLaunchKernelGGL(k_colsum, dim3((H + kColsumCols - 1) / kColsumCols), dim3(kColsumCols * kColsumRows), 0, s, dz1, nullptr, B, H, g + L.pb1);
     e = hipGetLastError();
   }
   if (e != hipSuccess || tr->lr <= 0.0f) return e;  // lr <= 0: gradients only

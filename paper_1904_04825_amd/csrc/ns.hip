@@ -605,10 +605,14 @@ static hipError_t ns_asm_pf(const fr_disc* d, const NSArgs& a, void* out, int pr
   if (precision == FR_F32) {
     if (!invert) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_ns_ejacobi<P, FLUX, float, true>), g2, block, 0, s, a, d->basis, out);
-  } else if (invert) {
-    hipLaunchKernelGGL((k_ns_ejacobi<P, FLUX, double, true>), g2, block, 0, s, a, d->basis, out);
   } else {
+    // FP64: the raw blocks, then their inverses in place
     hipLaunchKernelGGL((k_ns_ejacobi<P, FLUX, double, false>), g2, block, 0, s, a, d->basis, out);
+    if (invert) {
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      return launch_gj_rows_f64(4 * (P + 1) * (P + 1), static_cast<double*>(out), d->nel, s);
+    }
   }
   return hipGetLastError();
 }

@@ -11,7 +11,7 @@ from tests.gpu_common import rel, residual_parity, setup, to_gpu, to_np, vortex_
 
 pytestmark = pytest.mark.gpu
 
-# meshes span several tiles with a ragged tail for every tile shape (P2: 8x4, P3: 4x4, P4: 5x2)
+# meshes span several small tiles with a ragged tail for every order (P2: 7x3, P3: 4x4, P4: 5x2)
 MESHES = {2: (19, 9), 3: (13, 11), 4: (13, 7)}
 
 
@@ -52,6 +52,28 @@ def test_residual_minimum_mesh_and_full_workload_mesh():
         print(f"  {nx}x{ny} P{P}: rel err {rel(Rg, Ro):.3e}  budget measure {residual_parity(Rg, Ro, op, U):.3e}",
               flush=True)
         assert residual_parity(Rg, Ro, op, U) <= 1e-12
+
+
+# meshes large enough for the large tiles (P2: 16x5, P3: 8x8, P4: 10x5; at least 2048 of
+# them), ragged in both directions
+LARGE = {2: (507, 318), 3: (509, 250), 4: (333, 318)}
+
+
+@pytest.mark.parametrize("P", [2, 3, 4])
+def test_residual_and_matvec_parity_large_tiles(P):
+    nx, ny = LARGE[P]
+    print(f"large-tile parity P={P} mesh={nx}x{ny}", flush=True)
+    _, op, disc = setup(nx, ny, P, "rusanov", seed=4)
+    U = vortex_state(op)
+    Ro = op.residual(U)
+    Rg = to_np(disc.residual(to_gpu(U)))
+    print(f"  residual budget measure {residual_parity(Rg, Ro, op, U):.3e}", flush=True)
+    assert residual_parity(Rg, Ro, op, U) <= 1e-12
+    v = fi.random_vector(U.shape, seed=9, scale=1e-3)
+    Ao = linear.jf_matvec(op.residual, U, Ro, v, 4.0, mode="rms")
+    Ag = to_np(disc.jf_matvec(to_gpu(U), to_gpu(Ro), to_gpu(v), 4.0))
+    print(f"  matvec rel err {rel(Ag, Ao):.3e}", flush=True)
+    assert rel(Ag, Ao) <= 1e-6
 
 
 def test_solution_points():
@@ -112,6 +134,27 @@ def test_ejacobi_inverse_and_solve_parity(P):
     pcg = disc.ejacobi_factor(to_gpu(U), 2.0, F64)
     zf = to_np(disc.ejacobi_solve(pcg, to_gpu(r)))
     assert rel(zf, zo) <= 1e-6
+
+
+@pytest.mark.parametrize("P", [2, 3, 4])
+def test_fp64_block_inverse_needs_pivoting(P):
+    """Blocks with a zero diagonal and one dominant entry per row on a random
+    permutation: the FP64 inversion has to pivot in nearly every step."""
+    from paper_1904_04825_amd import F64
+    _, op, disc = setup(3, 2, P, "rusanov", seed=5)
+    nb = 4 * (P + 1) ** 2
+    rng = np.random.default_rng(11 + P)
+    B = rng.standard_normal((op.nel, nb, nb))
+    for e in range(op.nel):
+        B[e, np.arange(nb), np.arange(nb)] = 0.0
+        perm = rng.permutation(nb)
+        B[e, np.arange(nb), perm] += 4.0 * np.sqrt(nb)
+    r = fi.random_vector((4, op.nel, (P + 1) ** 2), seed=12)
+    zo = linear.ejacobi_apply(op, B, r)
+    zg = to_np(disc.ejacobi_solve(disc.ejacobi_factor_blocks(torch.as_tensor(B), F64), to_gpu(r)))
+    kappa = max(np.linalg.cond(b) for b in B)
+    print(f"P={P} kappa={kappa:.1f} rel={rel(zg, zo):.2e}", flush=True)
+    assert rel(zg, zo) <= 1e-14 * kappa * 10
 
 
 def test_l2_error_parity():
