@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--dt", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernels", action="store_true", help="skip the per-kernel timing block")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the per-kernel timing block, at the initial state (for profiler runs)")
     ap.add_argument("--no-learned", action="store_true", help="skip logging, training and the learned leg")
     ap.add_argument("--no-fp32-leg", action="store_true", help="skip the FP32-preconditioner legs")
     ap.add_argument("--allow-unconverged", action="store_true",
@@ -105,6 +107,55 @@ def cpu_baseline(nodes, U0, dt, p, scheme):
     return {"value": op.ndof * evals / wall, "unit": "DOF-residuals/s", "cores": 1, "kind": "oracle",
             "sample": f"R(U) + element-Jacobi assembly + {st.iters} FGMRES(20) iterations of ROW{scheme} stage 1 on "
                       f"the same mesh and state: {evals} residual evaluations in {wall:.1f} s, numpy, 1 thread"}
+
+
+def kernel_block(disc, Ustart, dt, scheme, ndof, workload):
+    """Per-kernel timings (HIP events on the launch stream) at state Ustart and the
+    roofline object of the dominant kernel."""
+    from paper_1904_04825_amd import F32, F64
+    import torch
+    out = {"extra": {}}
+    # live per-kernel timing on the launch stream (torch's current stream)
+    R0 = disc.residual(Ustart)
+    v = torch.randn_like(Ustart) * 1e-3
+    gam = {2: 0.25, 3: 0.4358665215084590, 4: 0.25}[scheme]
+    shift = 1.0 / (gam * dt)
+    nb = disc.nb
+    kernels = {}
+    t_res = time_kernel(lambda: disc.residual(Ustart, R0))
+    res_bytes = 16 * ndof
+    kernels["fr_residual"] = {"us": t_res * 1e6, "alg_bytes": res_bytes, "GBs": res_bytes / t_res / 1e9,
+                              "dof_res_per_s": ndof / t_res}
+    Av = disc.empty()
+    t_mv = time_kernel(lambda: disc.jf_matvec(Ustart, R0, v, shift, out=Av))
+    kernels["jf_matvec(norm+fused residual)"] = {"us": t_mv * 1e6, "alg_bytes": 40 * ndof,
+                                                 "GBs": 40 * ndof / t_mv / 1e9}
+    z = disc.empty()
+    for prec, name, es in ((F64, "fp64", 8), (F32, "fp32", 4)):
+        pc = disc.ejacobi_factor(Ustart, shift, prec)
+        t_sol = time_kernel(lambda: disc.ejacobi_solve(pc, v, z))
+        sb = disc.nel * nb * nb * es + 16 * ndof       # block inverse + r in + z out
+        kernels[f"ejacobi_solve_{name}"] = {"us": t_sol * 1e6, "alg_bytes": sb, "GBs": sb / t_sol / 1e9}
+        t_fac = time_kernel(lambda: disc.ejacobi_factor(Ustart, shift, prec, pc), reps=5, warm=1)
+        kernels[f"ejacobi_factor_{name}(assemble+invert)"] = {
+            "us": t_fac * 1e6, "inversion_TFLOPs": disc.nel * 2.0 * nb ** 3 / t_fac / 1e12}
+        del pc
+    out["extra"]["kernels"] = kernels
+    dom = "ejacobi_solve_fp64"
+    traffic = None
+    tp = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tp):
+        with open(tp) as fh:
+            tj = json.load(fh)
+        if tj.get("kernel") == dom and tj.get("workload") == workload \
+                and tj.get("source_sha") == source_sha(tj["source"]):
+            traffic = tj.get("bytes_per_launch")
+    ach = kernels[dom]["GBs"]
+    out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
+                       "alg_bytes_per_launch": kernels[dom]["alg_bytes"]}
+
+    return out["extra"]["kernels"], out["roofline"]
 
 
 def run_leg(disc, U, steps, scheme, dt, opts, allow_unconverged=False):
@@ -166,6 +217,12 @@ def main():
                                   f"Rusanov, eps_rms 1e-8; timed steps start after {args.warmup} untimed steps",
                       "ndof": ndof, "dt": dt},
            "extra": {}}
+
+    if args.kernels_only:
+        kernels, roof = kernel_block(disc, U0, dt, scheme, ndof, args.workload)
+        print(json.dumps({"mode": "kernels-only", "config": out["config"], "kernels": kernels, "roofline": roof}),
+              flush=True)
+        return
 
     # ---- (1) warm-up steps, logging the stage solves
     rng = np.random.default_rng(40)
@@ -246,45 +303,9 @@ def main():
     out["extra"]["legs"] = legs
 
     if not args.no_kernels:
-        # live per-kernel timing on the launch stream (torch's current stream)
-        R0 = disc.residual(Ustart)
-        v = torch.randn_like(Ustart) * 1e-3
-        gam = {2: 0.25, 3: 0.4358665215084590, 4: 0.25}[scheme]
-        shift = 1.0 / (gam * dt)
-        nb = disc.nb
-        kernels = {}
-        t_res = time_kernel(lambda: disc.residual(Ustart, R0))
-        res_bytes = 16 * ndof
-        kernels["fr_residual"] = {"us": t_res * 1e6, "alg_bytes": res_bytes, "GBs": res_bytes / t_res / 1e9,
-                                  "dof_res_per_s": ndof / t_res}
-        Av = disc.empty()
-        t_mv = time_kernel(lambda: disc.jf_matvec(Ustart, R0, v, shift, out=Av))
-        kernels["jf_matvec(norm+fused residual)"] = {"us": t_mv * 1e6, "alg_bytes": 40 * ndof,
-                                                     "GBs": 40 * ndof / t_mv / 1e9}
-        z = disc.empty()
-        for prec, name, es in ((F64, "fp64", 8), (F32, "fp32", 4)):
-            pc = disc.ejacobi_factor(Ustart, shift, prec)
-            t_sol = time_kernel(lambda: disc.ejacobi_solve(pc, v, z))
-            sb = disc.nel * nb * nb * es + 16 * ndof       # block inverse + r in + z out
-            kernels[f"ejacobi_solve_{name}"] = {"us": t_sol * 1e6, "alg_bytes": sb, "GBs": sb / t_sol / 1e9}
-            t_fac = time_kernel(lambda: disc.ejacobi_factor(Ustart, shift, prec, pc), reps=5, warm=1)
-            kernels[f"ejacobi_factor_{name}(assemble+invert)"] = {
-                "us": t_fac * 1e6, "inversion_TFLOPs": disc.nel * 2.0 * nb ** 3 / t_fac / 1e12}
-            del pc
+        kernels, roof = kernel_block(disc, Ustart, dt, scheme, ndof, args.workload)
         out["extra"]["kernels"] = kernels
-        dom = "ejacobi_solve_fp64"
-        traffic = None
-        tp = os.path.join(ROOT, "profiles", "traffic.json")
-        if os.path.exists(tp):
-            with open(tp) as fh:
-                tj = json.load(fh)
-            if tj.get("kernel") == dom and tj.get("workload") == args.workload \
-                    and tj.get("source_sha") == source_sha(tj["source"]):
-                traffic = tj.get("bytes_per_launch")
-        ach = kernels[dom]["GBs"]
-        out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": ach / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom,
-                           "alg_bytes_per_launch": kernels[dom]["alg_bytes"]}
+        out["roofline"] = roof
 
     if args.calib_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
