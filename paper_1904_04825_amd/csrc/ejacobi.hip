@@ -9,9 +9,10 @@
 // difference of exactly those terms (flux at k, four common fluxes with the
 // neighbours' traces held fixed), which equals [R_e(q + d e_j) - R_e(q)]
 // up to rounding without re-evaluating the whole element.
-// Inversion.  FP64: the raw blocks are written out and inverted in place with
-// the block rows in registers (gj_rows.hip).  FP32: the FP64 block is rounded
-// and inverted in LDS by blocked Gauss-Jordan with MFMA panel updates.
+// Inversion.  The raw blocks are written out and inverted in place: FP64 with
+// the block rows in registers (gj_rows.hip), FP32 (the FP64 block rounded) with
+// the block in MFMA registers and rank-16 updates on the matrix cores
+// (gj_mfma.hip).
 // Application.  One 64-lane group per block row set: z_i = sum_j Pinv(i,j) r_j
 // with the inverse stored column-major, so each step of the j loop is a
 // coalesced load of one column.
@@ -21,7 +22,6 @@
 
 #include "internal.h"
 #include "physics.h"
-#include "gj_invert.h"
 
 namespace frjf {
 
@@ -40,15 +40,11 @@ struct AsmArgs {
   void* out;
 };
 
-template <int P, int FLUX, typename T, bool INVERT>
+template <int P, int FLUX, typename T>
 __global__ void __launch_bounds__(EJ<P>::NT) k_ejacobi_assemble(const AsmArgs a, const Basis B) {
   using C = EJ<P>;
-  using L = BlockLds<C::Nb, T>;
-  constexpr int n = C::n, Np = C::Np, Nb = C::Nb, NT = C::NT, LD = L::LD;
-  __shared__ T A[L::NP * LD];
-  __shared__ T sf[L::NP];
-  __shared__ int piv_row, perm[L::NP];
-  __shared__ float Xs[L::mfma ? 16 * L::NP : 1], rowc[16];
+  constexpr int n = C::n, Np = C::Np, Nb = C::Nb, NT = C::NT, LD = C::LD;
+  __shared__ T A[Nb * LD];  // the block, column-major, padded leading dimension
   __shared__ double sq[4][Np], sF[4][Np], sG[4][Np], sIJ[Np];
   __shared__ double sqo[4][4][n], sqn[4][4][n], sFn[4][4][n];  // [face][var][j]
   __shared__ double sS[4][2];
@@ -205,28 +201,14 @@ __global__ void __launch_bounds__(EJ<P>::NT) k_ejacobi_assemble(const AsmArgs a,
     col[jc] = (T)((double)col[jc] + a.shift);
   }
   __syncthreads();
-  if constexpr (INVERT) invert_lds<T, Nb, NT>(A, sf, &piv_row, perm, Xs, rowc);
   T* out = reinterpret_cast<T*>(a.out) + (size_t)el * Nb * Nb;
   for (int idx = tid; idx < Nb * Nb; idx += NT) out[idx] = A[(idx / Nb) * LD + idx % Nb];
 }
 
-// Invert caller-provided FP64 blocks.
-template <int P, typename T>
-__global__ void __launch_bounds__(EJ<P>::NT) k_ejacobi_invert(const double* __restrict__ blocks, void* outp) {
-  using C = EJ<P>;
-  using L = BlockLds<C::Nb, T>;
-  constexpr int Nb = C::Nb, NT = C::NT, LD = L::LD;
-  __shared__ T A[L::NP * LD];
-  __shared__ T sf[L::NP];
-  __shared__ int piv_row, perm[L::NP];
-  __shared__ float Xs[L::mfma ? 16 * L::NP : 1], rowc[16];
-  const size_t el = blockIdx.x;
-  const double* src = blocks + el * Nb * Nb;
-  for (int idx = threadIdx.x; idx < Nb * Nb; idx += NT) A[(idx / Nb) * LD + idx % Nb] = (T)src[idx];
-  __syncthreads();
-  invert_lds<T, Nb, NT>(A, sf, &piv_row, perm, Xs, rowc);
-  T* out = reinterpret_cast<T*>(outp) + el * Nb * Nb;
-  for (int idx = threadIdx.x; idx < Nb * Nb; idx += NT) out[idx] = A[(idx / Nb) * LD + idx % Nb];
+// FP64 blocks rounded to FP32 (caller-provided blocks of the FP32 store).
+__global__ void k_round_f32(const double* __restrict__ src, float* __restrict__ dst, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
 }
 
 // z = Pinv r per element (+ per-workgroup partial sums of ||z||^2), r optionally
@@ -290,11 +272,15 @@ template <int P, int FLUX>
 static hipError_t asm_pf(const fr_disc* d, const AsmArgs& a, int precision, int invert, hipStream_t s) {
   dim3 grid(d->nel), block(EJ<P>::NT);
   if (precision == FR_F32) {
+    // FP32: the FP64 blocks rounded on the way out, then inverted in place on MFMA
     if (!invert) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_ejacobi_assemble<P, FLUX, float, true>), grid, block, 0, s, a, d->basis);
+    hipLaunchKernelGGL((k_ejacobi_assemble<P, FLUX, float>), grid, block, 0, s, a, d->basis);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_gj_mfma_f32(EJ<P>::Nb, static_cast<float*>(a.out), d->nel, s);
   } else {
     // FP64: the raw blocks, then their inverses in place
-    hipLaunchKernelGGL((k_ejacobi_assemble<P, FLUX, double, false>), grid, block, 0, s, a, d->basis);
+    hipLaunchKernelGGL((k_ejacobi_assemble<P, FLUX, double>), grid, block, 0, s, a, d->basis);
     if (invert) {
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
@@ -326,12 +312,15 @@ hipError_t launch_ejacobi_assemble(const fr_disc* d, const double* U, double shi
 
 template <int P>
 static hipError_t inv_p(const fr_disc* d, const double* blocks, void* out, int precision, hipStream_t s) {
-  dim3 grid(d->nel), block(EJ<P>::NT);
-  if (precision == FR_F32) {
-    hipLaunchKernelGGL((k_ejacobi_invert<P, float>), grid, block, 0, s, blocks, out);
-    return hipGetLastError();
-  }
   constexpr int Nb = EJ<P>::Nb;
+  if (precision == FR_F32) {
+    const size_t total = (size_t)d->nel * Nb * Nb;
+    hipLaunchKernelGGL(k_round_f32, dim3((unsigned)std::min<size_t>((total + 255) / 256, 65536)), dim3(256), 0, s,
+                       blocks, static_cast<float*>(out), total);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_gj_mfma_f32(Nb, static_cast<float*>(out), d->nel, s);
+  }
   const hipError_t e = hipMemcpyAsync(out, blocks, (size_t)d->nel * Nb * Nb * sizeof(double),
                                       hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return e;

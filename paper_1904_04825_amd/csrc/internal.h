@@ -98,6 +98,8 @@ hipError_t launch_ejacobi_assemble(const fr_disc* d, const double* U, double shi
                                    int precision, int invert, double* grad, hipStream_t s);
 // In-place inversion of nblk FP64 blocks of order nb (36, 64 or 100), column-major.
 hipError_t launch_gj_rows_f64(int nb, double* blocks, int nblk, hipStream_t s);
+// In-place inversion of nblk FP32 blocks of order nb (36, 64 or 100), column-major, on MFMA.
+hipError_t launch_gj_mfma_f32(int nb, float* blocks, int nblk, hipStream_t s);
 hipError_t launch_ejacobi_invert_blocks(const fr_disc* d, const double* blocks, void* out,
                                         int precision, hipStream_t s);
 hipError_t launch_ejacobi_solve(const fr_disc* d, const void* factors, int precision,

@@ -25,7 +25,6 @@
 
 #include "internal.h"
 #include "physics.h"
-#include "gj_invert.h"
 
 namespace frjf {
 
@@ -420,18 +419,14 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_res(const NSArgs a, const Basi
 
 // ---------------------------------------------------------------- kernel C: element-Jacobi blocks
 
-template <int P, int FLUX, typename T, bool INVERT>
+template <int P, int FLUX, typename T>
 __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const Basis B, void* outp) {
   using C = NS<P>;
-  using L = BlockLds<C::Nb, T>;
-  constexpr int n = C::n, Np = C::Np, Nb = C::Nb, ST = C::ST, SL = C::SLOTS, NT = C::NT, LD = L::LD;
+  constexpr int n = C::n, Np = C::Np, Nb = C::Nb, ST = C::ST, SL = C::SLOTS, NT = C::NT, LD = C::LD;
   __shared__ Slot<P> S[SL];
   __shared__ ElemGeo<P> Gm;
   __shared__ double q0[4][Np], R0[4][Np], qc0[4][4][n], cg[4][n][2];
-  __shared__ T A[L::NP * LD];
-  __shared__ T sf[L::NP];
-  __shared__ int piv_row, perm[L::NP];
-  __shared__ float Xs[L::mfma ? 16 * L::NP : 1], rowc[16];
+  __shared__ T A[Nb * LD];  // the block, column-major, padded leading dimension
   const int tid = threadIdx.x;
   const int sl = tid / ST, t = tid % ST;
   const int el = blockIdx.x;
@@ -536,7 +531,6 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const 
         }
     __syncthreads();
   }
-  if constexpr (INVERT) invert_lds<T, Nb, NT>(A, sf, &piv_row, perm, Xs, rowc);
   T* out = reinterpret_cast<T*>(outp) + (size_t)el * Nb * Nb;
   for (int idx = tid; idx < Nb * Nb; idx += NT) out[idx] = A[(idx / Nb) * LD + idx % Nb];
 }
@@ -603,11 +597,15 @@ static hipError_t ns_asm_pf(const fr_disc* d, const NSArgs& a, void* out, int pr
   hipLaunchKernelGGL((k_ns_grad<P, 0>), grid, block, 0, s, a, d->basis);
   dim3 g2(d->nel);
   if (precision == FR_F32) {
+    // FP32: the FP64 blocks rounded on the way out, then inverted in place on MFMA
     if (!invert) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_ns_ejacobi<P, FLUX, float, true>), g2, block, 0, s, a, d->basis, out);
+    hipLaunchKernelGGL((k_ns_ejacobi<P, FLUX, float>), g2, block, 0, s, a, d->basis, out);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_gj_mfma_f32(4 * (P + 1) * (P + 1), static_cast<float*>(out), d->nel, s);
   } else {
     // FP64: the raw blocks, then their inverses in place
-    hipLaunchKernelGGL((k_ns_ejacobi<P, FLUX, double, false>), g2, block, 0, s, a, d->basis, out);
+    hipLaunchKernelGGL((k_ns_ejacobi<P, FLUX, double>), g2, block, 0, s, a, d->basis, out);
     if (invert) {
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
