@@ -213,50 +213,92 @@ __global__ void k_round_f32(const double* __restrict__ src, float* __restrict__ 
 
 // z = Pinv r per element (+ per-workgroup partial sums of ||z||^2), r optionally
 // scaled by 1/(*r_scale) on load and stored back to r_store (fused normalisation of
-// the Arnoldi vector).  Workgroups stride over groups of NBLK elements.
-template <int P, typename T>
+// the Arnoldi vector).  The inverse is column-major, so column j of a block is
+// Nb contiguous entries: a thread owns RPT consecutive rows and reads them with one
+// load per column, eight columns in flight.  RPT = 1: one row per thread, the most
+// threads; RPT = 16 / sizeof(T): 16-byte loads and dense lanes for large P = 4 stores.  EPB elements share a 256-thread
+// workgroup; workgroups stride over groups of EPB elements.
+template <int P, typename T, int RPT_>
+struct SolveCfg {
+  static constexpr int Np = (P + 1) * (P + 1), Nb = 4 * Np;
+  static constexpr int RPT = RPT_;     // rows per thread
+  static constexpr int TPE = Nb / RPT;  // threads per element
+  static constexpr int EPB = 256 / TPE;  // elements per workgroup
+  static_assert(Nb % RPT == 0, "whole rows per thread");
+};
+
+template <typename T, int RPT>
+struct RowVec {
+  typedef T type __attribute__((ext_vector_type(RPT)));
+};
+template <typename T>
+struct RowVec<T, 1> {
+  typedef T type;
+};
+
+template <typename V>
+__device__ __forceinline__ double row_of(const V& a, int q) {
+  if constexpr (sizeof(V) == sizeof(double) || sizeof(V) == sizeof(float))
+    return (double)a;
+  else
+    return (double)a[q];
+}
+
+template <int P, typename T, int RPT>
 __global__ void __launch_bounds__(256) k_ejacobi_solve(const T* __restrict__ inv, const double* __restrict__ r,
                                                         const double* r_scale, double* r_store, double* __restrict__ z,
                                                         int nel, double* partials, const int* skip) {
-  using C = EJ<P>;
-  constexpr int Np = C::Np, Nb = C::Nb, TPB = C::NT, NBLK = 256 / TPB;
+  using C = SolveCfg<P, T, RPT>;
+  using V = typename RowVec<T, RPT>::type;
+  constexpr int Np = C::Np, Nb = C::Nb, TPE = C::TPE, EPB = C::EPB;
+  constexpr int JU = 8;  // columns in flight
   if (skip != nullptr && *skip) return;
-  __shared__ T sr[NBLK][Nb];
+  __shared__ T sr[EPB][Nb];
   const int tid = threadIdx.x;
-  const int blk = tid / TPB, i = tid % TPB;
+  const int blk = tid / TPE, i = tid - blk * TPE;  // element of the group, row block
   const double sc = (r_scale != nullptr) ? 1.0 / *r_scale : 1.0;
-  const int ngroups = (nel + NBLK - 1) / NBLK;
+  const int ngroups = (nel + EPB - 1) / EPB;
   double zz = 0.0;
   for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
-    const int el = grp * NBLK + blk;
     __syncthreads();
-    if (el < nel)
-      for (int jj = i; jj < Nb; jj += TPB) {
-        const int v = jj / Np, k = jj % Np;
-        const size_t gi = ((size_t)v * nel + el) * Np + k;
-        double rv = r[gi];
-        if (r_scale != nullptr) {
-          rv *= sc;
-          if (r_store != nullptr) r_store[gi] = rv;
-        }
-        sr[blk][jj] = (T)rv;
+    for (int t = tid; t < EPB * Nb; t += 256) {
+      const int e = t / Nb, jj = t - e * Nb, el = grp * EPB + e;
+      if (el >= nel) continue;
+      const int v = jj / Np, k = jj - v * Np;
+      const size_t gi = ((size_t)v * nel + el) * Np + k;
+      double rv = r[gi];
+      if (r_scale != nullptr) {
+        rv *= sc;
+        if (r_store != nullptr) r_store[gi] = rv;
       }
+      sr[e][jj] = (T)rv;
+    }
     __syncthreads();
-    if (el < nel && i < Nb) {
-      const T* col = inv + (size_t)el * Nb * Nb + i;
-      T acc0 = 0, acc1 = 0, acc2 = 0, acc3 = 0;
+    const int el = grp * EPB + blk;
+    if (blk < EPB && el < nel) {
+      const V* col = reinterpret_cast<const V*>(inv + (size_t)el * Nb * Nb) + i;  // rows RPT i .. RPT i + RPT - 1
+      V acc0 = {}, acc1 = {};
       int j = 0;
-      for (; j + 4 <= Nb; j += 4) {
-        acc0 = fma(col[(size_t)(j + 0) * Nb], sr[blk][j + 0], acc0);
-        acc1 = fma(col[(size_t)(j + 1) * Nb], sr[blk][j + 1], acc1);
-        acc2 = fma(col[(size_t)(j + 2) * Nb], sr[blk][j + 2], acc2);
-        acc3 = fma(col[(size_t)(j + 3) * Nb], sr[blk][j + 3], acc3);
+      for (; j + JU <= Nb; j += JU) {
+        V m[JU];
+#pragma unroll
+        for (int u = 0; u < JU; ++u) m[u] = col[(size_t)(j + u) * TPE];
+#pragma unroll
+        for (int u = 0; u < JU; u += 2) {
+          acc0 += m[u] * sr[blk][j + u];
+          acc1 += m[u + 1] * sr[blk][j + u + 1];
+        }
       }
-      for (; j < Nb; ++j) acc0 = fma(col[(size_t)j * Nb], sr[blk][j], acc0);
-      const double zi = (double)((acc0 + acc1) + (acc2 + acc3));
-      const int v = i / Np, k = i % Np;
-      z[((size_t)v * nel + el) * Np + k] = zi;
-      zz = fma(zi, zi, zz);
+      for (; j < Nb; ++j) acc0 += col[(size_t)j * TPE] * sr[blk][j];
+      const V acc = acc0 + acc1;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const int row = RPT * i + q;
+        const double zi = row_of(acc, q);
+        const int v = row / Np, k = row - v * Np;
+        z[((size_t)v * nel + el) * Np + k] = zi;
+        zz = fma(zi, zi, zz);
+      }
     }
   }
   if (partials == nullptr) return;
@@ -337,20 +379,38 @@ hipError_t launch_ejacobi_invert_blocks(const fr_disc* d, const double* blocks, 
   return hipErrorInvalidValue;
 }
 
+// 16-byte rows where one row per thread leaves lanes idle (Nb = 100: two blocks per
+// 256-thread workgroup use 200 lanes) and the store does not stay in the 256 MB
+// last-level cache.
+constexpr size_t kWideSolveBytes = size_t(256) << 20;
+
+template <int P, typename T, int RPT>
+static hipError_t solve_ptr(const fr_disc* d, const void* f, const double* r, const double* r_scale, double* r_store,
+                            double* z, double* partials, const int* skip, int* nb_out, hipStream_t s) {
+  constexpr int EPB = SolveCfg<P, T, RPT>::EPB;
+  const int ngroups = (d->nel + EPB - 1) / EPB;
+  const int nb = std::min(ngroups, kRedBlocks);
+  *nb_out = nb;
+  hipLaunchKernelGGL((k_ejacobi_solve<P, T, RPT>), dim3(nb), dim3(256), 0, s, (const T*)f, r, r_scale, r_store, z,
+                     d->nel, partials, skip);
+  return hipGetLastError();
+}
+
 template <int P>
 static hipError_t solve_p(const fr_disc* d, const void* f, int precision, const double* r, const double* r_scale,
                           double* r_store, double* z, double* partials, double* nrm2, const int* skip, hipStream_t s) {
-  constexpr int NBLK = 256 / EJ<P>::NT;
-  const int ngroups = (d->nel + NBLK - 1) / NBLK;
-  const int nb = std::min(ngroups, kRedBlocks);
+  constexpr int Nb = 4 * (P + 1) * (P + 1);
   double* part = nrm2 != nullptr ? partials : nullptr;
+  const size_t store = (size_t)d->nel * Nb * Nb * (precision == FR_F32 ? sizeof(float) : sizeof(double));
+  const bool wide = P == 4 && store >= kWideSolveBytes;
+  int nb = 0;
+  hipError_t e;
   if (precision == FR_F32)
-    hipLaunchKernelGGL((k_ejacobi_solve<P, float>), dim3(nb), dim3(256), 0, s, (const float*)f, r, r_scale, r_store, z,
-                       d->nel, part, skip);
+    e = wide ? solve_ptr<P, float, 4>(d, f, r, r_scale, r_store, z, part, skip, &nb, s)
+             : solve_ptr<P, float, 1>(d, f, r, r_scale, r_store, z, part, skip, &nb, s);
   else
-    hipLaunchKernelGGL((k_ejacobi_solve<P, double>), dim3(nb), dim3(256), 0, s, (const double*)f, r, r_scale, r_store,
-                       z, d->nel, part, skip);
-  hipError_t e = hipGetLastError();
+    e = wide ? solve_ptr<P, double, 2>(d, f, r, r_scale, r_store, z, part, skip, &nb, s)
+             : solve_ptr<P, double, 1>(d, f, r, r_scale, r_store, z, part, skip, &nb, s);
   if (e != hipSuccess || nrm2 == nullptr) return e;
   return launch_finalize(partials, nb, 1, 1, nrm2, skip, s);
 }

@@ -157,6 +157,27 @@ def test_fp64_block_inverse_needs_pivoting(P):
     assert rel(zg, zo) <= 1e-14 * kappa * 10
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_ejacobi_solve_large_store(prec):
+    """P4 blocks on 83x83 elements: the FP64 (551 MB) and FP32 (276 MB) stores are
+    above the size where the apply reads 16-byte rows; z against the oracle's
+    per-block solve of the same (well-conditioned random) blocks."""
+    from paper_1904_04825_amd import F32, F64
+    _, op, disc = setup(83, 83, 4, "rusanov", seed=6)
+    nb = 100
+    rng = np.random.default_rng(21)
+    B = rng.standard_normal((op.nel, nb, nb)) * 0.05
+    B[:, np.arange(nb), np.arange(nb)] += 3.0 + rng.random((op.nel, nb))
+    r = fi.random_vector((4, op.nel, 25), seed=13)
+    zo = linear.ejacobi_apply(op, B, r)
+    pc = disc.ejacobi_factor_blocks(torch.as_tensor(B), F64 if prec == "f64" else F32)
+    zg = to_np(disc.ejacobi_solve(pc, to_gpu(r)))
+    del pc
+    err = rel(zg, zo)
+    print(f"{prec}: rel {err:.2e}", flush=True)
+    assert err <= (1e-13 if prec == "f64" else 2e-6)
+
+
 def test_l2_error_parity():
     _, op, disc = setup(13, 11, 3)
     v = fi.Vortex()
