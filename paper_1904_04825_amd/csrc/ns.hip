@@ -83,11 +83,27 @@ __device__ __forceinline__ void viscous_fluxes(const double q[4], const double q
 }
 
 // Per-slot working set in LDS.
+// The point fluxes F, G replace the gradient qx, qy in place: each point's fluxes
+// need only that point's gradient, and the face gradients are taken before.
 template <int P>
 struct Slot {
   static constexpr int n = P + 1, Np = n * n;
-  double q[4][Np], qx[4][Np], qy[4][Np], F[4][Np], G[4][Np];
-  double tr[4][4][n], qc[4][4][n], gc[4][4][n][2], jmp[4][4][n];
+  double q[4][Np];
+  union {
+    struct {
+      double qx[4][Np], qy[4][Np];
+    };
+    struct {
+      double F[4][Np], G[4][Np];
+    };
+  };
+  // the face jumps replace the solution traces: the thread of a face point reads
+  // its traces before it writes that point's jumps
+  union {
+    double tr[4][4][n];
+    double jmp[4][4][n];
+  };
+  double qc[4][4][n], gc[4][4][n][2];
 };
 
 // Per-element geometry and neighbour data in LDS.
@@ -97,7 +113,6 @@ struct ElemGeo {
   double met[Np][5];      // x_xi, x_eta, y_xi, y_eta, 1/|J|
   double S[4][2];         // area-weighted face normals
   double nb[4][4][n];     // neighbours' solution traces on the shared faces
-  double gnb[4][4][n][2]; // neighbours' face gradients on the shared faces
   int nbr[4];             // neighbour element indices
 };
 
@@ -425,6 +440,7 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const 
   constexpr int n = C::n, Np = C::Np, Nb = C::Nb, ST = C::ST, SL = C::SLOTS, NT = C::NT, LD = C::LD;
   __shared__ Slot<P> S[SL];
   __shared__ ElemGeo<P> Gm;
+  __shared__ double gnb[4][4][P + 1][2];  // neighbours' face gradients on the shared faces
   __shared__ double q0[4][Np], R0[4][Np], qc0[4][4][n], cg[4][n][2];
   __shared__ T A[Nb * LD];  // the block, column-major, padded leading dimension
   const int tid = threadIdx.x;
@@ -447,8 +463,8 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const 
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const size_t gi = grad_index(ne, o, v, j, n);
-      Gm.gnb[f][v][j][0] = a.grad[gi];
-      Gm.gnb[f][v][j][1] = a.grad[gi + 1];
+      gnb[f][v][j][0] = a.grad[gi];
+      gnb[f][v][j][1] = a.grad[gi + 1];
     }
     double c8[8];
     load_corners(a.nodes, a.nx, ne % a.nx, ne / a.nx, c8);
@@ -505,8 +521,8 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const 
           double gx, gy;
           own_face_gradient<P>(S[sl], B, f, jj, v, &gx, &gy);
           const double dqc = S[sl].qc[f][v][jj] - qc0[f][v][jj];
-          const double nx_ = Gm.gnb[f][v][jj][0] + cg[f][jj][0] * dqc;
-          const double ny_ = Gm.gnb[f][v][jj][1] + cg[f][jj][1] * dqc;
+          const double nx_ = gnb[f][v][jj][0] + cg[f][jj][0] * dqc;
+          const double ny_ = gnb[f][v][jj][1] + cg[f][jj][1] * dqc;
           S[sl].gc[f][v][jj][0] = 0.5 * (gx + nx_);
           S[sl].gc[f][v][jj][1] = 0.5 * (gy + ny_);
         }
