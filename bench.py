@@ -54,6 +54,7 @@ def parse():
                     help="only the per-kernel timing block, at the initial state (for profiler runs)")
     ap.add_argument("--no-learned", action="store_true", help="skip logging, training and the learned leg")
     ap.add_argument("--no-fp32-leg", action="store_true", help="skip the FP32-preconditioner legs")
+    ap.add_argument("--no-schemes", action="store_true", help="skip the ESDIRK3 and BDF2 legs")
     ap.add_argument("--allow-unconverged", action="store_true",
                     help="count GMRES solves that reach the iteration cap instead of stopping")
     ap.add_argument("--calib-copy", action="store_true",
@@ -301,6 +302,49 @@ def main():
                 "rel_diff_vs_fp64": float(torch.linalg.norm(U - U_fp64) / torch.linalg.norm(U_fp64)),
                 "speedup_vs_plain_fp64": wall / w3}
     out["extra"]["legs"] = legs
+
+    # ---- (4) the other implicit schemes of the same workload, FP64 element-Jacobi:
+    # ESDIRK3 and BDF2 (BDF1 start) with pseudo-transient continuation, inexact
+    # Newton (GMRES rtol 1e-1 per PTC iteration), nonlinear tolerance 1e-8
+    if W["physics"] == "euler" and not args.no_schemes:
+        sopts = SolverOpts(lin=GmresOpts(m=20, rtol=1e-1), tol_nl=1e-8)
+        schemes = {}
+
+        def scheme_leg(step):
+            tot = {"gmres_iters": 0, "ptc_iters": 0, "rejections": 0, "residual_evals": 0}
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Ux = step(tot)
+            torch.cuda.synchronize()
+            w = time.perf_counter() - t0
+            return {"ms_per_step": w / args.steps * 1e3, "wall_s_per_time_unit": w / t_phys,
+                    "gmres_iters_per_step": tot["gmres_iters"] / args.steps,
+                    "ptc_iters_per_step": tot["ptc_iters"] / args.steps, "rejections": tot["rejections"],
+                    "residual_evals_per_step": tot["residual_evals"] / args.steps, "l2_err_rho": err(Ux)}
+
+        def add(tot, st, name):
+            if st["status"] != 0:
+                raise RuntimeError(f"{name} status {st['status']}")
+            for k in tot:
+                tot[k] += st[k]
+
+        def esdirk3(tot):
+            Ux = Ustart.clone()
+            for _ in range(args.steps):
+                add(tot, disc.esdirk_step(Ux, 3, dt, sopts), "esdirk_step")
+            return Ux
+
+        def bdf2(tot):
+            Unm1, Un = None, Ustart.clone()
+            for _ in range(args.steps):
+                Unp1, st = disc.bdf2_step(Unm1, Un, dt, sopts)
+                add(tot, st, "bdf2_step")
+                Unm1, Un = Un, Unp1
+            return Un
+
+        schemes["ESDIRK3"] = scheme_leg(esdirk3)
+        schemes["BDF2 (BDF1 start)"] = scheme_leg(bdf2)
+        out["extra"]["schemes"] = schemes
 
     if not args.no_kernels:
         kernels, roof = kernel_block(disc, Ustart, dt, scheme, ndof, args.workload)
