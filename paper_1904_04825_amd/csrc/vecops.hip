@@ -3,9 +3,9 @@
 // (CGS2) for the Arnoldi step, and the Givens least-squares update, all on
 // the device so that the host only polls a flag.
 //
-// Reductions: every block writes its partial sums; the last block to finish
-// (atomic ticket) adds the partials in block order and resets the ticket, so
-// results are bitwise reproducible for a given grid.
+// Reductions: every workgroup writes its partial sums, and a second kernel adds
+// the partials in block order, so results are bitwise reproducible for a given
+// grid.
 #include <cmath>
 
 #include "internal.h"
@@ -14,10 +14,99 @@ namespace frjf {
 
 constexpr int kChunk = 16;  // vectors per CGS dot-product pass
 
-__device__ __forceinline__ double wave_sum(double v) {
+// ---------------------------------------------------------------- wavefront sums
+// Lane exchanges without LDS, in six stages that each pair a lane with one whose
+// set of already summed lanes is disjoint from its own: stage 0 pairs lanes 32
+// apart and stage 1 lanes 16 apart (row-swap permutes), stages 2..5 work inside a
+// 16-lane row by DPP (rotate by 8, mirror inside 8 lanes, quad permutes 2 and 1
+// apart).  Stage S splits the pairs by lane bit 5 - S into a lower and an upper
+// lane.
+
+__device__ __forceinline__ unsigned lo32(double x) { return (unsigned)__double2loint(x); }
+__device__ __forceinline__ unsigned hi32(double x) { return (unsigned)__double2hiint(x); }
+__device__ __forceinline__ double mk64(unsigned hi, unsigned lo) { return __hiloint2double((int)hi, (int)lo); }
+
+// Swap stage S < 2: the lower lane of a pair gets a(own) + a(partner), the upper
+// one b(partner) + b(own).
+template <int S>
+__device__ __forceinline__ double swap_add(double a, double b) {
+  if constexpr (S == 0) {
+    const auto rl = __builtin_amdgcn_permlane32_swap(lo32(a), lo32(b), false, false);
+    const auto rh = __builtin_amdgcn_permlane32_swap(hi32(a), hi32(b), false, false);
+    return mk64(rh[0], rl[0]) + mk64(rh[1], rl[1]);
+  } else {
+    const auto rl = __builtin_amdgcn_permlane16_swap(lo32(a), lo32(b), false, false);
+    const auto rh = __builtin_amdgcn_permlane16_swap(hi32(a), hi32(b), false, false);
+    return mk64(rh[0], rl[0]) + mk64(rh[1], rl[1]);
+  }
+}
+
+// DPP stage 2 <= S < 6: the partner's x
+template <int S>
+__device__ __forceinline__ double dpp_partner(double x) {
+  constexpr int CTRL = S == 2 ? 0x128 : (S == 3 ? 0x141 : (S == 4 ? 0x4e : 0xb1));
+  const int l = __builtin_amdgcn_update_dpp((int)lo32(x), (int)lo32(x), CTRL, 0xf, 0xf, false);
+  const int h = __builtin_amdgcn_update_dpp((int)hi32(x), (int)hi32(x), CTRL, 0xf, 0xf, false);
+  return mk64((unsigned)h, (unsigned)l);
+}
+
+// Values each lane holds after wave_multi_sum of K values: a stage halves an even
+// count (each lane of a pair keeps half of the sums) and sums an odd one in full.
+constexpr int multi_sum_count(int K, int s = 0) {
+  return s == 6 ? K : multi_sum_count(K % 2 == 0 ? K / 2 : K, s + 1);
+}
+
+template <int S, int KC, int K>
+__device__ __forceinline__ void multi_sum(double (&a)[K], int lane, int& off, int& full) {
+  if constexpr (S < 6) {
+    constexpr int BIT = 5 - S;
+    const bool up = (lane >> BIT) & 1;
+    if constexpr (KC % 2 == 0) {
+      constexpr int H = KC / 2;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+      for (int i = 0; i < H; ++i) {
+        if constexpr (S < 2) {
+          a[i] = swap_add<S>(a[i], a[i + H]);
+        } else {
+          const double send = up ? a[i] : a[i + H];
+          const double keep = up ? a[i + H] : a[i];
+          a[i] = keep + dpp_partner<S>(send);
+        }
+      }
+      if (up) off += H;
+      multi_sum<S + 1, H>(a, lane, off, full);
+    } else {
+#pragma unroll
+      for (int i = 0; i < KC; ++i) {
+        if constexpr (S < 2)
+          a[i] = swap_add<S>(a[i], a[i]);
+        else
+          a[i] += dpp_partner<S>(a[i]);
+      }
+      full |= 1 << BIT;
+      multi_sum<S + 1, KC>(a, lane, off, full);
+    }
+  }
+}
+
+// Sums of a[t], t < K, over the wavefront, about K + 6 exchanges instead of 6 K.
+// Afterwards a[0 .. multi_sum_count(K) - 1] of a lane hold the sums of
+// t = off .. off + multi_sum_count(K) - 1; exactly one lane per range returns true.
+template <int K>
+__device__ __forceinline__ bool wave_multi_sum(double (&a)[K], int& off) {
+  const int lane = threadIdx.x & 63;
+  int full = 0;
+  off = 0;
+  multi_sum<0, K>(a, lane, off, full);
+  return (lane & full) == 0;
+}
+
+// Sum of v over the wavefront, in every lane
+__device__ __forceinline__ double wave_sum(double v) {
+  double a[1] = {v};
+  int off;
+  wave_multi_sum<1>(a, off);
+  return a[0];
 }
 
 // Block sum of one accumulator; thread 0 receives the result.
@@ -131,6 +220,16 @@ hipError_t launch_scale_dev(double* y, const double* x, const double* alpha, int
 }
 
 // ---------------------------------------------------------------- CGS2 Arnoldi step
+#ifndef FRJF_CGS_EPT
+#define FRJF_CGS_EPT 4
+#endif
+// Workgroups of the CGS passes: at least FRJF_CGS_EPT entries per thread, so the
+// partial sums of a workgroup cover enough of the vectors to pay for its reduction.
+static int cgs_blocks(size_t n) {
+  const size_t per = (size_t)kRedThreads * FRJF_CGS_EPT;
+  return (int)std::max<size_t>(1, std::min<size_t>((n + per - 1) / per, kRedBlocks));
+}
+
 // dots: partials[b*(kMaxM+2) + t] = block b's share of <w, V_t>, t < nv; grid.y splits the
 // vectors into chunks of kChunk (each chunk re-reads its slice of w).
 __global__ void __launch_bounds__(kRedThreads) k_cgs_dots(const double* __restrict__ V, int nv,
@@ -149,11 +248,11 @@ __global__ void __launch_bounds__(kRedThreads) k_cgs_dots(const double* __restri
       if (t < cnt) acc[t] = fma(wi, V[(size_t)(t0 + t) * n + i], acc[t]);
   }
   __shared__ double red[kRedThreads / 64][kChunk];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wv = threadIdx.x >> 6;
+  int off;
+  if (wave_multi_sum<kChunk>(acc, off)) {
 #pragma unroll
-  for (int t = 0; t < kChunk; ++t) {
-    const double s = wave_sum(acc[t]);
-    if (lane == 0) red[wv][t] = s;
+    for (int t = 0; t < multi_sum_count(kChunk); ++t) red[wv][off + t] = acc[t];
   }
   __syncthreads();
   if (threadIdx.x < cnt) {
@@ -185,59 +284,78 @@ __global__ void __launch_bounds__(256) k_cgs_update(const double* __restrict__ V
   }
 }
 
-// Fused CGS pass: w -= sum_t h[t] V_t (if h) and partial sums of <w, V_t>, reading each
-// V_t once; V_t(i) held in registers (NV >= nv, compile-time).
-template <int NV>
+// Fused CGS pass over V_0 .. V_{nv-1}, each read once: w -= sum_t h[t] V_t (when h
+// is given), then the partial sums of <w, V_t> (DOTS) or of ||w||^2 (!DOTS), one
+// row of partials per workgroup.  NV >= nv is a multiple of 4 and every slot loads
+// unconditionally, so the loads of an entry are issued together: the slots t >= nv
+// re-read V_{nv-1} with weight 0, and their sums are dropped.
+template <int NV, bool DOTS>
 __global__ void __launch_bounds__(kRedThreads) k_cgs_pass(const double* __restrict__ V, int nv, double* __restrict__ w,
                                                           const double* __restrict__ h, double* partials,
                                                           const int* skip, size_t n) {
   if (skip != nullptr && *skip) return;
+  constexpr int NA = DOTS ? NV : 1;
   __shared__ double sh[NV];
-  if (threadIdx.x < NV) sh[threadIdx.x] = (h != nullptr && threadIdx.x < nv) ? h[threadIdx.x] : 0.0;
+  __shared__ double red[kRedThreads / 64][NA];
+  if (threadIdx.x < NV) sh[threadIdx.x] = (h != nullptr && (int)threadIdx.x < nv) ? h[threadIdx.x] : 0.0;
   __syncthreads();
-  double acc[NV];
+  double acc[NA];
 #pragma unroll
-  for (int t = 0; t < NV; ++t) acc[t] = 0.0;
+  for (int t = 0; t < NA; ++t) acc[t] = 0.0;
   for (size_t i = blockIdx.x * (size_t)kRedThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kRedThreads) {
     double vr[NV];
 #pragma unroll
-    for (int t = 0; t < NV; ++t) vr[t] = (t < nv) ? V[(size_t)t * n + i] : 0.0;
+    for (int t = 0; t < NV; ++t) vr[t] = V[(size_t)min(t, nv - 1) * n + i];
     double s = w[i];
     if (h != nullptr) {
 #pragma unroll
       for (int t = 0; t < NV; ++t) s = fma(-sh[t], vr[t], s);
       w[i] = s;
     }
+    if constexpr (DOTS) {
 #pragma unroll
-    for (int t = 0; t < NV; ++t) acc[t] = fma(s, vr[t], acc[t]);
+      for (int t = 0; t < NV; ++t) acc[t] = fma(s, vr[t], acc[t]);
+    } else {
+      acc[0] = fma(s, s, acc[0]);
+    }
   }
-  __shared__ double red[kRedThreads / 64][NV];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wv = threadIdx.x >> 6;
+  int off;
+  if (wave_multi_sum<NA>(acc, off)) {
 #pragma unroll
-  for (int t = 0; t < NV; ++t) {
-    const double r = wave_sum(acc[t]);
-    if (lane == 0) red[wv][t] = r;
+    for (int t = 0; t < multi_sum_count(NA); ++t) red[wv][off + t] = acc[t];
   }
   __syncthreads();
-  if (threadIdx.x < nv) {
+  if ((int)threadIdx.x < (DOTS ? nv : 1)) {
     double r = 0.0;
+#pragma unroll
     for (int q = 0; q < kRedThreads / 64; ++q) r += red[q][threadIdx.x];
-    partials[(size_t)blockIdx.x * (kMaxM + 2) + threadIdx.x] = r;
+    partials[(size_t)blockIdx.x * (DOTS ? kMaxM + 2 : 1) + threadIdx.x] = r;
+  }
+}
+
+// k_cgs_pass with NV = nv rounded up to a multiple of 4 (nv <= 32); false beyond
+template <bool DOTS>
+static bool launch_cgs_pass(int nb, const double* V, int nv, double* w, const double* h, double* partials,
+                            const int* skip, size_t n, hipStream_t s) {
+  const dim3 g(nb), b(kRedThreads);
+  switch ((nv + 3) / 4) {
+    case 1: hipLaunchKernelGGL((k_cgs_pass<4, DOTS>), g, b, 0, s, V, nv, w, h, partials, skip, n); return true;
+    case 2: hipLaunchKernelGGL((k_cgs_pass<8, DOTS>), g, b, 0, s, V, nv, w, h, partials, skip, n); return true;
+    case 3: hipLaunchKernelGGL((k_cgs_pass<12, DOTS>), g, b, 0, s, V, nv, w, h, partials, skip, n); return true;
+    case 4: hipLaunchKernelGGL((k_cgs_pass<16, DOTS>), g, b, 0, s, V, nv, w, h, partials, skip, n); return true;
+    case 5: hipLaunchKernelGGL((k_cgs_pass<20, DOTS>), g, b, 0, s, V, nv, w, h, partials, skip, n); return true;
+    case 6: hipLaunchKernelGGL((k_cgs_pass<24, DOTS>), g, b, 0, s, V, nv, w, h, partials, skip, n); return true;
+    case 7: hipLaunchKernelGGL((k_cgs_pass<28, DOTS>), g, b, 0, s, V, nv, w, h, partials, skip, n); return true;
+    case 8: hipLaunchKernelGGL((k_cgs_pass<32, DOTS>), g, b, 0, s, V, nv, w, h, partials, skip, n); return true;
+    default: return false;
   }
 }
 
 static hipError_t cgs_pass(const double* V, int nv, double* w, const double* h, double* partials, double* out,
                            const int* skip, size_t n, hipStream_t s) {
-  const int nb = red_blocks(n);
-  if (nv <= 8)
-    hipLaunchKernelGGL(k_cgs_pass<8>, dim3(nb), dim3(kRedThreads), 0, s, V, nv, w, h, partials, skip, n);
-  else if (nv <= 16)
-    hipLaunchKernelGGL(k_cgs_pass<16>, dim3(nb), dim3(kRedThreads), 0, s, V, nv, w, h, partials, skip, n);
-  else if (nv <= 24)
-    hipLaunchKernelGGL(k_cgs_pass<24>, dim3(nb), dim3(kRedThreads), 0, s, V, nv, w, h, partials, skip, n);
-  else if (nv <= 32)
-    hipLaunchKernelGGL(k_cgs_pass<32>, dim3(nb), dim3(kRedThreads), 0, s, V, nv, w, h, partials, skip, n);
-  else {
+  const int nb = cgs_blocks(n);
+  if (!launch_cgs_pass<true>(nb, V, nv, w, h, partials, skip, n, s)) {
     // long restarts: plain update, then the chunked dot kernel
     if (h != nullptr) hipLaunchKernelGGL(k_cgs_update, dim3(nb), dim3(256), 0, s, V, nv, w, h, skip, n);
     hipLaunchKernelGGL(k_cgs_dots, dim3(nb, (nv + kChunk - 1) / kChunk), dim3(kRedThreads), 0, s, V, nv, w, partials,
@@ -253,7 +371,8 @@ hipError_t launch_cgs_update_dots(const double* V, int nv, double* w, const doub
   return cgs_pass(V, nv, w, h, partials, out, skip, n, s);
 }
 
-// Second update fused with the partial sums of ||w||^2.
+// Second update fused with the partial sums of ||w||^2, for restarts longer than the
+// register-held passes (nv > 32).
 __global__ void __launch_bounds__(kRedThreads) k_cgs_update_norm(const double* __restrict__ V, int nv,
                                                                  double* __restrict__ w, const double* __restrict__ h2,
                                                                  double* partials, const int* skip, size_t n) {
@@ -337,8 +456,9 @@ __global__ void __launch_bounds__(kRedThreads) k_givens(GmState* st, const doubl
 
 hipError_t launch_cgs_update_norm(const double* V, int nv, double* w, const double* h2, double* partials,
                                   unsigned*, GmState* st, int M, size_t n, hipStream_t s) {
-  const int nb = red_blocks(n);
-  hipLaunchKernelGGL(k_cgs_update_norm, dim3(nb), dim3(kRedThreads), 0, s, V, nv, w, h2, partials, &st->stop, n);
+  const int nb = cgs_blocks(n);
+  if (!launch_cgs_pass<false>(nb, V, nv, w, h2, partials, &st->stop, n, s))
+    hipLaunchKernelGGL(k_cgs_update_norm, dim3(nb), dim3(kRedThreads), 0, s, V, nv, w, h2, partials, &st->stop, n);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_givens, dim3(1), dim3(kRedThreads), 0, s, st, partials, nb, M);
