@@ -137,14 +137,11 @@ struct GmStatus {
   int j, stop, why, pad;
 };
 // V: nv vectors of n doubles stored back to back (vector i at V + i*n).
-hipError_t launch_cgs_dots(const double* V, int nv, const double* w, double* partials,
-                           unsigned* counter, double* out, const int* skip, size_t n, hipStream_t s);
-hipError_t launch_cgs_update_dots(const double* V, int nv, double* w, const double* h,
-                                  double* partials, unsigned* counter, double* out, const int* skip,
-                                  size_t n, hipStream_t s);
-hipError_t launch_cgs_update_norm(const double* V, int nv, double* w, const double* h2,
-                                  double* partials, unsigned* counter, GmState* st, int M,
-                                  size_t n, hipStream_t s);
+// One Arnoldi orthogonalisation by CGS2 and the Givens update of step st->j:
+// h1 = V^T w, w -= V h1, h2 = V^T w, w -= V h2, then the Hessenberg column h1 + h2,
+// ||w|| and the rotations.  partials: at least 2 kRedThreads (kMaxM + 2) doubles.
+hipError_t launch_arnoldi_cgs2(const double* V, int nv, double* w, double* partials, GmState* st, int M, size_t n,
+                               hipStream_t s);
 hipError_t launch_gm_init(GmState* st, const double* beta2, double target, int M, GmStatus* hslot, hipStream_t s);
 // Sum partials[b*stride + i] over b < nblocks into out[i], i < nv (one workgroup).
 hipError_t launch_finalize(const double* partials, int nblocks, int stride, int nv, double* out, const int* skip,

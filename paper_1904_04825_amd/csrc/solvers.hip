@@ -201,8 +201,9 @@ size_t ns_trace_bytes(const fr_disc* d) {
   return d->physics == FR_NS_BR1 ? (size_t)d->nel * 4 * d->n * 4 * 2 * sizeof(double) : 0;
 }
 
-// Partial sums: the grid-stride reductions use kRedBlocks x (kMaxM + 2) slots, the
-// preconditioner application one slot per workgroup (at most one per element).
+// Partial sums: the grid-stride reductions and the two sets of CGS partial rows use
+// at most kRedBlocks x (kMaxM + 2) slots, the preconditioner application one slot per
+// workgroup (at most one per element).
 size_t partials_count(const fr_disc* d) {
   return std::max<size_t>((size_t)kRedBlocks * (kMaxM + 2), (size_t)d->nel);
 }
@@ -355,9 +356,7 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
       a1.out = W.w;
       a1.skip = skip;
       FR_HIP(launch_residual(d, 1, a1, s));
-      FR_HIP(launch_cgs_dots(W.V, j + 1, W.w, W.partials, nullptr, W.st->h1, skip, n, s));
-      FR_HIP(launch_cgs_update_dots(W.V, j + 1, W.w, W.st->h1, W.partials, nullptr, W.st->h2, skip, n, s));
-      FR_HIP(launch_cgs_update_norm(W.V, j + 1, W.w, W.st->h2, W.partials, nullptr, W.st, m, n, s));
+      FR_HIP(launch_arnoldi_cgs2(W.V, j + 1, W.w, W.partials, W.st, m, n, s));
       FR_HIP(hipEventRecord(d->ev[j & 1], s));
       // wait for step j-1 while step j runs
       if (j >= 1) {

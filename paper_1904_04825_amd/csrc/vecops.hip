@@ -224,13 +224,20 @@ hipError_t launch_scale_dev(double* y, const double* x, const double* alpha, int
 #define FRJF_CGS_EPT 4
 #endif
 // Workgroups of the CGS passes: at least FRJF_CGS_EPT entries per thread, so the
-// partial sums of a workgroup cover enough of the vectors to pay for its reduction.
+// partial sums of a workgroup cover enough of the vectors to pay for its reduction,
+// and at most kRedThreads, so a workgroup of the next pass adds all of them with one
+// load per thread and value.
 static int cgs_blocks(size_t n) {
   const size_t per = (size_t)kRedThreads * FRJF_CGS_EPT;
-  return (int)std::max<size_t>(1, std::min<size_t>((n + per - 1) / per, kRedBlocks));
+  return (int)std::max<size_t>(1, std::min<size_t>((n + per - 1) / per, kRedThreads));
 }
 
-// dots: partials[b*(kMaxM+2) + t] = block b's share of <w, V_t>, t < nv; grid.y splits the
+// Row stride of the partial sums of the chunked dot kernel, and the offset of the
+// second set of partial sums of the fused passes
+constexpr int kPartStride = kMaxM + 2;
+constexpr size_t kPartSecond = (size_t)kRedThreads * 32;
+
+// dots: partials[b*kPartStride + t] = block b's share of <w, V_t>, t < nv; grid.y splits the
 // vectors into chunks of kChunk (each chunk re-reads its slice of w).
 __global__ void __launch_bounds__(kRedThreads) k_cgs_dots(const double* __restrict__ V, int nv,
                                                           const double* __restrict__ w, double* partials,
@@ -258,16 +265,8 @@ __global__ void __launch_bounds__(kRedThreads) k_cgs_dots(const double* __restri
   if (threadIdx.x < cnt) {
     double s = 0.0;
     for (int q = 0; q < kRedThreads / 64; ++q) s += red[q][threadIdx.x];
-    partials[(size_t)blockIdx.x * (kMaxM + 2) + t0 + threadIdx.x] = s;
+    partials[(size_t)blockIdx.x * kPartStride + t0 + threadIdx.x] = s;
   }
-}
-
-static hipError_t cgs_pass(const double* V, int nv, double* w, const double* h, double* partials, double* out,
-                           const int* skip, size_t n, hipStream_t s);
-
-hipError_t launch_cgs_dots(const double* V, int nv, const double* w, double* partials, unsigned*, double* out,
-                           const int* skip, size_t n, hipStream_t s) {
-  return cgs_pass(V, nv, const_cast<double*>(w), nullptr, partials, out, skip, n, s);
 }
 
 // w -= sum_t h[t] V_t (t < nv)
@@ -284,30 +283,60 @@ __global__ void __launch_bounds__(256) k_cgs_update(const double* __restrict__ V
   }
 }
 
-// Fused CGS pass over V_0 .. V_{nv-1}, each read once: w -= sum_t h[t] V_t (when h
-// is given), then the partial sums of <w, V_t> (DOTS) or of ||w||^2 (!DOTS), one
-// row of partials per workgroup.  NV >= nv is a multiple of 4 and every slot loads
-// unconditionally, so the loads of an entry are issued together: the slots t >= nv
-// re-read V_{nv-1} with weight 0, and their sums are dropped.
+// Fused CGS pass over V_0 .. V_{nv-1}, each read once, one partial sum per value and
+// workgroup, stored at partials[t kRedThreads + b] (value t, workgroup b):
+//   h = the sums over b < hnb of the previous pass's partials hpart, when hpart is
+//       given; every workgroup adds them in the same order, workgroup 0 stores h to
+//       hout;
+//   w -= sum_t h[t] V_t (when hpart is given);
+//   partial sums of <w, V_t> (DOTS) or of ||w||^2 (!DOTS).
+// NV >= nv is a multiple of 4 and every slot loads unconditionally, so the loads of
+// an entry are issued together: the slots t >= nv re-read V_{nv-1} with weight 0,
+// and their sums are dropped.  The first entry's loads are in flight while h is
+// summed.  Requires hnb <= kRedThreads.
 template <int NV, bool DOTS>
 __global__ void __launch_bounds__(kRedThreads) k_cgs_pass(const double* __restrict__ V, int nv, double* __restrict__ w,
-                                                          const double* __restrict__ h, double* partials,
-                                                          const int* skip, size_t n) {
+                                                          const double* __restrict__ hpart, int hnb, double* hout,
+                                                          double* __restrict__ partials, const int* skip, size_t n) {
   if (skip != nullptr && *skip) return;
   constexpr int NA = DOTS ? NV : 1;
   __shared__ double sh[NV];
-  __shared__ double red[kRedThreads / 64][NA];
-  if (threadIdx.x < NV) sh[threadIdx.x] = (h != nullptr && (int)threadIdx.x < nv) ? h[threadIdx.x] : 0.0;
-  __syncthreads();
+  __shared__ double red[kRedThreads / 64][NV];
+  const int tid = threadIdx.x, wv = tid >> 6;
+  const size_t stride = (size_t)gridDim.x * kRedThreads;
+  size_t i = blockIdx.x * (size_t)kRedThreads + tid;
+  double vr[NV], wi = 0.0;
+  auto load = [&](size_t k) {
+#pragma unroll
+    for (int t = 0; t < NV; ++t) vr[t] = V[(size_t)min(t, nv - 1) * n + k];
+    wi = w[k];
+  };
+  if (i < n) load(i);
+  if (hpart != nullptr) {
+    double hr[NV];
+#pragma unroll
+    for (int t = 0; t < NV; ++t) hr[t] = (tid < hnb) ? hpart[(size_t)min(t, nv - 1) * kRedThreads + tid] : 0.0;
+    int off;
+    if (wave_multi_sum<NV>(hr, off)) {
+#pragma unroll
+      for (int t = 0; t < multi_sum_count(NV); ++t) red[wv][off + t] = hr[t];
+    }
+    __syncthreads();
+    if (tid < NV) {
+      double r = 0.0;
+#pragma unroll
+      for (int q = 0; q < kRedThreads / 64; ++q) r += red[q][tid];
+      sh[tid] = tid < nv ? r : 0.0;
+      if (blockIdx.x == 0 && tid < nv) hout[tid] = r;
+    }
+    __syncthreads();
+  }
   double acc[NA];
 #pragma unroll
   for (int t = 0; t < NA; ++t) acc[t] = 0.0;
-  for (size_t i = blockIdx.x * (size_t)kRedThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kRedThreads) {
-    double vr[NV];
-#pragma unroll
-    for (int t = 0; t < NV; ++t) vr[t] = V[(size_t)min(t, nv - 1) * n + i];
-    double s = w[i];
-    if (h != nullptr) {
+  for (; i < n; i += stride) {
+    double s = wi;
+    if (hpart != nullptr) {
 #pragma unroll
       for (int t = 0; t < NV; ++t) s = fma(-sh[t], vr[t], s);
       w[i] = s;
@@ -318,57 +347,44 @@ __global__ void __launch_bounds__(kRedThreads) k_cgs_pass(const double* __restri
     } else {
       acc[0] = fma(s, s, acc[0]);
     }
+    if (i + stride < n) load(i + stride);
   }
-  const int wv = threadIdx.x >> 6;
   int off;
   if (wave_multi_sum<NA>(acc, off)) {
 #pragma unroll
     for (int t = 0; t < multi_sum_count(NA); ++t) red[wv][off + t] = acc[t];
   }
   __syncthreads();
-  if ((int)threadIdx.x < (DOTS ? nv : 1)) {
+  if (tid < (DOTS ? nv : 1)) {
     double r = 0.0;
 #pragma unroll
-    for (int q = 0; q < kRedThreads / 64; ++q) r += red[q][threadIdx.x];
-    partials[(size_t)blockIdx.x * (DOTS ? kMaxM + 2 : 1) + threadIdx.x] = r;
+    for (int q = 0; q < kRedThreads / 64; ++q) r += red[q][tid];
+    partials[(size_t)tid * kRedThreads + blockIdx.x] = r;
   }
 }
 
-// k_cgs_pass with NV = nv rounded up to a multiple of 4 (nv <= 32); false beyond
+// k_cgs_pass with NV = nv rounded up to a multiple of 4 (nv <= 32)
 template <bool DOTS>
-static bool launch_cgs_pass(int nb, const double* V, int nv, double* w, const double* h, double* partials,
-                            const int* skip, size_t n, hipStream_t s) {
+static void launch_cgs_pass(int nb, const double* V, int nv, double* w, const double* hpart, int hnb, double* hout,
+                            double* partials, const int* skip, size_t n, hipStream_t s) {
   const dim3 g(nb), b(kRedThreads);
+#define FRJF_CGS_CASE(K, NVV)                                                                                         \
+  case K:                                                                                                             \
+    hipLaunchKernelGGL((k_cgs_pass<NVV, DOTS>), g, b, 0, s, V, nv, w, hpart, hnb, hout, partials, skip, n);           \
+    break;
   switch ((nv + 3) / 4) {
-    case 1: hipLaunchKernelGGL((k_cgs_pass<4, DOTS>), g, b, 0, s, V, nv, w, h, partials, skip, n); return true;
-    case 2: hipLaunchKernelGGL((k_cgs_pass<8, DOTS>), g, b, 0, s, V, nv, w, h, partials, skip, n); return true;
-    case 3: hipLaunchKernelGGL((k_cgs_pass<12, DOTS>), g, b, 0, s, V, nv, w, h, partials, skip, n); return true;
-    case 4: hipLaunchKernelGGL((k_cgs_pass<16, DOTS>), g, b, 0, s, V, nv, w, h, partials, skip, n); return true;
-    case 5: hipLaunchKernelGGL((k_cgs_pass<20, DOTS>), g, b, 0, s, V, nv, w, h, partials, skip, n); return true;
-    case 6: hipLaunchKernelGGL((k_cgs_pass<24, DOTS>), g, b, 0, s, V, nv, w, h, partials, skip, n); return true;
-    case 7: hipLaunchKernelGGL((k_cgs_pass<28, DOTS>), g, b, 0, s, V, nv, w, h, partials, skip, n); return true;
-    case 8: hipLaunchKernelGGL((k_cgs_pass<32, DOTS>), g, b, 0, s, V, nv, w, h, partials, skip, n); return true;
-    default: return false;
+    FRJF_CGS_CASE(1, 4)
+    FRJF_CGS_CASE(2, 8)
+    FRJF_CGS_CASE(3, 12)
+    FRJF_CGS_CASE(4, 16)
+    FRJF_CGS_CASE(5, 20)
+    FRJF_CGS_CASE(6, 24)
+    FRJF_CGS_CASE(7, 28)
+    FRJF_CGS_CASE(8, 32)
+    default:
+      break;
   }
-}
-
-static hipError_t cgs_pass(const double* V, int nv, double* w, const double* h, double* partials, double* out,
-                           const int* skip, size_t n, hipStream_t s) {
-  const int nb = cgs_blocks(n);
-  if (!launch_cgs_pass<true>(nb, V, nv, w, h, partials, skip, n, s)) {
-    // long restarts: plain update, then the chunked dot kernel
-    if (h != nullptr) hipLaunchKernelGGL(k_cgs_update, dim3(nb), dim3(256), 0, s, V, nv, w, h, skip, n);
-    hipLaunchKernelGGL(k_cgs_dots, dim3(nb, (nv + kChunk - 1) / kChunk), dim3(kRedThreads), 0, s, V, nv, w, partials,
-                       skip, n);
-  }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_finalize(partials, nb, kMaxM + 2, nv, out, skip, s);
-}
-
-hipError_t launch_cgs_update_dots(const double* V, int nv, double* w, const double* h, double* partials,
-                                  unsigned*, double* out, const int* skip, size_t n, hipStream_t s) {
-  return cgs_pass(V, nv, w, h, partials, out, skip, n, s);
+#undef FRJF_CGS_CASE
 }
 
 // Second update fused with the partial sums of ||w||^2, for restarts longer than the
@@ -454,14 +470,30 @@ __global__ void __launch_bounds__(kRedThreads) k_givens(GmState* st, const doubl
   if (tid <= j + 1) st->H[(size_t)j * ld + tid] = col[tid];
 }
 
-hipError_t launch_cgs_update_norm(const double* V, int nv, double* w, const double* h2, double* partials,
-                                  unsigned*, GmState* st, int M, size_t n, hipStream_t s) {
+hipError_t launch_arnoldi_cgs2(const double* V, int nv, double* w, double* partials, GmState* st, int M, size_t n,
+                               hipStream_t s) {
   const int nb = cgs_blocks(n);
-  if (!launch_cgs_pass<false>(nb, V, nv, w, h2, partials, &st->stop, n, s))
-    hipLaunchKernelGGL(k_cgs_update_norm, dim3(nb), dim3(kRedThreads), 0, s, V, nv, w, h2, partials, &st->stop, n);
+  const int* skip = &st->stop;
+  double* P1 = partials;
+  double* P2 = partials + kPartSecond;
+  if (nv <= 32) {
+    launch_cgs_pass<true>(nb, V, nv, w, nullptr, 0, nullptr, P1, skip, n, s);  // h1 = V^T w
+    launch_cgs_pass<true>(nb, V, nv, w, P1, nb, st->h1, P2, skip, n, s);       // w -= V h1; h2 = V^T w
+    launch_cgs_pass<false>(nb, V, nv, w, P2, nb, st->h2, P1, skip, n, s);      // w -= V h2; ||w||^2
+  } else {
+    // long restarts: chunked dot kernels with separate sums, the update kernels
+    const dim3 gd(nb, (nv + kChunk - 1) / kChunk);
+    hipError_t e;
+    hipLaunchKernelGGL(k_cgs_dots, gd, dim3(kRedThreads), 0, s, V, nv, w, P1, skip, n);
+    if ((e = launch_finalize(P1, nb, kPartStride, nv, st->h1, skip, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cgs_update, dim3(nb), dim3(kRedThreads), 0, s, V, nv, w, st->h1, skip, n);
+    hipLaunchKernelGGL(k_cgs_dots, gd, dim3(kRedThreads), 0, s, V, nv, w, P1, skip, n);
+    if ((e = launch_finalize(P1, nb, kPartStride, nv, st->h2, skip, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cgs_update_norm, dim3(nb), dim3(kRedThreads), 0, s, V, nv, w, st->h2, P1, skip, n);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_givens, dim3(1), dim3(kRedThreads), 0, s, st, partials, nb, M);
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(kRedThreads), 0, s, st, P1, nb, M);
   return hipGetLastError();
 }
 
