@@ -398,9 +398,10 @@ static hipError_t solve_ptr(const fr_disc* d, const void* f, const double* r, co
 
 template <int P>
 static hipError_t solve_p(const fr_disc* d, const void* f, int precision, const double* r, const double* r_scale,
-                          double* r_store, double* z, double* partials, double* nrm2, const int* skip, hipStream_t s) {
+                          double* r_store, double* z, double* partials, int* nparts, double* nrm2, const int* skip,
+                          hipStream_t s) {
   constexpr int Nb = 4 * (P + 1) * (P + 1);
-  double* part = nrm2 != nullptr ? partials : nullptr;
+  double* part = (nrm2 != nullptr || nparts != nullptr) ? partials : nullptr;
   const size_t store = (size_t)d->nel * Nb * Nb * (precision == FR_F32 ? sizeof(float) : sizeof(double));
   const bool wide = P == 4 && store >= kWideSolveBytes;
   int nb = 0;
@@ -411,17 +412,18 @@ static hipError_t solve_p(const fr_disc* d, const void* f, int precision, const 
   else
     e = wide ? solve_ptr<P, double, 2>(d, f, r, r_scale, r_store, z, part, skip, &nb, s)
              : solve_ptr<P, double, 1>(d, f, r, r_scale, r_store, z, part, skip, &nb, s);
+  if (nparts != nullptr) *nparts = nb;
   if (e != hipSuccess || nrm2 == nullptr) return e;
   return launch_finalize(partials, nb, 1, 1, nrm2, skip, s);
 }
 
 hipError_t launch_ejacobi_solve(const fr_disc* d, const void* factors, int precision, const double* r,
                                 const double* r_scale, double* r_store, double* z, double* partials,
-                                unsigned*, double* nrm2, const int* skip, hipStream_t s) {
+                                int* nparts, double* nrm2, const int* skip, hipStream_t s) {
   switch (d->p) {
-    case 2: return solve_p<2>(d, factors, precision, r, r_scale, r_store, z, partials, nrm2, skip, s);
-    case 3: return solve_p<3>(d, factors, precision, r, r_scale, r_store, z, partials, nrm2, skip, s);
-    case 4: return solve_p<4>(d, factors, precision, r, r_scale, r_store, z, partials, nrm2, skip, s);
+    case 2: return solve_p<2>(d, factors, precision, r, r_scale, r_store, z, partials, nparts, nrm2, skip, s);
+    case 3: return solve_p<3>(d, factors, precision, r, r_scale, r_store, z, partials, nparts, nrm2, skip, s);
+    case 4: return solve_p<4>(d, factors, precision, r, r_scale, r_store, z, partials, nparts, nrm2, skip, s);
   }
   return hipErrorInvalidValue;
 }

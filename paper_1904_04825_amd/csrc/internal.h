@@ -72,7 +72,12 @@ struct ResArgs {
   const double* R0;
   const double* B;
   double* out;
-  const double* nrm2;   // device scalar ||v||^2 (rms mode)
+  double* nrm2;         // device scalar ||v||^2 (rms mode)
+  // optional, rms mode: nrm2_nb partial sums of ||v||^2 in place of a finished *nrm2;
+  // small meshes add them inside the residual kernel, otherwise the launcher first
+  // sums them into *nrm2
+  const double* nrm2_part;
+  int nrm2_nb;
   const int* skip;      // optional device flag: nonzero -> kernel returns at once
   double eps;
   int eps_mode;
@@ -102,9 +107,12 @@ hipError_t launch_gj_rows_f64(int nb, double* blocks, int nblk, hipStream_t s);
 hipError_t launch_gj_mfma_f32(int nb, float* blocks, int nblk, hipStream_t s);
 hipError_t launch_ejacobi_invert_blocks(const fr_disc* d, const double* blocks, void* out,
                                         int precision, hipStream_t s);
+// z = M^{-1} (r / r_scale) (r_store receives r / r_scale when given).  Partial sums of
+// ||z||^2 go to partials when nrm2 (then summed into *nrm2) or nparts (then only their
+// count is returned, for a consumer that adds them itself) is given.
 hipError_t launch_ejacobi_solve(const fr_disc* d, const void* factors, int precision,
                                 const double* r, const double* r_scale, double* r_store,
-                                double* z, double* partials, unsigned* counter, double* nrm2,
+                                double* z, double* partials, int* nparts, double* nrm2,
                                 const int* skip, hipStream_t s);
 
 hipError_t launch_solution_points(const fr_disc* d, double* xy, hipStream_t s);

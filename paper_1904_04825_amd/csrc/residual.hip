@@ -25,6 +25,7 @@
 
 #include "internal.h"
 #include "physics.h"
+#include "wavesum.h"
 
 namespace frjf {
 
@@ -204,7 +205,7 @@ __global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a
   bool zero_v = false;
   if constexpr (MODE != 0) {
     if (a.eps_mode == FR_EPS_RMS) {
-      const double n2 = *a.nrm2;
+      const double n2 = (!BIG && a.nrm2_part != nullptr) ? wave_sum_partials(a.nrm2_part, a.nrm2_nb) : *a.nrm2;
       if (n2 > 0.0)
         e = a.eps / sqrt(n2 / (double)(4 * nel * Np));
       else
@@ -568,12 +569,24 @@ static hipError_t launch_euler_tile(const fr_disc* d, int mode, const ResArgs& a
   return hipGetLastError();
 }
 
+// ||v||^2 from its partial sums for kernels that do not add them themselves
+static hipError_t finish_nrm2(int mode, ResArgs& a, hipStream_t s) {
+  if (mode == 0 || a.nrm2_part == nullptr || a.eps_mode != FR_EPS_RMS) return hipSuccess;
+  const hipError_t e = launch_finalize(a.nrm2_part, a.nrm2_nb, 1, 1, a.nrm2, a.skip, s);
+  a.nrm2_part = nullptr;
+  return e;
+}
+
 template <int P, int FLUX>
 static hipError_t launch_euler_pf(const fr_disc* d, int mode, const ResArgs& a, hipStream_t s) {
   using C = LineCfg<P, true>;
   const long big_blocks = (long)((d->nx + C::TX - 1) / C::TX) * ((d->ny + C::TY - 1) / C::TY);
-  return big_blocks >= kBigTileMinBlocks ? launch_euler_tile<P, FLUX, true>(d, mode, a, s)
-                                         : launch_euler_tile<P, FLUX, false>(d, mode, a, s);
+  if (big_blocks < kBigTileMinBlocks) return launch_euler_tile<P, FLUX, false>(d, mode, a, s);
+  // many tiles: one finalize kernel instead of every wavefront reading the partials
+  ResArgs b = a;
+  const hipError_t e = finish_nrm2(mode, b, s);
+  if (e != hipSuccess) return e;
+  return launch_euler_tile<P, FLUX, true>(d, mode, b, s);
 }
 
 template <int P>
@@ -584,7 +597,12 @@ static hipError_t launch_euler_p(const fr_disc* d, int mode, const ResArgs& a, h
 hipError_t launch_ns_residual(const fr_disc* d, int mode, const ResArgs& a, hipStream_t s);
 
 hipError_t launch_residual(const fr_disc* d, int mode, const ResArgs& a, hipStream_t s) {
-  if (d->physics == FR_NS_BR1) return launch_ns_residual(d, mode, a, s);
+  if (d->physics == FR_NS_BR1) {
+    ResArgs b = a;
+    const hipError_t e = finish_nrm2(mode, b, s);
+    if (e != hipSuccess) return e;
+    return launch_ns_residual(d, mode, b, s);
+  }
   switch (d->p) {
     case 2: return launch_euler_p<2>(d, mode, a, s);
     case 3: return launch_euler_p<3>(d, mode, a, s);

@@ -347,11 +347,14 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
       double* zj = W.Z + (size_t)j * n;
       const int* skip = &W.st->stop;
       // z_j = M^{-1} v_j; for j >= 1, v_j = w / h_{j,j-1} is formed on the fly and stored
+      int np = 0;
       if (j == 0)
-        FR_HIP(launch_ejacobi_solve(d, factors, prec, vj, nullptr, nullptr, zj, W.partials, nullptr, nz, skip, s));
+        FR_HIP(launch_ejacobi_solve(d, factors, prec, vj, nullptr, nullptr, zj, W.partials, &np, nullptr, skip, s));
       else
-        FR_HIP(launch_ejacobi_solve(d, factors, prec, W.w, &W.st->hn, vj, zj, W.partials, nullptr, nz, skip, s));
+        FR_HIP(launch_ejacobi_solve(d, factors, prec, W.w, &W.st->hn, vj, zj, W.partials, &np, nullptr, skip, s));
       ResArgs a1 = ra;
+      a1.nrm2_part = W.partials;  // ||z_j||^2 added by the product itself
+      a1.nrm2_nb = np;
       a1.V = zj;
       a1.out = W.w;
       a1.skip = skip;
