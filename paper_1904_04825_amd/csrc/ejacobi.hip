@@ -9,10 +9,10 @@
 // difference of exactly those terms (flux at k, four common fluxes with the
 // neighbours' traces held fixed), which equals [R_e(q + d e_j) - R_e(q)]
 // up to rounding without re-evaluating the whole element.
-// Inversion.  The raw blocks are written out and inverted in place: FP64 with
-// the block rows in registers (gj_rows.hip), FP32 (the FP64 block rounded) with
-// the block in MFMA registers and rank-16 updates on the matrix cores
-// (gj_mfma.hip).
+// Inversion.  The raw blocks are written out and inverted in place with the
+// block in MFMA registers and rank-16 updates on the matrix cores (gj_mfma.hip):
+// FP64, or FP32 (the FP64 block rounded).  FP64 blocks of order 100 do not fit one
+// wavefront's registers and keep the block rows in registers (gj_rows.hip).
 // Application.  One 64-lane group per block row set: z_i = sum_j Pinv(i,j) r_j
 // with the inverse stored column-major, so each step of the j loop is a
 // coalesced load of one column.
@@ -20,6 +20,7 @@
 #include <type_traits>
 #include <cmath>
 
+#include "arnoldi.h"
 #include "internal.h"
 #include "physics.h"
 
@@ -246,7 +247,7 @@ __device__ __forceinline__ double row_of(const V& a, int q) {
 
 template <int P, typename T, int RPT>
 __global__ void __launch_bounds__(256) k_ejacobi_solve(const T* __restrict__ inv, const double* __restrict__ r,
-                                                        const double* r_scale, double* r_store, double* __restrict__ z,
+                                                        const GivensIn gv, double* r_store, double* __restrict__ z,
                                                         int nel, double* partials, const int* skip) {
   using C = SolveCfg<P, T, RPT>;
   using V = typename RowVec<T, RPT>::type;
@@ -256,7 +257,16 @@ __global__ void __launch_bounds__(256) k_ejacobi_solve(const T* __restrict__ inv
   __shared__ T sr[EPB][Nb];
   const int tid = threadIdx.x;
   const int blk = tid / TPE, i = tid - blk * TPE;  // element of the group, row block
-  const double sc = (r_scale != nullptr) ? 1.0 / *r_scale : 1.0;
+  // with gv: every workgroup forms ||r||^2 from the same partials in the same order,
+  // workgroup 0 also runs the Givens update of the Arnoldi step that produced r
+  const bool scaled = gv.st != nullptr;
+  double sc = 1.0;
+  if (scaled) {
+    __shared__ GivensLds GL;
+    const double hn2 = block_sum_partials(gv.norm_part, gv.nb, GL.red);
+    sc = 1.0 / sqrt(hn2);
+    if (blockIdx.x == 0) givens_step(gv.st, hn2, gv.M, GL);
+  }
   const int ngroups = (nel + EPB - 1) / EPB;
   double zz = 0.0;
   for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
@@ -267,7 +277,7 @@ __global__ void __launch_bounds__(256) k_ejacobi_solve(const T* __restrict__ inv
       const int v = jj / Np, k = jj - v * Np;
       const size_t gi = ((size_t)v * nel + el) * Np + k;
       double rv = r[gi];
-      if (r_scale != nullptr) {
+      if (scaled) {
         rv *= sc;
         if (r_store != nullptr) r_store[gi] = rv;
       }
@@ -303,8 +313,7 @@ __global__ void __launch_bounds__(256) k_ejacobi_solve(const T* __restrict__ inv
   }
   if (partials == nullptr) return;
   __shared__ double red[4];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) zz += __shfl_xor(zz, off, 64);
+  zz = wave_sum(zz);
   if ((tid & 63) == 0) red[tid >> 6] = zz;
   __syncthreads();
   if (tid == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
@@ -326,7 +335,7 @@ static hipError_t asm_pf(const fr_disc* d, const AsmArgs& a, int precision, int 
     if (invert) {
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
-      return launch_gj_rows_f64(EJ<P>::Nb, static_cast<double*>(a.out), d->nel, s);
+      return launch_invert_f64(EJ<P>::Nb, static_cast<double*>(a.out), d->nel, s);
     }
   }
   return hipGetLastError();
@@ -366,7 +375,7 @@ static hipError_t inv_p(const fr_disc* d, const double* blocks, void* out, int p
   const hipError_t e = hipMemcpyAsync(out, blocks, (size_t)d->nel * Nb * Nb * sizeof(double),
                                       hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return e;
-  return launch_gj_rows_f64(Nb, static_cast<double*>(out), d->nel, s);
+  return launch_invert_f64(Nb, static_cast<double*>(out), d->nel, s);
 }
 
 hipError_t launch_ejacobi_invert_blocks(const fr_disc* d, const double* blocks, void* out, int precision,
@@ -385,45 +394,47 @@ hipError_t launch_ejacobi_invert_blocks(const fr_disc* d, const double* blocks, 
 constexpr size_t kWideSolveBytes = size_t(256) << 20;
 
 template <int P, typename T, int RPT>
-static hipError_t solve_ptr(const fr_disc* d, const void* f, const double* r, const double* r_scale, double* r_store,
+static hipError_t solve_ptr(const fr_disc* d, const void* f, const double* r, const GivensIn& gv, double* r_store,
                             double* z, double* partials, const int* skip, int* nb_out, hipStream_t s) {
   constexpr int EPB = SolveCfg<P, T, RPT>::EPB;
   const int ngroups = (d->nel + EPB - 1) / EPB;
   const int nb = std::min(ngroups, kRedBlocks);
   *nb_out = nb;
-  hipLaunchKernelGGL((k_ejacobi_solve<P, T, RPT>), dim3(nb), dim3(256), 0, s, (const T*)f, r, r_scale, r_store, z,
+  hipLaunchKernelGGL((k_ejacobi_solve<P, T, RPT>), dim3(nb), dim3(256), 0, s, (const T*)f, r, gv, r_store, z,
                      d->nel, partials, skip);
   return hipGetLastError();
 }
 
 template <int P>
-static hipError_t solve_p(const fr_disc* d, const void* f, int precision, const double* r, const double* r_scale,
+static hipError_t solve_p(const fr_disc* d, const void* f, int precision, const double* r, const GivensIn* gvp,
                           double* r_store, double* z, double* partials, int* nparts, double* nrm2, const int* skip,
                           hipStream_t s) {
   constexpr int Nb = 4 * (P + 1) * (P + 1);
+  const GivensIn gv = gvp != nullptr ? *gvp : GivensIn{nullptr, nullptr, 0, 0};
+  if (gv.st != nullptr && (gv.nb < 1 || gv.nb > kRedThreads || gv.norm_part == nullptr)) return hipErrorInvalidValue;
   double* part = (nrm2 != nullptr || nparts != nullptr) ? partials : nullptr;
   const size_t store = (size_t)d->nel * Nb * Nb * (precision == FR_F32 ? sizeof(float) : sizeof(double));
   const bool wide = P == 4 && store >= kWideSolveBytes;
   int nb = 0;
   hipError_t e;
   if (precision == FR_F32)
-    e = wide ? solve_ptr<P, float, 4>(d, f, r, r_scale, r_store, z, part, skip, &nb, s)
-             : solve_ptr<P, float, 1>(d, f, r, r_scale, r_store, z, part, skip, &nb, s);
+    e = wide ? solve_ptr<P, float, 4>(d, f, r, gv, r_store, z, part, skip, &nb, s)
+             : solve_ptr<P, float, 1>(d, f, r, gv, r_store, z, part, skip, &nb, s);
   else
-    e = wide ? solve_ptr<P, double, 2>(d, f, r, r_scale, r_store, z, part, skip, &nb, s)
-             : solve_ptr<P, double, 1>(d, f, r, r_scale, r_store, z, part, skip, &nb, s);
+    e = wide ? solve_ptr<P, double, 2>(d, f, r, gv, r_store, z, part, skip, &nb, s)
+             : solve_ptr<P, double, 1>(d, f, r, gv, r_store, z, part, skip, &nb, s);
   if (nparts != nullptr) *nparts = nb;
   if (e != hipSuccess || nrm2 == nullptr) return e;
   return launch_finalize(partials, nb, 1, 1, nrm2, skip, s);
 }
 
 hipError_t launch_ejacobi_solve(const fr_disc* d, const void* factors, int precision, const double* r,
-                                const double* r_scale, double* r_store, double* z, double* partials,
+                                const GivensIn* gv, double* r_store, double* z, double* partials,
                                 int* nparts, double* nrm2, const int* skip, hipStream_t s) {
   switch (d->p) {
-    case 2: return solve_p<2>(d, factors, precision, r, r_scale, r_store, z, partials, nparts, nrm2, skip, s);
-    case 3: return solve_p<3>(d, factors, precision, r, r_scale, r_store, z, partials, nparts, nrm2, skip, s);
-    case 4: return solve_p<4>(d, factors, precision, r, r_scale, r_store, z, partials, nparts, nrm2, skip, s);
+    case 2: return solve_p<2>(d, factors, precision, r, gv, r_store, z, partials, nparts, nrm2, skip, s);
+    case 3: return solve_p<3>(d, factors, precision, r, gv, r_store, z, partials, nparts, nrm2, skip, s);
+    case 4: return solve_p<4>(d, factors, precision, r, gv, r_store, z, partials, nparts, nrm2, skip, s);
   }
   return hipErrorInvalidValue;
 }

@@ -105,19 +105,27 @@ hipError_t launch_ejacobi_assemble(const fr_disc* d, const double* U, double shi
 hipError_t launch_gj_rows_f64(int nb, double* blocks, int nblk, hipStream_t s);
 // In-place inversion of nblk FP32 blocks of order nb (36, 64 or 100), column-major, on MFMA.
 hipError_t launch_gj_mfma_f32(int nb, float* blocks, int nblk, hipStream_t s);
+// In-place inversion of nblk FP64 blocks of order nb: on MFMA (k_gj_mfma) for 36 and 64,
+// by k_gj_rows for 100.
+hipError_t launch_invert_f64(int nb, double* blocks, int nblk, hipStream_t s);
 hipError_t launch_ejacobi_invert_blocks(const fr_disc* d, const double* blocks, void* out,
                                         int precision, hipStream_t s);
-// z = M^{-1} (r / r_scale) (r_store receives r / r_scale when given).  Partial sums of
-// ||z||^2 go to partials when nrm2 (then summed into *nrm2) or nparts (then only their
-// count is returned, for a consumer that adds them itself) is given.
+struct GivensIn;
+// z = M^{-1} r, or with gv: the Givens update of step gv->st->j, then
+// z = M^{-1} (r / ||r||) with r_store receiving r / ||r|| (||r||^2 from gv's partials).
+// Partial sums of ||z||^2 go to partials when nrm2 (then summed into *nrm2) or nparts
+// (then only their count is returned, for a consumer that adds them itself) is given.
 hipError_t launch_ejacobi_solve(const fr_disc* d, const void* factors, int precision,
-                                const double* r, const double* r_scale, double* r_store,
+                                const double* r, const GivensIn* gv, double* r_store,
                                 double* z, double* partials, int* nparts, double* nrm2,
                                 const int* skip, hipStream_t s);
 
 hipError_t launch_solution_points(const fr_disc* d, double* xy, hipStream_t s);
 hipError_t launch_l2_vortex(const fr_disc* d, const double* U, int var, double t, const double* prm,
                             double* partials, unsigned* counter, double* out, hipStream_t s);
+
+constexpr int kRedBlocks = 1024;  // blocks of the grid-stride vector kernels
+constexpr int kRedThreads = 256;
 
 // Arnoldi (CGS2) device state, one per GMRES solve, in the workspace.
 constexpr int kMaxM = 64;
@@ -145,11 +153,28 @@ struct GmStatus {
   int j, stop, why, pad;
 };
 // V: nv vectors of n doubles stored back to back (vector i at V + i*n).
-// One Arnoldi orthogonalisation by CGS2 and the Givens update of step st->j:
-// h1 = V^T w, w -= V h1, h2 = V^T w, w -= V h2, then the Hessenberg column h1 + h2,
-// ||w|| and the rotations.  partials: at least 2 kRedThreads (kMaxM + 2) doubles.
+// Partial sums of the Arnoldi step: the CGS passes use partials[0 ..) and
+// partials[kPartSecond ..) (at most kPartSecond doubles each); rows of the chunked dot
+// kernel for long restarts are kPartStride apart.
+constexpr int kPartStride = kMaxM + 2;
+constexpr size_t kPartSecond = (size_t)kRedThreads * 32;
+// Workgroups of the CGS passes over n entries (<= kRedThreads), i.e. the number of partial
+// sums of ||w||^2 that the last pass leaves at partials[0 ..).
+int cgs_blocks(size_t n);
+// One Arnoldi orthogonalisation by CGS2: h1 = V^T w, w -= V h1, h2 = V^T w,
+// w -= V h2, partial sums of ||w||^2; h1 and h2 go to st.  partials: at least
+// 2 kPartSecond doubles.
 hipError_t launch_arnoldi_cgs2(const double* V, int nv, double* w, double* partials, GmState* st, int M, size_t n,
                                hipStream_t s);
+// The Givens update of Arnoldi step st->j from the nb partial sums of ||w||^2.
+hipError_t launch_givens(GmState* st, const double* norm_part, int nb, int M, hipStream_t s);
+// The Givens update of the previous Arnoldi step, run by the preconditioner kernel that
+// starts the next step (which also scales w by the same 1/||w||).
+struct GivensIn {
+  GmState* st;
+  const double* norm_part;  // nb <= kRedThreads partial sums of ||w||^2
+  int nb, M;
+};
 hipError_t launch_gm_init(GmState* st, const double* beta2, double target, int M, GmStatus* hslot, hipStream_t s);
 // Sum partials[b*stride + i] over b < nblocks into out[i], i < nv (one workgroup).
 hipError_t launch_finalize(const double* partials, int nblocks, int stride, int nv, double* out, const int* skip,
@@ -176,7 +201,5 @@ hipError_t mlp_train_step(fr_mlp_trainer* tr, const float* raw, const int* idx, 
                           int* nparts, void* work, hipStream_t s);
 hipError_t mlp_sync_weights(fr_mlp_trainer* tr, hipStream_t s);
 
-constexpr int kRedBlocks = 1024;  // blocks of the grid-stride vector kernels
-constexpr int kRedThreads = 256;
 
 }  // namespace frjf

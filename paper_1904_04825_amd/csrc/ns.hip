@@ -625,7 +625,7 @@ static hipError_t ns_asm_pf(const fr_disc* d, const NSArgs& a, void* out, int pr
     if (invert) {
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
-      return launch_gj_rows_f64(4 * (P + 1) * (P + 1), static_cast<double*>(out), d->nel, s);
+      return launch_invert_f64(4 * (P + 1) * (P + 1), static_cast<double*>(out), d->nel, s);
     }
   }
   return hipGetLastError();

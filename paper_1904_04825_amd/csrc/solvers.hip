@@ -346,14 +346,20 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
       double* vj = W.V + (size_t)j * n;
       double* zj = W.Z + (size_t)j * n;
       const int* skip = &W.st->stop;
-      // z_j = M^{-1} v_j; for j >= 1, v_j = w / h_{j,j-1} is formed on the fly and stored
+      // z_j = M^{-1} v_j; for j >= 1 the same kernel first runs the Givens update of step
+      // j - 1 and forms v_j = w / h_{j,j-1} on the fly.  The partial sums of ||z_j||^2 go
+      // to the second CGS partial region (the last pass of step j - 1 left its ||w||^2
+      // partials in the first).
+      double* zpart = W.partials + kPartSecond;
       int np = 0;
-      if (j == 0)
-        FR_HIP(launch_ejacobi_solve(d, factors, prec, vj, nullptr, nullptr, zj, W.partials, &np, nullptr, skip, s));
-      else
-        FR_HIP(launch_ejacobi_solve(d, factors, prec, W.w, &W.st->hn, vj, zj, W.partials, &np, nullptr, skip, s));
+      if (j == 0) {
+        FR_HIP(launch_ejacobi_solve(d, factors, prec, vj, nullptr, nullptr, zj, zpart, &np, nullptr, skip, s));
+      } else {
+        const GivensIn gv{W.st, W.partials, cgs_blocks(n), m};  // step j - 1's Givens update, then v_j = w / ||w||
+        FR_HIP(launch_ejacobi_solve(d, factors, prec, W.w, &gv, vj, zj, zpart, &np, nullptr, skip, s));
+      }
       ResArgs a1 = ra;
-      a1.nrm2_part = W.partials;  // ||z_j||^2 added by the product itself
+      a1.nrm2_part = zpart;  // ||z_j||^2 added by the product itself
       a1.nrm2_nb = np;
       a1.V = zj;
       a1.out = W.w;
@@ -361,12 +367,15 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
       FR_HIP(launch_residual(d, 1, a1, s));
       FR_HIP(launch_arnoldi_cgs2(W.V, j + 1, W.w, W.partials, W.st, m, n, s));
       FR_HIP(hipEventRecord(d->ev[j & 1], s));
-      // wait for step j-1 while step j runs
+      // wait for step j-1 while step j runs; its status reflects the Givens update of
+      // step j-2 (kernels enqueued after a stop return at once)
       if (j >= 1) {
         FR_HIP(hipEventSynchronize(d->ev[(j - 1) & 1]));
         if (hstat->stop) break;
       }
     }
+    // the Givens update of the cycle's last step (returns at once after a stop)
+    if (budget > 0) FR_HIP(launch_givens(W.st, W.partials, cgs_blocks(n), m, s));
     FR_HIP(hipStreamSynchronize(s));
     GmStatus fin;
     rs = read_sync(d, &fin, (const char*)W.st + status_off, sizeof(GmStatus), s);

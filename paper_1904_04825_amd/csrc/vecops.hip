@@ -8,6 +8,7 @@
 // grid.
 #include <cmath>
 
+#include "arnoldi.h"
 #include "internal.h"
 #include "wavesum.h"
 
@@ -133,15 +134,10 @@ hipError_t launch_scale_dev(double* y, const double* x, const double* alpha, int
 // partial sums of a workgroup cover enough of the vectors to pay for its reduction,
 // and at most kRedThreads, so a workgroup of the next pass adds all of them with one
 // load per thread and value.
-static int cgs_blocks(size_t n) {
+int cgs_blocks(size_t n) {
   const size_t per = (size_t)kRedThreads * FRJF_CGS_EPT;
   return (int)std::max<size_t>(1, std::min<size_t>((n + per - 1) / per, kRedThreads));
 }
-
-// Row stride of the partial sums of the chunked dot kernel, and the offset of the
-// second set of partial sums of the fused passes
-constexpr int kPartStride = kMaxM + 2;
-constexpr size_t kPartSecond = (size_t)kRedThreads * 32;
 
 // dots: partials[b*kPartStride + t] = block b's share of <w, V_t>, t < nv; grid.y splits the
 // vectors into chunks of kChunk (each chunk re-reads its slice of w).
@@ -313,67 +309,19 @@ __global__ void __launch_bounds__(kRedThreads) k_cgs_update_norm(const double* _
   if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
-// One workgroup: ||w||^2 from the partials, then the Hessenberg column, the Givens
-// rotations and the stop decision of Arnoldi step j = st->j; the status block is
-// also written to mapped host memory for the host's poll.
+// One workgroup: the Givens update of Arnoldi step st->j on its own (the last step
+// of a cycle; the others run it inside the next step's preconditioner kernel).
 __global__ void __launch_bounds__(kRedThreads) k_givens(GmState* st, const double* __restrict__ partials, int nblocks,
                                                         int M) {
   if (st->stop) return;
-  __shared__ double col[kMaxM + 2], cs[kMaxM], sn[kMaxM];
-  const int tid = threadIdx.x;
-  const int j = st->j;
-  const int ld = M + 1;
-  if (tid <= j) col[tid] = st->h1[tid] + st->h2[tid];
-  if (tid < j) {
-    cs[tid] = st->cs[tid];
-    sn[tid] = st->sn[tid];
-  }
-  double s = 0.0;
-  for (int b = tid; b < nblocks; b += kRedThreads) s += partials[b];
-  const double hn2 = block_sum(s);  // (contains barriers: the staged column is visible below)
-  if (tid == 0) {
-    const double hn = sqrt(hn2);
-    double w02 = hn2;  // ||w||^2 before orthogonalisation (Pythagoras)
-    for (int i = 0; i <= j; ++i) w02 += col[i] * col[i];
-    st->w0 = sqrt(w02);
-    col[j + 1] = hn;
-    for (int i = 0; i < j; ++i) {
-      const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-      col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-      col[i] = t;
-    }
-    const double den = hypot(col[j], col[j + 1]);
-    st->cs[j] = col[j] / den;
-    st->sn[j] = col[j + 1] / den;
-    col[j] = den;
-    col[j + 1] = 0.0;
-    st->g[j + 1] = -st->sn[j] * st->g[j];
-    st->g[j] = st->cs[j] * st->g[j];
-    const double rest = fabs(st->g[j + 1]);
-    st->rest = rest;
-    st->hn = hn;
-    st->j = j + 1;
-    if (!(rest == rest) || !(den == den) || isinf(rest) || den == 0.0) {
-      st->stop = 1;
-      st->why = 3;
-    } else if (rest <= st->target) {
-      st->stop = 1;
-      st->why = 1;
-    } else if (hn <= 1e-14 * st->w0) {
-      st->stop = 1;
-      st->why = 2;
-    }
-    GmStatus* hs = st->hslot;
-    if (hs != nullptr) {
-      hs->rest = st->rest;
-      hs->beta = st->beta;
-      hs->j = st->j;
-      hs->stop = st->stop;
-      hs->why = st->why;
-    }
-  }
-  __syncthreads();
-  if (tid <= j + 1) st->H[(size_t)j * ld + tid] = col[tid];
+  __shared__ GivensLds L;
+  const double hn2 = block_sum_partials(partials, nblocks, L.red);
+  givens_step(st, hn2, M, L);
+}
+
+hipError_t launch_givens(GmState* st, const double* norm_part, int nb, int M, hipStream_t s) {
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(kRedThreads), 0, s, st, norm_part, nb, M);
+  return hipGetLastError();
 }
 
 hipError_t launch_arnoldi_cgs2(const double* V, int nv, double* w, double* partials, GmState* st, int M, size_t n,
@@ -397,9 +345,6 @@ hipError_t launch_arnoldi_cgs2(const double* V, int nv, double* w, double* parti
     if ((e = launch_finalize(P1, nb, kPartStride, nv, st->h2, skip, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_cgs_update_norm, dim3(nb), dim3(kRedThreads), 0, s, V, nv, w, st->h2, P1, skip, n);
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_givens, dim3(1), dim3(kRedThreads), 0, s, st, P1, nb, M);
   return hipGetLastError();
 }
 
