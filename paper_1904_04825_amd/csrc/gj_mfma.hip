@@ -166,8 +166,17 @@ __device__ __forceinline__ void panel_steps(typename ColT<S, T>::type& W, unsign
   }
 }
 
+// Waves per SIMD the register allocation aims at: FP64 with 4 x 4 tiles fits two
+// in 206 VGPRs (left alone, the allocation takes 288 with accumulation registers and
+// runs one wave per SIMD, 1.4x slower); the others keep the default.
+template <typename S, int T>
+struct GjWaves {
+  static constexpr int value = (sizeof(S) == 8 && T == 4) ? 2 : 1;
+};
+
 template <typename S, int T, int N>
-__global__ void __launch_bounds__(64) k_gj_mfma(S* __restrict__ blocks) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GjWaves<S, T>::value)))
+k_gj_mfma(S* __restrict__ blocks) {
   using O = GjOps<S>;
   constexpr int NP = 16 * T;
   __shared__ GjMfmaLds<S, NP> L;
