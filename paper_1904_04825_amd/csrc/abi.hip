@@ -141,10 +141,8 @@ fr_status fr_jf_matvec(const fr_disc* d, const double* U, const double* R0, cons
   Carver c(work);
   double* tr = (double*)c.take(ns_trace_bytes(d));
   double* scal = (double*)c.take(256);
-  unsigned* counter = (unsigned*)c.take(256);
   double* partials = (double*)c.take(sizeof(double) * partials_count(d));
-  FR_HIP(zero_counters(counter, S(s)));
-  if (eps_mode == FR_EPS_RMS) FR_HIP(launch_norm2(v, d->ndof, partials, counter, scal, nullptr, S(s)));
+  if (eps_mode == FR_EPS_RMS) FR_HIP(launch_norm2(v, d->ndof, partials, scal, nullptr, S(s)));
   ResArgs a{};
   a.U = U;
   a.V = v;
@@ -268,10 +266,8 @@ fr_status fr_l2_error_vortex(const fr_disc* d, const double* U, int var, double 
   CHECK(var == 0 || var == 1, "fr_l2_error_vortex: var must be 0 (rho) or 1 (u)");
   Carver c(work);
   double* scal = (double*)c.take(256);
-  unsigned* counter = (unsigned*)c.take(256);
   double* partials = (double*)c.take(sizeof(double) * partials_count(d));
-  FR_HIP(zero_counters(counter, S(s)));
-  FR_HIP(launch_l2_vortex(d, U, var, t, h_params, partials, counter, scal, S(s)));
+  FR_HIP(launch_l2_vortex(d, U, var, t, h_params, partials, scal, S(s)));
   double host[2];
   char* slot = (char*)d->h_pinned + 1024;
   FR_HIP(hipMemcpyAsync(slot, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, S(s)));

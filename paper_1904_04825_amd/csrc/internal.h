@@ -88,7 +88,7 @@ hipError_t launch_residual(const fr_disc* d, int mode, const ResArgs& a, hipStre
 
 // Vector operations (flat arrays of n doubles).
 // Sum of squares with a deterministic two-level reduction; result in *out (device).
-hipError_t launch_norm2(const double* x, size_t n, double* partials, unsigned* counter, double* out,
+hipError_t launch_norm2(const double* x, size_t n, double* partials, double* out,
                         const int* skip, hipStream_t s);
 // y = sum_i c[i] * x[i] (k <= 8); pointers and coefficients passed by value
 hipError_t launch_lincomb(double* y, int k, const double* const* x, const double* c, size_t n,
@@ -122,7 +122,7 @@ hipError_t launch_ejacobi_solve(const fr_disc* d, const void* factors, int preci
 
 hipError_t launch_solution_points(const fr_disc* d, double* xy, hipStream_t s);
 hipError_t launch_l2_vortex(const fr_disc* d, const double* U, int var, double t, const double* prm,
-                            double* partials, unsigned* counter, double* out, hipStream_t s);
+                            double* partials, double* out, hipStream_t s);
 
 constexpr int kRedBlocks = 1024;  // blocks of the grid-stride vector kernels
 constexpr int kRedThreads = 256;

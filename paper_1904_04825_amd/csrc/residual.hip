@@ -699,7 +699,7 @@ __global__ void __launch_bounds__(256) k_l2_vortex(const MeshArgs g, const Basis
 }
 
 hipError_t launch_l2_vortex(const fr_disc* d, const double* U, int var, double t, const double* prm,
-                            double* partials, unsigned* counter, double* out, hipStream_t s) {
+                            double* partials, double* out, hipStream_t s) {
   const MeshArgs g{d->nodes, d->nx, d->ny, d->nel, d->phys.gamma};
   VortexPrm P;
   for (int i = 0; i < 14; ++i) P.v[i] = prm[i];

@@ -21,7 +21,6 @@ struct GmWork {
   double* grad;  // BR1 gradient traces (Navier-Stokes only)
   GmState* st;
   double* scal;
-  unsigned* counter;
   double* partials;
   double* V;
   double* Z;
@@ -40,8 +39,7 @@ size_t ns_trace_bytes(const fr_disc* d);
 size_t small_bytes(const fr_disc* d);
 size_t partials_count(const fr_disc* d);
 GmWork carve_gmres(Carver& c, const fr_disc* d, int m);
-hipError_t zero_counters(unsigned* c, hipStream_t s);
-fr_status device_norm(const fr_disc* d, const double* x, double* partials, unsigned* counter, double* dev_out,
+fr_status device_norm(const fr_disc* d, const double* x, double* partials, double* dev_out,
                       double* host_out, hipStream_t s);
 
 fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const double* U, const double* R0,

@@ -209,11 +209,11 @@ size_t partials_count(const fr_disc* d) {
 }
 
 size_t gmres_bytes(const fr_disc* d, int m) {
-  return align256(ns_trace_bytes(d)) + align256(sizeof(GmState)) + 256 + 256 +
+  return align256(ns_trace_bytes(d)) + align256(sizeof(GmState)) + 256 +
          align256(sizeof(double) * partials_count(d)) + align256(sizeof(double) * d->ndof) * (size_t)(2 * m + 3);
 }
 
-size_t small_bytes(const fr_disc* d) { return 256 + 256 + align256(sizeof(double) * partials_count(d)); }
+size_t small_bytes(const fr_disc* d) { return 256 + align256(sizeof(double) * partials_count(d)); }
 
 Carver::Carver(void* base) : p((char*)base) {}
 void* Carver::take(size_t bytes) {
@@ -227,22 +227,12 @@ GmWork carve_gmres(Carver& c, const fr_disc* d, int m) {
   w.grad = d->physics == FR_NS_BR1 ? (double*)c.take(ns_trace_bytes(d)) : nullptr;
   w.st = (GmState*)c.take(sizeof(GmState));
   w.scal = (double*)c.take(256);
-  w.counter = (unsigned*)c.take(256);
   w.partials = (double*)c.take(sizeof(double) * partials_count(d));
   w.V = (double*)c.take(sizeof(double) * d->ndof * (size_t)(m + 1));
   w.Z = (double*)c.take(sizeof(double) * d->ndof * (size_t)m);
   w.w = (double*)c.take(sizeof(double) * d->ndof);
   w.r = (double*)c.take(sizeof(double) * d->ndof);
   return w;
-}
-
-__global__ void k_zero_u32(unsigned* p, int n) {
-  if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
-}
-
-hipError_t zero_counters(unsigned* c, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, c, 64);
-  return hipGetLastError();
 }
 
 // Read `bytes` from device into the pinned host scratch and wait.
@@ -254,9 +244,9 @@ static fr_status read_sync(const fr_disc* d, void* dst, const void* dev, size_t 
   return FR_OK;
 }
 
-fr_status device_norm(const fr_disc* d, const double* x, double* partials, unsigned* counter, double* dev_out,
+fr_status device_norm(const fr_disc* d, const double* x, double* partials, double* dev_out,
                       double* host_out, hipStream_t s) {
-  FR_HIP(launch_norm2(x, d->ndof, partials, counter, dev_out, nullptr, s));
+  FR_HIP(launch_norm2(x, d->ndof, partials, dev_out, nullptr, s));
   double v = 0.0;
   fr_status st = read_sync(d, &v, dev_out, sizeof(double), s);
   if (st != FR_OK) return st;
@@ -274,7 +264,6 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
   fr_gmres_stats S{};
   double* nz = W.scal + 0;     // ||z||^2 or ||x||^2 for the JF epsilon
   double* beta2 = W.scal + 1;  // ||r||^2
-  FR_HIP(zero_counters(W.counter, s));
 
   ResArgs ra{};
   ra.U = U;
@@ -290,13 +279,13 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
   if (fell_back != nullptr) *fell_back = 0;
   if (!x_is_zero && plain_fallback) {
     double bb = 0.0;
-    FR_HIP(launch_norm2(b, n, W.partials, W.counter, beta2, nullptr, s));
+    FR_HIP(launch_norm2(b, n, W.partials, beta2, nullptr, s));
     fr_status r0 = read_sync(d, &bb, beta2, sizeof(double), s);
     if (r0 != FR_OK) return r0;
     bnorm = std::sqrt(bb);
   }
   if (!x_is_zero) {
-    FR_HIP(launch_norm2(x, n, W.partials, W.counter, nz, nullptr, s));
+    FR_HIP(launch_norm2(x, n, W.partials, nz, nullptr, s));
     ResArgs a2 = ra;
     a2.V = x;
     a2.B = b;
@@ -305,7 +294,7 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
     S.residual_evals++;
     rsrc = W.r;
   }
-  FR_HIP(launch_norm2(rsrc, n, W.partials, W.counter, beta2, nullptr, s));
+  FR_HIP(launch_norm2(rsrc, n, W.partials, beta2, nullptr, s));
   double b2 = 0.0;
   fr_status rs = read_sync(d, &b2, beta2, sizeof(double), s);
   if (rs != FR_OK) return rs;
@@ -315,7 +304,7 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
     const double* none[1];
     double zc[1];
     FR_HIP(launch_lincomb(x, 0, none, zc, n, s));
-    FR_HIP(launch_norm2(b, n, W.partials, W.counter, beta2, nullptr, s));
+    FR_HIP(launch_norm2(b, n, W.partials, beta2, nullptr, s));
     rsrc = b;
     beta = bnorm;
     if (fell_back != nullptr) *fell_back = 1;
@@ -398,14 +387,14 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
       break;
     }
     // cycle exhausted (or breakdown): true residual r = b - A x
-    FR_HIP(launch_norm2(x, n, W.partials, W.counter, nz, nullptr, s));
+    FR_HIP(launch_norm2(x, n, W.partials, nz, nullptr, s));
     ResArgs a2 = ra;
     a2.V = x;
     a2.B = b;
     a2.out = W.r;
     FR_HIP(launch_residual(d, 2, a2, s));
     S.residual_evals++;
-    FR_HIP(launch_norm2(W.r, n, W.partials, W.counter, beta2, nullptr, s));
+    FR_HIP(launch_norm2(W.r, n, W.partials, beta2, nullptr, s));
     rs = read_sync(d, &b2, beta2, sizeof(double), s);
     if (rs != FR_OK) return rs;
     beta = std::sqrt(b2);
@@ -505,7 +494,7 @@ fr_status ptc_solve(const fr_disc* d, const double* cst, double omega_dt, double
   const double iw = 1.0 / omega_dt;
   FR_TRY(lincomb(negF, {{cst, iw}, {q, -iw}, {Rq, 1.0}}, n, s));
   double nF = 0.0;
-  FR_TRY(device_norm(d, negF, B.gw.partials, B.gw.counter, B.gw.scal + 2, &nF, s));
+  FR_TRY(device_norm(d, negF, B.gw.partials, B.gw.scal + 2, &nF, s));
   const double nF0 = nF;
   double dtau = o.dtau_init > 0 ? o.dtau_init : dt;
   double dtau_max = o.dtau_max > 0 ? o.dtau_max : 1e20;
@@ -542,7 +531,7 @@ fr_status ptc_solve(const fr_disc* d, const double* cst, double omega_dt, double
     st->residual_evals++;
     FR_TRY(lincomb(negF, {{cst, iw}, {q, -iw}, {Rq, 1.0}}, n, s));
     double nFn = 0.0;
-    FR_TRY(device_norm(d, negF, B.gw.partials, B.gw.counter, B.gw.scal + 2, &nFn, s));
+    FR_TRY(device_norm(d, negF, B.gw.partials, B.gw.scal + 2, &nFn, s));
     dtau = (nFn > 0.0) ? std::min(dtau * nF / nFn, dtau_max) : dtau_max;
     nF = nFn;
     ++k;
@@ -559,7 +548,6 @@ fr_status row_step_impl(const fr_disc* d, int scheme, double dt, double* U, cons
   const size_t n = d->ndof;
   const double t0 = now_s();
   StepBufs B = carve_step(d, work, o.lin.m, o.precond_precision);
-  FR_HIP(zero_counters(B.gw.counter, s));
   double* R0 = B.vec[0];
   double* Ui = B.vec[1];
   double* rhs = B.vec[2];
@@ -660,7 +648,6 @@ fr_status esdirk_step_impl(const fr_disc* d, int scheme, double dt, double* U, c
   const size_t n = d->ndof;
   const double t0 = now_s();
   StepBufs B = carve_step(d, work, o.lin.m, o.precond_precision);
-  FR_HIP(zero_counters(B.gw.counter, s));
   double** Rj = B.vec;      // vec[0..5]
   double* q = B.vec[6];
   double* cst = B.vec[7];
@@ -709,7 +696,6 @@ fr_status bdf2_step_impl(const fr_disc* d, double dt, const double* Unm1, const 
   const size_t n = d->ndof;
   const double t0 = now_s();
   StepBufs B = carve_step(d, work, o.lin.m, o.precond_precision);
-  FR_HIP(zero_counters(B.gw.counter, s));
   double* q = B.vec[0];
   double* Rq = B.vec[1];
   double* cst = B.vec[2];
