@@ -258,14 +258,24 @@ __global__ void __launch_bounds__(256) k_ejacobi_solve(const T* __restrict__ inv
   const int tid = threadIdx.x;
   const int blk = tid / TPE, i = tid - blk * TPE;  // element of the group, row block
   // with gv: every workgroup forms ||r||^2 from the same partials in the same order,
-  // workgroup 0 also runs the Givens update of the Arnoldi step that produced r
+  // workgroup 0 also finishes the Arnoldi step that produced r (CGS2: its Givens
+  // update; DCGS2: stores ||r|| as the first-pass h_{j+1,j}, and rotates the
+  // first-pass column on breakdown or NaN)
   const bool scaled = gv.st != nullptr;
   double sc = 1.0;
   if (scaled) {
     __shared__ GivensLds GL;
     const double hn2 = block_sum_partials(gv.norm_part, gv.nb, GL.red);
     sc = 1.0 / sqrt(hn2);
-    if (blockIdx.x == 0) givens_step(gv.st, hn2, gv.M, GL);
+    if (blockIdx.x == 0) {
+      if (gv.lagged) {
+        const double hn = sqrt(hn2), w0 = gv.st->w0;
+        if (tid == 0) gv.st->hn = hn;
+        if (!(hn > 1e-14 * w0)) givens_first_pass(gv.st, hn, gv.M, GL);  // breakdown or NaN
+      } else {
+        givens_step(gv.st, hn2, gv.M, GL);
+      }
+    }
   }
   const int ngroups = (nel + EPB - 1) / EPB;
   double zz = 0.0;
@@ -410,8 +420,8 @@ static hipError_t solve_p(const fr_disc* d, const void* f, int precision, const 
                           double* r_store, double* z, double* partials, int* nparts, double* nrm2, const int* skip,
                           hipStream_t s) {
   constexpr int Nb = 4 * (P + 1) * (P + 1);
-  const GivensIn gv = gvp != nullptr ? *gvp : GivensIn{nullptr, nullptr, 0, 0};
-  if (gv.st != nullptr && (gv.nb < 1 || gv.nb > kRedThreads || gv.norm_part == nullptr)) return hipErrorInvalidValue;
+  const GivensIn gv = gvp != nullptr ? *gvp : GivensIn{nullptr, nullptr, 0, 0, 0};
+  if (gv.st != nullptr && (gv.nb < 1 || gv.nb > kRedBlocks || gv.norm_part == nullptr)) return hipErrorInvalidValue;
   double* part = (nrm2 != nullptr || nparts != nullptr) ? partials : nullptr;
   const size_t store = (size_t)d->nel * Nb * Nb * (precision == FR_F32 ? sizeof(float) : sizeof(double));
   const bool wide = P == 4 && store >= kWideSolveBytes;

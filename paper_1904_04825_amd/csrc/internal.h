@@ -145,21 +145,23 @@ struct GmState {
   int j;               // Arnoldi steps done in this cycle
   int stop;            // 1: converged / breakdown / nan -> the rest of the cycle is skipped
   int why;             // 1 converged, 2 breakdown, 3 nan
-  int pad;
+  int evals;           // JF products of the cycle that ran (counted by the DCGS2 second pass)
   struct GmStatus* hslot;  // mapped host memory receiving the status after every step
 };
 struct GmStatus {
   double rest, beta;
-  int j, stop, why, pad;
+  int j, stop, why, evals;
 };
 // V: nv vectors of n doubles stored back to back (vector i at V + i*n).
-// Partial sums of the Arnoldi step: the CGS passes use partials[0 ..) and
-// partials[kPartSecond ..) (at most kPartSecond doubles each); rows of the chunked dot
-// kernel for long restarts are kPartStride apart.
+// Partial sums of the Arnoldi step, stored value-major (value t of workgroup b at
+// t kRedBlocks + b): the CGS2 passes use partials[0 ..) and partials[kPartSecond ..)
+// (32 values each), the DCGS2 first pass partials[0 ..) (up to 64 values) and its
+// second pass partials[2 kPartSecond ..); rows of the chunked dot kernel for long
+// restarts are kPartStride apart.
 constexpr int kPartStride = kMaxM + 2;
-constexpr size_t kPartSecond = (size_t)kRedThreads * 32;
-// Workgroups of the CGS passes over n entries (<= kRedThreads), i.e. the number of partial
-// sums of ||w||^2 that the last pass leaves at partials[0 ..).
+constexpr size_t kPartSecond = (size_t)kRedBlocks * 32;
+// Workgroups of the CGS passes over n entries (<= kRedBlocks), i.e. the number of partial
+// sums of ||w||^2 that the last pass leaves.
 int cgs_blocks(size_t n);
 // One Arnoldi orthogonalisation by CGS2: h1 = V^T w, w -= V h1, h2 = V^T w,
 // w -= V h2, partial sums of ||w||^2; h1 and h2 go to st.  partials: at least
@@ -168,12 +170,25 @@ hipError_t launch_arnoldi_cgs2(const double* V, int nv, double* w, double* parti
                                hipStream_t s);
 // The Givens update of Arnoldi step st->j from the nb partial sums of ||w||^2.
 hipError_t launch_givens(GmState* st, const double* norm_part, int nb, int M, hipStream_t s);
-// The Givens update of the previous Arnoldi step, run by the preconditioner kernel that
-// starts the next step (which also scales w by the same 1/||w||).
+// DCGS2 (restarts up to 32): one Arnoldi orthogonalisation in two passes over V, the
+// re-orthogonalisation of basis vector nv-1 delayed to this step; finishes column nv-2
+// of the Hessenberg matrix.  partials: at least 2 kPartSecond + kRedBlocks doubles.
+bool dcgs2_supported(int m);
+hipError_t launch_arnoldi_dcgs2(double* V, int nv, double* w, double* partials, GmState* st, int M, size_t n,
+                                hipStream_t s);
+// Where the second pass leaves its partial sums of ||w'||^2 (cgs_blocks(n) of them).
+const double* dcgs2_norm_partials(const double* partials);
+// The cycle's last column (first pass) rotated with ||w'|| from those partials.
+hipError_t launch_dcgs2_last(GmState* st, const double* partials, int nb, int M, hipStream_t s);
+// Run by the preconditioner kernel that starts the next Arnoldi step, which scales w by
+// 1/||w|| (||w||^2 from norm_part): CGS2: the Givens update of the previous step;
+// DCGS2 (lagged): ||w|| stored as the first-pass h_{j+1,j}, and on breakdown or NaN
+// the first-pass column rotated as it stands.
 struct GivensIn {
   GmState* st;
-  const double* norm_part;  // nb <= kRedThreads partial sums of ||w||^2
+  const double* norm_part;  // nb <= kRedBlocks partial sums of ||w||^2
   int nb, M;
+  int lagged;
 };
 hipError_t launch_gm_init(GmState* st, const double* beta2, double target, int M, GmStatus* hslot, hipStream_t s);
 // Sum partials[b*stride + i] over b < nblocks into out[i], i < nv (one workgroup).

@@ -322,6 +322,9 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
     return FR_OK;
   }
   // mapped host status written by the Givens kernel after every Arnoldi step
+  // orthogonalisation: DCGS2 (two passes over V per step, the Hessenberg column final
+  // one step later) up to m = 32, CGS2 beyond
+  const bool dcgs = dcgs2_supported(m);
   volatile GmStatus* hstat = (volatile GmStatus*)d->h_pinned;
   GmStatus* dstat = (GmStatus*)d->d_pinned;
   const size_t status_off = offsetof(GmState, rest);
@@ -344,7 +347,8 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
       if (j == 0) {
         FR_HIP(launch_ejacobi_solve(d, factors, prec, vj, nullptr, nullptr, zj, zpart, &np, nullptr, skip, s));
       } else {
-        const GivensIn gv{W.st, W.partials, cgs_blocks(n), m};  // step j - 1's Givens update, then v_j = w / ||w||
+        // finish step j - 1, then v_j = w / ||w||
+        const GivensIn gv{W.st, dcgs ? dcgs2_norm_partials(W.partials) : W.partials, cgs_blocks(n), m, dcgs ? 1 : 0};
         FR_HIP(launch_ejacobi_solve(d, factors, prec, W.w, &gv, vj, zj, zpart, &np, nullptr, skip, s));
       }
       ResArgs a1 = ra;
@@ -354,7 +358,10 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
       a1.out = W.w;
       a1.skip = skip;
       FR_HIP(launch_residual(d, 1, a1, s));
-      FR_HIP(launch_arnoldi_cgs2(W.V, j + 1, W.w, W.partials, W.st, m, n, s));
+      if (dcgs)
+        FR_HIP(launch_arnoldi_dcgs2(W.V, j + 1, W.w, W.partials, W.st, m, n, s));
+      else
+        FR_HIP(launch_arnoldi_cgs2(W.V, j + 1, W.w, W.partials, W.st, m, n, s));
       FR_HIP(hipEventRecord(d->ev[j & 1], s));
       // wait for step j-1 while step j runs; its status reflects the Givens update of
       // step j-2 (kernels enqueued after a stop return at once)
@@ -363,15 +370,21 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
         if (hstat->stop) break;
       }
     }
-    // the Givens update of the cycle's last step (returns at once after a stop)
-    if (budget > 0) FR_HIP(launch_givens(W.st, W.partials, cgs_blocks(n), m, s));
+    // the Givens update of the cycle's last column (returns at once after a stop)
+    if (budget > 0) {
+      if (dcgs)
+        FR_HIP(launch_dcgs2_last(W.st, W.partials, cgs_blocks(n), m, s));
+      else
+        FR_HIP(launch_givens(W.st, W.partials, cgs_blocks(n), m, s));
+    }
     FR_HIP(hipStreamSynchronize(s));
     GmStatus fin;
     rs = read_sync(d, &fin, (const char*)W.st + status_off, sizeof(GmStatus), s);
     if (rs != FR_OK) return rs;
     const int k = fin.j;
     S.iters += k;
-    S.residual_evals += k;
+    // DCGS2 finds convergence one step late: the JF product of that step also ran
+    S.residual_evals += dcgs ? std::max(k, fin.evals) : k;
     S.r_final = fin.rest;
     if (fin.why == 3) {
       result = FR_ENAN;

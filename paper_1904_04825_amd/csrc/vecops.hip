@@ -132,11 +132,12 @@ hipError_t launch_scale_dev(double* y, const double* x, const double* alpha, int
 #endif
 // Workgroups of the CGS passes: at least FRJF_CGS_EPT entries per thread, so the
 // partial sums of a workgroup cover enough of the vectors to pay for its reduction,
-// and at most kRedThreads, so a workgroup of the next pass adds all of them with one
-// load per thread and value.
+// and at most kRedBlocks (four waves per SIMD keep enough loads in flight on long
+// vectors); every workgroup of the next pass adds all of them, with one load per
+// thread and value up to kRedThreads workgroups.
 int cgs_blocks(size_t n) {
   const size_t per = (size_t)kRedThreads * FRJF_CGS_EPT;
-  return (int)std::max<size_t>(1, std::min<size_t>((n + per - 1) / per, kRedThreads));
+  return (int)std::max<size_t>(1, std::min<size_t>((n + per - 1) / per, kRedBlocks));
 }
 
 // dots: partials[b*kPartStride + t] = block b's share of <w, V_t>, t < nv; grid.y splits the
@@ -186,7 +187,7 @@ __global__ void __launch_bounds__(256) k_cgs_update(const double* __restrict__ V
 }
 
 // Fused CGS pass over V_0 .. V_{nv-1}, each read once, one partial sum per value and
-// workgroup, stored at partials[t kRedThreads + b] (value t, workgroup b):
+// workgroup, stored at partials[t kRedBlocks + b] (value t, workgroup b):
 //   h = the sums over b < hnb of the previous pass's partials hpart, when hpart is
 //       given; every workgroup adds them in the same order, workgroup 0 stores h to
 //       hout;
@@ -195,7 +196,7 @@ __global__ void __launch_bounds__(256) k_cgs_update(const double* __restrict__ V
 // NV >= nv is a multiple of 4 and every slot loads unconditionally, so the loads of
 // an entry are issued together: the slots t >= nv re-read V_{nv-1} with weight 0,
 // and their sums are dropped.  The first entry's loads are in flight while h is
-// summed.  Requires hnb <= kRedThreads.
+// summed.  Requires hnb <= kRedBlocks.
 template <int NV, bool DOTS>
 __global__ void __launch_bounds__(kRedThreads) k_cgs_pass(const double* __restrict__ V, int nv, double* __restrict__ w,
                                                           const double* __restrict__ hpart, int hnb, double* hout,
@@ -217,7 +218,11 @@ __global__ void __launch_bounds__(kRedThreads) k_cgs_pass(const double* __restri
   if (hpart != nullptr) {
     double hr[NV];
 #pragma unroll
-    for (int t = 0; t < NV; ++t) hr[t] = (tid < hnb) ? hpart[(size_t)min(t, nv - 1) * kRedThreads + tid] : 0.0;
+    for (int t = 0; t < NV; ++t) hr[t] = (tid < hnb) ? hpart[(size_t)min(t, nv - 1) * kRedBlocks + tid] : 0.0;
+    for (int b = tid + kRedThreads; b < hnb; b += kRedThreads) {
+#pragma unroll
+      for (int t = 0; t < NV; ++t) hr[t] += hpart[(size_t)min(t, nv - 1) * kRedBlocks + b];
+    }
     int off;
     if (wave_multi_sum<NV>(hr, off)) {
 #pragma unroll
@@ -261,7 +266,7 @@ __global__ void __launch_bounds__(kRedThreads) k_cgs_pass(const double* __restri
     double r = 0.0;
 #pragma unroll
     for (int q = 0; q < kRedThreads / 64; ++q) r += red[q][tid];
-    partials[(size_t)tid * kRedThreads + blockIdx.x] = r;
+    partials[(size_t)tid * kRedBlocks + blockIdx.x] = r;
   }
 }
 
@@ -348,6 +353,215 @@ hipError_t launch_arnoldi_cgs2(const double* V, int nv, double* w, double* parti
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- DCGS2 Arnoldi step
+// Classical Gram-Schmidt with the re-orthogonalisation of each basis vector delayed
+// to the next step, so both projections share the reads of V: at step j, V_0 ..
+// V_{j-1} are final and V_j = ~v_j is the new vector, orthogonalised once and of unit
+// norm; w = A z_j.
+//   pass 1, one read of V and w:  b_t = <V_t, w> (t <= j), a_t = <V_t, ~v_j> (t < j),
+//     <w, w>;
+//   pass 2, every workgroup adds pass 1's partials, alpha = sqrt(1 - |a|^2) (Pythagoras:
+//     ~v_j - V a is orthogonal to V_0 .. V_{j-1}), c_j = (b_j - a.b) / alpha, and for
+//     every entry: v_j = (~v_j - sum_{t<j} a_t V_t) / alpha (stored over ~v_j),
+//     w' = w - sum_{t<j} b_t V_t - c_j v_j, partial sums of ||w'||^2.  Workgroup 0
+//     makes column j-1 final (h_{t,j-1} += h_{j,j-1} a_t, h_{j,j-1} *= alpha: the
+//     correction of ~v_j expressed in the final basis), rotates it, and stores column
+//     j's first pass (b_t, c_j) and ||w||.
+// The next step's preconditioner kernel forms ~v_{j+1} = w' / ||w'||.
+// Offset of pass 2's partial sums of ||w'||^2 (pass 1 fills 2 NV <= 64 rows first).
+constexpr size_t kDcgsNormOff = 2 * kPartSecond;
+
+template <int NV>
+__global__ void __launch_bounds__(kRedThreads) k_dcgs_dots(const double* __restrict__ V, int nv,
+                                                           const double* __restrict__ w, double* __restrict__ partials,
+                                                           const int* skip, size_t n) {
+  if (*skip) return;
+  constexpr int NA = 2 * NV;  // b_t at t, a_t at NV + t (t < NV - 1), <w, w> at 2 NV - 1
+  __shared__ double red[kRedThreads / 64][NA];
+  const int tid = threadIdx.x, wv = tid >> 6;
+  const double* vj = V + (size_t)(nv - 1) * n;
+  double acc[NA];
+#pragma unroll
+  for (int t = 0; t < NA; ++t) acc[t] = 0.0;
+  for (size_t i = blockIdx.x * (size_t)kRedThreads + tid; i < n; i += (size_t)gridDim.x * kRedThreads) {
+    double vr[NV];
+#pragma unroll
+    for (int t = 0; t < NV; ++t) vr[t] = V[(size_t)min(t, nv - 1) * n + i];
+    const double wi = w[i], vji = vj[i];
+#pragma unroll
+    for (int t = 0; t < NV; ++t) acc[t] = fma(vr[t], wi, acc[t]);
+#pragma unroll
+    for (int t = 0; t + 1 < NV; ++t) acc[NV + t] = fma(vr[t], vji, acc[NV + t]);
+    acc[NA - 1] = fma(wi, wi, acc[NA - 1]);
+  }
+  int off;
+  if (wave_multi_sum<NA>(acc, off)) {
+#pragma unroll
+    for (int t = 0; t < multi_sum_count(NA); ++t) red[wv][off + t] = acc[t];
+  }
+  __syncthreads();
+  if (tid < NA) {
+    double r = 0.0;
+#pragma unroll
+    for (int q = 0; q < kRedThreads / 64; ++q) r += red[q][tid];
+    partials[(size_t)tid * kRedBlocks + blockIdx.x] = r;
+  }
+}
+
+template <int NV>
+__global__ void __launch_bounds__(kRedThreads) k_dcgs_update(double* __restrict__ V, int nv, double* __restrict__ w,
+                                                             const double* __restrict__ part1, int nb,
+                                                             double* __restrict__ normpart, GmState* st, int M,
+                                                             size_t n) {
+  if (st->stop) return;
+  constexpr int NA = 2 * NV;
+  __shared__ double red[kRedThreads / 64][NA];
+  __shared__ double val[NA];
+  __shared__ double sa[NV], sb[NV], sc[3];
+  __shared__ GivensLds L;
+  const int tid = threadIdx.x, wv = tid >> 6;
+  const int j = nv - 1;
+  double* vj = V + (size_t)j * n;
+  const size_t stride = (size_t)gridDim.x * kRedThreads;
+  size_t i = blockIdx.x * (size_t)kRedThreads + tid;
+  double vr[NV], wi = 0.0, vji = 0.0;
+  auto load = [&](size_t k) {
+#pragma unroll
+    for (int t = 0; t < NV; ++t) vr[t] = V[(size_t)min(t, nv - 1) * n + k];
+    wi = w[k];
+    vji = vj[k];
+  };
+  if (i < n) load(i);
+  // pass 1's sums, the same in every workgroup
+  {
+    double hr[NA];
+#pragma unroll
+    for (int t = 0; t < NA; ++t) hr[t] = (tid < nb) ? part1[(size_t)t * kRedBlocks + tid] : 0.0;
+    for (int b = tid + kRedThreads; b < nb; b += kRedThreads) {
+#pragma unroll
+      for (int t = 0; t < NA; ++t) hr[t] += part1[(size_t)t * kRedBlocks + b];
+    }
+    int off;
+    if (wave_multi_sum<NA>(hr, off)) {
+#pragma unroll
+      for (int t = 0; t < multi_sum_count(NA); ++t) red[wv][off + t] = hr[t];
+    }
+    __syncthreads();
+    if (tid < NA) {
+      double r = 0.0;
+#pragma unroll
+      for (int q = 0; q < kRedThreads / 64; ++q) r += red[q][tid];
+      val[tid] = r;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double aa = 0.0, ab = 0.0;
+    for (int t = 0; t < j; ++t) {
+      aa = fma(val[NV + t], val[NV + t], aa);
+      ab = fma(val[NV + t], val[t], ab);
+    }
+    const double alpha2 = 1.0 - aa;
+    const double alpha = alpha2 > 0.0 ? sqrt(alpha2) : 0.0;  // 0: ~v_j in the span of V (breakdown)
+    sc[0] = alpha;
+    sc[1] = alpha > 0.0 ? 1.0 / alpha : 0.0;
+    sc[2] = alpha > 0.0 ? (val[j] - ab) / alpha : 0.0;
+  }
+  if (tid < NV) {
+    sa[tid] = tid < j ? val[NV + tid] : 0.0;
+    sb[tid] = tid < j ? val[tid] : 0.0;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    if (j >= 1) {
+      const double hn = st->hn;  // first-pass h_{j,j-1} = ||w'|| of step j-1
+      if (tid < j) L.col[tid] = st->h1[tid] + hn * sa[tid];
+      if (tid == 0) L.col[j] = hn * sc[0];
+      load_rotations(st, j - 1, L);
+      __syncthreads();
+      if (tid == 0) givens_rotate(st, j - 1, L.col, L.cs, L.sn, st->w0);
+      __syncthreads();
+      store_column(st, j - 1, M, L);
+      __syncthreads();
+    }
+    if (tid < j) st->h1[tid] = val[tid];
+    if (tid == 0) {
+      st->h1[j] = sc[2];
+      st->w0 = sqrt(val[NA - 1]);
+      st->evals = j + 1;  // this step's JF product ran
+    }
+  }
+  const double ia = sc[1], cj = sc[2];
+  double acc = 0.0;
+  for (; i < n; i += stride) {
+    double s = vji;
+#pragma unroll
+    for (int t = 0; t < NV; ++t) s = fma(-sa[t], vr[t], s);
+    const double vn = s * ia;
+    if (j >= 1) vj[i] = vn;
+    double u = wi;
+#pragma unroll
+    for (int t = 0; t < NV; ++t) u = fma(-sb[t], vr[t], u);
+    u = fma(-cj, vn, u);
+    w[i] = u;
+    acc = fma(u, u, acc);
+    if (i + stride < n) load(i + stride);
+  }
+  acc = wave_sum(acc);
+  if ((tid & 63) == 0) red[wv][0] = acc;
+  __syncthreads();
+  if (tid == 0) {
+    double r = 0.0;
+#pragma unroll
+    for (int q = 0; q < kRedThreads / 64; ++q) r += red[q][0];
+    normpart[blockIdx.x] = r;
+  }
+}
+
+// The cycle's last column, first pass as it stands, with ||w'|| from the last pass 2.
+__global__ void __launch_bounds__(kRedThreads) k_dcgs_last(GmState* st, const double* __restrict__ normpart, int nb,
+                                                           int M) {
+  if (st->stop) return;
+  __shared__ GivensLds L;
+  const double hn2 = block_sum_partials(normpart, nb, L.red);
+  givens_first_pass(st, sqrt(hn2), M, L);
+}
+
+bool dcgs2_supported(int m) { return m <= 32; }
+
+hipError_t launch_arnoldi_dcgs2(double* V, int nv, double* w, double* partials, GmState* st, int M, size_t n,
+                                hipStream_t s) {
+  const int nb = cgs_blocks(n);
+  double* np = partials + kDcgsNormOff;
+  const dim3 g(nb), b(kRedThreads);
+#define FRJF_DCGS_CASE(K, NVV)                                                                                      \
+  case K:                                                                                                           \
+    hipLaunchKernelGGL((k_dcgs_dots<NVV>), g, b, 0, s, V, nv, w, partials, &st->stop, n);                          \
+    hipLaunchKernelGGL((k_dcgs_update<NVV>), g, b, 0, s, V, nv, w, partials, nb, np, st, M, n);                    \
+    break;
+  switch ((nv + 3) / 4) {
+    FRJF_DCGS_CASE(1, 4)
+    FRJF_DCGS_CASE(2, 8)
+    FRJF_DCGS_CASE(3, 12)
+    FRJF_DCGS_CASE(4, 16)
+    FRJF_DCGS_CASE(5, 20)
+    FRJF_DCGS_CASE(6, 24)
+    FRJF_DCGS_CASE(7, 28)
+    FRJF_DCGS_CASE(8, 32)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef FRJF_DCGS_CASE
+  return hipGetLastError();
+}
+
+const double* dcgs2_norm_partials(const double* partials) { return partials + kDcgsNormOff; }
+
+hipError_t launch_dcgs2_last(GmState* st, const double* partials, int nb, int M, hipStream_t s) {
+  hipLaunchKernelGGL(k_dcgs_last, dim3(1), dim3(kRedThreads), 0, s, st, partials + kDcgsNormOff, nb, M);
+  return hipGetLastError();
+}
+
 __global__ void k_gm_init(GmState* st, const double* beta2, double target, int M, GmStatus* hslot) {
   if (threadIdx.x != 0) return;
   st->hslot = hslot;
@@ -359,6 +573,7 @@ __global__ void k_gm_init(GmState* st, const double* beta2, double target, int M
   st->j = 0;
   st->stop = 0;
   st->why = 0;
+  st->evals = 0;
   st->rest = beta;
 }
 
