@@ -583,13 +583,22 @@ hipError_t launch_gm_init(GmState* st, const double* beta2, double target, int M
 }
 
 // y = H(0:k,0:k)^{-1} g(0:k) by back substitution (upper triangular after the rotations)
-__global__ void k_gm_solve_y(GmState* st, int k, int M) {
-  if (threadIdx.x != 0) return;
+// One wavefront: the triangle staged in LDS ([column][row]), lane i holds the right-hand
+// side of row i; column c's y_c = r_c / R_cc is broadcast and removed from the rows
+// above it in one step.
+__global__ void __launch_bounds__(64) k_gm_solve_y(GmState* st, int k, int M) {
+  __shared__ double R[kMaxM][kMaxM + 1];
+  const int lane = threadIdx.x;
   const int ld = M + 1;
-  for (int i = k - 1; i >= 0; --i) {
-    double s = st->g[i];
-    for (int c = i + 1; c < k; ++c) s -= st->H[(size_t)c * ld + i] * st->y[c];
-    st->y[i] = s / st->H[(size_t)i * ld + i];
+  for (int c = 0; c < k; ++c)
+    if (lane <= c) R[c][lane] = st->H[(size_t)c * ld + lane];
+  double r = lane < k ? st->g[lane] : 0.0;
+  __syncthreads();
+  for (int c = k - 1; c >= 0; --c) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(r), c), hi = __builtin_amdgcn_readlane(__double2hiint(r), c);
+    const double yc = __hiloint2double(hi, lo) / R[c][c];
+    if (lane == c) st->y[c] = yc;
+    if (lane < c) r = fma(-R[c][lane], yc, r);
   }
 }
 
@@ -598,20 +607,41 @@ hipError_t launch_gm_solve_y(GmState* st, int k, int M, hipStream_t s) {
   return hipGetLastError();
 }
 
+// x += sum_t y_t Z_t.  NV > 0: the k <= NV columns of an entry loaded together into
+// registers (slots t >= k re-read column k-1 with weight 0); NV = 0: a plain loop.
+template <int NV>
 __global__ void __launch_bounds__(256) k_gm_update_x(double* __restrict__ x, const double* __restrict__ Z, int k,
                                                      const GmState* st, size_t n) {
   __shared__ double sy[kMaxM];
-  if (threadIdx.x < k) sy[threadIdx.x] = st->y[threadIdx.x];
+  if (threadIdx.x < kMaxM) sy[threadIdx.x] = (int)threadIdx.x < k ? st->y[threadIdx.x] : 0.0;
   __syncthreads();
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     double s = x[i];
-    for (int t = 0; t < k; ++t) s = fma(sy[t], Z[(size_t)t * n + i], s);
+    if constexpr (NV > 0) {
+      double zr[NV];
+#pragma unroll
+      for (int t = 0; t < NV; ++t) zr[t] = Z[(size_t)min(t, k - 1) * n + i];
+#pragma unroll
+      for (int t = 0; t < NV; ++t) s = fma(sy[t], zr[t], s);
+    } else {
+      for (int t = 0; t < k; ++t) s = fma(sy[t], Z[(size_t)t * n + i], s);
+    }
     x[i] = s;
   }
 }
 
 hipError_t launch_gm_update_x(double* x, const double* Z, int k, const GmState* st, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_update_x, dim3(red_blocks(n)), dim3(256), 0, s, x, Z, k, st, n);
+  const dim3 g(red_blocks(n)), b(256);
+  if (k <= 8)
+    hipLaunchKernelGGL((k_gm_update_x<8>), g, b, 0, s, x, Z, k, st, n);
+  else if (k <= 16)
+    hipLaunchKernelGGL((k_gm_update_x<16>), g, b, 0, s, x, Z, k, st, n);
+  else if (k <= 24)
+    hipLaunchKernelGGL((k_gm_update_x<24>), g, b, 0, s, x, Z, k, st, n);
+  else if (k <= 32)
+    hipLaunchKernelGGL((k_gm_update_x<32>), g, b, 0, s, x, Z, k, st, n);
+  else
+    hipLaunchKernelGGL((k_gm_update_x<0>), g, b, 0, s, x, Z, k, st, n);
   return hipGetLastError();
 }
 

@@ -12,7 +12,9 @@ from tests.gpu_common import rel, setup, to_gpu, to_np, vortex_state
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("P,m", [(2, 20), (3, 8)])
+# m <= 32: DCGS2 orthogonalisation on the GPU; m = 40: CGS2 (register-held passes up to
+# 32 vectors, the chunked dot kernels beyond)
+@pytest.mark.parametrize("P,m", [(2, 20), (3, 8), (2, 32), (2, 40)])
 def test_gmres_parity(P, m):
     from paper_1904_04825_amd import F64, GmresOpts
     _, op, disc = setup(9, 7, P, "roe", seed=12)
@@ -51,7 +53,7 @@ def test_gmres_nonzero_initial_guess_and_restart():
         print(m, "oracle", so, "gpu", sg, flush=True)
         assert so.converged == conv and bool(sg["converged"]) == conv
         assert sg["status"] == (0 if conv else 1)
-        # restarted cycles diverge slowly (CGS2 vs MGS rounding, FD product): counts agree within 25 %
+        # restarted cycles diverge slowly (DCGS2 vs MGS rounding, FD product): counts agree within 25 %
         assert abs(sg["iters"] - so.iters) <= 0.25 * so.iters
         if conv:
             assert sg["restarts"] >= 1 and rel(to_np(xg), xo) <= 1e-7
