@@ -65,9 +65,11 @@ __device__ __forceinline__ void givens_rotate(GmState* st, int k, double* col, c
   if (!(rest == rest) || !(den == den) || isinf(rest) || den == 0.0) {
     st->stop = 1;
     st->why = 3;
+    st->done = 1;
   } else if (rest <= st->target) {
     st->stop = 1;
     st->why = 1;
+    st->done = 1;
   } else if (!(hn > 1e-14 * w0)) {
     st->stop = 1;
     st->why = 2;

@@ -146,6 +146,7 @@ struct GmState {
   int stop;            // 1: converged / breakdown / nan -> the rest of the cycle is skipped
   int why;             // 1 converged, 2 breakdown, 3 nan
   int evals;           // JF products of the cycle that ran (counted by the DCGS2 second pass)
+  int done;            // converged or NaN: the cycle's closing kernels for a restart return at once
   struct GmStatus* hslot;  // mapped host memory receiving the status after every step
 };
 struct GmStatus {
@@ -196,8 +197,10 @@ hipError_t launch_finalize(const double* partials, int nblocks, int stride, int 
                            hipStream_t s);
 // Number of workgroups of the grid-stride reductions over n entries (<= kRedBlocks).
 int red_blocks(size_t n);
-hipError_t launch_gm_solve_y(GmState* st, int k, int M, hipStream_t s);
-hipError_t launch_gm_update_x(double* x, const double* Z, int k, const GmState* st, size_t n,
+// y from the rotated Hessenberg matrix and x += Z y for the st->j columns of the cycle
+// (both return at once after NaN); M bounds st->j.
+hipError_t launch_gm_solve_y(GmState* st, int M, hipStream_t s);
+hipError_t launch_gm_update_x(double* x, const double* Z, int M, const GmState* st, size_t n,
                               hipStream_t s);
 
 // learned warm start (mlp.hip)

@@ -244,6 +244,18 @@ static fr_status read_sync(const fr_disc* d, void* dst, const void* dev, size_t 
   return FR_OK;
 }
 
+// The Arnoldi status block and ||r||^2 from the device in one round trip.
+static fr_status read_status(const fr_disc* d, GmStatus* fin, const void* dev_status, double* b2, const double* dev_b2,
+                             hipStream_t s) {
+  char* slot = (char*)d->h_pinned + 1024;
+  FR_HIP(hipMemcpyAsync(slot, dev_status, sizeof(GmStatus), hipMemcpyDeviceToHost, s));
+  FR_HIP(hipMemcpyAsync(slot + 64, dev_b2, sizeof(double), hipMemcpyDeviceToHost, s));
+  FR_HIP(hipStreamSynchronize(s));
+  std::memcpy(fin, slot, sizeof(GmStatus));
+  std::memcpy(b2, slot + 64, sizeof(double));
+  return FR_OK;
+}
+
 fr_status device_norm(const fr_disc* d, const double* x, double* partials, double* dev_out,
                       double* host_out, hipStream_t s) {
   FR_HIP(launch_norm2(x, d->ndof, partials, dev_out, nullptr, s));
@@ -377,9 +389,22 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
       else
         FR_HIP(launch_givens(W.st, W.partials, cgs_blocks(n), m, s));
     }
-    FR_HIP(hipStreamSynchronize(s));
+    // the cycle's end is enqueued without waiting for its status: y and x += Z y
+    // (skipped after NaN), then the true residual r = b - A x for a restart (skipped
+    // once converged or NaN); one host round trip reads the status and ||r||^2
+    FR_HIP(launch_gm_solve_y(W.st, m, s));
+    FR_HIP(launch_gm_update_x(x, W.Z, m, W.st, n, s));
+    const int* done = &W.st->done;
+    FR_HIP(launch_norm2(x, n, W.partials, nz, done, s));
+    ResArgs a2 = ra;
+    a2.V = x;
+    a2.B = b;
+    a2.out = W.r;
+    a2.skip = done;
+    FR_HIP(launch_residual(d, 2, a2, s));
+    FR_HIP(launch_norm2(W.r, n, W.partials, beta2, done, s));
     GmStatus fin;
-    rs = read_sync(d, &fin, (const char*)W.st + status_off, sizeof(GmStatus), s);
+    rs = read_status(d, &fin, (const char*)W.st + status_off, &b2, beta2, s);
     if (rs != FR_OK) return rs;
     const int k = fin.j;
     S.iters += k;
@@ -390,26 +415,12 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
       result = FR_ENAN;
       break;
     }
-    if (k > 0) {
-      FR_HIP(launch_gm_solve_y(W.st, k, m, s));
-      FR_HIP(launch_gm_update_x(x, W.Z, k, W.st, n, s));
-    }
     if (fin.why == 1) {
       S.converged = 1;
       result = FR_OK;
       break;
     }
-    // cycle exhausted (or breakdown): true residual r = b - A x
-    FR_HIP(launch_norm2(x, n, W.partials, nz, nullptr, s));
-    ResArgs a2 = ra;
-    a2.V = x;
-    a2.B = b;
-    a2.out = W.r;
-    FR_HIP(launch_residual(d, 2, a2, s));
-    S.residual_evals++;
-    FR_HIP(launch_norm2(W.r, n, W.partials, beta2, nullptr, s));
-    rs = read_sync(d, &b2, beta2, sizeof(double), s);
-    if (rs != FR_OK) return rs;
+    S.residual_evals++;  // the restart's true residual
     beta = std::sqrt(b2);
     S.r_final = beta;
     rsrc = W.r;

@@ -574,6 +574,7 @@ __global__ void k_gm_init(GmState* st, const double* beta2, double target, int M
   st->stop = 0;
   st->why = 0;
   st->evals = 0;
+  st->done = 0;
   st->rest = beta;
 }
 
@@ -586,8 +587,10 @@ hipError_t launch_gm_init(GmState* st, const double* beta2, double target, int M
 // One wavefront: the triangle staged in LDS ([column][row]), lane i holds the right-hand
 // side of row i; column c's y_c = r_c / R_cc is broadcast and removed from the rows
 // above it in one step.
-__global__ void __launch_bounds__(64) k_gm_solve_y(GmState* st, int k, int M) {
+__global__ void __launch_bounds__(64) k_gm_solve_y(GmState* st, int M) {
   __shared__ double R[kMaxM][kMaxM + 1];
+  const int k = st->j;
+  if (st->why == 3 || k <= 0) return;
   const int lane = threadIdx.x;
   const int ld = M + 1;
   for (int c = 0; c < k; ++c)
@@ -602,16 +605,19 @@ __global__ void __launch_bounds__(64) k_gm_solve_y(GmState* st, int k, int M) {
   }
 }
 
-hipError_t launch_gm_solve_y(GmState* st, int k, int M, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_solve_y, dim3(1), dim3(64), 0, s, st, k, M);
+hipError_t launch_gm_solve_y(GmState* st, int M, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_solve_y, dim3(1), dim3(64), 0, s, st, M);
   return hipGetLastError();
 }
 
-// x += sum_t y_t Z_t.  NV > 0: the k <= NV columns of an entry loaded together into
-// registers (slots t >= k re-read column k-1 with weight 0); NV = 0: a plain loop.
+// x += sum_t y_t Z_t, k = st->j.  NV > 0: the k <= NV columns of an entry loaded
+// together into registers (slots t >= k re-read column k-1 with weight 0); NV = 0: a
+// plain loop.
 template <int NV>
-__global__ void __launch_bounds__(256) k_gm_update_x(double* __restrict__ x, const double* __restrict__ Z, int k,
+__global__ void __launch_bounds__(256) k_gm_update_x(double* __restrict__ x, const double* __restrict__ Z,
                                                      const GmState* st, size_t n) {
+  const int k = st->j;
+  if (st->why == 3 || k <= 0) return;
   __shared__ double sy[kMaxM];
   if (threadIdx.x < kMaxM) sy[threadIdx.x] = (int)threadIdx.x < k ? st->y[threadIdx.x] : 0.0;
   __syncthreads();
@@ -630,18 +636,18 @@ __global__ void __launch_bounds__(256) k_gm_update_x(double* __restrict__ x, con
   }
 }
 
-hipError_t launch_gm_update_x(double* x, const double* Z, int k, const GmState* st, size_t n, hipStream_t s) {
+hipError_t launch_gm_update_x(double* x, const double* Z, int M, const GmState* st, size_t n, hipStream_t s) {
   const dim3 g(red_blocks(n)), b(256);
-  if (k <= 8)
-    hipLaunchKernelGGL((k_gm_update_x<8>), g, b, 0, s, x, Z, k, st, n);
-  else if (k <= 16)
-    hipLaunchKernelGGL((k_gm_update_x<16>), g, b, 0, s, x, Z, k, st, n);
-  else if (k <= 24)
-    hipLaunchKernelGGL((k_gm_update_x<24>), g, b, 0, s, x, Z, k, st, n);
-  else if (k <= 32)
-    hipLaunchKernelGGL((k_gm_update_x<32>), g, b, 0, s, x, Z, k, st, n);
+  if (M <= 8)
+    hipLaunchKernelGGL((k_gm_update_x<8>), g, b, 0, s, x, Z, st, n);
+  else if (M <= 16)
+    hipLaunchKernelGGL((k_gm_update_x<16>), g, b, 0, s, x, Z, st, n);
+  else if (M <= 24)
+    hipLaunchKernelGGL((k_gm_update_x<24>), g, b, 0, s, x, Z, st, n);
+  else if (M <= 32)
+    hipLaunchKernelGGL((k_gm_update_x<32>), g, b, 0, s, x, Z, st, n);
   else
-    hipLaunchKernelGGL((k_gm_update_x<0>), g, b, 0, s, x, Z, k, st, n);
+    hipLaunchKernelGGL((k_gm_update_x<0>), g, b, 0, s, x, Z, st, n);
   return hipGetLastError();
 }
 
