@@ -57,6 +57,10 @@ def parse():
     ap.add_argument("--no-schemes", action="store_true", help="skip the ESDIRK3 and BDF2 legs")
     ap.add_argument("--allow-unconverged", action="store_true",
                     help="count GMRES solves that reach the iteration cap instead of stopping")
+    ap.add_argument("--order-study", action="store_true",
+                    help="instead of the bench line: ROW3, ESDIRK3 and BDF2 over t in [0, 10] at dt 0.2, 0.1, 0.05 "
+                         "on the 64x64 P3 vortex; errors against the exact vortex and against a ROW4 run at "
+                         "dt 0.0125, observed orders, wall seconds per unit time")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy (counter calibration for rocprofv3 --pmc runs)")
     return ap.parse_args()
@@ -87,7 +91,7 @@ def time_kernel(fn, reps=50, warm=5):
 
 def cpu_baseline(nodes, U0, dt, p, scheme):
     """The FP64 oracle on the host: R(U), the element-Jacobi blocks at q^n and the
-    first 30 FGMRES iterations of the first ROW stage of the same workload (one thread)."""
+    first 60 FGMRES iterations of the first ROW stage of the same workload (one thread)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import integrators as I
@@ -102,7 +106,7 @@ def cpu_baseline(nodes, U0, dt, p, scheme):
         shift = 1.0 / (ROW[f"ROW{scheme}"].gamma * dt)
         pc = linear.ElementJacobi(op, U0, shift)
         x, st = linear.fgmres(lambda v: linear.jf_matvec(R, U0, R0, v, shift), pc.apply, R0, m=20, rtol=1e-8,
-                              max_iters=30)
+                              max_iters=60)
         wall = time.perf_counter() - t0
     evals = R.count
     return {"value": op.ndof * evals / wall, "unit": "DOF-residuals/s", "cores": 1, "kind": "oracle",
@@ -157,6 +161,73 @@ def kernel_block(disc, Ustart, dt, scheme, ndof, workload):
                        "alg_bytes_per_launch": kernels[dom]["alg_bytes"]}
 
     return out["extra"]["kernels"], out["roofline"]
+
+
+def order_study(disc, U0, vortex):
+    """Temporal order of ROW3, ESDIRK3 (PTC) and BDF2 (BDF1 start) on one mesh: every run
+    goes from t = 0 to 10 (one period of the vortex), FP64 element-Jacobi.  E_exact is the
+    rho L2 error against the exact vortex (it carries the spatial error); E_time is the rms
+    rho difference to a ROW4 run at dt = 0.0125, i.e. the temporal error of the same
+    spatial discretisation; the observed order is log2 of the ratio of E_time at dt and dt/2."""
+    import math
+
+    import torch
+
+    from paper_1904_04825_amd import GmresOpts, SolverOpts
+    T = 10.0
+    lin = GmresOpts(m=20, rtol=1e-8)
+    sopts = SolverOpts(lin=GmresOpts(m=20, rtol=1e-1), tol_nl=1e-8)
+
+    def run(kind, dt):
+        n = int(round(T / dt))
+        tot = {"gmres_iters": 0, "ptc_iters": 0, "rejections": 0, "residual_evals": 0}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if kind.startswith("ROW"):
+            U = U0.clone()
+            for _ in range(n):
+                st = disc.row_step(U, int(kind[3]), dt, SolverOpts(lin=lin))
+                if st["status"] != 0:
+                    raise RuntimeError(f"row_step status {st['status']}")
+                tot["gmres_iters"] += st["gmres_iters"]
+                tot["residual_evals"] += st["residual_evals"]
+        elif kind == "ESDIRK3":
+            U = U0.clone()
+            for _ in range(n):
+                st = disc.esdirk_step(U, 3, dt, sopts)
+                if st["status"] != 0:
+                    raise RuntimeError(f"esdirk_step status {st['status']}")
+                for k in tot:
+                    tot[k] += st[k]
+        else:
+            Unm1, U = None, U0.clone()
+            for _ in range(n):
+                Unp1, st = disc.bdf2_step(Unm1, U, dt, sopts)
+                if st["status"] != 0:
+                    raise RuntimeError(f"bdf2_step status {st['status']}")
+                for k in tot:
+                    tot[k] += st[k]
+                Unm1, U = U, Unp1
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        rec = {"dt": dt, "steps": n, "wall_s_per_time_unit": wall / T, "l2_err_rho_exact":
+               disc.l2_error_vortex(U, 0, T, vortex), **{k: v / n for k, v in tot.items() if k != "rejections"},
+               "rejections": tot["rejections"]}
+        print(f"# {kind} dt={dt}: {n} steps in {wall:.1f} s", flush=True)
+        return U, rec
+
+    Uref, ref = run("ROW4", 0.0125)
+    res = {"reference": {"scheme": "ROW4", **ref}}
+    for kind in ("ROW3", "ESDIRK3", "BDF2"):
+        rows = []
+        for dt in (0.2, 0.1, 0.05):
+            U, rec = run(kind, dt)
+            rec["e_time_rho"] = float(torch.linalg.norm(U[0] - Uref[0]) / math.sqrt(U[0].numel()))
+            if rows:
+                rec["order"] = math.log2(rows[-1]["e_time_rho"] / rec["e_time_rho"])
+            rows.append(rec)
+        res[kind] = rows
+    return res
 
 
 def run_leg(disc, U, steps, scheme, dt, opts, allow_unconverged=False):
@@ -218,6 +289,13 @@ def main():
                                   f"Rusanov, eps_rms 1e-8; timed steps start after {args.warmup} untimed steps",
                       "ndof": ndof, "dt": dt},
            "extra": {}}
+
+    if args.order_study:
+        if args.workload != "vortex64_p3":
+            raise SystemExit("--order-study runs on the 64x64 P3 vortex")
+        print(json.dumps({"mode": "order-study", "workload": W["label"],
+                          "study": order_study(disc, U0, vortex)}), flush=True)
+        return
 
     if args.kernels_only:
         kernels, roof = kernel_block(disc, U0, dt, scheme, ndof, args.workload)
