@@ -54,7 +54,7 @@ def parse():
                     help="only the per-kernel timing block, at the initial state (for profiler runs)")
     ap.add_argument("--no-learned", action="store_true", help="skip logging, training and the learned leg")
     ap.add_argument("--no-fp32-leg", action="store_true", help="skip the FP32-preconditioner legs")
-    ap.add_argument("--no-schemes", action="store_true", help="skip the ESDIRK3 and BDF2 legs")
+    ap.add_argument("--no-schemes", action="store_true", help="skip the ESDIRK and BDF2 legs")
     ap.add_argument("--allow-unconverged", action="store_true",
                     help="count GMRES solves that reach the iteration cap instead of stopping")
     ap.add_argument("--order-study", action="store_true",
@@ -382,7 +382,7 @@ def main():
     out["extra"]["legs"] = legs
 
     # ---- (4) the other implicit schemes of the same workload, FP64 element-Jacobi:
-    # ESDIRK3 and BDF2 (BDF1 start) with pseudo-transient continuation, inexact
+    # ESDIRK3 (ESDIRK4 beside ROW4) and BDF2 (BDF1 start) with pseudo-transient continuation, inexact
     # Newton (GMRES rtol 1e-1 per PTC iteration), nonlinear tolerance 1e-8
     if W["physics"] == "euler" and not args.no_schemes:
         sopts = SolverOpts(lin=GmresOpts(m=20, rtol=1e-1), tol_nl=1e-8)
@@ -406,10 +406,12 @@ def main():
             for k in tot:
                 tot[k] += st[k]
 
-        def esdirk3(tot):
+        ek = 4 if scheme == 4 else 3   # the ESDIRK of the same order as the ROW scheme (3 or 4)
+
+        def esdirk(tot):
             Ux = Ustart.clone()
             for _ in range(args.steps):
-                add(tot, disc.esdirk_step(Ux, 3, dt, sopts), "esdirk_step")
+                add(tot, disc.esdirk_step(Ux, ek, dt, sopts), "esdirk_step")
             return Ux
 
         def bdf2(tot):
@@ -420,7 +422,7 @@ def main():
                 Unm1, Un = Un, Unp1
             return Un
 
-        schemes["ESDIRK3"] = scheme_leg(esdirk3)
+        schemes[f"ESDIRK{ek}"] = scheme_leg(esdirk)
         schemes["BDF2 (BDF1 start)"] = scheme_leg(bdf2)
         out["extra"]["schemes"] = schemes
 
