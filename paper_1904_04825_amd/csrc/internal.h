@@ -101,7 +101,7 @@ hipError_t launch_scale_dev(double* y, const double* x, const double* alpha, int
 // grad: BR1 gradient-trace workspace (Navier-Stokes only, else unused)
 hipError_t launch_ejacobi_assemble(const fr_disc* d, const double* U, double shift, void* out,
                                    int precision, int invert, double* grad, hipStream_t s);
-// In-place inversion of nblk FP64 blocks of order nb (36, 64 or 100), column-major.
+// In-place inversion of nblk FP64 blocks of order 100, column-major (other orders: hipErrorInvalidValue).
 hipError_t launch_gj_rows_f64(int nb, double* blocks, int nblk, hipStream_t s);
 // In-place inversion of nblk FP32 blocks of order nb (36, 64 or 100), column-major, on MFMA.
 hipError_t launch_gj_mfma_f32(int nb, float* blocks, int nblk, hipStream_t s);
