@@ -305,7 +305,7 @@ def main():
 
     # ---- (1) warm-up steps, logging the stage solves
     rng = np.random.default_rng(40)
-    learned = not args.no_learned and W["physics"] == "euler"
+    learned = not args.no_learned
     per_stage = min(256, disc.nel)
     logs = StageLogs([StageLog(disc, max(args.warmup, 1) * per_stage, rng.choice(disc.nel, per_stage, replace=False))
                       for _ in range(nstage)]) if learned else None
@@ -384,7 +384,7 @@ def main():
     # ---- (4) the other implicit schemes of the same workload, FP64 element-Jacobi:
     # ESDIRK3 (ESDIRK4 beside ROW4) and BDF2 (BDF1 start) with pseudo-transient continuation, inexact
     # Newton (GMRES rtol 1e-1 per PTC iteration), nonlinear tolerance 1e-8
-    if W["physics"] == "euler" and not args.no_schemes:
+    if not args.no_schemes:
         sopts = SolverOpts(lin=GmresOpts(m=20, rtol=1e-1), tol_nl=1e-8)
         schemes = {}
 
