@@ -382,7 +382,8 @@ def main():
     out["extra"]["legs"] = legs
 
     # ---- (4) the other implicit schemes of the same workload, FP64 element-Jacobi:
-    # ESDIRK3 (ESDIRK4 beside ROW4) and BDF2 (BDF1 start) with pseudo-transient continuation, inexact
+    # ESDIRK3 (ESDIRK4 beside ROW4) and BDF2 (BDF1 start), each also with the FP32
+    # element-Jacobi, with pseudo-transient continuation, inexact
     # Newton (GMRES rtol 1e-1 per PTC iteration), nonlinear tolerance 1e-8
     if not args.no_schemes:
         sopts = SolverOpts(lin=GmresOpts(m=20, rtol=1e-1), tol_nl=1e-8)
@@ -408,22 +409,30 @@ def main():
 
         ek = 4 if scheme == 4 else 3   # the ESDIRK of the same order as the ROW scheme (3 or 4)
 
-        def esdirk(tot):
-            Ux = Ustart.clone()
-            for _ in range(args.steps):
-                add(tot, disc.esdirk_step(Ux, ek, dt, sopts), "esdirk_step")
-            return Ux
+        def esdirk(o):
+            def run(tot):
+                Ux = Ustart.clone()
+                for _ in range(args.steps):
+                    add(tot, disc.esdirk_step(Ux, ek, dt, o), "esdirk_step")
+                return Ux
+            return run
 
-        def bdf2(tot):
-            Unm1, Un = None, Ustart.clone()
-            for _ in range(args.steps):
-                Unp1, st = disc.bdf2_step(Unm1, Un, dt, sopts)
-                add(tot, st, "bdf2_step")
-                Unm1, Un = Un, Unp1
-            return Un
+        def bdf2(o):
+            def run(tot):
+                Unm1, Un = None, Ustart.clone()
+                for _ in range(args.steps):
+                    Unp1, st = disc.bdf2_step(Unm1, Un, dt, o)
+                    add(tot, st, "bdf2_step")
+                    Unm1, Un = Un, Unp1
+                return Un
+            return run
 
-        schemes[f"ESDIRK{ek}"] = scheme_leg(esdirk)
-        schemes["BDF2 (BDF1 start)"] = scheme_leg(bdf2)
+        # the same PTC with the FP32 MFMA element-Jacobi (formed at every pseudo-iterate)
+        sopts32 = SolverOpts(lin=GmresOpts(m=20, rtol=1e-1), tol_nl=1e-8, precond_precision=F32)
+        schemes[f"ESDIRK{ek}"] = scheme_leg(esdirk(sopts))
+        schemes[f"ESDIRK{ek}, FP32 element-Jacobi"] = scheme_leg(esdirk(sopts32))
+        schemes["BDF2 (BDF1 start)"] = scheme_leg(bdf2(sopts))
+        schemes["BDF2 (BDF1 start), FP32 element-Jacobi"] = scheme_leg(bdf2(sopts32))
         out["extra"]["schemes"] = schemes
 
     if not args.no_kernels:
