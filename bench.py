@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-kernel timing block, at the initial state (for profiler runs)")
     ap.add_argument("--no-learned", action="store_true", help="skip logging, training and the learned leg")
+    ap.add_argument("--log-elems", type=int, default=1024, help="elements logged per stage solve (training samples)")
+    ap.add_argument("--adam-steps", type=int, default=1500, help="Adam steps per stage network")
+    ap.add_argument("--batch", type=int, default=1024, help="training batch (samples)")
     ap.add_argument("--no-fp32-leg", action="store_true", help="skip the FP32-preconditioner legs")
     ap.add_argument("--no-schemes", action="store_true", help="skip the ESDIRK and BDF2 legs")
     ap.add_argument("--allow-unconverged", action="store_true",
@@ -306,7 +309,7 @@ def main():
     # ---- (1) warm-up steps, logging the stage solves
     rng = np.random.default_rng(40)
     learned = not args.no_learned
-    per_stage = min(256, disc.nel)
+    per_stage = min(args.log_elems, disc.nel)
     logs = StageLogs([StageLog(disc, max(args.warmup, 1) * per_stage, rng.choice(disc.nel, per_stage, replace=False))
                       for _ in range(nstage)]) if learned else None
     yhist = torch.zeros((2, ndof), dtype=torch.float64, device=dev)
@@ -334,16 +337,16 @@ def main():
             tr = MlpTrainer(disc, n_hidden=256, seed=4 + i, lr=1e-3)
             tr.fit_stats(lg)
             ls = []
-            for it in range(400):
-                idx = torch.as_tensor(rng.choice(lg.count, min(512, lg.count), replace=False), dtype=torch.int32,
+            for it in range(args.adam_steps):
+                idx = torch.as_tensor(rng.choice(lg.count, min(args.batch, lg.count), replace=False), dtype=torch.int32,
                                       device=dev)
-                ls.append(tr.step(lg, idx, lr=1e-3 * 0.5 * (1 + np.cos(np.pi * it / 400))))
+                ls.append(tr.step(lg, idx, lr=1e-3 * 0.5 * (1 + np.cos(np.pi * it / args.adam_steps))))
             trainers.append(tr)
             final_loss.append(float(np.mean(ls[-20:])))
         torch.cuda.synchronize()
         warm = WarmStart([t.net for t in trainers])
-        out["extra"]["learned_training"] = {"samples_per_stage": logs.logs[0].count, "adam_steps_per_stage": 400,
-                                            "batch": 512, "final_mse_normalised": final_loss,
+        out["extra"]["learned_training"] = {"samples_per_stage": logs.logs[0].count, "adam_steps_per_stage": args.adam_steps,
+                                            "batch": args.batch, "final_mse_normalised": final_loss,
                                             "train_s": time.perf_counter() - t_tr}
 
     # ---- (3) timed legs from the same state
