@@ -45,10 +45,11 @@ __device__ __forceinline__ unsigned lane_xor32(unsigned x) {
   return ((threadIdx.x >> 5) & 1) ? r[0] : r[1];
 }
 
-// x broadcast from lane C of each 16-lane row
+// x broadcast from lane C of each 16-lane row (every lane has a source, so no
+// old value is kept: the move needs no copy of x)
 template <int C>
 __device__ __forceinline__ unsigned row_bcast_u(unsigned x) {
-  return (unsigned)__builtin_amdgcn_update_dpp((int)x, (int)x, 0x150 + C, 0xf, 0xf, false);
+  return (unsigned)__builtin_amdgcn_mov_dpp((int)x, 0x150 + C, 0xf, 0xf, true);
 }
 
 // The lane operations and the matrix instruction for one precision.  key_bits: 32
@@ -103,10 +104,17 @@ struct GjMfmaLds {
   int pstep[NP];         // row pivoted in each step
 };
 
+// Per held row: the key mask 0x7fffff80 | (127 - (32 g + 4 rt + r)) while the row is
+// a candidate, 0 once it is pivoted.
+template <int T>
+struct KeyMask {
+  typedef unsigned type __attribute__((ext_vector_type(4 * T)));
+};
+
 // One elimination step on the panel copy W (panel column C, global step s).
 template <typename S, int T, int C>
-__device__ __forceinline__ void panel_step(typename ColT<S, T>::type& W, unsigned& used, int s, int n, int g,
-                                           GjMfmaLds<S, 16 * T>& L) {
+__device__ __forceinline__ void panel_step(typename ColT<S, T>::type& W, typename KeyMask<T>::type& km, int s, int n,
+                                           int g, GjMfmaLds<S, 16 * T>& L) {
   using O = GjOps<S>;
   // pivot: largest |a| of column C among the rows not pivoted yet.  Each entry
   // becomes one 32-bit key, the bits of |a| (monotone for non-negative values; the
@@ -114,22 +122,22 @@ __device__ __forceinline__ void panel_step(typename ColT<S, T>::type& W, unsigne
   // 127 - (32 g + 4 rt + r): the unsigned maximum picks the largest entry (entries
   // within 2^-16 (FP32) or 2^-13 (FP64) of each other count as equal, the lower row
   // code winning) and always decodes to a candidate row.  The four lanes of column C
-  // combine their maxima.
+  // combine their maxima.  (bits | 127) & mask: the key of a candidate, 0 for a row
+  // already pivoted.
   unsigned key = 0u;
 #pragma unroll
-  for (int rt = 0; rt < T; ++rt)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const unsigned k = (O::key_bits(W[4 * rt + r]) & 0x7fffff80u) | (127u - (32u * g + 4u * rt + r));
-      key = max(key, ((used >> (4 * rt + r)) & 1u) ? 0u : k);
-    }
+  for (int e = 0; e < 4 * T; ++e) key = max(key, (O::key_bits(W[e]) | 127u) & km[e]);
   key = max(key, lane_xor16(key));
   key = max(key, lane_xor32(key));
   const unsigned code = 127u - ((unsigned)__builtin_amdgcn_readlane((int)key, C) & 127u);
   const int p = min(16 * (int)((code & 31u) >> 2) + (int)(code >> 5) + 4 * (int)(code & 3u), 16 * T - 1);
   const int rtp = p >> 4, gp = (p & 15) & 3, rp = (p & 15) >> 2;
   const int idx = 4 * rtp + rp;
-  if (g == gp) used |= 1u << idx;
+  {
+    // one indexed read and one indexed write (a conditional write would copy the vector)
+    const unsigned cur = km[idx];
+    km[idx] = (g == gp) ? 0u : cur;
+  }
   if (n == 0 && g == 0) {
     L.kstep[p] = s;
     L.pstep[s] = p;
@@ -144,25 +152,30 @@ __device__ __forceinline__ void panel_step(typename ColT<S, T>::type& W, unsigne
   const S ipiv = S(1) / piv;
   const S t = pr * ipiv;
   const bool colC = n == C;
-  // other rows: a_ij -= a_iC a_pj / pivot; column C: -a_iC / pivot; row p: a_pj / pivot, 1/pivot
+  // other rows: a_ij -= a_iC a_pj / pivot; column C: -a_iC / pivot; row p: a_pj / pivot, 1/pivot.
+  // One form for every lane, f (a_iC) + nt * (column C ? 0 : a_ij): on lane C, f is the
+  // lane's own entry, so its new entry is f * (-1/pivot) exactly as a separate product
+  // would round it
+  const S nt = colC ? -ipiv : -t;
 #pragma unroll
   for (int rt = 0; rt < T; ++rt)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const S f = O::template bcast<C>(W[4 * rt + r]);
-      const S u = fma(-f, t, W[4 * rt + r]);
-      W[4 * rt + r] = colC ? -f * ipiv : u;
+      const S ws = colC ? S(0) : W[4 * rt + r];
+      W[4 * rt + r] = fma(f, nt, ws);
     }
   const S wp = W[idx];
   W[idx] = (g == gp) ? (colC ? ipiv : t) : wp;
 }
 
 template <typename S, int T, int C = 0>
-__device__ __forceinline__ void panel_steps(typename ColT<S, T>::type& W, unsigned& used, int K, int n, int g,
+__device__ __forceinline__ void panel_steps(typename ColT<S, T>::type& W, typename KeyMask<T>::type& km, int K, int n,
+                                            int g,
                                             GjMfmaLds<S, 16 * T>& L) {
   if constexpr (C < 16) {
-    panel_step<S, T, C>(W, used, 16 * K + C, n, g, L);
-    panel_steps<S, T, C + 1>(W, used, K, n, g, L);
+    panel_step<S, T, C>(W, km, 16 * K + C, n, g, L);
+    panel_steps<S, T, C + 1>(W, km, K, n, g, L);
   }
 }
 
@@ -194,7 +207,11 @@ k_gj_mfma(S* __restrict__ blocks) {
         const int i = 16 * rt + g + 4 * r, j = 16 * ct + n;
         M[ct][4 * rt + r] = (i < N && j < N) ? A[(size_t)j * N + i] : (i == j ? S(1) : S(0));
       }
-  unsigned used = 0;  // bit 4 rt + r: row 16 rt + g + 4 r is pivoted
+  typename KeyMask<T>::type km;  // entry 4 rt + r: row 16 rt + g + 4 r
+#pragma unroll
+  for (int rt = 0; rt < T; ++rt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) km[4 * rt + r] = 0x7fffff80u | (127u - (32u * g + 4u * rt + r));
   for (int i = l; i < NP; i += 64) L.kstep[i] = -1;
   __syncthreads();
 
@@ -202,7 +219,7 @@ k_gj_mfma(S* __restrict__ blocks) {
   // every panel, so after T panels they are back in place.
   for (int K = 0; K < T; ++K) {
     // ---- panel: the 16 exchanges on tile column 0
-    panel_steps<S, T>(M[0], used, K, n, g, L);
+    panel_steps<S, T>(M[0], km, K, n, g, L);
 
     // ---- stage W and the pivot rows of the other columns in LDS; zero those rows
 #pragma unroll
