@@ -30,7 +30,8 @@ template <int P>
 struct EJ {
   static constexpr int n = P + 1, Np = n * n, Nb = 4 * Np;
   static constexpr int NT = ((Nb + 63) / 64) * 64;
-  static constexpr int LD = Nb + 1;  // padded LDS leading dimension
+  static constexpr int NZ = 4 * (2 * n - 1);  // structural nonzeros of a column
+  static constexpr int LZ = NZ + 1;            // padded LDS leading dimension
 };
 
 struct AsmArgs {
@@ -44,8 +45,10 @@ struct AsmArgs {
 template <int P, int FLUX, typename T>
 __global__ void __launch_bounds__(EJ<P>::NT) k_ejacobi_assemble(const AsmArgs a, const Basis B) {
   using C = EJ<P>;
-  constexpr int n = C::n, Np = C::Np, Nb = C::Nb, NT = C::NT, LD = C::LD;
-  __shared__ T A[Nb * LD];  // the block, column-major, padded leading dimension
+  constexpr int n = C::n, Np = C::Np, Nb = C::Nb, NT = C::NT, LZ = C::LZ;
+  // the block's structural nonzeros, per column: variable v, then the points of the
+  // column point's eta-row (a = 0..n-1) and of its xi-column (b != its own b)
+  __shared__ T Z[Nb * LZ];
   __shared__ double sq[4][Np], sF[4][Np], sG[4][Np], sIJ[Np];
   __shared__ double sqo[4][4][n], sqn[4][4][n], sFn[4][4][n];  // [face][var][j]
   __shared__ double sS[4][2];
@@ -123,8 +126,7 @@ __global__ void __launch_bounds__(EJ<P>::NT) k_ejacobi_assemble(const AsmArgs a,
   // one finite-difference column per thread
   for (int jc = tid; jc < Nb; jc += NT) {
     const int vv = jc / Np, k = jc % Np, ak = k % n, bk = k / n;
-    T* col = A + jc * LD;
-    for (int i = 0; i < Nb; ++i) col[i] = (T)0;
+    T* col = Z + jc * LZ;
     double q[4], f[4], g[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) q[v] = sq[v][k];
@@ -186,7 +188,8 @@ __global__ void __launch_bounds__(EJ<P>::NT) k_ejacobi_assemble(const AsmArgs a,
       for (int v = 0; v < 4; ++v) {
         double t = B.D[ia][ak] * dF[v] + dJW[v] * B.gL[ia] + dJE[v] * B.gR[ia];
         if (ia == ak) t += B.D[bk][bk] * dG[v] + dJS[v] * B.gL[bk] + dJN[v] * B.gR[bk];
-        col[v * Np + kk] = (T)(s * (-sIJ[kk] * t));
+        const T e = (T)(s * (-sIJ[kk] * t));
+        col[v * (2 * n - 1) + ia] = (ia == ak && v == vv) ? (T)((double)e + a.shift) : e;
       }
     }
     // points of k's xi-column (ak, b), b != bk
@@ -196,14 +199,28 @@ __global__ void __launch_bounds__(EJ<P>::NT) k_ejacobi_assemble(const AsmArgs a,
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const double t = B.D[ib][bk] * dG[v] + dJS[v] * B.gL[ib] + dJN[v] * B.gR[ib];
-        col[v * Np + kk] = (T)(s * (-sIJ[kk] * t));
+        col[v * (2 * n - 1) + n + (ib < bk ? ib : ib - 1)] = (T)(s * (-sIJ[kk] * t));
       }
     }
-    col[jc] = (T)((double)col[jc] + a.shift);
   }
   __syncthreads();
+  // write-out, column-major: thread = block row, so each store is contiguous across
+  // the lanes; entries off the row point's eta-row and xi-column are zero
   T* out = reinterpret_cast<T*>(a.out) + (size_t)el * Nb * Nb;
-  for (int idx = tid; idx < Nb * Nb; idx += NT) out[idx] = A[(idx / Nb) * LD + idx % Nb];
+  if (tid < Nb) {
+    const int vr = tid / Np, kr = tid % Np, ar = kr % n, br = kr / n;
+    const T* zr = Z + vr * (2 * n - 1);
+#pragma unroll
+    for (int col = 0; col < Nb; ++col) {
+      const int kc = col % Np, ac = kc % n, bc = kc / n;
+      T val = (T)0;
+      if (br == bc)
+        val = zr[col * LZ + ar];
+      else if (ar == ac)
+        val = zr[col * LZ + n + (br < bc ? br : br - 1)];
+      out[(size_t)col * Nb + tid] = val;
+    }
+  }
 }
 
 // FP64 blocks rounded to FP32 (caller-provided blocks of the FP32 store).
