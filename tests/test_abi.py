@@ -85,3 +85,25 @@ def test_ctypes_layouts_match_the_c_compiler(tmp_path):
                                        _lib.SolverOptsC, _lib.StepStatsC, _lib.MlpC, _lib.MlpTrainerC,
                                        _lib.StageLogC)]
     assert got == want
+
+
+def test_invalid_arguments_are_rejected_before_any_device_work():
+    """Caller errors come back as FR_EINVAL (-1) with a message, from checks that run
+    before the library touches a GPU; outputs are left as they were."""
+    from paper_1904_04825_amd import _lib
+    L = _lib.lib()
+    nodes = ctypes.c_double(0.0)
+    good = dict(nx=4, ny=4, p=3, physics=0, flux=0, gamma=1.4, rgas=1.0, mu=0.0, prandtl=0.71,
+                d_nodes=ctypes.cast(ctypes.pointer(nodes), ctypes.c_void_p))
+    cases = [({"p": 5}, "p must be"), ({"p": 1}, "p must be"), ({"nx": 1}, "nx and ny"), ({"physics": 7}, "physics"),
+             ({"flux": 9}, "flux"), ({"d_nodes": None}, "d_nodes"), ({"gamma": 1.0}, "gamma"),
+             ({"nx": 1 << 16, "ny": 1 << 15}, "too large")]
+    for change, msg in cases:
+        kw = dict(good, **change)
+        desc = _lib.DiscDesc(**kw)
+        out = ctypes.c_void_p(12345)
+        st = L.fr_disc_create(ctypes.byref(desc), ctypes.byref(out))
+        assert st == -1, (change, st)
+        assert msg in L.fr_last_error().decode(), (change, L.fr_last_error())
+        assert out.value == 12345
+    assert L.fr_disc_create(None, None) == -1
