@@ -233,7 +233,7 @@ __global__ void k_round_f32(const double* __restrict__ src, float* __restrict__ 
 // scaled by 1/(*r_scale) on load and stored back to r_store (fused normalisation of
 // the Arnoldi vector).  The inverse is column-major, so column j of a block is
 // Nb contiguous entries: a thread owns RPT consecutive rows and reads them with one
-// load per column, eight columns in flight.  RPT = 1: one row per thread, the most
+// load per column, a batch of columns in flight (the first batch issued before r is staged).  RPT = 1: one row per thread, the most
 // threads; RPT = 16 / sizeof(T): 16-byte loads and dense lanes for large P = 4 stores.  EPB elements share a 256-thread
 // workgroup; workgroups stride over groups of EPB elements.
 template <int P, typename T, int RPT_>
@@ -242,6 +242,11 @@ struct SolveCfg {
   static constexpr int RPT = RPT_;     // rows per thread
   static constexpr int TPE = Nb / RPT;  // threads per element
   static constexpr int EPB = 256 / TPE;  // elements per workgroup
+  // columns in flight per thread: single rows (latency-bound stores that stay in the
+  // last-level cache) about 64 VGPRs of loads, 32 FP64 or 64 FP32 columns; 16-byte
+  // rows (large stores streamed from HBM) 8 columns, which measured faster there
+  static constexpr int JU0 = RPT == 1 ? 256 / (int)sizeof(T) : 8;
+  static constexpr int JU = JU0 < Nb ? JU0 : Nb;
   static_assert(Nb % RPT == 0, "whole rows per thread");
 };
 
@@ -269,7 +274,7 @@ __global__ void __launch_bounds__(256) k_ejacobi_solve(const T* __restrict__ inv
   using C = SolveCfg<P, T, RPT>;
   using V = typename RowVec<T, RPT>::type;
   constexpr int Np = C::Np, Nb = C::Nb, TPE = C::TPE, EPB = C::EPB;
-  constexpr int JU = 8;  // columns in flight
+  constexpr int JU = C::JU;  // columns in flight
   if (skip != nullptr && *skip) return;
   __shared__ T sr[EPB][Nb];
   const int tid = threadIdx.x;
@@ -278,6 +283,20 @@ __global__ void __launch_bounds__(256) k_ejacobi_solve(const T* __restrict__ inv
   // workgroup 0 also finishes the Arnoldi step that produced r (CGS2: its Givens
   // update; DCGS2: stores ||r|| as the first-pass h_{j+1,j}, and rotates the
   // first-pass column on breakdown or NaN)
+  const int ngroups = (nel + EPB - 1) / EPB;
+  // single rows: the first JU columns of the first group are on their way during the
+  // set-up below and while r goes through LDS (16-byte rows load after staging: held
+  // through it they cost occupancy, measured slower)
+  constexpr bool kEarly = C::RPT == 1;
+  V m[JU];
+  if constexpr (kEarly) {
+    const int el = blockIdx.x * EPB + blk;
+    if (blockIdx.x < ngroups && blk < EPB && el < nel) {
+      const V* col = reinterpret_cast<const V*>(inv + (size_t)el * Nb * Nb) + i;
+#pragma unroll
+      for (int u = 0; u < JU; ++u) m[u] = col[(size_t)u * TPE];
+    }
+  }
   const bool scaled = gv.st != nullptr;
   double sc = 1.0;
   if (scaled) {
@@ -294,9 +313,15 @@ __global__ void __launch_bounds__(256) k_ejacobi_solve(const T* __restrict__ inv
       }
     }
   }
-  const int ngroups = (nel + EPB - 1) / EPB;
   double zz = 0.0;
   for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int el = grp * EPB + blk;
+    const bool live = blk < EPB && el < nel;
+    const V* col = reinterpret_cast<const V*>(inv + (size_t)(live ? el : 0) * Nb * Nb) + i;  // rows RPT i .. RPT i + RPT - 1
+    if (kEarly && live && grp != (int)blockIdx.x) {
+#pragma unroll
+      for (int u = 0; u < JU; ++u) m[u] = col[(size_t)u * TPE];
+    }
     __syncthreads();
     for (int t = tid; t < EPB * Nb; t += 256) {
       const int e = t / Nb, jj = t - e * Nb, el = grp * EPB + e;
@@ -311,20 +336,20 @@ __global__ void __launch_bounds__(256) k_ejacobi_solve(const T* __restrict__ inv
       sr[e][jj] = (T)rv;
     }
     __syncthreads();
-    const int el = grp * EPB + blk;
-    if (blk < EPB && el < nel) {
-      const V* col = reinterpret_cast<const V*>(inv + (size_t)el * Nb * Nb) + i;  // rows RPT i .. RPT i + RPT - 1
+    if (live) {
       V acc0 = {}, acc1 = {};
       int j = 0;
       for (; j + JU <= Nb; j += JU) {
-        V m[JU];
+        if (j > 0 || !kEarly) {
 #pragma unroll
-        for (int u = 0; u < JU; ++u) m[u] = col[(size_t)(j + u) * TPE];
+          for (int u = 0; u < JU; ++u) m[u] = col[(size_t)(j + u) * TPE];
+        }
 #pragma unroll
-        for (int u = 0; u < JU; u += 2) {
+        for (int u = 0; u + 1 < JU; u += 2) {
           acc0 += m[u] * sr[blk][j + u];
           acc1 += m[u + 1] * sr[blk][j + u + 1];
         }
+        if constexpr (JU % 2 == 1) acc0 += m[JU - 1] * sr[blk][j + JU - 1];
       }
       for (; j < Nb; ++j) acc0 += col[(size_t)j * TPE] * sr[blk][j];
       const V acc = acc0 + acc1;
