@@ -229,7 +229,7 @@ __global__ void __launch_bounds__(256) k_mse_grad(const float* __restrict__ Y, c
 // g[n] = sum_m D[m][n] (bf16 or fp32 source).  A workgroup takes 64 columns;
 // its 16 row groups each sum every 16th row (coalesced along n), then LDS adds
 // the 16 partial sums in a fixed order.
-constexpr int kColsumCols = 64, kColsumRows = 16;
+constexpr int kColsumCols = 16, kColsumRows = 64;  // 16 columns per workgroup: enough workgroups for N = 256
 __global__ void __launch_bounds__(kColsumCols* kColsumRows)
     k_colsum(const uint16_t* __restrict__ Db, const float* __restrict__ Df, int M, int N, float* __restrict__ g) {
   __shared__ double part[kColsumRows][kColsumCols];

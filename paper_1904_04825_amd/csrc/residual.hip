@@ -203,7 +203,11 @@ __global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a
   const size_t nel = (size_t)g.nel, vstride = nel * Np;
   double e = 0.0, ie = 0.0;
   bool zero_v = false;
-  if constexpr (MODE != 0) {
+  // e = eps / rms(v): on small meshes every wavefront adds the partial sums of ||v||^2
+  // itself, after the tile's and the halo's loads are on their way (the halo keeps U and
+  // v apart until e is known); on large meshes ||v||^2 is one finished value
+  constexpr bool kLateE = MODE != 0 && !BIG && P <= 3;  // P4: the separate halo registers cost occupancy
+  auto eps_of = [&]() {
     if (a.eps_mode == FR_EPS_RMS) {
       const double n2 = (!BIG && a.nrm2_part != nullptr) ? wave_sum_partials(a.nrm2_part, a.nrm2_nb) : *a.nrm2;
       if (n2 > 0.0)
@@ -214,7 +218,8 @@ __global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a
       e = a.eps;
     }
     ie = zero_v ? 0.0 : 1.0 / e;
-  }
+  };
+  if constexpr (MODE != 0 && !kLateE) eps_of();
 
   // ---- the tile's state and the halo lines.  Every global load of the phase is
   // issued before the first use, so the tile and halo reads overlap.  Each tile row
@@ -237,6 +242,7 @@ __global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a
     // ---- halo lines: the row (west / east neighbour) or column (south / north
     // neighbour) of the element across a border face, loaded before the state lands
     double hq[NHI][n][4];
+    double hv[kLateE ? NHI : 1][kLateE ? n : 1][4];
     int hslot[NHI];
     bool hplus[NHI];
 #pragma unroll
@@ -271,9 +277,25 @@ __global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a
 #pragma unroll
         for (int c = 0; c < n; ++c)
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            hq[it][c][v] = state_at<MODE>(a, v * vstride + base + c * stride, e);
+          for (int v = 0; v < 4; ++v) {
+            const size_t gi = v * vstride + base + c * stride;
+            if constexpr (kLateE) {
+              hq[it][c][v] = a.U[gi];
+              hv[kLateE ? it : 0][kLateE ? c : 0][v] = a.V[gi];
+            } else {
+              hq[it][c][v] = state_at<MODE>(a, gi, e);
+            }
+          }
       }
+    }
+    if constexpr (kLateE) {
+      eps_of();
+#pragma unroll
+      for (int it = 0; it < NHI; ++it)
+#pragma unroll
+        for (int c = 0; c < n; ++c)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) hq[it][c][v] = fma(e, hv[kLateE ? it : 0][kLateE ? c : 0][v], hq[it][c][v]);
     }
 
     // ---- the state into LDS
