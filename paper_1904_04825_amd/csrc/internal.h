@@ -93,9 +93,6 @@ hipError_t launch_norm2(const double* x, size_t n, double* partials, double* out
 // y = sum_i c[i] * x[i] (k <= 8); pointers and coefficients passed by value
 hipError_t launch_lincomb(double* y, int k, const double* const* x, const double* c, size_t n,
                           hipStream_t s);
-// y = alpha_dev[0] * x  (alpha read on device; inv=1: y = x / alpha)
-hipError_t launch_scale_dev(double* y, const double* x, const double* alpha, int inv, size_t n,
-                            const int* skip, hipStream_t s);
 
 // element-Jacobi
 // grad: BR1 gradient-trace workspace (Navier-Stokes only, else unused)
@@ -191,7 +188,9 @@ struct GivensIn {
   int nb, M;
   int lagged;
 };
-hipError_t launch_gm_init(GmState* st, const double* beta2, double target, int M, GmStatus* hslot, hipStream_t s);
+// Cycle start: beta = sqrt(*beta2), v0 = r / beta, the cycle state reset (target, hslot).
+hipError_t launch_gm_start(GmState* st, const double* beta2, double target, int M, GmStatus* hslot, double* v0,
+                           const double* r, size_t n, hipStream_t s);
 // Sum partials[b*stride + i] over b < nblocks into out[i], i < nv (one workgroup).
 hipError_t launch_finalize(const double* partials, int nblocks, int stride, int nv, double* out, const int* skip,
                            hipStream_t s);

@@ -348,8 +348,7 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
   for (;;) {
     hstat->stop = 0;
     hstat->j = 0;
-    FR_HIP(launch_gm_init(W.st, beta2, target, m, dstat, s));
-    FR_HIP(launch_scale_dev(W.V, rsrc, &W.st->beta, 1, n, nullptr, s));
+    FR_HIP(launch_gm_start(W.st, beta2, target, m, dstat, W.V, rsrc, n, s));
     const int budget = std::min(m, max_iters - S.iters);
     for (int j = 0; j < budget; ++j) {
       if (j >= 8 && j % 4 == 0) FR_HIP(hipEventSynchronize(d->ev[(j / 4 - 2) & 3]));  // step j - 5 done

@@ -111,21 +111,6 @@ hipError_t launch_lincomb(double* y, int k, const double* const* x, const double
   return hipGetLastError();
 }
 
-__global__ void __launch_bounds__(256) k_scale_dev(double* __restrict__ y, const double* __restrict__ x,
-                                                   const double* alpha, int inv, size_t n, const int* skip) {
-  if (skip != nullptr && *skip) return;
-  const double a = inv ? 1.0 / *alpha : *alpha;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    y[i] = a * x[i];
-}
-
-hipError_t launch_scale_dev(double* y, const double* x, const double* alpha, int inv, size_t n, const int* skip,
-                            hipStream_t s) {
-  const unsigned blocks = (unsigned)red_blocks(n);
-  hipLaunchKernelGGL(k_scale_dev, dim3(blocks ? blocks : 1), dim3(256), 0, s, y, x, alpha, inv, n, skip);
-  return hipGetLastError();
-}
-
 // ---------------------------------------------------------------- CGS2 Arnoldi step
 #ifndef FRJF_CGS_EPT
 #define FRJF_CGS_EPT 4
@@ -562,10 +547,17 @@ hipError_t launch_dcgs2_last(GmState* st, const double* partials, int nb, int M,
   return hipGetLastError();
 }
 
-__global__ void k_gm_init(GmState* st, const double* beta2, double target, int M, GmStatus* hslot) {
-  if (threadIdx.x != 0) return;
-  st->hslot = hslot;
+// Start of a restart cycle: every workgroup forms beta = ||r|| from ||r||^2 and stores
+// the first basis vector v_0 = r / beta; workgroup 0 also resets the cycle state.
+__global__ void __launch_bounds__(256) k_gm_start(GmState* st, const double* beta2, double target, int M,
+                                                  GmStatus* hslot, double* __restrict__ v0,
+                                                  const double* __restrict__ r, size_t n) {
   const double beta = sqrt(*beta2);
+  const double a = 1.0 / beta;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    v0[i] = a * r[i];
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  st->hslot = hslot;
   for (int i = 0; i <= M; ++i) st->g[i] = 0.0;
   st->g[0] = beta;
   st->beta = beta;
@@ -578,8 +570,10 @@ __global__ void k_gm_init(GmState* st, const double* beta2, double target, int M
   st->rest = beta;
 }
 
-hipError_t launch_gm_init(GmState* st, const double* beta2, double target, int M, GmStatus* hslot, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_init, dim3(1), dim3(64), 0, s, st, beta2, target, M, hslot);
+hipError_t launch_gm_start(GmState* st, const double* beta2, double target, int M, GmStatus* hslot, double* v0,
+                           const double* r, size_t n, hipStream_t s) {
+  const unsigned blocks = (unsigned)red_blocks(n);
+  hipLaunchKernelGGL(k_gm_start, dim3(blocks ? blocks : 1), dim3(256), 0, s, st, beta2, target, M, hslot, v0, r, n);
   return hipGetLastError();
 }
 
