@@ -264,6 +264,7 @@ def main():
     import fr_inputs as fi
     from paper_1904_04825_amd import (F32, F64, Disc, GmresOpts, MlpTrainer, SolverOpts, StageLog, StageLogs,
                                       WarmStart)
+    from paper_1904_04825_amd.api import scheme_table
 
     W = WORKLOADS[args.workload]
     dt = args.dt if args.dt is not None else W["dt"]
@@ -329,12 +330,12 @@ def main():
     Ustart, hstart = U.clone(), yhist.clone()
 
     # ---- (2) train one network per stage on the GPU
-    warm = None
-    if learned and args.warmup > 0:
+    def train(stage_logs, seed0):
+        """One network per stage, trained on the GPU from the stage's log (cosine-decayed Adam)."""
         t_tr = time.perf_counter()
         trainers, final_loss = [], []
-        for i, lg in enumerate(logs.logs):
-            tr = MlpTrainer(disc, n_hidden=256, seed=4 + i, lr=1e-3)
+        for i, lg in enumerate(stage_logs.logs):
+            tr = MlpTrainer(disc, n_hidden=256, seed=seed0 + i, lr=1e-3)
             tr.fit_stats(lg)
             ls = []
             for it in range(args.adam_steps):
@@ -344,10 +345,13 @@ def main():
             trainers.append(tr)
             final_loss.append(float(np.mean(ls[-20:])))
         torch.cuda.synchronize()
-        warm = WarmStart([t.net for t in trainers])
-        out["extra"]["learned_training"] = {"samples_per_stage": logs.logs[0].count, "adam_steps_per_stage": args.adam_steps,
-                                            "batch": args.batch, "final_mse_normalised": final_loss,
-                                            "train_s": time.perf_counter() - t_tr}
+        info = {"samples_per_stage": stage_logs.logs[0].count, "adam_steps_per_stage": args.adam_steps,
+                "batch": args.batch, "final_mse_normalised": final_loss, "train_s": time.perf_counter() - t_tr}
+        return WarmStart([t.net for t in trainers]), info
+
+    warm = None
+    if learned and args.warmup > 0:
+        warm, out["extra"]["learned_training"] = train(logs, 4)
 
     # ---- (3) timed legs from the same state
     t_phys = args.steps * dt
@@ -393,7 +397,8 @@ def main():
         schemes = {}
 
         def scheme_leg(step):
-            tot = {"gmres_iters": 0, "ptc_iters": 0, "rejections": 0, "residual_evals": 0}
+            tot = {"gmres_iters": 0, "ptc_iters": 0, "rejections": 0, "residual_evals": 0, "warm_used": 0,
+                   "warm_rejected": 0}
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             Ux = step(tot)
@@ -402,7 +407,8 @@ def main():
             return {"ms_per_step": w / args.steps * 1e3, "wall_s_per_time_unit": w / t_phys,
                     "gmres_iters_per_step": tot["gmres_iters"] / args.steps,
                     "ptc_iters_per_step": tot["ptc_iters"] / args.steps, "rejections": tot["rejections"],
-                    "residual_evals_per_step": tot["residual_evals"] / args.steps, "l2_err_rho": err(Ux)}
+                    "residual_evals_per_step": tot["residual_evals"] / args.steps, "l2_err_rho": err(Ux),
+                    "learned_starts_used": tot["warm_used"], "learned_starts_rejected": tot["warm_rejected"]}
 
         def add(tot, st, name):
             if st["status"] != 0:
@@ -412,17 +418,21 @@ def main():
 
         ek = 4 if scheme == 4 else 3   # the ESDIRK of the same order as the ROW scheme (3 or 4)
 
-        def esdirk(o):
+        def esdirk(o, hist=None):
             def run(tot):
                 Ux = Ustart.clone()
+                if hist is not None:
+                    o.yhist = hist.clone()
                 for _ in range(args.steps):
                     add(tot, disc.esdirk_step(Ux, ek, dt, o), "esdirk_step")
                 return Ux
             return run
 
-        def bdf2(o):
+        def bdf2(o, hist=None):
             def run(tot):
                 Unm1, Un = None, Ustart.clone()
+                if hist is not None:
+                    o.yhist = hist.clone()
                 for _ in range(args.steps):
                     Unp1, st = disc.bdf2_step(Unm1, Un, dt, o)
                     add(tot, st, "bdf2_step")
@@ -436,6 +446,36 @@ def main():
         schemes[f"ESDIRK{ek}, FP32 element-Jacobi"] = scheme_leg(esdirk(sopts32))
         schemes["BDF2 (BDF1 start)"] = scheme_leg(bdf2(sopts))
         schemes["BDF2 (BDF1 start), FP32 element-Jacobi"] = scheme_leg(bdf2(sopts32))
+        if learned and args.warmup > 0:
+            # learned PTC starts: a logging run of each scheme from t = 0 (FP32 element-Jacobi),
+            # one network per implicit stage trained on it, then the timed leg from the same
+            # state as the other legs
+            n_imp = len(scheme_table(1, ek)[2]) - 1
+            for name, nst, kind in ((f"ESDIRK{ek}", n_imp, "esdirk"), ("BDF2 (BDF1 start)", 1, "bdf2")):
+                slogs = StageLogs([StageLog(disc, args.warmup * per_stage, rng.choice(disc.nel, per_stage,
+                                                                                     replace=False))
+                                   for _ in range(nst)])
+                h = torch.zeros((2, ndof), dtype=torch.float64, device=dev)
+                o_log = SolverOpts(lin=GmresOpts(m=20, rtol=1e-1), tol_nl=1e-8, precond_precision=F32, log=slogs,
+                                   yhist=h)
+                Ux, Um1 = U0.clone(), None
+                for _ in range(args.warmup):
+                    for lg in slogs.logs:
+                        lg.set_elems(rng.choice(disc.nel, per_stage, replace=False))
+                    if kind == "esdirk":
+                        st = disc.esdirk_step(Ux, ek, dt, o_log)
+                    else:
+                        Unew, st = disc.bdf2_step(Um1, Ux, dt, o_log)
+                        Um1, Ux = Ux, Unew
+                    if st["status"] != 0:
+                        raise RuntimeError(f"{kind} logging step status {st['status']}")
+                wnet, info = train(slogs, 20 if kind == "esdirk" else 40)
+                o_w = SolverOpts(lin=GmresOpts(m=20, rtol=1e-1), tol_nl=1e-8, precond_precision=F32, warm=wnet)
+                leg = scheme_leg(esdirk(o_w, h) if kind == "esdirk" else bdf2(o_w, h))
+                leg["speedup_vs_plain_fp64"] = schemes[name]["ms_per_step"] / leg["ms_per_step"]
+                leg["learned_training"] = {"samples_per_stage": info["samples_per_stage"],
+                                           "final_mse_normalised": info["final_mse_normalised"]}
+                schemes[f"{name}, FP32 element-Jacobi + learned start"] = leg
         out["extra"]["schemes"] = schemes
 
     if not args.no_kernels:

@@ -240,14 +240,20 @@ typedef struct {
   int max_reject;        /* PTC rejections per stage; <= 0 means 30 */
   int precond_precision; /* FR_F64 or FR_F32 element-Jacobi */
   int commit_unconverged;/* 1: apply the update even if a linear/nonlinear solve did not converge */
-  /* ROW only: */
-  const fr_mlp* warm;    /* NULL, or one network per stage: stage i starts GMRES from its
-                            prediction; if that guess's residual is not below ||b|| (the zero
-                            guess's), GMRES starts from zero instead.  The tolerance stays
-                            relative to ||b|| in both cases. */
-  fr_stage_log* log;     /* NULL, or one log per stage (training data) */
-  double* d_yhist;       /* NULL, or 2 x ndof: in, the previous step's last two stage
-                            increments (Y_{s-2}, Y_{s-1}); out, this step's.  NULL = zeros. */
+  /* Learned starts (an addition to the method).  ROW: one network per stage; stage i
+     starts GMRES from its prediction of Y_i; if that guess's residual is not below ||b||
+     (the zero guess's), GMRES starts from zero instead, the tolerance staying relative to
+     ||b||.  ESDIRK: one network per implicit stage (s - 1); BDF2: one network; the
+     prediction y of the increment q_i - q^n gives a second PTC starting point q^n + y,
+     used when its ||F|| is below that of the plain start (q_{i-1}, or q^n), the
+     nonlinear tolerance staying relative to the plain start's ||F||.  Network inputs:
+     q^n, R(q^n) and the two previous increments (stage increments Y or q_j - q^n; for
+     the first stages, and for BDF2, the previous step's, from d_yhist). */
+  const fr_mlp* warm;    /* NULL, or the networks */
+  fr_stage_log* log;     /* NULL, or one log per (implicit) stage: training samples after
+                            each converged stage */
+  double* d_yhist;       /* NULL, or 2 x ndof: in, the previous step's last two increments
+                            (older first); out, this step's.  NULL = zeros. */
   void* d_mlp_work;      /* fr_mlp_work_bytes bytes when warm != NULL */
 } fr_solver_opts;
 

@@ -65,9 +65,9 @@ class SolverOpts:
     max_reject: int = 0
     precond_precision: int = F64
     commit_unconverged: int = 0
-    warm: "WarmStart" = None          # ROW: learned initial guesses, one network per stage
-    log: "StageLogs" = None           # ROW: log training samples after each stage solve
-    yhist: torch.Tensor = None        # ROW: (2, ndof) previous step's last two increments (in/out)
+    warm: "WarmStart" = None          # learned starts, one network per (implicit) stage
+    log: "StageLogs" = None           # log training samples after each (implicit) stage solve
+    yhist: torch.Tensor = None        # (2, ndof) previous step's last two increments (in/out)
 
     def c(self):
         lin = self.lin or GmresOpts()
@@ -239,15 +239,18 @@ class Disc:
         lin = opts.lin or GmresOpts()
         return self.workspace(L.WS_STEP, lin.m, opts.precond_precision)
 
+    def _check_hist(self, opts):
+        if opts.yhist is not None:
+            self._vec(opts.yhist.view(-1)[: self.ndof], "yhist")
+            if opts.yhist.numel() != 2 * self.ndof or not opts.yhist.is_contiguous():
+                raise ValueError("yhist: expected a contiguous (2, ndof) float64 tensor")
+
     def row_step(self, U, scheme, dt, opts=None):
         opts = opts or SolverOpts(lin=GmresOpts())
         self._vec(U, "U")
         st = L.StepStatsC()
         oc = opts.c()
-        if opts.yhist is not None:
-            self._vec(opts.yhist.view(-1)[: self.ndof], "yhist")
-            if opts.yhist.numel() != 2 * self.ndof or not opts.yhist.is_contiguous():
-                raise ValueError("yhist: expected a contiguous (2, ndof) float64 tensor")
+        self._check_hist(opts)
         status = self.lib.fr_row_step(self.handle, int(scheme), dt, _ptr(U), ctypes.byref(oc), ctypes.byref(st),
                                       _ptr(self._step_ws(opts)), _stream())
         _check("fr_row_step", status, allow_numerical=True)
@@ -260,9 +263,12 @@ class Disc:
         self._vec(U, "U")
         st = L.StepStatsC()
         oc = opts.c()
+        self._check_hist(opts)
         status = self.lib.fr_esdirk_step(self.handle, int(scheme), dt, _ptr(U), ctypes.byref(oc), ctypes.byref(st),
                                          _ptr(self._step_ws(opts)), _stream())
         _check("fr_esdirk_step", status, allow_numerical=True)
+        if opts.log is not None:
+            opts.log.pull()
         return dict(_stats(st), status=status)
 
     def bdf2_step(self, Unm1, Un, dt, opts=None, out=None):
@@ -273,9 +279,12 @@ class Disc:
         out = self.empty() if out is None else self._vec(out, "out")
         st = L.StepStatsC()
         oc = opts.c()
+        self._check_hist(opts)
         status = self.lib.fr_bdf2_step(self.handle, dt, _ptr(Unm1), _ptr(Un), _ptr(out), ctypes.byref(oc),
                                        ctypes.byref(st), _ptr(self._step_ws(opts)), _stream())
         _check("fr_bdf2_step", status, allow_numerical=True)
+        if opts.log is not None:
+            opts.log.pull()
         return out, dict(_stats(st), status=status)
 
     def l2_error_vortex(self, U, var, t, vortex):

@@ -104,7 +104,8 @@ size_t fr_workspace_bytes(const fr_disc* d, int what, int m, int precision) {
     case FR_WS_MATVEC: return tr + small_bytes(d);
     case FR_WS_GMRES: return gmres_bytes(d, m < 1 ? 1 : m);
     case FR_WS_STEP:
-      return gmres_bytes(d, m < 1 ? 1 : m) + ((fr_ejacobi_bytes(d, precision) + 255) & ~(size_t)255) + 12 * vec;
+      return gmres_bytes(d, m < 1 ? 1 : m) + ((fr_ejacobi_bytes(d, precision) + 255) & ~(size_t)255) +
+             kStepVecs * vec;
   }
   return 0;
 }

@@ -121,6 +121,8 @@ hipError_t launch_solution_points(const fr_disc* d, double* xy, hipStream_t s);
 hipError_t launch_l2_vortex(const fr_disc* d, const double* U, int var, double t, const double* prm,
                             double* partials, double* out, hipStream_t s);
 
+// State vectors of a time step's workspace (stage vectors, PTC state, increments).
+constexpr int kStepVecs = 15;
 constexpr int kRedBlocks = 1024;  // blocks of the grid-stride vector kernels
 constexpr int kRedThreads = 256;
 

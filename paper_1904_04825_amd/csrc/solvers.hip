@@ -454,7 +454,7 @@ namespace {
 struct StepBufs {
   GmWork gw;
   void* pc;
-  double* vec[12];
+  double* vec[kStepVecs];
 };
 
 StepBufs carve_step(const fr_disc* d, void* work, int m, int precision) {
@@ -462,7 +462,7 @@ StepBufs carve_step(const fr_disc* d, void* work, int m, int precision) {
   StepBufs b{};
   b.gw = carve_gmres(c, d, m);
   b.pc = c.take(fr_ejacobi_bytes(d, precision));
-  for (int i = 0; i < 12; ++i) b.vec[i] = (double*)c.take(sizeof(double) * d->ndof);
+  for (int i = 0; i < kStepVecs; ++i) b.vec[i] = (double*)c.take(sizeof(double) * d->ndof);
   return b;
 }
 
@@ -505,9 +505,12 @@ fr_status lincomb_v(double* y, int k, const double* const* xs, const double* cs,
   } while (0)
 
 // PTC for F(q) = (q - cst)/(omega dt) - R(q) = 0, in place on q; Rq holds R(q) on entry
-// (if rq_valid) and on exit.
+// (if rq_valid) and on exit.  q_alt (may be null): a second starting point (the learned
+// guess); PTC starts from it when its ||F|| is below that of q, and the stopping test
+// stays relative to ||F(q)|| either way.  R_alt: scratch for R(q_alt).
 fr_status ptc_solve(const fr_disc* d, const double* cst, double omega_dt, double dt, double* q, double* Rq,
-                    bool rq_valid, const fr_solver_opts& o, StepBufs& B, fr_step_stats* st, hipStream_t s) {
+                    bool rq_valid, const fr_solver_opts& o, StepBufs& B, fr_step_stats* st, hipStream_t s,
+                    const double* q_alt = nullptr, double* R_alt = nullptr) {
   const size_t n = d->ndof;
   double* negF = B.vec[9];
   double* dq = B.vec[10];
@@ -520,6 +523,22 @@ fr_status ptc_solve(const fr_disc* d, const double* cst, double omega_dt, double
   double nF = 0.0;
   FR_TRY(device_norm(d, negF, B.gw.partials, B.gw.scal + 2, &nF, s));
   const double nF0 = nF;
+  if (q_alt != nullptr) {
+    FR_TRY(residual_into(d, q_alt, R_alt, B.gw.grad, s));
+    st->residual_evals++;
+    FR_TRY(lincomb(dq, {{cst, iw}, {q_alt, -iw}, {R_alt, 1.0}}, n, s));
+    double nFa = 0.0;
+    FR_TRY(device_norm(d, dq, B.gw.partials, B.gw.scal + 2, &nFa, s));
+    if (nFa < nF) {
+      FR_TRY(lincomb(q, {{q_alt, 1.0}}, n, s));
+      FR_TRY(lincomb(Rq, {{R_alt, 1.0}}, n, s));
+      FR_TRY(lincomb(negF, {{dq, 1.0}}, n, s));
+      nF = nFa;
+      st->warm_used++;
+    } else {
+      st->warm_rejected++;
+    }
+  }
   double dtau = o.dtau_init > 0 ? o.dtau_init : dt;
   double dtau_max = o.dtau_max > 0 ? o.dtau_max : 1e20;
   const int max_ptc = o.max_ptc > 0 ? o.max_ptc : 200;
@@ -678,6 +697,15 @@ fr_status esdirk_step_impl(const fr_disc* d, int scheme, double dt, double* U, c
   FR_TRY(residual_into(d, U, Rj[0], B.gw.grad, s));
   st->residual_evals++;
   FR_TRY(lincomb(q, {{U, 1.0}}, n, s));
+  // learned start (warm: one network per implicit stage) and logging: the stage
+  // increments q_i - q^n of the two previous stages, reaching back into the previous
+  // step's last two (d_yhist) for the first implicit stages
+  const bool incs = o.warm != nullptr || o.log != nullptr || o.d_yhist != nullptr;
+  double* inc[2] = {B.vec[12], B.vec[13]};  // increment of stage i at inc[i & 1]
+  double* cand = B.vec[14];
+  double* R_alt = B.vec[8];
+  const double* hist_last = o.d_yhist ? o.d_yhist + n : nullptr;
+  const double* hist_prev = o.d_yhist ? o.d_yhist : nullptr;
   fr_status worst = FR_OK;
   for (int i = 1; i < T->s; ++i) {
     const double* xs[8];
@@ -692,10 +720,22 @@ fr_status esdirk_step_impl(const fr_disc* d, int scheme, double dt, double* U, c
       }
     FR_TRY(lincomb_v(cst, k, xs, cs, n, s));
     FR_TRY(lincomb(Rj[i], {{Rj[i - 1], 1.0}}, n, s));  // R(q) at the stage's starting guess q_{i-1}
-    fr_status p = ptc_solve(d, cst, T->gamma * dt, dt, q, Rj[i], true, o, B, st, s);
+    const double* Y1 = i >= 2 ? inc[(i - 1) & 1] : hist_last;
+    const double* Y2 = i >= 3 ? inc[(i - 2) & 1] : (i == 2 ? hist_last : hist_prev);
+    const double* q_alt = nullptr;
+    if (o.warm != nullptr) {
+      FR_HIP(mlp_infer(d, &o.warm[i - 1], U, Rj[0], Y1, Y2, dt, cand, o.d_mlp_work, s));
+      FR_TRY(lincomb(cand, {{U, 1.0}, {cand, 1.0}}, n, s));
+      q_alt = cand;
+    }
+    fr_status p = ptc_solve(d, cst, T->gamma * dt, dt, q, Rj[i], true, o, B, st, s, q_alt, R_alt);
     if (p < 0) return p;
     if (p != FR_OK && worst == FR_OK) worst = p;
     if (p == FR_ENAN || (p != FR_OK && !o.commit_unconverged)) break;  // the step will not be committed
+    if (incs) {
+      FR_TRY(lincomb(inc[i & 1], {{q, 1.0}, {U, -1.0}}, n, s));
+      if (o.log != nullptr && p == FR_OK) FR_HIP(mlp_log(d, &o.log[i - 1], U, Rj[0], Y1, Y2, inc[i & 1], dt, s));
+    }
   }
   if (worst == FR_OK || (o.commit_unconverged && worst != FR_ENAN)) {
     const double* xs[8];
@@ -709,6 +749,10 @@ fr_status esdirk_step_impl(const fr_disc* d, int scheme, double dt, double* U, c
         cs[k++] = dt * T->b[i];
       }
     FR_TRY(lincomb_v(U, k, xs, cs, n, s));
+    if (o.d_yhist != nullptr) {
+      FR_TRY(lincomb(o.d_yhist, {{inc[(T->s - 2) & 1], 1.0}}, n, s));
+      FR_TRY(lincomb(o.d_yhist + n, {{inc[(T->s - 1) & 1], 1.0}}, n, s));
+    }
   }
   FR_HIP(hipStreamSynchronize(s));
   st->wall_s = now_s() - t0;
@@ -732,8 +776,37 @@ fr_status bdf2_step_impl(const fr_disc* d, double dt, const double* Unm1, const 
     FR_TRY(lincomb(cst, {{Un, 4.0 / 3.0}, {Unm1, -1.0 / 3.0}}, n, s));
   }
   FR_TRY(lincomb(q, {{Un, 1.0}}, n, s));
-  fr_status p = ptc_solve(d, cst, omega * dt, dt, q, Rq, false, o, B, st, s);
+  // learned start and logging: the increment q^{n+1} - q^n predicted from q^n, R(q^n)
+  // and the previous two step increments (d_yhist)
+  const bool incs = o.warm != nullptr || o.log != nullptr || o.d_yhist != nullptr;
+  const double* Y1 = o.d_yhist ? o.d_yhist + n : nullptr;
+  const double* Y2 = o.d_yhist ? o.d_yhist : nullptr;
+  double* inc = B.vec[12];
+  double* cand = B.vec[14];
+  double* R_alt = B.vec[8];
+  const double* q_alt = nullptr;
+  bool rq_valid = false;
+  if (incs) {
+    FR_TRY(residual_into(d, q, Rq, B.gw.grad, s));  // R(q^n): features, and PTC's start
+    st->residual_evals++;
+    rq_valid = true;
+  }
+  if (o.warm != nullptr) {
+    FR_HIP(mlp_infer(d, &o.warm[0], Un, Rq, Y1, Y2, dt, cand, o.d_mlp_work, s));
+    FR_TRY(lincomb(cand, {{Un, 1.0}, {cand, 1.0}}, n, s));
+    q_alt = cand;
+  }
+  if (o.log != nullptr) FR_TRY(lincomb(B.vec[13], {{Rq, 1.0}}, n, s));  // R(q^n) kept for the log
+  fr_status p = ptc_solve(d, cst, omega * dt, dt, q, Rq, rq_valid, o, B, st, s, q_alt, R_alt);
   if (p < 0) return p;
+  if (incs && (p == FR_OK || (o.commit_unconverged && p != FR_ENAN))) {
+    FR_TRY(lincomb(inc, {{q, 1.0}, {Un, -1.0}}, n, s));
+    if (o.log != nullptr && p == FR_OK) FR_HIP(mlp_log(d, &o.log[0], Un, B.vec[13], Y1, Y2, inc, dt, s));
+    if (o.d_yhist != nullptr) {
+      FR_TRY(lincomb(o.d_yhist, {{o.d_yhist + n, 1.0}}, n, s));
+      FR_TRY(lincomb(o.d_yhist + n, {{inc, 1.0}}, n, s));
+    }
+  }
   if (p == FR_OK || (o.commit_unconverged && p != FR_ENAN)) FR_TRY(lincomb(Unp1, {{q, 1.0}}, n, s));
   FR_HIP(hipStreamSynchronize(s));
   st->wall_s = now_s() - t0;

@@ -162,3 +162,64 @@ def test_row3_learned_warm_start():
           f"(guesses used {used}, rejected {rej})", flush=True)
     assert it_w <= 1.05 * it_p
     assert rel(to_np(Uw), to_np(Up)) <= 1e-7
+
+
+def _train(disc, logs, rng, steps=400):
+    from paper_1904_04825_amd import MlpTrainer, WarmStart
+    trainers = []
+    for i, lg in enumerate(logs.logs):
+        tr = MlpTrainer(disc, n_hidden=256, seed=14 + i, lr=1e-3)
+        tr.fit_stats(lg)
+        losses = [tr.step(lg, torch.as_tensor(rng.choice(lg.count, 512, replace=False), dtype=torch.int32,
+                                              device="cuda")) for _ in range(steps)]
+        assert np.mean(losses[-20:]) < 0.5 * losses[0]
+        trainers.append(tr)
+    return WarmStart([t.net for t in trainers])
+
+
+@pytest.mark.parametrize("kind", ["esdirk3", "bdf2"])
+def test_ptc_learned_start(kind):
+    """ESDIRK3 and BDF2: log the converged stage increments, train one network per
+    implicit stage, then start PTC from the learned guess where its ||F|| is smaller.
+    Same nonlinear tolerance (relative to the plain start's ||F||): the states agree
+    with the plain run's within the tolerance, and PTC needs no more iterations."""
+    from paper_1904_04825_amd import GmresOpts, SolverOpts, StageLog, StageLogs
+    _, op, disc = setup(16, 16, 3, "rusanov", seed=2)
+    U0 = to_gpu(vortex_state(op, 0.0))
+    dt, nst = 0.1, (3 if kind == "esdirk3" else 1)
+    rng = np.random.default_rng(41)
+    logs = StageLogs([StageLog(disc, 6000, rng.choice(disc.nel, 200, replace=False)) for _ in range(nst)])
+    yh = torch.zeros((2, disc.ndof), dtype=torch.float64, device="cuda")
+    lin = GmresOpts(m=20, rtol=1e-1)
+
+    def step(U, Um1, opts):
+        if kind == "esdirk3":
+            st = disc.esdirk_step(U, 3, dt, opts)
+            return U, None, st
+        Un1, st = disc.bdf2_step(Um1, U, dt, opts)
+        return Un1, U, st
+
+    U, Um1 = U0.clone(), None
+    for n in range(24):
+        for lg in logs.logs:
+            lg.set_elems(rng.choice(disc.nel, 200, replace=False))
+        U, Um1, st = step(U, Um1, SolverOpts(lin=lin, tol_nl=1e-8, log=logs, yhist=yh))
+        assert st["status"] == 0
+    assert all(lg.count == 24 * 200 for lg in logs.logs)
+    warm = _train(disc, logs, rng)
+    Up, Upm1, hp = U.clone(), (Um1.clone() if Um1 is not None else None), yh.clone()
+    Uw, Uwm1, hw = U.clone(), (Um1.clone() if Um1 is not None else None), yh.clone()
+    ptc_p = ptc_w = used = 0
+    for n in range(6):
+        Up, Upm1, sp = step(Up, Upm1, SolverOpts(lin=lin, tol_nl=1e-8, yhist=hp))
+        Uw, Uwm1, sw = step(Uw, Uwm1, SolverOpts(lin=lin, tol_nl=1e-8, yhist=hw, warm=warm))
+        assert sp["status"] == 0 and sw["status"] == 0
+        ptc_p += sp["ptc_iters"]
+        ptc_w += sw["ptc_iters"]
+        used += sw["warm_used"]
+        assert sw["warm_used"] + sw["warm_rejected"] == nst
+    print(f"{kind}: PTC iterations over 6 steps: plain {ptc_p}, learned start {ptc_w} (guesses used {used})",
+          flush=True)
+    assert used >= 3
+    assert ptc_w <= ptc_p
+    assert rel(to_np(Uw), to_np(Up)) <= 1e-6
