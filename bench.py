@@ -11,7 +11,9 @@ Phases: (1) untimed warm-up: `--warmup` plain steps from t = 0 that also log the
 stage solves (training data); (2) one network per ROW stage trained on the GPU
 from those logs; (3) timed: `--steps` steps from the warm-up's end state with the
 FP64 element-Jacobi (the headline `value`), then the same steps with the FP32
-MFMA element-Jacobi, then FP32 + learned warm start.
+MFMA element-Jacobi, then FP32 + learned warm start; (4) the ESDIRK (3, or 4 beside
+ROW4) and BDF2 legs from the same state: FP64, FP32, and FP32 + learned PTC starts
+(networks trained on a logging run of each scheme from t = 0).
 
 value = DOF-residuals/s = ndof x (residual evaluations incl. JF products) / wall time
 of the FP64 leg.  The JSON line also carries the dominant kernel's roofline (live
