@@ -368,16 +368,29 @@ __global__ void __launch_bounds__(kRedThreads) k_dcgs_dots(const double* __restr
   double acc[NA];
 #pragma unroll
   for (int t = 0; t < NA; ++t) acc[t] = 0.0;
-  for (size_t i = blockIdx.x * (size_t)kRedThreads + tid; i < n; i += (size_t)gridDim.x * kRedThreads) {
-    double vr[NV];
+  // the next entry's loads are issued before this entry's FMAs (one round trip per
+  // entry hidden behind the previous one)
+  const size_t stride = (size_t)gridDim.x * kRedThreads;
+  size_t i = blockIdx.x * (size_t)kRedThreads + tid;
+  double vr[NV], wi = 0.0, vji = 0.0;
+  auto load = [&](size_t k) {
 #pragma unroll
-    for (int t = 0; t < NV; ++t) vr[t] = V[(size_t)min(t, nv - 1) * n + i];
-    const double wi = w[i], vji = vj[i];
+    for (int t = 0; t < NV; ++t) vr[t] = V[(size_t)min(t, nv - 1) * n + k];
+    wi = w[k];
+    vji = vj[k];
+  };
+  if (i < n) load(i);
+  for (; i < n; i += stride) {
+    double cr[NV];
 #pragma unroll
-    for (int t = 0; t < NV; ++t) acc[t] = fma(vr[t], wi, acc[t]);
+    for (int t = 0; t < NV; ++t) cr[t] = vr[t];
+    const double cw = wi, cj = vji;
+    if (i + stride < n) load(i + stride);
 #pragma unroll
-    for (int t = 0; t + 1 < NV; ++t) acc[NV + t] = fma(vr[t], vji, acc[NV + t]);
-    acc[NA - 1] = fma(wi, wi, acc[NA - 1]);
+    for (int t = 0; t < NV; ++t) acc[t] = fma(cr[t], cw, acc[t]);
+#pragma unroll
+    for (int t = 0; t + 1 < NV; ++t) acc[NV + t] = fma(cr[t], cj, acc[NV + t]);
+    acc[NA - 1] = fma(cw, cw, acc[NA - 1]);
   }
   int off;
   if (wave_multi_sum<NA>(acc, off)) {
