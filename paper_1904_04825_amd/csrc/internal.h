@@ -198,11 +198,11 @@ hipError_t launch_finalize(const double* partials, int nblocks, int stride, int 
                            hipStream_t s);
 // Number of workgroups of the grid-stride reductions over n entries (<= kRedBlocks).
 int red_blocks(size_t n);
-// y from the rotated Hessenberg matrix and x += Z y for the st->j columns of the cycle
-// (both return at once after NaN); M bounds st->j.
-hipError_t launch_gm_solve_y(GmState* st, int M, hipStream_t s);
-hipError_t launch_gm_update_x(double* x, const double* Z, int M, const GmState* st, size_t n,
-                              hipStream_t s);
+// End of a cycle: y from the rotated Hessenberg matrix and x += Z y for the st->j
+// columns (x unchanged after NaN or without columns), with partial sums of ||x||^2 in
+// xpart (*nb_out of them, at most kRedBlocks; M bounds st->j).
+hipError_t launch_gm_update_x(double* x, const double* Z, int M, const GmState* st, size_t n, double* xpart,
+                              int* nb_out, hipStream_t s);
 
 // learned warm start (mlp.hip)
 size_t mlp_weight_elems(int In, int H, int Out);

@@ -392,11 +392,12 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
     // the cycle's end is enqueued without waiting for its status: y and x += Z y
     // (skipped after NaN), then the true residual r = b - A x for a restart (skipped
     // once converged or NaN); one host round trip reads the status and ||r||^2
-    FR_HIP(launch_gm_solve_y(W.st, m, s));
-    FR_HIP(launch_gm_update_x(x, W.Z, m, W.st, n, s));
+    int nbx = 0;
+    FR_HIP(launch_gm_update_x(x, W.Z, m, W.st, n, W.partials, &nbx, s));
     const int* done = &W.st->done;
-    FR_HIP(launch_norm2(x, n, W.partials, nz, done, s));
     ResArgs a2 = ra;
+    a2.nrm2_part = W.partials;  // ||x||^2 from the update's partial sums
+    a2.nrm2_nb = nbx;
     a2.V = x;
     a2.B = b;
     a2.out = W.r;

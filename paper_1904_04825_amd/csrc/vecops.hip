@@ -590,71 +590,92 @@ hipError_t launch_gm_start(GmState* st, const double* beta2, double target, int 
   return hipGetLastError();
 }
 
-// y = H(0:k,0:k)^{-1} g(0:k) by back substitution (upper triangular after the rotations)
-// One wavefront: the triangle staged in LDS ([column][row]), lane i holds the right-hand
-// side of row i; column c's y_c = r_c / R_cc is broadcast and removed from the rows
-// above it in one step.
-__global__ void __launch_bounds__(64) k_gm_solve_y(GmState* st, int M) {
-  __shared__ double R[kMaxM][kMaxM + 1];
-  const int k = st->j;
-  if (st->why == 3 || k <= 0) return;
-  const int lane = threadIdx.x;
-  const int ld = M + 1;
-  for (int c = 0; c < k; ++c)
-    if (lane <= c) R[c][lane] = st->H[(size_t)c * ld + lane];
-  double r = lane < k ? st->g[lane] : 0.0;
-  __syncthreads();
-  for (int c = k - 1; c >= 0; --c) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(r), c), hi = __builtin_amdgcn_readlane(__double2hiint(r), c);
-    const double yc = __hiloint2double(hi, lo) / R[c][c];
-    if (lane == c) st->y[c] = yc;
-    if (lane < c) r = fma(-R[c][lane], yc, r);
-  }
-}
-
-hipError_t launch_gm_solve_y(GmState* st, int M, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_solve_y, dim3(1), dim3(64), 0, s, st, M);
-  return hipGetLastError();
-}
-
-// x += sum_t y_t Z_t, k = st->j.  NV > 0: the k <= NV columns of an entry loaded
-// together into registers (slots t >= k re-read column k-1 with weight 0); NV = 0: a
-// plain loop.
+// End of a cycle: x += sum_t y_t Z_t with y = H(0:k,0:k)^{-1} g(0:k), k = st->j (H is
+// upper triangular after the rotations), and per-workgroup partial sums of ||x||^2 for
+// the epsilon of the restart's true residual.  Every workgroup solves the small system
+// itself: all threads stage the triangle in LDS ([column][row]), then one wavefront
+// back-substitutes (lane i holds the right-hand side of row i; column c's
+// y_c = r_c / R_cc is broadcast and removed from the rows above it) while the first
+// entries of Z are on their way.  NV > 0: the k <= NV columns of an entry loaded
+// together (slots t >= k re-read column k-1 with weight 0); NV = 0: a plain loop.
+// After NaN (why = 3) or with k = 0, x is left as it is.
 template <int NV>
 __global__ void __launch_bounds__(256) k_gm_update_x(double* __restrict__ x, const double* __restrict__ Z,
-                                                     const GmState* st, size_t n) {
-  const int k = st->j;
-  if (st->why == 3 || k <= 0) return;
+                                                     const GmState* st, int M, size_t n, double* __restrict__ xpart) {
+  __shared__ double R[kMaxM][kMaxM + 1];
   __shared__ double sy[kMaxM];
-  if (threadIdx.x < kMaxM) sy[threadIdx.x] = (int)threadIdx.x < k ? st->y[threadIdx.x] : 0.0;
-  __syncthreads();
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    double s = x[i];
-    if constexpr (NV > 0) {
-      double zr[NV];
+  __shared__ double red[4];
+  const int k = st->j;
+  const bool upd = !(st->why == 3 || k <= 0);
+  const int tid = threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i = blockIdx.x * (size_t)blockDim.x + tid;
+  double zr[NV > 0 ? NV : 1];
+  if constexpr (NV > 0) {
+    if (upd && i < n) {
 #pragma unroll
       for (int t = 0; t < NV; ++t) zr[t] = Z[(size_t)min(t, k - 1) * n + i];
-#pragma unroll
-      for (int t = 0; t < NV; ++t) s = fma(sy[t], zr[t], s);
-    } else {
-      for (int t = 0; t < k; ++t) s = fma(sy[t], Z[(size_t)t * n + i], s);
     }
-    x[i] = s;
   }
+  if (upd) {
+    const int ld = M + 1;
+    for (int idx = tid; idx < k * k; idx += blockDim.x) {
+      const int c = idx / k, r = idx - c * k;
+      if (r <= c) R[c][r] = st->H[(size_t)c * ld + r];
+    }
+    if (tid < kMaxM) sy[tid] = 0.0;
+    __syncthreads();
+    if (tid < 64) {
+      double r = tid < k ? st->g[tid] : 0.0;
+      for (int c = k - 1; c >= 0; --c) {
+        const int lo = __builtin_amdgcn_readlane(__double2loint(r), c), hi = __builtin_amdgcn_readlane(__double2hiint(r), c);
+        const double yc = __hiloint2double(hi, lo) / R[c][c];
+        if (tid == c) sy[c] = yc;
+        if (tid < c) r = fma(-R[c][tid], yc, r);
+      }
+    }
+    __syncthreads();
+  }
+  double acc = 0.0;
+  for (; i < n; i += stride) {
+    double s = x[i];
+    if (upd) {
+      if constexpr (NV > 0) {
+#pragma unroll
+        for (int t = 0; t < NV; ++t) s = fma(sy[t], zr[t], s);
+        if (i + stride < n) {
+#pragma unroll
+          for (int t = 0; t < NV; ++t) zr[t] = Z[(size_t)min(t, k - 1) * n + i + stride];
+        }
+      } else {
+        for (int t = 0; t < k; ++t) s = fma(sy[t], Z[(size_t)t * n + i], s);
+      }
+      x[i] = s;
+    }
+    acc = fma(s, s, acc);
+  }
+  acc = wave_sum(acc);
+  if ((tid & 63) == 0) red[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0) xpart[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-hipError_t launch_gm_update_x(double* x, const double* Z, int M, const GmState* st, size_t n, hipStream_t s) {
-  const dim3 g(red_blocks(n)), b(256);
+hipError_t launch_gm_update_x(double* x, const double* Z, int M, const GmState* st, size_t n, double* xpart,
+                              int* nb_out, hipStream_t s) {
+  if (M < 1 || M > kMaxM) return hipErrorInvalidValue;
+  const int nb = red_blocks(n);
+  *nb_out = nb;
+  const dim3 g(nb), b(256);
   if (M <= 8)
-    hipLaunchKernelGGL((k_gm_update_x<8>), g, b, 0, s, x, Z, st, n);
+    hipLaunchKernelGGL((k_gm_update_x<8>), g, b, 0, s, x, Z, st, M, n, xpart);
   else if (M <= 16)
-    hipLaunchKernelGGL((k_gm_update_x<16>), g, b, 0, s, x, Z, st, n);
+    hipLaunchKernelGGL((k_gm_update_x<16>), g, b, 0, s, x, Z, st, M, n, xpart);
   else if (M <= 24)
-    hipLaunchKernelGGL((k_gm_update_x<24>), g, b, 0, s, x, Z, st, n);
+    hipLaunchKernelGGL((k_gm_update_x<24>), g, b, 0, s, x, Z, st, M, n, xpart);
   else if (M <= 32)
-    hipLaunchKernelGGL((k_gm_update_x<32>), g, b, 0, s, x, Z, st, n);
+    hipLaunchKernelGGL((k_gm_update_x<32>), g, b, 0, s, x, Z, st, M, n, xpart);
   else
-    hipLaunchKernelGGL((k_gm_update_x<0>), g, b, 0, s, x, Z, st, n);
+    hipLaunchKernelGGL((k_gm_update_x<0>), g, b, 0, s, x, Z, st, M, n, xpart);
   return hipGetLastError();
 }
 
