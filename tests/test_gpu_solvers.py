@@ -34,6 +34,31 @@ def test_gmres_parity(P, m):
     assert rel(to_np(xg), xo) <= 10 * rtol * 100
 
 
+# A shift so large that s + O(|J|) rounds to s: the JF product is s z and the element-Jacobi
+# inverse I / s to the last bit, so A M^{-1} is the identity, the first Arnoldi step leaves
+# w' at rounding level and the Krylov space is invariant after one step.  Both
+# orthogonalisations (DCGS2, m = 20; CGS2, m = 40) report a breakdown after that step with
+# the exact least-squares solution x = b / s; the oracle stops there as converged.
+@pytest.mark.parametrize("m", [20, 40])
+def test_gmres_breakdown_on_invariant_krylov_space(m):
+    from paper_1904_04825_amd import F64, GmresOpts
+    _, op, disc = setup(4, 4, 2, "rusanov", seed=15)
+    U = vortex_state(op)
+    R0 = op.residual(U)
+    shift = 1e30
+    b = fi.random_vector(U.shape, seed=24)
+    pc_o = linear.ElementJacobi(op, U, shift)
+    xo, so = linear.fgmres(lambda v: linear.jf_matvec(op.residual, U, R0, v, shift), pc_o.apply, b, m=m, rtol=0.0)
+    Ug = to_gpu(U)
+    pc = disc.ejacobi_factor(Ug, shift, F64)
+    xg, sg = disc.gmres_solve(pc, Ug, to_gpu(R0), shift, to_gpu(b), opts=GmresOpts(m=m, rtol=0.0))
+    print(m, "oracle", so, "gpu", sg, flush=True)
+    assert so.iters == 1 and so.converged
+    assert sg["status"] == 2 and sg["iters"] == 1 and sg["restarts"] == 0
+    assert rel(to_np(xg), b / shift) <= 1e-14
+    assert rel(to_np(xg), xo) <= 1e-14
+
+
 def test_gmres_nonzero_initial_guess_and_restart():
     from paper_1904_04825_amd import F64, GmresOpts
     _, op, disc = setup(6, 6, 2, "rusanov", seed=13)

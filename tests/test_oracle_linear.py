@@ -84,6 +84,19 @@ def test_fgmres_full_space_equals_dense_solve(n):
     assert np.linalg.norm(x - xd) <= kappa * 1e-13 * np.linalg.norm(xd)
 
 
+def test_fgmres_exact_preconditioner_breaks_down_after_one_step():
+    # M^{-1} = A^{-1}: A z_0 = v_0, so the first Arnoldi step leaves w' at rounding level,
+    # the Krylov space is invariant and x = A^{-1} b after one step even with rtol = 0
+    rng = np.random.default_rng(8)
+    n = 30
+    A = 2 * np.eye(n) + rng.standard_normal((n, n)) / np.sqrt(n)
+    Ainv = np.linalg.inv(A)
+    b = rng.standard_normal(n)
+    x, st = linear.fgmres(lambda v: A @ v, lambda r: Ainv @ r, b, m=20, rtol=0.0)
+    assert st.iters == 1 and st.converged and st.restarts == 0
+    assert np.linalg.norm(x - np.linalg.solve(A, b)) <= 1e-13 * np.linalg.cond(A) * np.linalg.norm(b)
+
+
 def test_fgmres_residual_estimate_monotone_and_true():
     rng = np.random.default_rng(5)
     n = 40
