@@ -50,14 +50,21 @@ template <bool BIG> struct LineTile<2, BIG> : TilePick<BIG, FRJF_TILE_P2> {};
 template <bool BIG> struct LineTile<3, BIG> : TilePick<BIG, FRJF_TILE_P3> {};
 template <bool BIG> struct LineTile<4, BIG> : TilePick<BIG, FRJF_TILE_P4> {};
 
+#ifndef FRJF_SPLIT_SMALL
+#define FRJF_SPLIT_SMALL 1
+#endif
 template <int P, bool BIG>
 struct LineCfg {
   static constexpr int n = P + 1, Np = n * n;
   // element stride of the LDS state: row writes and column reads without bank conflicts
   static constexpr int ES = (n == 4) ? Np + 3 : Np;
   static constexpr int TX = LineTile<P, BIG>::TX, TY = LineTile<P, BIG>::TY, NE = TX * TY;
-  static constexpr int NL = NE * n;                 // element lines = working threads
-  static constexpr int NT = (NL + 63) / 64 * 64;
+  static constexpr int NL = NE * n;                 // element lines
+  // small tiles: one set of wavefronts takes the rows (xi), another the columns (eta) of
+  // every element, so the two passes and their faces run side by side
+  static constexpr bool SPLIT = FRJF_SPLIT_SMALL && !BIG;
+  static constexpr int NTH = (NL + 63) / 64 * 64;   // threads of one role
+  static constexpr int NT = SPLIT ? 2 * NTH : NTH;
   static constexpr int NFX = TY * (TX + 1) * n;     // xi-face points
   static constexpr int NFE = (TY + 1) * TX * n;     // eta-face points
   static constexpr int NF = NFX + NFE;
@@ -323,10 +330,13 @@ __global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a
     }
     __syncthreads();
 
-    // ---- rows
-    const int le = tid / n, t = tid - le * n;
+    // ---- rows (with split roles, the first C::NTH threads; the others take the columns)
+    const bool colrole = C::SPLIT && tid >= C::NTH;
+    const int lt = colrole ? tid - C::NTH : tid;
+    const int le = lt / n, t = lt - le * n;
     const int lx = le % TX, ly = le / TX;
-    const bool live = tid < C::NL && lx < mX && ly < mY;
+    const bool live = lt < C::NL && lx < mX && ly < mY;
+    const bool rows = live && !colrole, cols = live && (colrole || !C::SPLIT);
     const double tp = pick<n>(B.x, t);  // eta of row t, xi of column t
     // bilinear map: x_xi = ax + bx eta, x_eta = cx + dx xi (and the same for y)
     double ax = 0, bx = 0, ay = 0, by = 0, cx = 0, dx = 0, cy = 0, dy = 0;
@@ -349,6 +359,8 @@ __global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a
       nW[1] = -0.5 * (c[4] - c[0]);
       nS[0] = -0.5 * (c[3] - c[1]);
       nS[1] = 0.5 * (c[2] - c[0]);
+    }
+    if (rows) {
       double q[n][4];
 #pragma unroll
       for (int cc = 0; cc < n; ++cc)
@@ -383,11 +395,11 @@ __global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a
         sT[v * NS + C::SE + le * n + t] = qE[v];
       }
     }
-    __syncthreads();
+    if constexpr (!C::SPLIT) __syncthreads();
 
     // ---- columns
     double dG[n][4], GlS[4], GlN[4];
-    if (live) {
+    if (cols) {
       const double xeta = fma(dx, tp, cx), yeta = fma(dy, tp, cy);
       double qS[4] = {0, 0, 0, 0}, qN[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -427,9 +439,9 @@ __global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a
     // Slots: xi-face point j of face f in tile row fy at (fy (TX+1) + f) n + j, then
     // eta-face point i of face row fy, column fx at NFX + (fy TX + fx) n + i.
     const int nstride = g.nx + 1;
-    if (live) {  // the west face point t and the south face point t of the thread's element
+    if (rows) {  // the west face point t of the thread's element
       double qL[4], qR[4], Fn[4];
-      int sL = (lx == 0) ? C::SHW + ly * n + t : C::SE + (le - 1) * n + t;
+      const int sL = (lx == 0) ? C::SHW + ly * n + t : C::SE + (le - 1) * n + t;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         qL[v] = sT[v * NS + sL];
@@ -439,7 +451,10 @@ __global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a
       const int fW = (ly * (TX + 1) + lx) * n + t;
 #pragma unroll
       for (int v = 0; v < 4; ++v) sA[v * NF + fW] = Fn[v];
-      sL = (ly == 0) ? C::SHS + lx * n + t : C::SN + (le - TX) * n + t;
+    }
+    if (cols) {  // the south face point t
+      double qL[4], qR[4], Fn[4];
+      const int sL = (ly == 0) ? C::SHS + lx * n + t : C::SN + (le - TX) * n + t;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         qL[v] = sT[v * NS + sL];
@@ -490,17 +505,22 @@ __global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a
     __syncthreads();
 
     // ---- corrections: rows take the W/E jumps, columns the S/N jumps
-    if (live) {
-      const int fW = (ly * (TX + 1) + lx) * n + t, fS = C::NFX + (ly * TX + lx) * n + t;
+    if (rows) {
+      const int fW = (ly * (TX + 1) + lx) * n + t;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const double jW = sA[v * NF + fW] - FlW[v], jE = sA[v * NF + fW + n] - FlE[v];
+#pragma unroll
+        for (int i = 0; i < n; ++i) dF[i][v] = fma(B.gL[i], jW, fma(B.gR[i], jE, dF[i][v]));
+      }
+    }
+    if (cols) {
+      const int fS = C::NFX + (ly * TX + lx) * n + t;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
         const double jS = sA[v * NF + fS] - GlS[v], jN = sA[v * NF + fS + TX * n] - GlN[v];
 #pragma unroll
-        for (int i = 0; i < n; ++i) {
-          dF[i][v] = fma(B.gL[i], jW, fma(B.gR[i], jE, dF[i][v]));
-          dG[i][v] = fma(B.gL[i], jS, fma(B.gR[i], jN, dG[i][v]));
-        }
+        for (int i = 0; i < n; ++i) dG[i][v] = fma(B.gL[i], jS, fma(B.gR[i], jN, dG[i][v]));
       }
     }
     // v and R0 of the write-out positions, on their way during the last passes
@@ -520,7 +540,7 @@ __global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a
       }
     }
     __syncthreads();
-    if (live) {
+    if (cols) {
 #pragma unroll
       for (int r = 0; r < n; ++r)
 #pragma unroll
@@ -529,7 +549,7 @@ __global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a
     __syncthreads();
 
     // ---- R = -(D_xi F + D_eta G + corrections) / J on row t, back into LDS
-    if (live) {
+    if (rows) {
       const double xxi = fma(bx, tp, ax), yxi = fma(by, tp, ay);
 #pragma unroll
       for (int i = 0; i < n; ++i) {
