@@ -243,9 +243,10 @@ struct SolveCfg {
   static constexpr int TPE = Nb / RPT;  // threads per element
   static constexpr int EPB = 256 / TPE;  // elements per workgroup
   // columns in flight per thread: single rows (latency-bound stores that stay in the
-  // last-level cache) about 64 VGPRs of loads, 32 FP64 or 64 FP32 columns; 16-byte
-  // rows (large stores streamed from HBM) 8 columns, which measured faster there
-  static constexpr int JU0 = RPT == 1 ? 256 / (int)sizeof(T) : 8;
+  // last-level cache) 32 columns, FP32 ones at five waves per SIMD (the kernel's launch
+  // bounds); 16-byte rows (large stores streamed from HBM) 8 columns, which measured
+  // faster there
+  static constexpr int JU0 = RPT == 1 ? 32 : 8;
   static constexpr int JU = JU0 < Nb ? JU0 : Nb;
   static_assert(Nb % RPT == 0, "whole rows per thread");
 };
@@ -268,7 +269,7 @@ __device__ __forceinline__ double row_of(const V& a, int q) {
 }
 
 template <int P, typename T, int RPT>
-__global__ void __launch_bounds__(256) k_ejacobi_solve(const T* __restrict__ inv, const double* __restrict__ r,
+__global__ void __launch_bounds__(256, (sizeof(T) == 4 && RPT == 1) ? 5 : 1) k_ejacobi_solve(const T* __restrict__ inv, const double* __restrict__ r,
                                                         const GivensIn gv, double* r_store, double* __restrict__ z,
                                                         int nel, double* partials, const int* skip) {
   using C = SolveCfg<P, T, RPT>;
