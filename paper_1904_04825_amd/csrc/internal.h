@@ -83,8 +83,18 @@ struct ResArgs {
   int eps_mode;
   double shift;
   double* grad;         // BR1 face-gradient traces (workspace)
+  // optional, JF product on small Euler meshes (see residual_dots_blocks): the first
+  // DCGS2 pass over the product's output w, dnv <= 8 basis vectors at dV (n apart):
+  // per-workgroup partial sums of <V_t, w>, <V_t, V_{dnv-1}> and <w, w> in the row
+  // layout of launch_dcgs2_dots, into dpart
+  const double* dV;
+  int dnv;
+  double* dpart;
 };
 hipError_t launch_residual(const fr_disc* d, int mode, const ResArgs& a, hipStream_t s);
+// Workgroups of the JF product when it can also run the first DCGS2 pass (small Euler
+// meshes, at most kRedBlocks tiles), else 0.
+int residual_dots_blocks(const fr_disc* d);
 
 // Vector operations (flat arrays of n doubles).
 // Sum of squares with a deterministic two-level reduction; result in *out (device).
@@ -180,6 +190,10 @@ hipError_t launch_arnoldi_dcgs2(double* V, int nv, double* w, double* partials, 
 const double* dcgs2_norm_partials(const double* partials);
 // The cycle's last column (first pass) rotated with ||w'|| from those partials.
 hipError_t launch_dcgs2_last(GmState* st, const double* partials, int nb, int M, hipStream_t s);
+// The second DCGS2 pass alone, its first pass's partial rows from nb1 workgroups of
+// another kernel (the JF product).
+hipError_t launch_dcgs2_update(double* V, int nv, double* w, double* partials, int nb1, GmState* st, int M,
+                               size_t n, hipStream_t s);
 // Run by the preconditioner kernel that starts the next Arnoldi step, which scales w by
 // 1/||w|| (||w||^2 from norm_part): CGS2: the Givens update of the previous step;
 // DCGS2 (lagged): ||w|| stored as the first-pass h_{j+1,j}, and on breakdown or NaN

@@ -193,8 +193,9 @@ struct TileIdx {
   }
 };
 
-template <int P, int FLUX, int MODE, bool BIG>
+template <int P, int FLUX, int MODE, bool BIG, int DOTS = 0>
 __global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a, const MeshArgs g, const Basis B) {
+  static_assert(DOTS == 0 || (MODE == 1 && !BIG), "the first DCGS2 pass rides on small-tile JF products only");
   using C = LineCfg<P, BIG>;
   constexpr int n = C::n, Np = C::Np, ES = C::ES, TX = C::TX, TY = C::TY, NT = C::NT;
   constexpr int QS = C::QS, NS = C::NS, NF = C::NF;
@@ -564,7 +565,13 @@ __global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a
     }
     __syncthreads();
 
-    // ---- coalesced write-out, the matrix-free combinations on the fly
+    // ---- coalesced write-out, the matrix-free combinations on the fly (with DOTS, the
+    // first DCGS2 pass over w = A v: the basis vectors' entries at the written positions
+    // and their sums, as k_dcgs_dots forms them)
+    constexpr int NA = 2 * DOTS;
+    double dacc[DOTS > 0 ? NA : 1];
+#pragma unroll
+    for (int q = 0; q < (DOTS > 0 ? NA : 1); ++q) dacc[q] = 0.0;
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
       const int idx = tid + it * NT, ry = idx / RUN, kk = idx - ry * RUN;
@@ -583,8 +590,35 @@ __global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a
               a.out[gi] = av;
             else
               a.out[gi] = a.B[gi] - av;
+            if constexpr (DOTS > 0) {
+              const size_t ndof = 4 * vstride;
+              double vr[DOTS > 0 ? DOTS : 1];
+#pragma unroll
+              for (int q = 0; q < DOTS; ++q) vr[q] = a.dV[(size_t)min(q, a.dnv - 1) * ndof + gi];
+              const double vj = a.dV[(size_t)(a.dnv - 1) * ndof + gi];
+#pragma unroll
+              for (int q = 0; q < DOTS; ++q) dacc[q] = fma(vr[q], av, dacc[q]);
+#pragma unroll
+              for (int q = 0; q + 1 < DOTS; ++q) dacc[DOTS + q] = fma(vr[q], vj, dacc[DOTS + q]);
+              dacc[NA - 1] = fma(av, av, dacc[NA - 1]);
+            }
           }
         }
+      }
+    }
+    if constexpr (DOTS > 0) {
+      __shared__ double dred[NT / 64][NA > 0 ? NA : 1];
+      int off;
+      if (wave_multi_sum<NA>(dacc, off)) {
+#pragma unroll
+        for (int q = 0; q < multi_sum_count(NA); ++q) dred[tid >> 6][off + q] = dacc[q];
+      }
+      __syncthreads();
+      if (tid < NA) {
+        double r = 0.0;
+#pragma unroll
+        for (int q = 0; q < NT / 64; ++q) r += dred[q][tid];
+        a.dpart[(size_t)tid * kRedBlocks + blockIdx.x] = r;
       }
     }
   }
@@ -602,6 +636,20 @@ static hipError_t launch_euler_tile(const fr_disc* d, int mode, const ResArgs& a
   const int ntx = (d->nx + C::TX - 1) / C::TX, nty = (d->ny + C::TY - 1) / C::TY;
   const MeshArgs g{d->nodes, d->nx, d->ny, d->nel, d->phys.gamma};
   dim3 grid(ntx * nty), block(C::NT);
+  if (a.dV != nullptr) {
+    // the JF product with the first DCGS2 pass: small tiles, one partial row slot per tile
+    if constexpr (BIG) {
+      return hipErrorInvalidValue;
+    } else {
+      if (mode != 1 || a.dnv < 1 || a.dnv > 8 || a.dpart == nullptr || ntx * nty > kRedBlocks)
+        return hipErrorInvalidValue;
+      if (a.dnv <= 4)
+        hipLaunchKernelGGL((k_euler<P, FLUX, 1, false, 4>), grid, block, 0, s, a, g, d->basis);
+      else
+        hipLaunchKernelGGL((k_euler<P, FLUX, 1, false, 8>), grid, block, 0, s, a, g, d->basis);
+      return hipGetLastError();
+    }
+  }
   if (mode == 0)
     hipLaunchKernelGGL((k_euler<P, FLUX, 0, BIG>), grid, block, 0, s, a, g, d->basis);
   else if (mode == 1)
@@ -619,11 +667,38 @@ static hipError_t finish_nrm2(int mode, ResArgs& a, hipStream_t s) {
   return e;
 }
 
+template <int P>
+static long big_tiles(const fr_disc* d) {
+  using C = LineCfg<P, true>;
+  return (long)((d->nx + C::TX - 1) / C::TX) * ((d->ny + C::TY - 1) / C::TY);
+}
+
+template <int P>
+static int small_tiles(const fr_disc* d) {
+  using C = LineCfg<P, false>;
+  return ((d->nx + C::TX - 1) / C::TX) * ((d->ny + C::TY - 1) / C::TY);
+}
+
+template <int P>
+static int dots_blocks_p(const fr_disc* d) {
+  if (big_tiles<P>(d) >= kBigTileMinBlocks) return 0;
+  const int nb = small_tiles<P>(d);
+  return nb <= kRedBlocks ? nb : 0;
+}
+
+int residual_dots_blocks(const fr_disc* d) {
+  if (d->physics != FR_EULER) return 0;
+  switch (d->p) {
+    case 2: return dots_blocks_p<2>(d);
+    case 3: return dots_blocks_p<3>(d);
+    case 4: return dots_blocks_p<4>(d);
+  }
+  return 0;
+}
+
 template <int P, int FLUX>
 static hipError_t launch_euler_pf(const fr_disc* d, int mode, const ResArgs& a, hipStream_t s) {
-  using C = LineCfg<P, true>;
-  const long big_blocks = (long)((d->nx + C::TX - 1) / C::TX) * ((d->ny + C::TY - 1) / C::TY);
-  if (big_blocks < kBigTileMinBlocks) return launch_euler_tile<P, FLUX, false>(d, mode, a, s);
+  if (big_tiles<P>(d) < kBigTileMinBlocks) return launch_euler_tile<P, FLUX, false>(d, mode, a, s);
   // many tiles: one finalize kernel instead of every wavefront reading the partials
   ResArgs b = a;
   const hipError_t e = finish_nrm2(mode, b, s);

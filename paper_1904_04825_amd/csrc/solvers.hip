@@ -337,6 +337,9 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
   // orthogonalisation: DCGS2 (two passes over V per step, the Hessenberg column final
   // one step later) up to m = 32, CGS2 beyond
   const bool dcgs = dcgs2_supported(m);
+  // small Euler meshes: the JF product of steps with at most 8 basis vectors also runs
+  // the first DCGS2 pass (one kernel fewer per early step)
+  const int jf_dots = dcgs ? residual_dots_blocks(d) : 0;
   volatile GmStatus* hstat = (volatile GmStatus*)d->h_pinned;
   GmStatus* dstat = (GmStatus*)d->d_pinned;
   const size_t status_off = offsetof(GmState, rest);
@@ -375,8 +378,16 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
       a1.V = zj;
       a1.out = W.w;
       a1.skip = skip;
+      const bool fused_dots = jf_dots > 0 && j + 1 <= 8;
+      if (fused_dots) {
+        a1.dV = W.V;
+        a1.dnv = j + 1;
+        a1.dpart = W.partials;
+      }
       FR_HIP(launch_residual(d, 1, a1, s));
-      if (dcgs)
+      if (fused_dots)
+        FR_HIP(launch_dcgs2_update(W.V, j + 1, W.w, W.partials, jf_dots, W.st, m, n, s));
+      else if (dcgs)
         FR_HIP(launch_arnoldi_dcgs2(W.V, j + 1, W.w, W.partials, W.st, m, n, s));
       else
         FR_HIP(launch_arnoldi_cgs2(W.V, j + 1, W.w, W.partials, W.st, m, n, s));

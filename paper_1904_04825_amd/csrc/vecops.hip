@@ -527,15 +527,18 @@ __global__ void __launch_bounds__(kRedThreads) k_dcgs_last(GmState* st, const do
 
 bool dcgs2_supported(int m) { return m <= 32; }
 
-hipError_t launch_arnoldi_dcgs2(double* V, int nv, double* w, double* partials, GmState* st, int M, size_t n,
-                                hipStream_t s) {
+// which: 1 the first pass, 2 the second (its partial rows from nb1 workgroups), 3 both
+static hipError_t dcgs2_passes(int which, double* V, int nv, double* w, double* partials, int nb1, GmState* st,
+                               int M, size_t n, hipStream_t s) {
   const int nb = cgs_blocks(n);
+  if (which == 3) nb1 = nb;
+  if (nb1 < 1 || nb1 > kRedBlocks) return hipErrorInvalidValue;
   double* np = partials + kDcgsNormOff;
   const dim3 g(nb), b(kRedThreads);
 #define FRJF_DCGS_CASE(K, NVV)                                                                                      \
   case K:                                                                                                           \
-    hipLaunchKernelGGL((k_dcgs_dots<NVV>), g, b, 0, s, V, nv, w, partials, &st->stop, n);                          \
-    hipLaunchKernelGGL((k_dcgs_update<NVV>), g, b, 0, s, V, nv, w, partials, nb, np, st, M, n);                    \
+    if (which & 1) hipLaunchKernelGGL((k_dcgs_dots<NVV>), g, b, 0, s, V, nv, w, partials, &st->stop, n);           \
+    if (which & 2) hipLaunchKernelGGL((k_dcgs_update<NVV>), g, b, 0, s, V, nv, w, partials, nb1, np, st, M, n);    \
     break;
   switch ((nv + 3) / 4) {
     FRJF_DCGS_CASE(1, 4)
@@ -551,6 +554,16 @@ hipError_t launch_arnoldi_dcgs2(double* V, int nv, double* w, double* partials, 
   }
 #undef FRJF_DCGS_CASE
   return hipGetLastError();
+}
+
+hipError_t launch_arnoldi_dcgs2(double* V, int nv, double* w, double* partials, GmState* st, int M, size_t n,
+                                hipStream_t s) {
+  return dcgs2_passes(3, V, nv, w, partials, 0, st, M, n, s);
+}
+
+hipError_t launch_dcgs2_update(double* V, int nv, double* w, double* partials, int nb1, GmState* st, int M,
+                               size_t n, hipStream_t s) {
+  return dcgs2_passes(2, V, nv, w, partials, nb1, st, M, n, s);
 }
 
 const double* dcgs2_norm_partials(const double* partials) { return partials + kDcgsNormOff; }
