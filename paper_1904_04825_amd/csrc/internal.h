@@ -84,7 +84,7 @@ struct ResArgs {
   double shift;
   double* grad;         // BR1 face-gradient traces (workspace)
   // optional, JF product on small Euler meshes (see residual_dots_blocks): the first
-  // DCGS2 pass over the product's output w, dnv <= 8 basis vectors at dV (n apart):
+  // DCGS2 pass over the product's output w, dnv <= kJfDotsMax basis vectors at dV:
   // per-workgroup partial sums of <V_t, w>, <V_t, V_{dnv-1}> and <w, w> in the row
   // layout of launch_dcgs2_dots, into dpart
   const double* dV;
@@ -93,7 +93,8 @@ struct ResArgs {
 };
 hipError_t launch_residual(const fr_disc* d, int mode, const ResArgs& a, hipStream_t s);
 // Workgroups of the JF product when it can also run the first DCGS2 pass (small Euler
-// meshes, at most kRedBlocks tiles), else 0.
+// meshes, at most kRedBlocks tiles, up to kJfDotsMax basis vectors), else 0.
+constexpr int kJfDotsMax = 20;
 int residual_dots_blocks(const fr_disc* d);
 
 // Vector operations (flat arrays of n doubles).

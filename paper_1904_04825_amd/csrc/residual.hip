@@ -641,12 +641,18 @@ static hipError_t launch_euler_tile(const fr_disc* d, int mode, const ResArgs& a
     if constexpr (BIG) {
       return hipErrorInvalidValue;
     } else {
-      if (mode != 1 || a.dnv < 1 || a.dnv > 8 || a.dpart == nullptr || ntx * nty > kRedBlocks)
+      if (mode != 1 || a.dnv < 1 || a.dnv > kJfDotsMax || a.dpart == nullptr || ntx * nty > kRedBlocks)
         return hipErrorInvalidValue;
       if (a.dnv <= 4)
         hipLaunchKernelGGL((k_euler<P, FLUX, 1, false, 4>), grid, block, 0, s, a, g, d->basis);
-      else
+      else if (a.dnv <= 8)
         hipLaunchKernelGGL((k_euler<P, FLUX, 1, false, 8>), grid, block, 0, s, a, g, d->basis);
+      else if (a.dnv <= 12)
+        hipLaunchKernelGGL((k_euler<P, FLUX, 1, false, 12>), grid, block, 0, s, a, g, d->basis);
+      else if (a.dnv <= 16)
+        hipLaunchKernelGGL((k_euler<P, FLUX, 1, false, 16>), grid, block, 0, s, a, g, d->basis);
+      else
+        hipLaunchKernelGGL((k_euler<P, FLUX, 1, false, 20>), grid, block, 0, s, a, g, d->basis);
       return hipGetLastError();
     }
   }

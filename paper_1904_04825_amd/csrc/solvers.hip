@@ -337,8 +337,8 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
   // orthogonalisation: DCGS2 (two passes over V per step, the Hessenberg column final
   // one step later) up to m = 32, CGS2 beyond
   const bool dcgs = dcgs2_supported(m);
-  // small Euler meshes: the JF product of steps with at most 8 basis vectors also runs
-  // the first DCGS2 pass (one kernel fewer per early step)
+  // small Euler meshes: the JF product of steps with at most kJfDotsMax basis vectors
+  // also runs the first DCGS2 pass (one kernel fewer per such step)
   const int jf_dots = dcgs ? residual_dots_blocks(d) : 0;
   volatile GmStatus* hstat = (volatile GmStatus*)d->h_pinned;
   GmStatus* dstat = (GmStatus*)d->d_pinned;
@@ -378,7 +378,7 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
       a1.V = zj;
       a1.out = W.w;
       a1.skip = skip;
-      const bool fused_dots = jf_dots > 0 && j + 1 <= 8;
+      const bool fused_dots = jf_dots > 0 && j + 1 <= kJfDotsMax;
       if (fused_dots) {
         a1.dV = W.V;
         a1.dnv = j + 1;
