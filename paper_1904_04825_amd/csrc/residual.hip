@@ -77,14 +77,6 @@ struct LineCfg {
   static constexpr int A = (4 * QS > 4 * NF) ? 4 * QS : 4 * NF;
 };
 
-__device__ __forceinline__ int xcd_remap(int i, int T) {
-  // tiles handed to the 8 XCDs in contiguous ranges (workgroup i runs on XCD i % 8),
-  // so neighbouring tiles share an L2
-  const int q = T >> 3, r = T & 7;
-  const int x = i & 7, l = i >> 3;
-  return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
-}
-
 struct MeshArgs {
   const double* nodes;
   int nx, ny, nel;

@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(kRedThreads) k_dcgs_dots(const double* __restr
   // the next entry's loads are issued before this entry's FMAs (one round trip per
   // entry hidden behind the previous one)
   const size_t stride = (size_t)gridDim.x * kRedThreads;
-  size_t i = blockIdx.x * (size_t)kRedThreads + tid;
+  size_t i = (size_t)xcd_remap(blockIdx.x, gridDim.x) * kRedThreads + tid;
   double vr[NV], wi = 0.0, vji = 0.0;
   auto load = [&](size_t k) {
 #pragma unroll
@@ -421,7 +421,7 @@ __global__ void __launch_bounds__(kRedThreads) k_dcgs_update(double* __restrict_
   const int j = nv - 1;
   double* vj = V + (size_t)j * n;
   const size_t stride = (size_t)gridDim.x * kRedThreads;
-  size_t i = blockIdx.x * (size_t)kRedThreads + tid;
+  size_t i = (size_t)xcd_remap(blockIdx.x, gridDim.x) * kRedThreads + tid;
   double vr[NV], wi = 0.0, vji = 0.0;
   auto load = [&](size_t k) {
 #pragma unroll

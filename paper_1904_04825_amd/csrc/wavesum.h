@@ -6,6 +6,16 @@
 
 namespace frjf {
 
+// Workgroup i of T runs on XCD i % 8; the work item it takes is xcd_remap(i, T), so
+// each XCD takes one contiguous range of items (neighbouring tiles, or the same range
+// of vector entries in every kernel of a chain) and they share its L2.  A bijection
+// on [0, T).
+__device__ __forceinline__ int xcd_remap(int i, int T) {
+  const int q = T >> 3, r = T & 7;
+  const int x = i & 7, l = i >> 3;
+  return (x < r) ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
 // ---------------------------------------------------------------- wavefront sums
 // Lane exchanges without LDS, in six stages that each pair a lane with one whose
 // set of already summed lanes is disjoint from its own: stage 0 pairs lanes 32
