@@ -158,6 +158,13 @@ struct GmState {
   int evals;           // JF products of the cycle that ran (counted by the DCGS2 second pass)
   int done;            // converged or NaN: the cycle's closing kernels for a restart return at once
   struct GmStatus* hslot;  // mapped host memory receiving the status after every step
+  // restart decisions on the device, so the host enqueues the next cycle without waiting
+  struct Final {
+    int fin;             // the solve has ended: its later kernels return at once
+    int result;          // its fr_status once fin
+    int iters, evals, restarts;
+    double r_final;      // least-squares or true residual norm
+  } fz;
 };
 struct GmStatus {
   double rest, beta;
@@ -205,9 +212,13 @@ struct GivensIn {
   int nb, M;
   int lagged;
 };
-// Cycle start: beta = sqrt(*beta2), v0 = r / beta, the cycle state reset (target, hslot).
+// Cycle start: beta = sqrt(*beta2), v0 = r / beta, the cycle state reset (target, hslot);
+// first: the solve's totals reset too, otherwise nothing happens once the solve has ended.
 hipError_t launch_gm_start(GmState* st, const double* beta2, double target, int M, GmStatus* hslot, double* v0,
-                           const double* r, size_t n, hipStream_t s);
+                           const double* r, size_t n, int first, hipStream_t s);
+// End of a restart cycle (after the true residual's ||r||^2 in *beta2): the totals, and
+// the decision to end the solve (converged, NaN, breakdown, max_iters) or restart.
+hipError_t launch_gm_cycle_end(GmState* st, const double* beta2, int max_iters, int dcgs, hipStream_t s);
 // Sum partials[b*stride + i] over b < nblocks into out[i], i < nv (one workgroup).
 hipError_t launch_finalize(const double* partials, int nblocks, int stride, int nv, double* out, const int* skip,
                            hipStream_t s);

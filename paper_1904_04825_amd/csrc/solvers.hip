@@ -244,18 +244,6 @@ static fr_status read_sync(const fr_disc* d, void* dst, const void* dev, size_t 
   return FR_OK;
 }
 
-// The Arnoldi status block and ||r||^2 from the device in one round trip.
-static fr_status read_status(const fr_disc* d, GmStatus* fin, const void* dev_status, double* b2, const double* dev_b2,
-                             hipStream_t s) {
-  char* slot = (char*)d->h_pinned + 1024;
-  FR_HIP(hipMemcpyAsync(slot, dev_status, sizeof(GmStatus), hipMemcpyDeviceToHost, s));
-  FR_HIP(hipMemcpyAsync(slot + 64, dev_b2, sizeof(double), hipMemcpyDeviceToHost, s));
-  FR_HIP(hipStreamSynchronize(s));
-  std::memcpy(fin, slot, sizeof(GmStatus));
-  std::memcpy(b2, slot + 64, sizeof(double));
-  return FR_OK;
-}
-
 fr_status device_norm(const fr_disc* d, const double* x, double* partials, double* dev_out,
                       double* host_out, hipStream_t s) {
   FR_HIP(launch_norm2(x, d->ndof, partials, dev_out, nullptr, s));
@@ -342,17 +330,18 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
   const int jf_dots = dcgs ? residual_dots_blocks(d) : 0;
   volatile GmStatus* hstat = (volatile GmStatus*)d->h_pinned;
   GmStatus* dstat = (GmStatus*)d->d_pinned;
-  const size_t status_off = offsetof(GmState, rest);
-  fr_status result = FR_NOTCONV;
   // The host runs ahead of the GPU and stops enqueueing once the mapped status shows a
   // stop (kernels enqueued after a stop return at once).  An event recorded after every
   // fourth step bounds the lead to about eight steps: an event per step cost about 5 us
-  // of GPU idle time each on small meshes.
-  for (;;) {
-    hstat->stop = 0;
-    hstat->j = 0;
-    FR_HIP(launch_gm_start(W.st, beta2, target, m, dstat, W.V, rsrc, n, s));
-    const int budget = std::min(m, max_iters - S.iters);
+  // of GPU idle time each on small meshes.  Restart decisions are taken on the device
+  // (k_gm_cycle_end): the next cycle is enqueued behind the current one without a host
+  // round trip and does nothing if the solve has ended.  Every cycle but the last runs
+  // all m steps (an early stop ends the solve), so cycle c starts after c m iterations.
+  hstat->stop = 0;
+  hstat->j = 0;
+  for (int c = 0; c * m < max_iters; ++c) {
+    const int budget = std::min(m, max_iters - c * m);
+    FR_HIP(launch_gm_start(W.st, beta2, target, m, dstat, W.V, c == 0 ? rsrc : W.r, n, c == 0, s));
     for (int j = 0; j < budget; ++j) {
       if (j >= 8 && j % 4 == 0) FR_HIP(hipEventSynchronize(d->ev[(j / 4 - 2) & 3]));  // step j - 5 done
       if (hstat->stop) break;
@@ -394,15 +383,12 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
       if (j % 4 == 3) FR_HIP(hipEventRecord(d->ev[(j / 4) & 3], s));
     }
     // the Givens update of the cycle's last column (returns at once after a stop)
-    if (budget > 0) {
-      if (dcgs)
-        FR_HIP(launch_dcgs2_last(W.st, W.partials, cgs_blocks(n), m, s));
-      else
-        FR_HIP(launch_givens(W.st, W.partials, cgs_blocks(n), m, s));
-    }
-    // the cycle's end is enqueued without waiting for its status: y and x += Z y
-    // (skipped after NaN), then the true residual r = b - A x for a restart (skipped
-    // once converged or NaN); one host round trip reads the status and ||r||^2
+    if (dcgs)
+      FR_HIP(launch_dcgs2_last(W.st, W.partials, cgs_blocks(n), m, s));
+    else
+      FR_HIP(launch_givens(W.st, W.partials, cgs_blocks(n), m, s));
+    // y and x += Z y (skipped after NaN), then the true residual r = b - A x for a
+    // restart (skipped once converged or NaN), then the device's decision
     int nbx = 0;
     FR_HIP(launch_gm_update_x(x, W.Z, m, W.st, n, W.partials, &nbx, s));
     const int* done = &W.st->done;
@@ -415,47 +401,18 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
     a2.skip = done;
     FR_HIP(launch_residual(d, 2, a2, s));
     FR_HIP(launch_norm2(W.r, n, W.partials, beta2, done, s));
-    GmStatus fin;
-    rs = read_status(d, &fin, (const char*)W.st + status_off, &b2, beta2, s);
-    if (rs != FR_OK) return rs;
-    const int k = fin.j;
-    S.iters += k;
-    // DCGS2 finds convergence one step late: the JF product of that step also ran
-    S.residual_evals += dcgs ? std::max(k, fin.evals) : k;
-    S.r_final = fin.rest;
-    if (fin.why == 3) {
-      result = FR_ENAN;
-      break;
-    }
-    if (fin.why == 1) {
-      S.converged = 1;
-      result = FR_OK;
-      break;
-    }
-    S.residual_evals++;  // the restart's true residual
-    beta = std::sqrt(b2);
-    S.r_final = beta;
-    rsrc = W.r;
-    if (!std::isfinite(beta)) {
-      result = FR_ENAN;
-      break;
-    }
-    if (beta <= target) {
-      S.converged = 1;
-      result = FR_OK;
-      break;
-    }
-    if (fin.why == 2) {
-      result = FR_BREAKDOWN;
-      break;
-    }
-    if (S.iters >= max_iters) {
-      result = FR_NOTCONV;
-      break;
-    }
-    S.restarts++;
+    FR_HIP(launch_gm_cycle_end(W.st, beta2, max_iters, dcgs ? 1 : 0, s));
+    if (hstat->stop) break;  // the solve has ended, or its stop is on the way
   }
-  FR_HIP(hipStreamSynchronize(s));
+  GmState::Final fz;
+  rs = read_sync(d, &fz, (const char*)W.st + offsetof(GmState, fz), sizeof(fz), s);
+  if (rs != FR_OK) return rs;
+  S.iters = fz.iters;
+  S.residual_evals += fz.evals;
+  S.restarts = fz.restarts;
+  S.r_final = fz.r_final;
+  const fr_status result = fz.fin ? (fr_status)fz.result : FR_NOTCONV;
+  S.converged = result == FR_OK ? 1 : 0;
   *stats = S;
   return result;
 }

@@ -577,12 +577,21 @@ hipError_t launch_dcgs2_last(GmState* st, const double* partials, int nb, int M,
 // the first basis vector v_0 = r / beta; workgroup 0 also resets the cycle state.
 __global__ void __launch_bounds__(256) k_gm_start(GmState* st, const double* beta2, double target, int M,
                                                   GmStatus* hslot, double* __restrict__ v0,
-                                                  const double* __restrict__ r, size_t n) {
+                                                  const double* __restrict__ r, size_t n, int first) {
+  if (!first && st->fz.fin) return;
   const double beta = sqrt(*beta2);
   const double a = 1.0 / beta;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     v0[i] = a * r[i];
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  if (first) {
+    st->fz.fin = 0;
+    st->fz.result = FR_NOTCONV;
+    st->fz.iters = 0;
+    st->fz.evals = 0;
+    st->fz.restarts = 0;
+    st->fz.r_final = beta;
+  }
   st->hslot = hslot;
   for (int i = 0; i <= M; ++i) st->g[i] = 0.0;
   st->g[0] = beta;
@@ -597,9 +606,57 @@ __global__ void __launch_bounds__(256) k_gm_start(GmState* st, const double* bet
 }
 
 hipError_t launch_gm_start(GmState* st, const double* beta2, double target, int M, GmStatus* hslot, double* v0,
-                           const double* r, size_t n, hipStream_t s) {
+                           const double* r, size_t n, int first, hipStream_t s) {
   const unsigned blocks = (unsigned)red_blocks(n);
-  hipLaunchKernelGGL(k_gm_start, dim3(blocks ? blocks : 1), dim3(256), 0, s, st, beta2, target, M, hslot, v0, r, n);
+  hipLaunchKernelGGL(k_gm_start, dim3(blocks ? blocks : 1), dim3(256), 0, s, st, beta2, target, M, hslot, v0, r, n,
+                     first);
+  return hipGetLastError();
+}
+
+// One thread: the cycle's steps and JF products into the totals (DCGS2 finds
+// convergence one step late: the product of that step also ran), then NaN or
+// convergence of the least-squares residual end the solve; otherwise the restart's
+// true residual (one more product) decides: NaN, converged, breakdown, or the
+// iteration limit end it, else the solve restarts.  An end stops every later kernel
+// and is mirrored to the mapped host status.
+__global__ void k_gm_cycle_end(GmState* st, const double* beta2, int max_iters, int dcgs) {
+  if (threadIdx.x != 0 || st->fz.fin) return;
+  const int k = st->j, why = st->why;
+  st->fz.iters += k;
+  st->fz.evals += dcgs ? max(k, st->evals) : k;
+  double rf = st->rest;
+  int res = -1;
+  if (why == 3) {
+    res = FR_ENAN;
+  } else if (why == 1) {
+    res = FR_OK;
+  } else {
+    st->fz.evals += 1;
+    const double beta = sqrt(*beta2);
+    rf = beta;
+    if (!isfinite(beta))
+      res = FR_ENAN;
+    else if (beta <= st->target)
+      res = FR_OK;
+    else if (why == 2)
+      res = FR_BREAKDOWN;
+    else if (st->fz.iters >= max_iters)
+      res = FR_NOTCONV;
+    else
+      st->fz.restarts += 1;
+  }
+  st->fz.r_final = rf;
+  if (res >= 0) {
+    st->fz.fin = 1;
+    st->fz.result = res;
+    st->stop = 1;
+    st->done = 1;
+    if (st->hslot != nullptr) st->hslot->stop = 1;
+  }
+}
+
+hipError_t launch_gm_cycle_end(GmState* st, const double* beta2, int max_iters, int dcgs, hipStream_t s) {
+  hipLaunchKernelGGL(k_gm_cycle_end, dim3(1), dim3(64), 0, s, st, beta2, max_iters, dcgs);
   return hipGetLastError();
 }
 
@@ -611,7 +668,7 @@ hipError_t launch_gm_start(GmState* st, const double* beta2, double target, int 
 // y_c = r_c / R_cc is broadcast and removed from the rows above it) while the first
 // entries of Z are on their way.  NV > 0: the k <= NV columns of an entry loaded
 // together (slots t >= k re-read column k-1 with weight 0); NV = 0: a plain loop.
-// After NaN (why = 3) or with k = 0, x is left as it is.
+// After NaN (why = 3), with k = 0 or once the solve has ended, x is left as it is.
 template <int NV>
 __global__ void __launch_bounds__(256) k_gm_update_x(double* __restrict__ x, const double* __restrict__ Z,
                                                      const GmState* st, int M, size_t n, double* __restrict__ xpart) {
@@ -619,7 +676,7 @@ __global__ void __launch_bounds__(256) k_gm_update_x(double* __restrict__ x, con
   __shared__ double sy[kMaxM];
   __shared__ double red[4];
   const int k = st->j;
-  const bool upd = !(st->why == 3 || k <= 0);
+  const bool upd = !(st->fz.fin || st->why == 3 || k <= 0);
   const int tid = threadIdx.x;
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   size_t i = blockIdx.x * (size_t)blockDim.x + tid;
