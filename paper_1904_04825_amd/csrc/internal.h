@@ -164,6 +164,7 @@ struct GmState {
     int result;          // its fr_status once fin
     int iters, evals, restarts;
     double r_final;      // least-squares or true residual norm
+    double r_ref;        // the norm the tolerance is relative to
   } fz;
 };
 struct GmStatus {
@@ -212,10 +213,12 @@ struct GivensIn {
   int nb, M;
   int lagged;
 };
-// Cycle start: beta = sqrt(*beta2), v0 = r / beta, the cycle state reset (target, hslot);
-// first: the solve's totals reset too, otherwise nothing happens once the solve has ended.
-hipError_t launch_gm_start(GmState* st, const double* beta2, double target, int M, GmStatus* hslot, double* v0,
-                           const double* r, size_t n, int first, hipStream_t s);
+// Cycle start: beta = sqrt(*beta2), v0 = r / beta, the cycle state reset (hslot); first:
+// the solve's reference norm (ref, or beta for ref <= 0), target rtol * r_ref and totals,
+// and an end before any step for a non-finite or converged beta; a later cycle does
+// nothing once the solve has ended.
+hipError_t launch_gm_start(GmState* st, const double* beta2, double rtol, double ref, int M, GmStatus* hslot,
+                           double* v0, const double* r, size_t n, int first, hipStream_t s);
 // End of a restart cycle (after the true residual's ||r||^2 in *beta2): the totals, and
 // the decision to end the solve (converged, NaN, breakdown, max_iters) or restart.
 hipError_t launch_gm_cycle_end(GmState* st, const double* beta2, int max_iters, int dcgs, hipStream_t s);

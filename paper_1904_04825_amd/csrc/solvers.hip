@@ -277,7 +277,10 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
   const double* rsrc = b;
   double bnorm = -1.0;  // ||b||, the residual of the zero (plain) guess
   if (fell_back != nullptr) *fell_back = 0;
-  if (!x_is_zero && plain_fallback) {
+  // a supplied guess that may fall back to zero needs ||b|| and ||r_0|| on the host;
+  // otherwise the first cycle's start kernel takes the reference norm and the checks
+  const bool host_start = !x_is_zero && plain_fallback;
+  if (host_start) {
     double bb = 0.0;
     FR_HIP(launch_norm2(b, n, W.partials, beta2, nullptr, s));
     fr_status r0 = read_sync(d, &bb, beta2, sizeof(double), s);
@@ -295,31 +298,35 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
     rsrc = W.r;
   }
   FR_HIP(launch_norm2(rsrc, n, W.partials, beta2, nullptr, s));
-  double b2 = 0.0;
-  fr_status rs = read_sync(d, &b2, beta2, sizeof(double), s);
-  if (rs != FR_OK) return rs;
-  double beta = std::sqrt(b2);
-  if (bnorm >= 0.0 && !(beta < bnorm)) {
-    // the supplied guess is no better than zero: start from zero
-    const double* none[1];
-    double zc[1];
-    FR_HIP(launch_lincomb(x, 0, none, zc, n, s));
-    FR_HIP(launch_norm2(b, n, W.partials, beta2, nullptr, s));
-    rsrc = b;
-    beta = bnorm;
-    if (fell_back != nullptr) *fell_back = 1;
-  }
-  S.r_ref = o.ref_norm > 0 ? o.ref_norm : (bnorm >= 0.0 ? bnorm : beta);
-  const double target = o.rtol * S.r_ref;
-  S.r_final = beta;
-  if (!std::isfinite(beta)) {
-    *stats = S;
-    return FR_ENAN;
-  }
-  if (beta <= target) {
-    S.converged = 1;
-    *stats = S;
-    return FR_OK;
+  fr_status rs = FR_OK;
+  double ref = o.ref_norm > 0 ? o.ref_norm : 0.0;  // 0: the start kernel takes ||r_0||
+  if (host_start) {
+    double b2 = 0.0;
+    rs = read_sync(d, &b2, beta2, sizeof(double), s);
+    if (rs != FR_OK) return rs;
+    double beta = std::sqrt(b2);
+    if (!(beta < bnorm)) {
+      // the supplied guess is no better than zero: start from zero
+      const double* none[1];
+      double zc[1];
+      FR_HIP(launch_lincomb(x, 0, none, zc, n, s));
+      FR_HIP(launch_norm2(b, n, W.partials, beta2, nullptr, s));
+      rsrc = b;
+      beta = bnorm;
+      if (fell_back != nullptr) *fell_back = 1;
+    }
+    S.r_ref = o.ref_norm > 0 ? o.ref_norm : bnorm;
+    S.r_final = beta;
+    if (!std::isfinite(beta)) {
+      *stats = S;
+      return FR_ENAN;
+    }
+    if (beta <= o.rtol * S.r_ref) {
+      S.converged = 1;
+      *stats = S;
+      return FR_OK;
+    }
+    ref = S.r_ref;
   }
   // mapped host status written by the Givens kernel after every Arnoldi step
   // orthogonalisation: DCGS2 (two passes over V per step, the Hessenberg column final
@@ -341,7 +348,7 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
   hstat->j = 0;
   for (int c = 0; c * m < max_iters; ++c) {
     const int budget = std::min(m, max_iters - c * m);
-    FR_HIP(launch_gm_start(W.st, beta2, target, m, dstat, W.V, c == 0 ? rsrc : W.r, n, c == 0, s));
+    FR_HIP(launch_gm_start(W.st, beta2, o.rtol, ref, m, dstat, W.V, c == 0 ? rsrc : W.r, n, c == 0, s));
     for (int j = 0; j < budget; ++j) {
       if (j >= 8 && j % 4 == 0) FR_HIP(hipEventSynchronize(d->ev[(j / 4 - 2) & 3]));  // step j - 5 done
       if (hstat->stop) break;
@@ -411,6 +418,7 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
   S.residual_evals += fz.evals;
   S.restarts = fz.restarts;
   S.r_final = fz.r_final;
+  S.r_ref = fz.r_ref;
   const fr_status result = fz.fin ? (fr_status)fz.result : FR_NOTCONV;
   S.converged = result == FR_OK ? 1 : 0;
   *stats = S;

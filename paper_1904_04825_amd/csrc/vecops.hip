@@ -575,14 +575,24 @@ hipError_t launch_dcgs2_last(GmState* st, const double* partials, int nb, int M,
 
 // Start of a restart cycle: every workgroup forms beta = ||r|| from ||r||^2 and stores
 // the first basis vector v_0 = r / beta; workgroup 0 also resets the cycle state.
-__global__ void __launch_bounds__(256) k_gm_start(GmState* st, const double* beta2, double target, int M,
+// Start of a restart cycle: every workgroup forms beta = ||r|| from ||r||^2 and stores
+// the first basis vector v_0 = r / beta; workgroup 0 also resets the cycle state.  The
+// solve's first cycle also sets the reference norm (ref, or beta when ref <= 0), the
+// target rtol * r_ref and the totals, and ends the solve before any step when beta is
+// not finite or already at the target.  A later cycle does nothing once the solve ended.
+__global__ void __launch_bounds__(256) k_gm_start(GmState* st, const double* beta2, double rtol, double ref, int M,
                                                   GmStatus* hslot, double* __restrict__ v0,
                                                   const double* __restrict__ r, size_t n, int first) {
   if (!first && st->fz.fin) return;
   const double beta = sqrt(*beta2);
-  const double a = 1.0 / beta;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    v0[i] = a * r[i];
+  const double r_ref = ref > 0.0 ? ref : beta;
+  const double target = first ? rtol * r_ref : st->target;
+  const bool end0 = first && (!isfinite(beta) || beta <= target);
+  if (!end0) {
+    const double a = 1.0 / beta;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+      v0[i] = a * r[i];
+  }
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   if (first) {
     st->fz.fin = 0;
@@ -591,25 +601,33 @@ __global__ void __launch_bounds__(256) k_gm_start(GmState* st, const double* bet
     st->fz.evals = 0;
     st->fz.restarts = 0;
     st->fz.r_final = beta;
+    st->fz.r_ref = r_ref;
+    st->target = target;
   }
   st->hslot = hslot;
   for (int i = 0; i <= M; ++i) st->g[i] = 0.0;
   st->g[0] = beta;
   st->beta = beta;
-  st->target = target;
   st->j = 0;
   st->stop = 0;
   st->why = 0;
   st->evals = 0;
   st->done = 0;
   st->rest = beta;
+  if (end0) {
+    st->fz.fin = 1;
+    st->fz.result = isfinite(beta) ? FR_OK : FR_ENAN;
+    st->stop = 1;
+    st->done = 1;
+    if (hslot != nullptr) hslot->stop = 1;
+  }
 }
 
-hipError_t launch_gm_start(GmState* st, const double* beta2, double target, int M, GmStatus* hslot, double* v0,
-                           const double* r, size_t n, int first, hipStream_t s) {
+hipError_t launch_gm_start(GmState* st, const double* beta2, double rtol, double ref, int M, GmStatus* hslot,
+                           double* v0, const double* r, size_t n, int first, hipStream_t s) {
   const unsigned blocks = (unsigned)red_blocks(n);
-  hipLaunchKernelGGL(k_gm_start, dim3(blocks ? blocks : 1), dim3(256), 0, s, st, beta2, target, M, hslot, v0, r, n,
-                     first);
+  hipLaunchKernelGGL(k_gm_start, dim3(blocks ? blocks : 1), dim3(256), 0, s, st, beta2, rtol, ref, M, hslot, v0, r,
+                     n, first);
   return hipGetLastError();
 }
 
