@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 # m <= 32: DCGS2 orthogonalisation on the GPU; m = 40: CGS2 (register-held passes up to
 # 32 vectors, the chunked dot kernels beyond)
-@pytest.mark.parametrize("P,m", [(2, 20), (3, 8), (2, 32), (2, 40)])
+@pytest.mark.parametrize("P,m", [(2, 20), (3, 8), (4, 20), (2, 32), (2, 40)])
 def test_gmres_parity(P, m):
     from paper_1904_04825_amd import F64, GmresOpts
     _, op, disc = setup(9, 7, P, "roe", seed=12)
