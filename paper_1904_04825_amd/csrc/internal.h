@@ -90,6 +90,9 @@ struct ResArgs {
   const double* dV;
   int dnv;
   double* dpart;
+  // optional, b - A x on small Euler meshes (residual_dots_blocks > 0): per-tile partial
+  // sums of ||b - A x||^2 into opart
+  double* opart;
 };
 hipError_t launch_residual(const fr_disc* d, int mode, const ResArgs& a, hipStream_t s);
 // Workgroups of the JF product when it can also run the first DCGS2 pass (small Euler
@@ -222,6 +225,9 @@ hipError_t launch_gm_start(GmState* st, const double* beta2, double rtol, double
 // End of a restart cycle (after the true residual's ||r||^2 in *beta2): the totals, and
 // the decision to end the solve (converged, NaN, breakdown, max_iters) or restart.
 hipError_t launch_gm_cycle_end(GmState* st, const double* beta2, int max_iters, int dcgs, hipStream_t s);
+// The same with ||r||^2 from nbo <= kRedBlocks partial sums (stored to *beta2 as well).
+hipError_t launch_gm_cycle_end_parts(GmState* st, double* beta2, const double* opart, int nbo, int max_iters,
+                                     int dcgs, hipStream_t s);
 // Sum partials[b*stride + i] over b < nblocks into out[i], i < nv (one workgroup).
 hipError_t launch_finalize(const double* partials, int nblocks, int stride, int nv, double* out, const int* skip,
                            hipStream_t s);

@@ -562,6 +562,7 @@ __global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a
     // and their sums, as k_dcgs_dots forms them)
     constexpr int NA = 2 * DOTS;
     double dacc[DOTS > 0 ? NA : 1];
+    double oacc = 0.0;  // mode 2: ||b - A x||^2 of the written entries
 #pragma unroll
     for (int q = 0; q < (DOTS > 0 ? NA : 1); ++q) dacc[q] = 0.0;
 #pragma unroll
@@ -578,10 +579,13 @@ __global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a
             a.out[gi] = R;
           } else {
             const double av = zero_v ? 0.0 : a.shift * ov[MODE ? it : 0][v] - (R - orr[MODE ? it : 0][v]) * ie;
-            if constexpr (MODE == 1)
+            if constexpr (MODE == 1) {
               a.out[gi] = av;
-            else
-              a.out[gi] = a.B[gi] - av;
+            } else {
+              const double o = a.B[gi] - av;
+              a.out[gi] = o;
+              oacc = fma(o, o, oacc);
+            }
             if constexpr (DOTS > 0) {
               const size_t ndof = 4 * vstride;
               double vr[DOTS > 0 ? DOTS : 1];
@@ -595,6 +599,20 @@ __global__ void __launch_bounds__((LineCfg<P, BIG>::NT)) k_euler(const ResArgs a
               dacc[NA - 1] = fma(av, av, dacc[NA - 1]);
             }
           }
+        }
+      }
+    }
+    if constexpr (MODE == 2 && !BIG) {
+      if (a.opart != nullptr) {
+        __shared__ double ored[NT / 64];
+        oacc = wave_sum(oacc);
+        if ((tid & 63) == 0) ored[tid >> 6] = oacc;
+        __syncthreads();
+        if (tid == 0) {
+          double r = 0.0;
+#pragma unroll
+          for (int q = 0; q < NT / 64; ++q) r += ored[q];
+          a.opart[blockIdx.x] = r;
         }
       }
     }
@@ -628,6 +646,11 @@ static hipError_t launch_euler_tile(const fr_disc* d, int mode, const ResArgs& a
   const int ntx = (d->nx + C::TX - 1) / C::TX, nty = (d->ny + C::TY - 1) / C::TY;
   const MeshArgs g{d->nodes, d->nx, d->ny, d->nel, d->phys.gamma};
   dim3 grid(ntx * nty), block(C::NT);
+  if constexpr (BIG) {
+    if (a.opart != nullptr) return hipErrorInvalidValue;
+  } else {
+    if (a.opart != nullptr && (mode != 2 || ntx * nty > kRedBlocks)) return hipErrorInvalidValue;
+  }
   if (a.dV != nullptr) {
     // the JF product with the first DCGS2 pass: small tiles, one partial row slot per tile
     if constexpr (BIG) {

@@ -406,9 +406,16 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
     a2.B = b;
     a2.out = W.r;
     a2.skip = done;
-    FR_HIP(launch_residual(d, 2, a2, s));
-    FR_HIP(launch_norm2(W.r, n, W.partials, beta2, done, s));
-    FR_HIP(launch_gm_cycle_end(W.st, beta2, max_iters, dcgs ? 1 : 0, s));
+    if (jf_dots > 0) {
+      // small Euler meshes: the residual kernel leaves ||r||^2 per tile, the decision adds them
+      a2.opart = W.partials + kPartSecond;
+      FR_HIP(launch_residual(d, 2, a2, s));
+      FR_HIP(launch_gm_cycle_end_parts(W.st, beta2, a2.opart, jf_dots, max_iters, dcgs ? 1 : 0, s));
+    } else {
+      FR_HIP(launch_residual(d, 2, a2, s));
+      FR_HIP(launch_norm2(W.r, n, W.partials, beta2, done, s));
+      FR_HIP(launch_gm_cycle_end(W.st, beta2, max_iters, dcgs ? 1 : 0, s));
+    }
     if (hstat->stop) break;  // the solve has ended, or its stop is on the way
   }
   GmState::Final fz;

@@ -637,8 +637,21 @@ hipError_t launch_gm_start(GmState* st, const double* beta2, double rtol, double
 // true residual (one more product) decides: NaN, converged, breakdown, or the
 // iteration limit end it, else the solve restarts.  An end stops every later kernel
 // and is mirrored to the mapped host status.
-__global__ void k_gm_cycle_end(GmState* st, const double* beta2, int max_iters, int dcgs) {
-  if (threadIdx.x != 0 || st->fz.fin) return;
+__global__ void __launch_bounds__(64) k_gm_cycle_end(GmState* st, double* beta2, const double* opart, int nbo,
+                                                     int max_iters, int dcgs) {
+  if (st->fz.fin) return;
+  // ||r||^2 from the true residual's partial sums (one wavefront, fixed order) when given
+  double b2 = 0.0;
+  if (opart != nullptr) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nbo; b += 64) v += opart[b];
+    b2 = wave_sum(v);
+  }
+  if (threadIdx.x != 0) return;
+  if (opart != nullptr)
+    *beta2 = b2;  // the next cycle's start reads it
+  else
+    b2 = *beta2;
   const int k = st->j, why = st->why;
   st->fz.iters += k;
   st->fz.evals += dcgs ? max(k, st->evals) : k;
@@ -650,7 +663,7 @@ __global__ void k_gm_cycle_end(GmState* st, const double* beta2, int max_iters, 
     res = FR_OK;
   } else {
     st->fz.evals += 1;
-    const double beta = sqrt(*beta2);
+    const double beta = sqrt(b2);
     rf = beta;
     if (!isfinite(beta))
       res = FR_ENAN;
@@ -674,7 +687,15 @@ __global__ void k_gm_cycle_end(GmState* st, const double* beta2, int max_iters, 
 }
 
 hipError_t launch_gm_cycle_end(GmState* st, const double* beta2, int max_iters, int dcgs, hipStream_t s) {
-  hipLaunchKernelGGL(k_gm_cycle_end, dim3(1), dim3(64), 0, s, st, beta2, max_iters, dcgs);
+  hipLaunchKernelGGL(k_gm_cycle_end, dim3(1), dim3(64), 0, s, st, const_cast<double*>(beta2), nullptr, 0, max_iters,
+                     dcgs);
+  return hipGetLastError();
+}
+
+hipError_t launch_gm_cycle_end_parts(GmState* st, double* beta2, const double* opart, int nbo, int max_iters,
+                                     int dcgs, hipStream_t s) {
+  if (opart == nullptr || nbo < 1 || nbo > kRedBlocks) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gm_cycle_end, dim3(1), dim3(64), 0, s, st, beta2, opart, nbo, max_iters, dcgs);
   return hipGetLastError();
 }
 
