@@ -95,6 +95,35 @@ def test_gmres_breakdown_on_invariant_krylov_space(m):
     assert rel(to_np(xg), xo) <= 1e-14
 
 
+def test_gmres_zero_rhs_and_iteration_limit():
+    """The solve's start and restart decisions on the device: b = 0 ends before any step
+    with x = 0; an iteration limit that is not a multiple of m ends the second, shorter
+    cycle with FR_NOTCONV after exactly max_iters steps (the oracle stops at the same
+    count)."""
+    from paper_1904_04825_amd import F64, GmresOpts
+    _, op, disc = setup(6, 5, 2, "rusanov", seed=18)
+    U = vortex_state(op)
+    R0 = op.residual(U)
+    shift = 2.0
+    Ug, R0g = to_gpu(U), to_gpu(R0)
+    pc = disc.ejacobi_factor(Ug, shift, F64)
+    x0, s0 = disc.gmres_solve(pc, Ug, R0g, shift, torch.zeros_like(Ug), opts=GmresOpts(m=20, rtol=1e-8))
+    print("b = 0:", s0, flush=True)
+    assert s0["status"] == 0 and s0["converged"] == 1 and s0["iters"] == 0
+    assert float(torch.count_nonzero(x0)) == 0
+    b = fi.random_vector(U.shape, seed=26)
+    pc_o = linear.ElementJacobi(op, U, shift)
+    xo, so = linear.fgmres(lambda v: linear.jf_matvec(op.residual, U, R0, v, shift), pc_o.apply, b, m=20, rtol=1e-15,
+                           max_iters=25)
+    xg, sg = disc.gmres_solve(pc, Ug, R0g, shift, to_gpu(b), opts=GmresOpts(m=20, rtol=1e-15, max_iters=25))
+    print("limit:", so, sg, flush=True)
+    assert not so.converged and so.iters == 25
+    assert sg["status"] == 1 and sg["converged"] == 0 and sg["iters"] == 25 and sg["restarts"] == 1
+    # not converged: the two orthogonalisations' rounding (DCGS2 against MGS) and the FD
+    # products' differ at this level after a restart
+    assert rel(to_np(xg), xo) <= 1e-6
+
+
 def test_gmres_nonzero_initial_guess_and_restart():
     from paper_1904_04825_amd import F64, GmresOpts
     _, op, disc = setup(6, 6, 2, "rusanov", seed=13)
