@@ -45,6 +45,7 @@ class StepStats:
     residual_evals: int = 0
     converged: bool = True
     per_solve: list = field(default_factory=list)
+    stage_increments: list = field(default_factory=list)   # ROW: the stage solutions Y_i
 
 
 class Counted:
@@ -100,6 +101,7 @@ def row_step(op, table, dt, U, lin: LinOpts = LinOpts()):
         st.converged &= gs.converged
         Y.append(y)
     st.residual_evals = R.count
+    st.stage_increments = Y
     return U + sum(table.m[j] * Y[j] for j in range(table.s)), st
 
 

@@ -68,7 +68,9 @@ def mse(y, t):
 
 def backward(p, cache, y, t, emulate_bf16=True):
     """Gradients of the mean squared error; the backward operands are rounded to
-    bfloat16 where the kernels round them (output error and hidden gradients)."""
+    bfloat16 where the kernels round them (the output error and the hidden-layer
+    gradients as operands of the weight-gradient and back-propagation products).  The
+    bias gradients are sums of the same gradients before that rounding."""
     r = bf16 if emulate_bf16 else (lambda a: np.asarray(a, dtype=np.float64))
     x, z1, h1, z2, h2 = cache
     B = y.shape[0]
@@ -80,11 +82,11 @@ def backward(p, cache, y, t, emulate_bf16=True):
     dh2 = dyr @ r(p["W3"])
     dz2 = r(dh2 * gelu_grad(z2))
     g["W2"] = dz2.T @ h1
-    g["b2"] = (dh2 * gelu_grad(z2)).sum(axis=0) if not emulate_bf16 else dz2.sum(axis=0)
+    g["b2"] = (dh2 * gelu_grad(z2)).sum(axis=0)
     dh1 = dz2 @ r(p["W2"])
     dz1 = r(dh1 * gelu_grad(z1))
     g["W1"] = dz1.T @ x
-    g["b1"] = dz1.sum(axis=0)
+    g["b1"] = (dh1 * gelu_grad(z1)).sum(axis=0)
     return g
 
 

@@ -182,6 +182,17 @@ struct GmStatus {
 // restarts are kPartStride apart.
 constexpr int kPartStride = kMaxM + 2;
 constexpr size_t kPartSecond = (size_t)kRedBlocks * 32;
+// Offset of the DCGS2 second pass's partial sums of ||w'||^2 (the first pass, alone or
+// fused into the JF product, fills up to 2 x 32 rows before it).
+constexpr size_t kDcgsNormOff = 2 * kPartSecond;
+// Offset of the preconditioner application's partial sums of ||z_j||^2 inside an
+// Arnoldi step.  The JF product that reads them may also write the first DCGS2 pass's
+// rows (up to 2 kJfDotsMax of them) while other tiles still read, so this slot lies
+// past every row of both passes.
+constexpr size_t kPartZ = kDcgsNormOff + kRedBlocks;
+static_assert(2 * (size_t)kJfDotsMax * kRedBlocks <= kPartZ, "fused DCGS2 rows overlap the ||z||^2 partials");
+static_assert(2 * kPartSecond <= kPartZ, "DCGS2 first-pass rows overlap the ||z||^2 partials");
+static_assert(kPartZ + kRedBlocks <= (size_t)kRedBlocks * (kMaxM + 2), "||z||^2 partials past the workspace");
 // Workgroups of the CGS passes over n entries (<= kRedBlocks), i.e. the number of partial
 // sums of ||w||^2 that the last pass leaves.
 int cgs_blocks(size_t n);

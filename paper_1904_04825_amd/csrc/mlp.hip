@@ -48,7 +48,7 @@ __device__ __forceinline__ bf16x4 load4(const uint16_t* __restrict__ p, int row,
 //   EPI_F32:       Cf[m][n] = C
 //   EPI_BIAS_F32:  Cf[m][n] = C + bias[n]
 //   EPI_BIAS_GELU: z = C + bias -> Z[m][n] (if Z), H[m][n] = bf16(gelu z), Ht[n][m] (if Ht)
-//   EPI_GELU_GRAD: d = C * gelu'(Zin[m][n]) -> H[m][n] = bf16(d), Ht[n][m]
+//   EPI_GELU_GRAD: d = C * gelu'(Zin[m][n]) -> Cf[m][n] = d (if Cf), H[m][n] = bf16(d), Ht[n][m]
 template <int EPI>
 __global__ void __launch_bounds__(256) k_gemm_nt(const uint16_t* __restrict__ A, const uint16_t* __restrict__ B, int M,
                                                  int N, int K, const float* __restrict__ bias, float* __restrict__ Cf,
@@ -82,7 +82,9 @@ __global__ void __launch_bounds__(256) k_gemm_nt(const uint16_t* __restrict__ A,
       H[i] = h;
       if (Ht != nullptr) Ht[(size_t)col * M + row] = h;
     } else {
-      const uint16_t d = f2bf(c * gelu_grad_f(Zin[i]));
+      const float dv = c * gelu_grad_f(Zin[i]);
+      if (Cf != nullptr) Cf[i] = dv;
+      const uint16_t d = f2bf(dv);
       H[i] = d;
       if (Ht != nullptr) Ht[(size_t)col * M + row] = d;
     }
@@ -369,7 +371,7 @@ hipError_t mlp_stats(const float* raw, int count, int Np, float* norm, hipStream
 
 size_t mlp_train_bytes(int B, int In, int H, int Out) {
   auto a = [](size_t b) { return (b + 255) / 256 * 256; };
-  return 2 * a((size_t)B * In * 2) + 2 * a((size_t)B * H * 4) + 4 * a((size_t)B * H * 2) + a((size_t)B * Out * 4) * 3 +
+  return 2 * a((size_t)B * In * 2) + 4 * a((size_t)B * H * 4) + 4 * a((size_t)B * H * 2) + a((size_t)B * Out * 4) * 3 +
          2 * a((size_t)B * Out * 2) + 4 * a((size_t)B * H * 2) + a(sizeof(double) * 4096);
 }
 
@@ -397,6 +399,8 @@ hipError_t mlp_train_step(fr_mlp_trainer* tr, const float* raw, const int* idx, 
   uint16_t* dz2t = (uint16_t*)take((size_t)B * H * 2);
   uint16_t* dz1 = (uint16_t*)take((size_t)B * H * 2);
   uint16_t* dz1t = (uint16_t*)take((size_t)B * H * 2);
+  float* dz2f = (float*)take((size_t)B * H * 4);  // hidden gradients before the bf16 rounding (bias sums)
+  float* dz1f = (float*)take((size_t)B * H * 4);
   const uint16_t* W = (const uint16_t*)net->d_w;
   float* g = tr->d_grad;
   hipLaunchKernelGGL(k_batch, dim3(grid_for((size_t)B * (In + Out))), dim3(256), 0, s, raw, 20 * Np, idx, B, Np,
@@ -414,16 +418,16 @@ hipError_t mlp_train_step(fr_mlp_trainer* tr, const float* raw, const int* idx, 
     hipLaunchKernelGGL(k_colsum, dim3((Out + kColsumCols - 1) / kColsumCols), dim3(kColsumCols * kColsumRows), 0, s, nullptr, dy32, B, Out, g + L.pb3);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) e = gemm<EPI_GELU_GRAD>(dyr, W + L.w3t, B, H, Out, nullptr, nullptr, Z2, nullptr, dz2, dz2t, s);
+  if (e == hipSuccess) e = gemm<EPI_GELU_GRAD>(dyr, W + L.w3t, B, H, Out, nullptr, dz2f, Z2, nullptr, dz2, dz2t, s);
   if (e == hipSuccess) e = gemm<EPI_F32>(dz2t, H1t, H, H, B, nullptr, g + L.pW2, nullptr, nullptr, nullptr, nullptr, s);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_colsum, dim3((H + kColsumCols - 1) / kColsumCols), dim3(kColsumCols * kColsumRows), 0, s, dz2, nullptr, B, H, g + L.pb2);
+    hipLaunchKernelGGL(k_colsum, dim3((H + kColsumCols - 1) / kColsumCols), dim3(kColsumCols * kColsumRows), 0, s, nullptr, dz2f, B, H, g + L.pb2);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) e = gemm<EPI_GELU_GRAD>(dz2, W + L.w2t, B, H, H, nullptr, nullptr, Z1, nullptr, dz1, dz1t, s);
+  if (e == hipSuccess) e = gemm<EPI_GELU_GRAD>(dz2, W + L.w2t, B, H, H, nullptr, dz1f, Z1, nullptr, dz1, dz1t, s);
   if (e == hipSuccess) e = gemm<EPI_F32>(dz1t, Xt, H, In, B, nullptr, g + L.pW1, nullptr, nullptr, nullptr, nullptr, s);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_colsum, dim3((H + kColsumCols - 1) / kColsumCols), dim3(kColsumCols * kColsumRows), 0, s, dz1, nullptr, B, H, g + L.pb1);
+    hipLaunchKernelGGL(k_colsum, dim3((H + kColsumCols - 1) / kColsumCols), dim3(kColsumCols * kColsumRows), 0, s, nullptr, dz1f, B, H, g + L.pb1);
     e = hipGetLastError();
   }
   if (e != hipSuccess || tr->lr <= 0.0f) return e;  // lr <= 0: gradients only

@@ -357,9 +357,9 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
       const int* skip = &W.st->stop;
       // z_j = M^{-1} v_j; for j >= 1 the same kernel first runs the Givens update of step
       // j - 1 and forms v_j = w / h_{j,j-1} on the fly.  The partial sums of ||z_j||^2 go
-      // to the second CGS partial region (the last pass of step j - 1 left its ||w||^2
-      // partials in the first).
-      double* zpart = W.partials + kPartSecond;
+      // to their own slot, past the rows of both orthogonalisation passes (the JF product
+      // that reads them may write the first pass's rows meanwhile).
+      double* zpart = W.partials + kPartZ;
       int np = 0;
       if (j == 0) {
         FR_HIP(launch_ejacobi_solve(d, factors, prec, vj, nullptr, nullptr, zj, zpart, &np, nullptr, skip, s));

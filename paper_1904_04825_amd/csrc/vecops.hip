@@ -353,8 +353,6 @@ hipError_t launch_arnoldi_cgs2(const double* V, int nv, double* w, double* parti
 //     correction of ~v_j expressed in the final basis), rotates it, and stores column
 //     j's first pass (b_t, c_j) and ||w||.
 // The next step's preconditioner kernel forms ~v_{j+1} = w' / ||w'||.
-// Offset of pass 2's partial sums of ||w'||^2 (pass 1 fills 2 NV <= 64 rows first).
-constexpr size_t kDcgsNormOff = 2 * kPartSecond;
 
 template <int NV>
 __global__ void __launch_bounds__(kRedThreads) k_dcgs_dots(const double* __restrict__ V, int nv,

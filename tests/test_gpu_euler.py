@@ -7,7 +7,7 @@ import torch
 import fr_inputs as fi
 from oracle import linear
 from oracle.problem import l2_error, sample_state
-from tests.gpu_common import rel, residual_parity, setup, to_gpu, to_np, vortex_state
+from tests.gpu_common import check_residual, rel, setup, to_gpu, to_np, vortex_state
 
 pytestmark = pytest.mark.gpu
 
@@ -24,8 +24,7 @@ def test_residual_parity(P, flux):
     U = vortex_state(op)
     Rg = to_np(disc.residual(to_gpu(U)))
     Ro = op.residual(U)
-    print(f"  rel err {rel(Rg, Ro):.3e}  budget measure {residual_parity(Rg, Ro, op, U):.3e}", flush=True)
-    assert residual_parity(Rg, Ro, op, U) <= 1e-12
+    check_residual(Rg, Ro, op.residual, U)
 
 
 @pytest.mark.parametrize("P", [2, 3, 4])
@@ -49,9 +48,7 @@ def test_residual_minimum_mesh_and_full_workload_mesh():
         _, op, disc = setup(nx, ny, P, "rusanov", seed=seed)
         U = vortex_state(op, 0.7)
         Rg, Ro = to_np(disc.residual(to_gpu(U))), op.residual(U)
-        print(f"  {nx}x{ny} P{P}: rel err {rel(Rg, Ro):.3e}  budget measure {residual_parity(Rg, Ro, op, U):.3e}",
-              flush=True)
-        assert residual_parity(Rg, Ro, op, U) <= 1e-12
+        check_residual(Rg, Ro, op.residual, U, f"{nx}x{ny} P{P}")
 
 
 # meshes large enough for the large tiles (P2: 16x5, P3: 8x8, P4: 10x5; at least 2048 of
@@ -67,8 +64,7 @@ def test_residual_and_matvec_parity_large_tiles(P):
     U = vortex_state(op)
     Ro = op.residual(U)
     Rg = to_np(disc.residual(to_gpu(U)))
-    print(f"  residual budget measure {residual_parity(Rg, Ro, op, U):.3e}", flush=True)
-    assert residual_parity(Rg, Ro, op, U) <= 1e-12
+    check_residual(Rg, Ro, op.residual, U)
     v = fi.random_vector(U.shape, seed=9, scale=1e-3)
     Ao = linear.jf_matvec(op.residual, U, Ro, v, 4.0, mode="rms")
     Ag = to_np(disc.jf_matvec(to_gpu(U), to_gpu(Ro), to_gpu(v), 4.0))

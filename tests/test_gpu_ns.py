@@ -10,7 +10,7 @@ from oracle import integrators as I
 from oracle import linear
 from oracle.problem import make_ns, sample_state
 from oracle.tableaux import ESDIRK, ROW
-from tests.gpu_common import rel, residual_parity, to_gpu, to_np
+from tests.gpu_common import check_residual, rel, to_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -39,8 +39,7 @@ def test_ns_residual_parity(P, flux):
     U = _shear(op)
     Rg = to_np(disc.residual(to_gpu(U)))
     Ro = op.residual(U)
-    print(f"NS P={P} {flux}: rel {rel(Rg, Ro):.3e} budget {residual_parity(Rg, Ro, op, U):.3e}", flush=True)
-    assert residual_parity(Rg, Ro, op, U) <= 1e-12
+    check_residual(Rg, Ro, op.residual, U, f"NS P={P} {flux}")
 
 
 def test_ns_residual_conservation_and_freestream():
