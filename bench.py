@@ -1,24 +1,26 @@
 """Benchmark: Jacobian-free implicit time steps of FR/CPR flows on one MI355X.
 
-Default workload (64x64 perturbed quads, P = 3, 262,144 DOFs, the isentropic
-vortex): a step is one ROW3 (ROS34PW2) time step with dt = 0.1, FGMRES(20) at
-rtol 1e-8, Rusanov flux.  Residual evaluations, Jacobian-free products,
-element-Jacobi assembly/inversion/application, the Arnoldi/Givens loop and the
-learned warm start all run in the HIP library; inputs are synthetic and resident
-in HBM before timing.
+Default workload (the combined-at-scale configuration): the isentropic vortex on
+512x512 perturbed quads (mesh seed 5), P = 4, 26,214,400 DOFs, 100x100 element
+blocks; a step is one ROW4 (RODASP) time step with dt = 0.0125, FGMRES(20) at rtol
+1e-8, Rusanov flux.  Residual evaluations, Jacobian-free products, element-Jacobi
+assembly/inversion/application, the Arnoldi/Givens loop and the learned warm start
+all run in the HIP library; inputs are synthetic and resident in HBM before timing.
 
-Phases: (1) untimed warm-up: `--warmup` plain steps from t = 0 that also log the
-stage solves (training data); (2) one network per ROW stage trained on the GPU
-from those logs; (3) timed: `--steps` steps from the warm-up's end state with the
-FP64 element-Jacobi (the headline `value`), then the same steps with the FP32
-MFMA element-Jacobi, then FP32 + learned warm start; (4) the ESDIRK (3, or 4 beside
-ROW4) and BDF2 legs from the same state: FP64, FP32, and FP32 + learned PTC starts
-(networks trained on a logging run of each scheme from t = 0).
+Phases: (1) untimed warm-up: `--warmup` steps from t = 0 (FP32 element-Jacobi) that
+also log the stage solves (training data); (2) one network per ROW stage trained on
+the GPU from those logs; (3) timed: `--steps` steps from the warm-up's end state with
+the plain FP64 element-Jacobi (the headline `value`), then the same steps with the
+FP32 MFMA element-Jacobi, then FP32 + learned warm start; all three legs end at the
+same time with the same rho L2 error against the exact vortex (reported, and their
+relative difference); (4) optional (`--schemes`): the ESDIRK and BDF2 legs from the
+same state.
 
 value = DOF-residuals/s = ndof x (residual evaluations incl. JF products) / wall time
-of the FP64 leg.  The JSON line also carries the dominant kernel's roofline (live
-HIP-event timing on the launch stream), wall-seconds per unit physical time and the
-L2 error of every leg, and the FP64 oracle's rate on one host core.
+of the FP64 leg.  The JSON line also carries wall-seconds per unit physical time of
+every leg at the matched error, the learned leg's training and logging cost and its
+break-even step count, the dominant kernel's roofline (live HIP-event timing on the
+launch stream) and the FP64 oracle's rate on the host's cores.
 """
 from __future__ import annotations
 
@@ -46,9 +48,9 @@ WORKLOADS = {
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=24, help="untimed logging steps (training data for the warm start)")
-    ap.add_argument("--workload", default="vortex64_p3", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=6, help="untimed logging steps (training data for the warm start)")
+    ap.add_argument("--workload", default="vortex512_p4", choices=sorted(WORKLOADS))
     ap.add_argument("--dt", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernels", action="store_true", help="skip the per-kernel timing block")
@@ -59,13 +61,21 @@ def parse():
     ap.add_argument("--adam-steps", type=int, default=1500, help="Adam steps per stage network")
     ap.add_argument("--batch", type=int, default=1024, help="training batch (samples)")
     ap.add_argument("--no-fp32-leg", action="store_true", help="skip the FP32-preconditioner legs")
-    ap.add_argument("--no-schemes", action="store_true", help="skip the ESDIRK and BDF2 legs")
+    ap.add_argument("--schemes", action="store_true", help="also run the ESDIRK and BDF2 legs")
     ap.add_argument("--allow-unconverged", action="store_true",
                     help="count GMRES solves that reach the iteration cap instead of stopping")
     ap.add_argument("--order-study", action="store_true",
                     help="instead of the bench line: ROW3, ESDIRK3 and BDF2 over t in [0, 10] at dt 0.2, 0.1, 0.05 "
                          "on the 64x64 P3 vortex; errors against the exact vortex and against a ROW4 run at "
                          "dt 0.0125, observed orders, wall seconds per unit time")
+    ap.add_argument("--cpu-sample", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--paper-vortex", default=None,
+                    help="instead of the bench line: the paper's vortex study (50x50 P6, Roe, GMRES(60)); a comma "
+                         "list of SCHEME/STEPS entries of tests/golden/paper_vortex_tables.json, or 'all'")
+    ap.add_argument("--mach-reading", default="magnitude", choices=["magnitude", "u"],
+                    help="velocity of the paper's Mach number: |V| or u")
+    ap.add_argument("--study-eps", default="abs", choices=["abs", "rms"],
+                    help="JF perturbation of the paper-vortex study: the literal eps (abs) or eps / rms(v)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy (counter calibration for rocprofv3 --pmc runs)")
     return ap.parse_args()
@@ -94,29 +104,87 @@ def time_kernel(fn, reps=50, warm=5):
     return s.elapsed_time(e) / reps * 1e-3
 
 
-def cpu_baseline(nodes, U0, dt, p, scheme):
-    """The FP64 oracle on the host: R(U), the element-Jacobi blocks at q^n and the
-    first 60 FGMRES iterations of the first ROW stage of the same workload (one thread)."""
+def cpu_sample(spec):
+    """One bounded sample of the FP64 oracle on one host core (run in a child process that
+    never touches the GPU): the first ROW stage of the workload's kind on a smaller mesh --
+    R(U), the element-Jacobi blocks at q^n and `iters` FGMRES(20) iterations -- or, with
+    iters = 0, one residual evaluation on the full mesh.  Prints one JSON line."""
     from threadpoolctl import threadpool_limits
 
+    import fr_inputs as fi
     from oracle import integrators as I
     from oracle import linear
-    from oracle.problem import make_euler
+    from oracle.problem import make_euler, sample_state
     from oracle.tableaux import ROW
+    nx, p, seed, iters, scheme, dt = (spec[k] for k in ("nx", "p", "seed", "iters", "scheme", "dt"))
+    nodes = fi.workload_nodes(spec["nodes"]) if spec.get("nodes") else fi.perturbed_nodes(nx, nx, -5.0, -5.0, 10.0,
+                                                                                          10.0, 0.1, seed)
     op = make_euler(nodes, p, flux="rusanov")
+    vx = fi.Vortex()
+    U = sample_state(op, lambda x, y: vx.conservative(x, y, 0.0))
     with threadpool_limits(1):
-        t0 = time.perf_counter()
         R = I.Counted(op)
-        R0 = R(U0)
-        shift = 1.0 / (ROW[f"ROW{scheme}"].gamma * dt)
-        pc = linear.ElementJacobi(op, U0, shift)
-        x, st = linear.fgmres(lambda v: linear.jf_matvec(R, U0, R0, v, shift), pc.apply, R0, m=20, rtol=1e-8,
-                              max_iters=60)
+        t0 = time.perf_counter()
+        R0 = R(U)
+        if iters > 0:
+            shift = 1.0 / (ROW[f"ROW{scheme}"].gamma * dt)
+            pc = linear.ElementJacobi(op, U, shift)
+            _, st = linear.fgmres(lambda v: linear.jf_matvec(R, U, R0, v, shift), pc.apply, R0, m=20, rtol=1e-8,
+                                  max_iters=iters)
         wall = time.perf_counter() - t0
-    evals = R.count
-    return {"value": op.ndof * evals / wall, "unit": "DOF-residuals/s", "cores": 1, "kind": "oracle",
-            "sample": f"R(U) + element-Jacobi assembly + {st.iters} FGMRES(20) iterations of ROW{scheme} stage 1 on "
-                      f"the same mesh and state: {evals} residual evaluations in {wall:.1f} s, numpy, 1 thread"}
+    print(json.dumps({"ndof": op.ndof, "evals": R.count, "wall": wall}), flush=True)
+
+
+def _children(spec, n):
+    """Run n concurrent single-thread oracle samples as child processes; returns their results."""
+    import subprocess
+    cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--cpu-sample", json.dumps(spec)]
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    procs = [subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+             for _ in range(n)]
+    res = []
+    for pr in procs:
+        so, se = pr.communicate()
+        if pr.returncode != 0:
+            raise RuntimeError(f"oracle sample failed: {se[-2000:]}")
+        res.append(json.loads(so.strip().splitlines()[-1]))
+    return res
+
+
+def cpu_baseline(W, dt, scheme):
+    """The FP64 oracle (numpy, as it stands) on the host's cores.  Bounded samples: the first
+    ROW stage of the same kind of workload on a 64x64 perturbed mesh at the same degree
+    (R(U), element-Jacobi blocks, 20 FGMRES(20) iterations; every operation is linear in
+    the number of elements, so the per-DOF rate carries over), once on one core and as
+    concurrent single-thread processes on all cores (aggregate rate); plus one residual
+    evaluation on the full mesh, which shows the per-DOF rate at full size."""
+    import platform
+    ncpu = os.cpu_count() or 1
+    ncores = max(1, min(ncpu, 16))
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    spec = {"nx": 64, "p": W["p"], "seed": 5, "iters": 20, "scheme": scheme, "dt": dt}
+    one = _children(spec, 1)[0]
+    allc = _children(spec, ncores)
+    full = _children({**spec, "nodes": W["nodes"], "iters": 0}, 1)[0]
+    rate1 = one["ndof"] * one["evals"] / one["wall"]
+    rate_all = sum(r["ndof"] * r["evals"] for r in allc) / max(r["wall"] for r in allc)
+    return {"value": rate_all, "unit": "DOF-residuals/s", "cores": ncores, "kind": "oracle",
+            "sample": f"ROW{scheme} stage-1 pipeline of the FP64 numpy oracle (R(U), element-Jacobi blocks at q^n, "
+                      f"FGMRES(20) to rtol 1e-8, at most 20 iterations; {one['evals']} residual evaluations) on a 64x64 perturbed P{W['p']} "
+                      f"vortex mesh ({one['ndof']} DOFs), {ncores} concurrent single-thread processes (aggregate "
+                      f"rate, per-DOF rate taken as the full mesh's: every step is linear in the element count)",
+            "one_core": {"value": rate1, "wall_s": one["wall"]},
+            "full_mesh_residual": {"dof_res_per_s": full["ndof"] * full["evals"] / full["wall"],
+                                   "ndof": full["ndof"], "wall_s": full["wall"], "cores": 1},
+            "host": {"nproc": ncpu, "cpu_model": model}}
 
 
 def kernel_block(disc, Ustart, dt, scheme, ndof, workload):
@@ -235,6 +303,72 @@ def order_study(disc, U0, vortex):
     return res
 
 
+def paper_vortex_study(select, speed, eps_mode="abs", progress=True):
+    """The paper's own vortex study (Section 5.1): 50x50 uniform quads on [-10,10]^2, P6,
+    Roe flux, GMRES(60) with the literal eps = 1e-8, FP64 element-Jacobi, one period
+    (T = 20) at the table's step counts and tolerances; E(rho) and E(u) against the exact
+    vortex beside the values the paper prints (tests/golden/paper_vortex_tables.json)."""
+    import torch
+
+    import fr_inputs as fi
+    from paper_1904_04825_amd import EPS_ABS, EPS_RMS, Disc, GmresOpts, SolverOpts
+    em = EPS_ABS if eps_mode == "abs" else EPS_RMS
+    with open(os.path.join(ROOT, "tests", "golden", "paper_vortex_tables.json")) as fh:
+        golden = json.load(fh)
+    T = golden["workload"]["period"]
+    vx = fi.paper_vortex(speed=speed)
+    disc = Disc(fi.workload_nodes("vortex50_p6_paper"), 6, flux="roe")
+    xy = disc.solution_points().cpu().numpy()
+    U0 = torch.as_tensor(vx.conservative(xy[0], xy[1], 0.0), device=disc.device).contiguous()
+    rows = []
+    for ent in golden["entries"]:
+        key = f"{ent['scheme']}/{ent['steps']}"
+        if select != "all" and key not in select:
+            continue
+        sch, n = ent["scheme"], ent["steps"]
+        dt = T / n
+        U = U0.clone()
+        tot = {"gmres_iters": 0, "ptc_iters": 0, "rejections": 0, "residual_evals": 0}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        status = 0
+        if sch.startswith("ROW"):
+            o = SolverOpts(lin=GmresOpts(m=60, rtol=ent["tol_lin"], eps_mode=em))
+            for _ in range(n):
+                st = disc.row_step(U, int(sch[3]), dt, o)
+                status = status or st["status"]
+                tot["gmres_iters"] += st["gmres_iters"]
+                tot["residual_evals"] += st["residual_evals"]
+        else:
+            o = SolverOpts(lin=GmresOpts(m=60, rtol=ent["tol_lin"], eps_mode=em), tol_nl=ent["tol_nl"])
+            Um1 = None
+            for _ in range(n):
+                if sch.startswith("ESDIRK"):
+                    st = disc.esdirk_step(U, int(sch[6]), dt, o)
+                else:
+                    Un, st = disc.bdf2_step(Um1, U, dt, o)
+                    Um1, U = U, Un
+                status = status or st["status"]
+                for k in tot:
+                    tot[k] += st[k]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        e_rho = disc.l2_error_vortex(U, 0, T, vx)
+        e_u = disc.l2_error_vortex(U, 1, T, vx)
+        row = {"scheme": sch, "steps": n, "dt": dt, "tol_lin": ent["tol_lin"], "tol_nl": ent.get("tol_nl"),
+               "status": status, "e_rho": e_rho, "e_rho_paper": ent["e_rho"], "ratio_rho": e_rho / ent["e_rho"],
+               "e_u": e_u, "e_u_paper": ent["e_u"], "wall_s": wall, "wall_s_per_time_unit": wall / T,
+               **{k: v / n for k, v in tot.items() if k != "rejections"}, "rejections": tot["rejections"]}
+        if ent.get("note"):
+            row["paper_scheme"] = ent["note"]
+        rows.append(row)
+        if progress:
+            print(f"# {sch} T/{n}: E(rho) {e_rho:.4e} (paper {ent['e_rho']:.4e}, ratio {e_rho / ent['e_rho']:.3f}), "
+                  f"E(u) {e_u:.4e} (paper {ent['e_u']:.4e}), {wall:.1f} s", flush=True)
+    return {"mode": "paper-vortex", "mach_reading": speed, "eps_mode": eps_mode, "workload": golden["workload"],
+            "rows": rows}
+
+
 def run_leg(disc, U, steps, scheme, dt, opts, allow_unconverged=False):
     import torch
     evals = iters = 0
@@ -257,6 +391,13 @@ def run_leg(disc, U, steps, scheme, dt, opts, allow_unconverged=False):
 
 def main():
     args = parse()
+    if args.cpu_sample is not None:
+        cpu_sample(json.loads(args.cpu_sample))
+        return
+    if args.paper_vortex is not None:
+        sel = "all" if args.paper_vortex == "all" else set(args.paper_vortex.split(","))
+        print(json.dumps(paper_vortex_study(sel, args.mach_reading, args.study_eps)), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -322,7 +463,7 @@ def main():
         if logs is not None:
             for lg in logs.logs:
                 lg.set_elems(rng.choice(disc.nel, per_stage, replace=False))
-        st = disc.row_step(U, scheme, dt, SolverOpts(lin=lin, log=logs, yhist=yhist,
+        st = disc.row_step(U, scheme, dt, SolverOpts(lin=lin, log=logs, yhist=yhist, precond_precision=F32,
                                                      commit_unconverged=int(args.allow_unconverged)))
         if st["status"] != 0 and not (args.allow_unconverged and st["status"] == 1):
             raise RuntimeError(f"warm-up row_step status {st['status']}")
@@ -339,13 +480,9 @@ def main():
         for i, lg in enumerate(stage_logs.logs):
             tr = MlpTrainer(disc, n_hidden=256, seed=seed0 + i, lr=1e-3)
             tr.fit_stats(lg)
-            ls = []
-            for it in range(args.adam_steps):
-                idx = torch.as_tensor(rng.choice(lg.count, min(args.batch, lg.count), replace=False), dtype=torch.int32,
-                                      device=dev)
-                ls.append(tr.step(lg, idx, lr=1e-3 * 0.5 * (1 + np.cos(np.pi * it / args.adam_steps))))
+            ls = tr.fit(lg, args.adam_steps, args.batch, lr=1e-3, seed=seed0 + 100 + i, report_every=250)
             trainers.append(tr)
-            final_loss.append(float(np.mean(ls[-20:])))
+            final_loss.append(float(ls[-1][1]))
         torch.cuda.synchronize()
         info = {"samples_per_stage": stage_logs.logs[0].count, "adam_steps_per_stage": args.adam_steps,
                 "batch": args.batch, "final_mse_normalised": final_loss, "train_s": time.perf_counter() - t_tr}
@@ -388,13 +525,25 @@ def main():
                 "gmres_iters_per_step": i3 / args.steps, "l2_err_rho": err(U), **x3,
                 "rel_diff_vs_fp64": float(torch.linalg.norm(U - U_fp64) / torch.linalg.norm(U_fp64)),
                 "speedup_vs_plain_fp64": wall / w3}
+            # cost of the learned part: the logging warm-up and the training, against the
+            # time it saves per step (over the FP32 leg, and over the plain FP64 leg)
+            tr_s = out["extra"]["learned_training"]["train_s"]
+            save32 = (w2 - w3) / args.steps
+            save64 = (wall - w3) / args.steps
+            legs["fp32_precond_learned"]["cost"] = {
+                "logging_warmup_s": out["extra"]["warmup_s"], "train_s": tr_s,
+                "saved_s_per_step_vs_fp32": save32, "saved_s_per_step_vs_fp64": save64,
+                "break_even_steps_vs_fp32": (tr_s / save32) if save32 > 0 else None,
+                "break_even_steps_vs_fp64": (tr_s / save64) if save64 > 0 else None,
+                "note": "the logging steps are ordinary time steps of the run (FP32 element-Jacobi) that also "
+                        "store training samples; training is the extra cost"}
     out["extra"]["legs"] = legs
 
     # ---- (4) the other implicit schemes of the same workload, FP64 element-Jacobi:
     # ESDIRK3 (ESDIRK4 beside ROW4) and BDF2 (BDF1 start), each also with the FP32
     # element-Jacobi, with pseudo-transient continuation, inexact
     # Newton (GMRES rtol 1e-1 per PTC iteration), nonlinear tolerance 1e-8
-    if not args.no_schemes:
+    if args.schemes:
         sopts = SolverOpts(lin=GmresOpts(m=20, rtol=1e-1), tol_nl=1e-8)
         schemes = {}
 
@@ -494,7 +643,7 @@ def main():
         out["extra"]["calib_copy_bytes"] = src.numel() * 8
 
     if not args.no_cpu_baseline and W["physics"] == "euler":
-        out["cpu_baseline"] = cpu_baseline(nodes, Ustart.cpu().numpy().reshape(4, disc.nel, -1), dt, W["p"], scheme)
+        out["cpu_baseline"] = cpu_baseline(W, dt, scheme)
     print(json.dumps(out), flush=True)
 
 

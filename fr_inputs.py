@@ -96,6 +96,17 @@ class Vortex:
         return np.stack([rho, rho * u, rho * v, p / (self.gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
 
 
+def paper_vortex(mach: float = 0.5, speed: str = "magnitude") -> Vortex:
+    """The vortex of the paper's own study (Section 5.1): free stream (rho, u, v) = (1, 1, 1)
+    at Mach 0.5, R = 1, alpha = 5, phi = 1/2, periodic box [-10, 10]^2 (period 20).  The
+    velocity the Mach number refers to is not stated: speed = "magnitude" reads
+    Ma = |V|/c with |V| = sqrt(2) (c = 2 sqrt 2, p = 8/1.4), speed = "u" reads Ma = u/c
+    (c = 2, p = 4/1.4)."""
+    vel = math.sqrt(2.0) if speed == "magnitude" else 1.0
+    c = vel / mach
+    return Vortex(p_inf=c * c / GAMMA, xlo=-10.0, ylo=-10.0, lx=20.0, ly=20.0)
+
+
 def _wrap(d, L):
     """Map a displacement into [-L/2, L/2)."""
     return d - L * np.floor(d / L + 0.5)
@@ -142,6 +153,8 @@ WORKLOADS = {
     "vortex64_p3_perturbed": dict(nx=64, ny=64, p=3, x0=-5.0, y0=-5.0, lx=10.0, ly=10.0, perturb=0.1, seed=2),
     "shear256_p3": dict(nx=256, ny=256, p=3, x0=0.0, y0=0.0, lx=1.0, ly=1.0, perturb=0.0, seed=None),
     "vortex512_p4_perturbed": dict(nx=512, ny=512, p=4, x0=-5.0, y0=-5.0, lx=10.0, ly=10.0, perturb=0.1, seed=5),
+    # the paper's own vortex study (Section 5.1)
+    "vortex50_p6_paper": dict(nx=50, ny=50, p=6, x0=-10.0, y0=-10.0, lx=20.0, ly=20.0, perturb=0.0, seed=None),
 }
 
 

@@ -69,7 +69,7 @@ typedef struct fr_disc fr_disc; /* opaque: host metadata + borrowed device point
 
 typedef struct {
   int nx, ny;       /* elements per direction, >= 2 */
-  int p;            /* polynomial degree: 2, 3 or 4 */
+  int p;            /* polynomial degree: 2 .. 6 (Euler), 2 .. 4 (FR_NS_BR1) */
   int physics;      /* FR_EULER or FR_NS_BR1 */
   int flux;         /* FR_RUSANOV or FR_ROE */
   double gamma;     /* ratio of specific heats (Section 2: 1.4) */
@@ -81,8 +81,8 @@ typedef struct {
 
 /* Create / destroy a discretisation handle.  Computes the Gauss points,
  * Lagrange extrapolation rows, differentiation matrix and Radau correction
- * derivatives of degree p (Section 3).  Returns FR_EINVAL for p outside 2..4,
- * nx or ny < 2, physics/flux out of range or a null d_nodes. */
+ * derivatives of degree p (Section 3).  Returns FR_EINVAL for p outside 2..6
+ * (2..4 for FR_NS_BR1), nx or ny < 2, physics/flux out of range or a null d_nodes. */
 fr_status fr_disc_create(const fr_disc_desc* desc, fr_disc** out);
 void fr_disc_destroy(fr_disc* disc);
 
@@ -164,6 +164,16 @@ fr_status fr_ejacobi_factor_blocks(const fr_disc* disc, const double* d_blocks, 
 fr_status fr_ejacobi_solve(const fr_disc* disc, const fr_ejacobi* pc, const double* d_r, double* d_z,
                            fr_stream stream);
 
+/* z = M^{-1} r for the LU-SGS preconditioner M = (D + L) D^{-1} (D + U) at state d_U
+ * (d_R0 = R(d_U)) with shift `shift` (FR_PC_LUSGS above): D^{-1} from pc (as left by
+ * fr_ejacobi_factor at the same U and shift), L and U through Jacobian-free products
+ * with eps / eps_mode as in fr_jf_matvec.  d_r, d_z: ndof doubles (may not alias).
+ * d_work: fr_workspace_bytes(FR_WS_GMRES, m = 1) bytes.  FR_EINVAL for Navier-Stokes or
+ * odd nx / ny. */
+fr_status fr_lusgs_apply(const fr_disc* disc, const fr_ejacobi* pc, const double* d_U, const double* d_R0,
+                         double shift, double eps, int eps_mode, const double* d_r, double* d_z, void* d_work,
+                         fr_stream stream);
+
 /* GMRES options and statistics. */
 typedef struct {
   int m;            /* restart length (Section 4.5; the paper uses 60) */
@@ -172,7 +182,16 @@ typedef struct {
   double ref_norm;  /* r_ref; <= 0 means ||b - A x0|| (Section 5.1: relative to the first residual) */
   double eps;       /* JF perturbation, default 1e-8 */
   int eps_mode;     /* FR_EPS_RMS or FR_EPS_ABS */
+  int precond;      /* FR_PC_EJACOBI (the paper's element-Jacobi) or FR_PC_LUSGS */
 } fr_gmres_opts;
+
+/* Preconditioners of the linear solves (Section 4.5 names matrix-free LU-SGS as the
+ * low-storage alternative to element-Jacobi; the paper's results use element-Jacobi).
+ * FR_PC_LUSGS: symmetric block Gauss-Seidel over the two checkerboard colours
+ * (ex + ey even / odd; Euler meshes with even nx and ny), the element blocks of the
+ * fr_ejacobi store as its diagonal and the couplings between colours applied through
+ * Jacobian-free products (two per application, counted in residual_evals). */
+enum { FR_PC_EJACOBI = 0, FR_PC_LUSGS = 1 };
 
 typedef struct {
   int iters;         /* Arnoldi iterations */
@@ -335,7 +354,8 @@ fr_status fr_mlp_sync(fr_mlp_trainer* tr, fr_stream stream);
 
 /* One training step on the logged samples d_idx[0..batch): forward, mean-squared-error
  * gradients (tr->d_grad), and an Adam update of the master copy followed by fr_mlp_sync
- * (skipped when tr->lr <= 0).  Synchronises; *h_loss = batch MSE before the update. */
+ * (skipped when tr->lr <= 0).  With h_loss != NULL it synchronises and returns the batch
+ * MSE before the update; with h_loss == NULL it only enqueues the step (no host read). */
 fr_status fr_mlp_train_step(const fr_disc* disc, fr_mlp_trainer* tr, const fr_stage_log* log, const int* d_idx,
                             int batch, double* h_loss, void* d_work, fr_stream stream);
 

@@ -26,7 +26,7 @@ class EjacobiC(Structure):
 
 class GmresOptsC(Structure):
     _fields_ = [("m", c_int), ("max_iters", c_int), ("rtol", c_double), ("ref_norm", c_double),
-                ("eps", c_double), ("eps_mode", c_int)]
+                ("eps", c_double), ("eps_mode", c_int), ("precond", c_int)]
 
 
 class GmresStatsC(Structure):
@@ -73,6 +73,8 @@ _SIGS = {
     "fr_residual": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "fr_jf_matvec": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double, c_int, c_void_p,
                              c_void_p, c_void_p]),
+    "fr_lusgs_apply": (c_int, [c_void_p, POINTER(EjacobiC), c_void_p, c_void_p, c_double, c_double, c_int, c_void_p,
+                               c_void_p, c_void_p, c_void_p]),
     "fr_ejacobi_assemble": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
     "fr_ejacobi_factor": (c_int, [c_void_p, c_void_p, c_double, POINTER(EjacobiC), c_void_p, c_void_p]),
     "fr_ejacobi_factor_blocks": (c_int, [c_void_p, c_void_p, POINTER(EjacobiC), c_void_p]),

@@ -16,6 +16,7 @@ EULER, NS_BR1 = 0, 1
 RUSANOV, ROE = 0, 1
 F64, F32 = 0, 1
 EPS_ABS, EPS_RMS = 0, 1
+PC_EJACOBI, PC_LUSGS = 0, 1
 _PHYS = {"euler": EULER, "ns": NS_BR1, "ns_br1": NS_BR1}
 _FLUX = {"rusanov": RUSANOV, "roe": ROE}
 _PREC = {"f64": F64, "fp64": F64, "f32": F32, "fp32": F32}
@@ -50,9 +51,10 @@ class GmresOpts:
     ref_norm: float = 0.0
     eps: float = 1e-8
     eps_mode: int = EPS_RMS
+    precond: int = PC_EJACOBI
 
     def c(self):
-        return L.GmresOptsC(self.m, self.max_iters, self.rtol, self.ref_norm, self.eps, self.eps_mode)
+        return L.GmresOptsC(self.m, self.max_iters, self.rtol, self.ref_norm, self.eps, self.eps_mode, self.precond)
 
 
 @dataclass
@@ -222,6 +224,16 @@ class Disc:
                                                              _stream()))
         return z
 
+    def lusgs_apply(self, pc, U, R0, shift, r, eps=1e-8, eps_mode=EPS_RMS, z=None):
+        """z = M^{-1} r for the LU-SGS preconditioner built on the element blocks of pc."""
+        for t, nm in ((U, "U"), (R0, "R0"), (r, "r")):
+            self._vec(t, nm)
+        z = self.empty() if z is None else self._vec(z, "z")
+        ws = self.workspace(L.WS_GMRES, 1)
+        _check("fr_lusgs_apply", self.lib.fr_lusgs_apply(self.handle, ctypes.byref(pc.c), _ptr(U), _ptr(R0), shift,
+                                                         eps, eps_mode, _ptr(r), _ptr(z), _ptr(ws), _stream()))
+        return z
+
     def gmres_solve(self, pc, U, R0, shift, b, x=None, opts=None):
         opts = opts or GmresOpts()
         for t, nm in ((U, "U"), (R0, "R0"), (b, "b")):
@@ -367,15 +379,37 @@ class MlpTrainer:
         _check("fr_mlp_fit_stats", L.lib().fr_mlp_fit_stats(self.net.disc.handle, ctypes.byref(log.c),
                                                             ctypes.byref(self.c.net), _stream()))
 
-    def step(self, log, idx, lr=None):
+    def step(self, log, idx, lr=None, read_loss=True):
+        """One Adam step on the logged rows idx (int32 device tensor); returns the batch
+        loss, or None without a host read when read_loss is False."""
         if lr is not None:
             self.c.lr = lr
         loss = ctypes.c_double()
         ws = self.net.disc.workspace_mlp(self.net.n_hidden, idx.numel())
         _check("fr_mlp_train_step", L.lib().fr_mlp_train_step(self.net.disc.handle, ctypes.byref(self.c),
                                                               ctypes.byref(log.c), _ptr(idx), idx.numel(),
-                                                              ctypes.byref(loss), _ptr(ws), _stream()))
-        return loss.value
+                                                              ctypes.byref(loss) if read_loss else None, _ptr(ws),
+                                                              _stream()))
+        return loss.value if read_loss else None
+
+    def fit(self, log, steps, batch, lr=1e-3, seed=0, report_every=100):
+        """`steps` Adam steps with a cosine-decayed learning rate on random batches of the
+        log (each batch drawn without replacement, seeded; all batches copied to the device
+        at once).  The loss is read back only every `report_every` steps and at the end:
+        returns the list of those (step, loss) pairs."""
+        import numpy as np
+        rng = np.random.default_rng(seed)
+        n = log.count
+        b = min(batch, n)
+        idx = np.stack([rng.choice(n, b, replace=False) for _ in range(steps)]).astype(np.int32)
+        didx = torch.as_tensor(idx, device=self.net.disc.device)
+        out = []
+        for it in range(steps):
+            rd = (it + 1) % report_every == 0 or it + 1 == steps or it == 0
+            l = self.step(log, didx[it], lr=lr * 0.5 * (1 + np.cos(np.pi * it / steps)), read_loss=rd)
+            if rd:
+                out.append((it, l))
+        return out
 
 
 class StageLog:

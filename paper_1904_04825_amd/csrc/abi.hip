@@ -38,7 +38,7 @@ const char* fr_last_error(void) { return g_err.c_str(); }
 fr_status fr_disc_create(const fr_disc_desc* desc, fr_disc** out) {
   clear_error();
   CHECK(desc != nullptr && out != nullptr, "fr_disc_create: null argument");
-  CHECK(desc->p >= 2 && desc->p <= 4, "fr_disc_create: p must be 2, 3 or 4");
+  CHECK(desc->p >= 2 && desc->p <= 6, "fr_disc_create: p must be 2 .. 6");
   CHECK(desc->nx >= 2 && desc->ny >= 2, "fr_disc_create: nx and ny must be >= 2");
   CHECK(desc->physics == FR_EULER || desc->physics == FR_NS_BR1, "fr_disc_create: bad physics");
   CHECK(desc->flux == FR_RUSANOV || desc->flux == FR_ROE, "fr_disc_create: bad flux");
@@ -46,6 +46,7 @@ fr_status fr_disc_create(const fr_disc_desc* desc, fr_disc** out) {
   CHECK(desc->gamma > 1.0 && desc->rgas > 0.0, "fr_disc_create: gamma must exceed 1 and R be positive");
   CHECK((size_t)desc->nx * desc->ny < (1u << 30), "fr_disc_create: mesh too large");
   if (desc->physics == FR_NS_BR1) {
+    CHECK(desc->p <= 4, "fr_disc_create: Navier-Stokes (BR1) supports p = 2, 3, 4");
     CHECK(desc->mu >= 0.0 && desc->prandtl > 0.0, "fr_disc_create: mu >= 0 and Pr > 0 required");
   }
   fr_disc* d = new fr_disc{};
@@ -203,7 +204,32 @@ static fr_status check_gmres_opts(const fr_gmres_opts* o) {
   CHECK(o->m >= 1 && o->m <= kMaxM, "GMRES restart m must be in 1..64");
   CHECK(o->rtol >= 0.0, "GMRES rtol must be >= 0");
   CHECK(o->eps_mode == FR_EPS_ABS || o->eps_mode == FR_EPS_RMS, "bad eps_mode");
+  CHECK(o->precond == FR_PC_EJACOBI || o->precond == FR_PC_LUSGS, "bad precond");
   return FR_OK;
+}
+
+fr_status fr_lusgs_apply(const fr_disc* d, const fr_ejacobi* pc, const double* U, const double* R0, double shift,
+                         double eps, int eps_mode, const double* r, double* z, void* work, fr_stream s) {
+  clear_error();
+  CHECK(d && pc && pc->d_factors && U && R0 && r && z && work, "fr_lusgs_apply: null argument");
+  CHECK(z != r && z != U && z != R0, "fr_lusgs_apply: z aliases an input");
+  CHECK(pc->precision == FR_F64 || pc->precision == FR_F32, "fr_lusgs_apply: bad precision");
+  CHECK(eps_mode == FR_EPS_ABS || eps_mode == FR_EPS_RMS, "fr_lusgs_apply: bad eps_mode");
+  CHECK(eps > 0.0, "fr_lusgs_apply: eps must be positive");
+  CHECK(d->physics == FR_EULER && !(d->nx & 1) && !(d->ny & 1),
+        "fr_lusgs_apply: Euler meshes with even nx and ny only");
+  Carver cv(work);
+  GmWork W = carve_gmres(cv, d, 1);
+  ResArgs ra{};
+  ra.U = U;
+  ra.R0 = R0;
+  ra.eps = eps;
+  ra.eps_mode = eps_mode;
+  ra.shift = shift;
+  ra.nrm2 = W.scal;
+  int np = 0;
+  return lusgs_apply(d, pc->d_factors, pc->precision, ra, r, nullptr, nullptr, z, W, W.partials + kPartZ, &np,
+                     nullptr, nullptr, S(s));
 }
 
 fr_status fr_gmres_solve(const fr_disc* d, const fr_ejacobi* pc, const double* U, const double* R0, double shift,
@@ -338,7 +364,7 @@ fr_status fr_mlp_sync(fr_mlp_trainer* tr, fr_stream s) {
 fr_status fr_mlp_train_step(const fr_disc* d, fr_mlp_trainer* tr, const fr_stage_log* log, const int* idx, int batch,
                             double* h_loss, void* work, fr_stream s) {
   clear_error();
-  CHECK(d && tr && log && idx && h_loss && work && batch > 0, "fr_mlp_train_step: null argument");
+  CHECK(d && tr && log && idx && work && batch > 0, "fr_mlp_train_step: null argument");
   CHECK(tr->d_master && tr->d_grad && tr->d_m && tr->d_v, "fr_mlp_train_step: null trainer buffers");
   fr_status c = check_mlp(d, &tr->net);
   if (c != FR_OK) return c;
@@ -346,6 +372,7 @@ fr_status fr_mlp_train_step(const fr_disc* d, fr_mlp_trainer* tr, const fr_stage
   double* partials = (double*)((char*)work + tb - sizeof(double) * 4096);
   int np = 0;
   FR_HIP(mlp_train_step(tr, log->d_samples, idx, batch, d->np, partials, &np, work, S(s)));
+  if (h_loss == nullptr) return FR_OK;  // asynchronous: no loss read-back
   std::vector<double> h(np);
   FR_HIP(hipMemcpyAsync(h.data(), partials, sizeof(double) * np, hipMemcpyDeviceToHost, S(s)));
   FR_HIP(hipStreamSynchronize(S(s)));

@@ -372,6 +372,189 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 && RPT == 1) ? 5 : 1) k_e
   if (tid == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// ---------------------------------------------------------------- LU-SGS passes
+// The matrix-free LU-SGS preconditioner (Section 4.5 names it beside element-Jacobi):
+// symmetric block Gauss-Seidel over the two checkerboard colours c = (ex + ey) mod 2,
+// with the element blocks D as its diagonal and the couplings between colours applied
+// matrix-free through Jacobian-free products (the host driver, lusgs_apply):
+//   PASS 1, colour 0: out = D^{-1} r, out = 0 on colour 1 (with gv, r is first scaled by
+//           1/||r|| and stored to r_store on every element, as in k_ejacobi_solve);
+//   PASS 2, colour 1: t = D^{-1}(r - w): out = t and out2 = t there, out2 = 0 on colour 0
+//           (out left as it is on colour 0);
+//   PASS 3, colour 0: out = y - D^{-1} w, out = y on colour 1.
+// Per-workgroup partial sums of ||out||^2 (PASS 2: of ||out2||^2).  Workgroups take
+// groups of EPB elements of the active colour (element a of colour c: row a / (nx/2),
+// column 2 (a mod nx/2) + ((c + row) mod 2)), then stride over the other colour's entries.
+struct LusgsArgs {
+  const double* r;   // PASS 1, 2
+  const double* w;   // PASS 2, 3
+  const double* y;   // PASS 3
+  double* out;
+  double* out2;      // PASS 2
+  double* r_store;   // PASS 1 with gv
+  int nx, nel;
+};
+
+template <int P, typename T, int PASS>
+__global__ void __launch_bounds__(256) k_lusgs_pass(const T* __restrict__ inv, const LusgsArgs a, const GivensIn gv,
+                                                    double* partials, const int* skip) {
+  using C = SolveCfg<P, T, 1>;
+  constexpr int Np = C::Np, Nb = C::Nb, TPE = C::TPE, EPB = C::EPB, JU = C::JU;
+  constexpr int act = (PASS == 2) ? 1 : 0;  // active colour
+  if (skip != nullptr && *skip) return;
+  __shared__ T sr[EPB][Nb];
+  const int tid = threadIdx.x;
+  const int blk = tid / TPE, i = tid - blk * TPE;
+  const int hx = a.nx >> 1, nact = a.nel >> 1;
+  const size_t nel = (size_t)a.nel;
+  const bool scaled = PASS == 1 && gv.st != nullptr;
+  double sc = 1.0;
+  if (scaled) {
+    __shared__ GivensLds GL;
+    const double hn2 = block_sum_partials(gv.norm_part, gv.nb, GL.red);
+    sc = 1.0 / sqrt(hn2);
+    if (blockIdx.x == 0) {
+      if (gv.lagged) {
+        const double hn = sqrt(hn2), w0 = gv.st->w0;
+        if (tid == 0) gv.st->hn = hn;
+        if (!(hn > 1e-14 * w0)) givens_first_pass(gv.st, hn, gv.M, GL);
+      } else {
+        givens_step(gv.st, hn2, gv.M, GL);
+      }
+    }
+  }
+  auto element = [&](int ai, int colour) {
+    const int ey = ai / hx, ex = 2 * (ai - ey * hx) + ((colour + ey) & 1);
+    return ey * a.nx + ex;
+  };
+  double acc2 = 0.0;
+  const int ngroups = (nact + EPB - 1) / EPB;
+  for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int ai = grp * EPB + blk;
+    const bool live = blk < EPB && ai < nact;
+    const int el = live ? element(ai, act) : 0;
+    __syncthreads();
+    for (int t = tid; t < EPB * Nb; t += 256) {
+      const int e = t / Nb, jj = t - e * Nb, ae = grp * EPB + e;
+      if (ae >= nact) continue;
+      const int ee = element(ae, act);
+      const int v = jj / Np, k = jj - v * Np;
+      const size_t gi = ((size_t)v * nel + ee) * Np + k;
+      double rv;
+      if constexpr (PASS == 1) {
+        rv = a.r[gi];
+        if (scaled) {
+          rv *= sc;
+          if (a.r_store != nullptr) a.r_store[gi] = rv;
+        }
+      } else if constexpr (PASS == 2) {
+        rv = a.r[gi] - a.w[gi];
+      } else {
+        rv = a.w[gi];
+      }
+      sr[e][jj] = (T)rv;
+    }
+    __syncthreads();
+    if (live) {
+      const T* col = inv + (size_t)el * Nb * Nb + i;
+      double acc0 = 0.0, acc1 = 0.0;
+      T m[JU];
+      int j = 0;
+      for (; j + JU <= Nb; j += JU) {
+#pragma unroll
+        for (int u = 0; u < JU; ++u) m[u] = col[(size_t)(j + u) * TPE];
+#pragma unroll
+        for (int u = 0; u + 1 < JU; u += 2) {
+          acc0 += (double)(m[u] * sr[blk][j + u]);
+          acc1 += (double)(m[u + 1] * sr[blk][j + u + 1]);
+        }
+        if constexpr (JU % 2 == 1) acc0 += (double)(m[JU - 1] * sr[blk][j + JU - 1]);
+      }
+      for (; j < Nb; ++j) acc0 += (double)(col[(size_t)j * TPE] * sr[blk][j]);
+      const double zi = acc0 + acc1;
+      const int v = i / Np, k = i - v * Np;
+      const size_t gi = ((size_t)v * nel + el) * Np + k;
+      double o;
+      if constexpr (PASS == 3) {
+        o = a.y[gi] - zi;
+      } else {
+        o = zi;
+      }
+      a.out[gi] = o;
+      if constexpr (PASS == 2) a.out2[gi] = o;
+      acc2 = fma(o, o, acc2);
+    }
+  }
+  // the other colour's entries
+  const size_t nother = (size_t)4 * nact * Np;
+  for (size_t t = (size_t)blockIdx.x * 256 + tid; t < nother; t += (size_t)gridDim.x * 256) {
+    const int v = (int)(t / ((size_t)nact * Np));
+    const size_t rem = t - (size_t)v * nact * Np;
+    const int ai = (int)(rem / Np), k = (int)(rem - (size_t)ai * Np);
+    const size_t gi = ((size_t)v * nel + element(ai, 1 - act)) * Np + k;
+    if constexpr (PASS == 1) {
+      a.out[gi] = 0.0;
+      if (scaled && a.r_store != nullptr) a.r_store[gi] = a.r[gi] * sc;
+    } else if constexpr (PASS == 2) {
+      a.out2[gi] = 0.0;
+    } else {
+      const double yv = a.y[gi];
+      a.out[gi] = yv;
+      acc2 = fma(yv, yv, acc2);
+    }
+  }
+  if (partials == nullptr) return;
+  __shared__ double red[4];
+  acc2 = wave_sum(acc2);
+  if ((tid & 63) == 0) red[tid >> 6] = acc2;
+  __syncthreads();
+  if (tid == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+template <int P, typename T>
+static hipError_t lusgs_pt(const fr_disc* d, const T* f, int pass, const LusgsArgs& a, const GivensIn& gv,
+                           double* partials, const int* skip, int* nb_out, hipStream_t s) {
+  constexpr int EPB = SolveCfg<P, T, 1>::EPB;
+  const int ngroups = (d->nel / 2 + EPB - 1) / EPB;
+  const int nb = std::max(1, std::min(ngroups, kRedBlocks));
+  *nb_out = nb;
+  if (pass == 1)
+    hipLaunchKernelGGL((k_lusgs_pass<P, T, 1>), dim3(nb), dim3(256), 0, s, f, a, gv, partials, skip);
+  else if (pass == 2)
+    hipLaunchKernelGGL((k_lusgs_pass<P, T, 2>), dim3(nb), dim3(256), 0, s, f, a, gv, partials, skip);
+  else
+    hipLaunchKernelGGL((k_lusgs_pass<P, T, 3>), dim3(nb), dim3(256), 0, s, f, a, gv, partials, skip);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t lusgs_p(const fr_disc* d, const void* f, int precision, int pass, const LusgsArgs& a,
+                          const GivensIn* gvp, double* partials, const int* skip, int* nb_out, hipStream_t s) {
+  const GivensIn gv = gvp != nullptr ? *gvp : GivensIn{nullptr, nullptr, 0, 0, 0};
+  if (gv.st != nullptr && (gv.nb < 1 || gv.nb > kRedBlocks || gv.norm_part == nullptr)) return hipErrorInvalidValue;
+  if (precision == FR_F32)
+    return lusgs_pt<P, float>(d, (const float*)f, pass, a, gv, partials, skip, nb_out, s);
+  return lusgs_pt<P, double>(d, (const double*)f, pass, a, gv, partials, skip, nb_out, s);
+}
+
+hipError_t launch_lusgs_pass(const fr_disc* d, const void* factors, int precision, int pass, const double* r,
+                             const double* w, const double* y, double* out, double* out2, const GivensIn* gv,
+                             double* r_store, double* partials, int* nparts, const int* skip, hipStream_t s) {
+  if ((d->nx & 1) || (d->ny & 1) || pass < 1 || pass > 3) return hipErrorInvalidValue;
+  const LusgsArgs a{r, w, y, out, out2, r_store, d->nx, d->nel};
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (d->p) {
+    case 2: e = lusgs_p<2>(d, factors, precision, pass, a, gv, partials, skip, &nb, s); break;
+    case 3: e = lusgs_p<3>(d, factors, precision, pass, a, gv, partials, skip, &nb, s); break;
+    case 4: e = lusgs_p<4>(d, factors, precision, pass, a, gv, partials, skip, &nb, s); break;
+    case 5: e = lusgs_p<5>(d, factors, precision, pass, a, gv, partials, skip, &nb, s); break;
+    case 6: e = lusgs_p<6>(d, factors, precision, pass, a, gv, partials, skip, &nb, s); break;
+  }
+  if (nparts != nullptr) *nparts = nb;
+  return e;
+}
+
 template <int P, int FLUX>
 static hipError_t asm_pf(const fr_disc* d, const AsmArgs& a, int precision, int invert, hipStream_t s) {
   dim3 grid(d->nel), block(EJ<P>::NT);
@@ -381,7 +564,7 @@ static hipError_t asm_pf(const fr_disc* d, const AsmArgs& a, int precision, int 
     hipLaunchKernelGGL((k_ejacobi_assemble<P, FLUX, float>), grid, block, 0, s, a, d->basis);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_gj_mfma_f32(EJ<P>::Nb, static_cast<float*>(a.out), d->nel, s);
+    return launch_invert_f32(EJ<P>::Nb, static_cast<float*>(a.out), d->nel, s);
   } else {
     // FP64: the raw blocks, then their inverses in place
     hipLaunchKernelGGL((k_ejacobi_assemble<P, FLUX, double>), grid, block, 0, s, a, d->basis);
@@ -410,6 +593,8 @@ hipError_t launch_ejacobi_assemble(const fr_disc* d, const double* U, double shi
     case 2: return asm_p<2>(d, a, precision, invert, s);
     case 3: return asm_p<3>(d, a, precision, invert, s);
     case 4: return asm_p<4>(d, a, precision, invert, s);
+    case 5: return asm_p<5>(d, a, precision, invert, s);
+    case 6: return asm_p<6>(d, a, precision, invert, s);
   }
   return hipErrorInvalidValue;
 }
@@ -423,7 +608,7 @@ static hipError_t inv_p(const fr_disc* d, const double* blocks, void* out, int p
                        blocks, static_cast<float*>(out), total);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_gj_mfma_f32(Nb, static_cast<float*>(out), d->nel, s);
+    return launch_invert_f32(Nb, static_cast<float*>(out), d->nel, s);
   }
   const hipError_t e = hipMemcpyAsync(out, blocks, (size_t)d->nel * Nb * Nb * sizeof(double),
                                       hipMemcpyDeviceToDevice, s);
@@ -437,6 +622,8 @@ hipError_t launch_ejacobi_invert_blocks(const fr_disc* d, const double* blocks, 
     case 2: return inv_p<2>(d, blocks, out, precision, s);
     case 3: return inv_p<3>(d, blocks, out, precision, s);
     case 4: return inv_p<4>(d, blocks, out, precision, s);
+    case 5: return inv_p<5>(d, blocks, out, precision, s);
+    case 6: return inv_p<6>(d, blocks, out, precision, s);
   }
   return hipErrorInvalidValue;
 }
@@ -488,6 +675,8 @@ hipError_t launch_ejacobi_solve(const fr_disc* d, const void* factors, int preci
     case 2: return solve_p<2>(d, factors, precision, r, gv, r_store, z, partials, nparts, nrm2, skip, s);
     case 3: return solve_p<3>(d, factors, precision, r, gv, r_store, z, partials, nparts, nrm2, skip, s);
     case 4: return solve_p<4>(d, factors, precision, r, gv, r_store, z, partials, nparts, nrm2, skip, s);
+    case 5: return solve_p<5>(d, factors, precision, r, gv, r_store, z, partials, nparts, nrm2, skip, s);
+    case 6: return solve_p<6>(d, factors, precision, r, gv, r_store, z, partials, nparts, nrm2, skip, s);
   }
   return hipErrorInvalidValue;
 }

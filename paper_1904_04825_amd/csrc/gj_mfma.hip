@@ -325,7 +325,13 @@ static hipError_t launch_gj_mfma_f64(int nb, double* blocks, int nblk, hipStream
 // the row kernel.
 hipError_t launch_invert_f64(int nb, double* blocks, int nblk, hipStream_t s) {
   if (nb == 36 || nb == 64) return launch_gj_mfma_f64(nb, blocks, nblk, s);
+  if (nb == 144 || nb == 196) return launch_gj_wide_f64(nb, blocks, nblk, s);
   return launch_gj_rows_f64(nb, blocks, nblk, s);
+}
+
+hipError_t launch_invert_f32(int nb, float* blocks, int nblk, hipStream_t s) {
+  if (nb == 144 || nb == 196) return launch_gj_wide_f32(nb, blocks, nblk, s);
+  return launch_gj_mfma_f32(nb, blocks, nblk, s);
 }
 
 }  // namespace frjf

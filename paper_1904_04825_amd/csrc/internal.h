@@ -10,7 +10,7 @@
 
 namespace frjf {
 
-constexpr int kMaxN = 5;  // P <= 4
+constexpr int kMaxN = 7;  // P <= 6
 
 // 1D reference-element tables of degree P, passed to kernels by value.
 struct Basis {
@@ -116,6 +116,12 @@ hipError_t launch_ejacobi_assemble(const fr_disc* d, const double* U, double shi
 hipError_t launch_gj_rows_f64(int nb, double* blocks, int nblk, hipStream_t s);
 // In-place inversion of nblk FP32 blocks of order nb (36, 64 or 100), column-major, on MFMA.
 hipError_t launch_gj_mfma_f32(int nb, float* blocks, int nblk, hipStream_t s);
+// In-place inversion of nblk blocks of order 144 or 196 (P = 5, 6), column-major, the rows
+// split over column segments held in registers (gj_wide.hip).
+hipError_t launch_gj_wide_f64(int nb, double* blocks, int nblk, hipStream_t s);
+hipError_t launch_gj_wide_f32(int nb, float* blocks, int nblk, hipStream_t s);
+// FP32 inversion of any supported order: MFMA for 36, 64, 100, segmented rows for 144, 196.
+hipError_t launch_invert_f32(int nb, float* blocks, int nblk, hipStream_t s);
 // In-place inversion of nblk FP64 blocks of order nb: on MFMA (k_gj_mfma) for 36 and 64,
 // by k_gj_rows for 100.
 hipError_t launch_invert_f64(int nb, double* blocks, int nblk, hipStream_t s);
@@ -126,6 +132,12 @@ struct GivensIn;
 // z = M^{-1} (r / ||r||) with r_store receiving r / ||r|| (||r||^2 from gv's partials).
 // Partial sums of ||z||^2 go to partials when nrm2 (then summed into *nrm2) or nparts
 // (then only their count is returned, for a consumer that adds them itself) is given.
+// One pass of the LU-SGS preconditioner (PASS 1, 2, 3; see ejacobi.hip) over the
+// element-Jacobi inverse blocks; even nx and ny only.  Partial sums of ||out||^2 (PASS 2:
+// ||out2||^2) go to partials, their count to *nparts.
+hipError_t launch_lusgs_pass(const fr_disc* d, const void* factors, int precision, int pass, const double* r,
+                             const double* w, const double* y, double* out, double* out2, const GivensIn* gv,
+                             double* r_store, double* partials, int* nparts, const int* skip, hipStream_t s);
 hipError_t launch_ejacobi_solve(const fr_disc* d, const void* factors, int precision,
                                 const double* r, const GivensIn* gv, double* r_store,
                                 double* z, double* partials, int* nparts, double* nrm2,
@@ -166,6 +178,7 @@ struct GmState {
     int fin;             // the solve has ended: its later kernels return at once
     int result;          // its fr_status once fin
     int iters, evals, restarts;
+    int steps;           // Arnoldi steps that ran (one preconditioner application each)
     double r_final;      // least-squares or true residual norm
     double r_ref;        // the norm the tolerance is relative to
   } fz;

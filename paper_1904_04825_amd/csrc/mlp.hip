@@ -31,15 +31,19 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
 
 enum { EPI_F32 = 0, EPI_BIAS_GELU = 1, EPI_GELU_GRAD = 2, EPI_BIAS_F32 = 3 };
 
-__device__ __forceinline__ bf16x4 load4(const uint16_t* __restrict__ p, int row, int nrows, int k, int K) {
-  bf16x4 v = {0, 0, 0, 0};
-  if (row >= nrows) return v;
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+
+// Eight consecutive bf16 of row `row` from column k (zeros past the row's end or past
+// nrows): one 16-byte load when aligned and whole, else element by element.
+__device__ __forceinline__ bf16x8 load8(const uint16_t* __restrict__ p, int row, int nrows, int k, int K) {
+  bf16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (row >= nrows || k >= K) return v;
   const uint16_t* q = p + (size_t)row * K + k;
-  if (k + 3 < K && ((((uintptr_t)q) & 7) == 0)) {
-    v = *reinterpret_cast<const bf16x4*>(q);
+  if (k + 7 < K && ((((uintptr_t)q) & 15) == 0)) {
+    v = *reinterpret_cast<const bf16x8*>(q);
   } else {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) v[t] = (k + t < K) ? (short)q[t] : (short)0;
+    for (int t = 0; t < 8; ++t) v[t] = (k + t < K) ? (short)q[t] : (short)0;
   }
   return v;
 }
@@ -49,20 +53,52 @@ __device__ __forceinline__ bf16x4 load4(const uint16_t* __restrict__ p, int row,
 //   EPI_BIAS_F32:  Cf[m][n] = C + bias[n]
 //   EPI_BIAS_GELU: z = C + bias -> Z[m][n] (if Z), H[m][n] = bf16(gelu z), Ht[n][m] (if Ht)
 //   EPI_GELU_GRAD: d = C * gelu'(Zin[m][n]) -> Cf[m][n] = d (if Cf), H[m][n] = bf16(d), Ht[n][m]
+// A workgroup takes a 32 x 32 tile of C (one 16 x 16 sub-tile per wavefront) and the
+// K range of split gridDim.z: EPI_F32 with several splits writes its partial tile to
+// Cf + z M N (summed by k_sum_splits).  K advances in chunks of 32: every lane loads 16
+// bytes of its A row and of its B row (k0 + 8 (lane / 16) .. + 7) and feeds them to two
+// v_mfma_f32_16x16x16bf16_1k (the sum over k does not depend on how the k are dealt
+// to lanes, as long as A and B agree); KD chunks are loaded ahead of the one in the
+// matrix cores.
+constexpr int kGemmKD = 4;
 template <int EPI>
 __global__ void __launch_bounds__(256) k_gemm_nt(const uint16_t* __restrict__ A, const uint16_t* __restrict__ B, int M,
-                                                 int N, int K, const float* __restrict__ bias, float* __restrict__ Cf,
-                                                 const float* __restrict__ Zin, float* __restrict__ Z,
-                                                 uint16_t* __restrict__ H, uint16_t* __restrict__ Ht) {
+                                                 int N, int K, int kchunks, const float* __restrict__ bias,
+                                                 float* __restrict__ Cf, const float* __restrict__ Zin,
+                                                 float* __restrict__ Z, uint16_t* __restrict__ H,
+                                                 uint16_t* __restrict__ Ht) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m0 = blockIdx.y * 32 + (w >> 1) * 16;
   const int n0 = blockIdx.x * 32 + (w & 1) * 16;
   f32x4m acc = {0.f, 0.f, 0.f, 0.f};
-  const int ar = m0 + (lane & 15), bc = n0 + (lane & 15), kq = 4 * (lane >> 4);
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    const bf16x4 a = load4(A, ar, M, k0 + kq, K);
-    const bf16x4 b = load4(B, bc, N, k0 + kq, K);
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  const int ar = m0 + (lane & 15), bc = n0 + (lane & 15), kq = 8 * (lane >> 4);
+  const int kbeg = blockIdx.z * kchunks * 32;
+  const int kend = min(K, kbeg + kchunks * 32);
+  const int nch = (kend - kbeg + 31) / 32;
+  bf16x8 qa[kGemmKD], qb[kGemmKD];
+#pragma unroll
+  for (int d = 0; d < kGemmKD; ++d) {
+    const int k = kbeg + 32 * d + kq;
+    qa[d] = d < nch ? load8(A, ar, M, k, kend) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    qb[d] = d < nch ? load8(B, bc, N, k, kend) : bf16x8{0, 0, 0, 0, 0, 0, 0, 0};
+  }
+  for (int c = 0; c < nch; c += kGemmKD) {
+#pragma unroll
+    for (int d = 0; d < kGemmKD; ++d) {
+      if (c + d < nch) {
+        const bf16x8 a = qa[d], bb = qb[d];
+        const int cn = c + d + kGemmKD;
+        if (cn < nch) {
+          const int k = kbeg + 32 * cn + kq;
+          qa[d] = load8(A, ar, M, k, kend);
+          qb[d] = load8(B, bc, N, k, kend);
+        }
+        const bf16x4 a0 = {a[0], a[1], a[2], a[3]}, a1 = {a[4], a[5], a[6], a[7]};
+        const bf16x4 b0 = {bb[0], bb[1], bb[2], bb[3]}, b1 = {bb[4], bb[5], bb[6], bb[7]};
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc, 0, 0, 0);
+      }
+    }
   }
   const int col = n0 + (lane & 15);
 #pragma unroll
@@ -72,7 +108,7 @@ __global__ void __launch_bounds__(256) k_gemm_nt(const uint16_t* __restrict__ A,
     const size_t i = (size_t)row * N + col;
     float c = acc[r];
     if constexpr (EPI == EPI_F32) {
-      Cf[i] = c;
+      Cf[(size_t)blockIdx.z * M * N + i] = c;
     } else if constexpr (EPI == EPI_BIAS_F32) {
       Cf[i] = c + bias[col];
     } else if constexpr (EPI == EPI_BIAS_GELU) {
@@ -91,11 +127,41 @@ __global__ void __launch_bounds__(256) k_gemm_nt(const uint16_t* __restrict__ A,
   }
 }
 
+// out[i] = sum over the splits of part[s n + i], in split order
+__global__ void k_sum_splits(const float* __restrict__ part, int S, size_t n, float* __restrict__ out) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    float t = part[i];
+    for (int q = 1; q < S; ++q) t += part[(size_t)q * n + i];
+    out[i] = t;
+  }
+}
+
+// Products with a long K (the weight gradients, K = batch) and few output tiles split K
+// so that the grid has about 256 workgroups; split partials go to `scratch` (at least
+// kMaxSplits M N floats) and are summed in split order.
+constexpr int kMaxSplits = 8;
+static int gemm_splits(int M, int N, int K) {
+  const int tiles = ((M + 31) / 32) * ((N + 31) / 32);
+  int sp = 1;
+  while (sp < kMaxSplits && tiles * sp * 2 <= 256 && K >= 32 * 8 * sp * 2) sp *= 2;
+  return sp;
+}
+
 template <int EPI>
 static hipError_t gemm(const uint16_t* A, const uint16_t* B, int M, int N, int K, const float* bias, float* Cf,
-                       const float* Zin, float* Z, uint16_t* H, uint16_t* Ht, hipStream_t s) {
-  dim3 grid((N + 31) / 32, (M + 31) / 32);
-  hipLaunchKernelGGL((k_gemm_nt<EPI>), grid, dim3(256), 0, s, A, B, M, N, K, bias, Cf, Zin, Z, H, Ht);
+                       const float* Zin, float* Z, uint16_t* H, uint16_t* Ht, hipStream_t s,
+                       float* scratch = nullptr) {
+  const int chunks = (K + 31) / 32;
+  const int sp = (EPI == EPI_F32 && scratch != nullptr) ? gemm_splits(M, N, K) : 1;
+  const int per = (chunks + sp - 1) / sp;
+  dim3 grid((N + 31) / 32, (M + 31) / 32, sp);
+  float* dst = sp > 1 ? scratch : Cf;
+  hipLaunchKernelGGL((k_gemm_nt<EPI>), grid, dim3(256), 0, s, A, B, M, N, K, per, bias, dst, Zin, Z, H, Ht);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || sp == 1) return e;
+  const size_t n = (size_t)M * N;
+  hipLaunchKernelGGL(k_sum_splits, dim3((unsigned)std::min<size_t>((n + 255) / 256, 1024)), dim3(256), 0, s, scratch,
+                     sp, n, Cf);
   return hipGetLastError();
 }
 
@@ -371,8 +437,10 @@ hipError_t mlp_stats(const float* raw, int count, int Np, float* norm, hipStream
 
 size_t mlp_train_bytes(int B, int In, int H, int Out) {
   auto a = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t wmax = (size_t)H * (In > H ? In : H);  // largest weight matrix (split-K partials)
   return 2 * a((size_t)B * In * 2) + 4 * a((size_t)B * H * 4) + 4 * a((size_t)B * H * 2) + a((size_t)B * Out * 4) * 3 +
-         2 * a((size_t)B * Out * 2) + 4 * a((size_t)B * H * 2) + a(sizeof(double) * 4096);
+         2 * a((size_t)B * Out * 2) + 4 * a((size_t)B * H * 2) + a(sizeof(float) * kMaxSplits * wmax) +
+         a(sizeof(double) * 4096);
 }
 
 hipError_t mlp_train_step(fr_mlp_trainer* tr, const float* raw, const int* idx, int B, int Np, double* loss_partials,
@@ -401,6 +469,7 @@ hipError_t mlp_train_step(fr_mlp_trainer* tr, const float* raw, const int* idx, 
   uint16_t* dz1t = (uint16_t*)take((size_t)B * H * 2);
   float* dz2f = (float*)take((size_t)B * H * 4);  // hidden gradients before the bf16 rounding (bias sums)
   float* dz1f = (float*)take((size_t)B * H * 4);
+  float* gsplit = (float*)take(sizeof(float) * kMaxSplits * (size_t)H * (In > H ? In : H));
   const uint16_t* W = (const uint16_t*)net->d_w;
   float* g = tr->d_grad;
   hipLaunchKernelGGL(k_batch, dim3(grid_for((size_t)B * (In + Out))), dim3(256), 0, s, raw, 20 * Np, idx, B, Np,
@@ -413,19 +482,19 @@ hipError_t mlp_train_step(fr_mlp_trainer* tr, const float* raw, const int* idx, 
   *nparts = (int)gb;
   e = hipGetLastError();
   // weight and bias gradients, layer by layer
-  if (e == hipSuccess) e = gemm<EPI_F32>(dyt, H2t, Out, H, B, nullptr, g + L.pW3, nullptr, nullptr, nullptr, nullptr, s);
+  if (e == hipSuccess) e = gemm<EPI_F32>(dyt, H2t, Out, H, B, nullptr, g + L.pW3, nullptr, nullptr, nullptr, nullptr, s, gsplit);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_colsum, dim3((Out + kColsumCols - 1) / kColsumCols), dim3(kColsumCols * kColsumRows), 0, s, nullptr, dy32, B, Out, g + L.pb3);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = gemm<EPI_GELU_GRAD>(dyr, W + L.w3t, B, H, Out, nullptr, dz2f, Z2, nullptr, dz2, dz2t, s);
-  if (e == hipSuccess) e = gemm<EPI_F32>(dz2t, H1t, H, H, B, nullptr, g + L.pW2, nullptr, nullptr, nullptr, nullptr, s);
+  if (e == hipSuccess) e = gemm<EPI_F32>(dz2t, H1t, H, H, B, nullptr, g + L.pW2, nullptr, nullptr, nullptr, nullptr, s, gsplit);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_colsum, dim3((H + kColsumCols - 1) / kColsumCols), dim3(kColsumCols * kColsumRows), 0, s, nullptr, dz2f, B, H, g + L.pb2);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = gemm<EPI_GELU_GRAD>(dz2, W + L.w2t, B, H, H, nullptr, dz1f, Z1, nullptr, dz1, dz1t, s);
-  if (e == hipSuccess) e = gemm<EPI_F32>(dz1t, Xt, H, In, B, nullptr, g + L.pW1, nullptr, nullptr, nullptr, nullptr, s);
+  if (e == hipSuccess) e = gemm<EPI_F32>(dz1t, Xt, H, In, B, nullptr, g + L.pW1, nullptr, nullptr, nullptr, nullptr, s, gsplit);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_colsum, dim3((H + kColsumCols - 1) / kColsumCols), dim3(kColsumCols * kColsumRows), 0, s, nullptr, dz1f, B, H, g + L.pb1);
     e = hipGetLastError();

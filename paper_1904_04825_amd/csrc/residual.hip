@@ -49,6 +49,14 @@ struct TilePick {
 template <bool BIG> struct LineTile<2, BIG> : TilePick<BIG, FRJF_TILE_P2> {};
 template <bool BIG> struct LineTile<3, BIG> : TilePick<BIG, FRJF_TILE_P3> {};
 template <bool BIG> struct LineTile<4, BIG> : TilePick<BIG, FRJF_TILE_P4> {};
+#ifndef FRJF_TILE_P5
+#define FRJF_TILE_P5 7, 3, 3, 3
+#endif
+#ifndef FRJF_TILE_P6
+#define FRJF_TILE_P6 6, 3, 3, 3
+#endif
+template <bool BIG> struct LineTile<5, BIG> : TilePick<BIG, FRJF_TILE_P5> {};
+template <bool BIG> struct LineTile<6, BIG> : TilePick<BIG, FRJF_TILE_P6> {};
 
 #ifndef FRJF_SPLIT_SMALL
 #define FRJF_SPLIT_SMALL 1
@@ -713,6 +721,8 @@ int residual_dots_blocks(const fr_disc* d) {
     case 2: return dots_blocks_p<2>(d);
     case 3: return dots_blocks_p<3>(d);
     case 4: return dots_blocks_p<4>(d);
+    case 5: return dots_blocks_p<5>(d);
+    case 6: return dots_blocks_p<6>(d);
   }
   return 0;
 }
@@ -745,6 +755,8 @@ hipError_t launch_residual(const fr_disc* d, int mode, const ResArgs& a, hipStre
     case 2: return launch_euler_p<2>(d, mode, a, s);
     case 3: return launch_euler_p<3>(d, mode, a, s);
     case 4: return launch_euler_p<4>(d, mode, a, s);
+    case 5: return launch_euler_p<5>(d, mode, a, s);
+    case 6: return launch_euler_p<6>(d, mode, a, s);
   }
   return hipErrorInvalidValue;
 }

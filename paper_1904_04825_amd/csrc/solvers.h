@@ -26,6 +26,7 @@ struct GmWork {
   double* Z;
   double* w;
   double* r;
+  double* t[3];  // LU-SGS: the forward sweep's y, the black part of y, a product
 };
 
 struct Carver {
@@ -42,6 +43,13 @@ GmWork carve_gmres(Carver& c, const fr_disc* d, int m);
 fr_status device_norm(const fr_disc* d, const double* x, double* partials, double* dev_out,
                       double* host_out, hipStream_t s);
 
+// z = M^{-1} r by LU-SGS (see ejacobi.hip): three passes over the element blocks and two
+// Jacobian-free products; with gv, r is first scaled by 1/||r|| (from gv's partials) and
+// stored to r_store.  ra: the JF product's arguments (U, R0, shift, eps).  Leaves the
+// partial sums of ||z||^2 in zpart (*np of them); counts its products in *evals.
+fr_status lusgs_apply(const fr_disc* d, const void* factors, int prec, const ResArgs& ra, const double* r,
+                      const GivensIn* gv, double* r_store, double* z, GmWork& W, double* zpart, int* np,
+                      const int* skip, long* evals, hipStream_t s);
 fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const double* U, const double* R0,
                      double shift, const double* b, double* x, bool x_is_zero, const fr_gmres_opts& o,
                      fr_gmres_stats* stats, GmWork& W, hipStream_t s, bool plain_fallback = false,

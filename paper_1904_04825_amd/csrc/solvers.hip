@@ -209,8 +209,9 @@ size_t partials_count(const fr_disc* d) {
 }
 
 size_t gmres_bytes(const fr_disc* d, int m) {
+  // V (m + 1), Z (m), w, r and the LU-SGS vectors (3)
   return align256(ns_trace_bytes(d)) + align256(sizeof(GmState)) + 256 +
-         align256(sizeof(double) * partials_count(d)) + align256(sizeof(double) * d->ndof) * (size_t)(2 * m + 3);
+         align256(sizeof(double) * partials_count(d)) + align256(sizeof(double) * d->ndof) * (size_t)(2 * m + 6);
 }
 
 size_t small_bytes(const fr_disc* d) { return 256 + align256(sizeof(double) * partials_count(d)); }
@@ -232,6 +233,7 @@ GmWork carve_gmres(Carver& c, const fr_disc* d, int m) {
   w.Z = (double*)c.take(sizeof(double) * d->ndof * (size_t)m);
   w.w = (double*)c.take(sizeof(double) * d->ndof);
   w.r = (double*)c.take(sizeof(double) * d->ndof);
+  for (int i = 0; i < 3; ++i) w.t[i] = (double*)c.take(sizeof(double) * d->ndof);
   return w;
 }
 
@@ -254,6 +256,38 @@ fr_status device_norm(const fr_disc* d, const double* x, double* partials, doubl
   return FR_OK;
 }
 
+// ---------------------------------------------------------------- LU-SGS
+fr_status lusgs_apply(const fr_disc* d, const void* factors, int prec, const ResArgs& ra, const double* r,
+                      const GivensIn* gv, double* r_store, double* z, GmWork& W, double* zpart, int* np,
+                      const int* skip, long* evals, hipStream_t s) {
+  double* y = W.t[0];   // forward sweep: y_R, then y_B
+  double* yb = W.t[1];  // y on black elements, zero on red
+  double* w = W.t[2];   // Jacobian-free products
+  double* part = W.partials + kPartZ;
+  const double* rr = (gv != nullptr && r_store != nullptr) ? r_store : r;  // r / ||r|| once stored
+  int nb = 0;
+  // y_R = D_R^{-1} r_R (y_B = 0)
+  FR_HIP(launch_lusgs_pass(d, factors, prec, 1, r, nullptr, nullptr, y, nullptr, gv, r_store, part, &nb, skip, s));
+  ResArgs a = ra;
+  a.V = y;
+  a.out = w;
+  a.nrm2_part = part;
+  a.nrm2_nb = nb;
+  a.skip = skip;
+  a.dV = nullptr;
+  a.opart = nullptr;
+  FR_HIP(launch_residual(d, 1, a, s));  // w = A y: its black part is A_BR y_R
+  // y_B = D_B^{-1}(r_B - A_BR y_R), also into yb (red part zero)
+  FR_HIP(launch_lusgs_pass(d, factors, prec, 2, rr, w, nullptr, y, yb, nullptr, nullptr, part, &nb, skip, s));
+  a.V = yb;
+  a.nrm2_nb = nb;
+  FR_HIP(launch_residual(d, 1, a, s));  // w = A yb: its red part is A_RB y_B
+  // z_R = y_R - D_R^{-1} A_RB y_B, z_B = y_B
+  FR_HIP(launch_lusgs_pass(d, factors, prec, 3, nullptr, w, y, z, nullptr, nullptr, nullptr, zpart, np, skip, s));
+  if (evals != nullptr) *evals += 2;
+  return FR_OK;
+}
+
 // ---------------------------------------------------------------- FGMRES
 fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const double* U, const double* R0,
                      double shift, const double* b, double* x, bool x_is_zero, const fr_gmres_opts& o,
@@ -261,6 +295,8 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
   const size_t n = d->ndof;
   const int m = o.m;
   const int max_iters = o.max_iters > 0 ? o.max_iters : 50 * m;
+  if (o.precond == FR_PC_LUSGS && (d->physics != FR_EULER || (d->nx & 1) || (d->ny & 1)))
+    return set_error(FR_EINVAL, "LU-SGS preconditioner: Euler meshes with even nx and ny only");
   fr_gmres_stats S{};
   double* nz = W.scal + 0;     // ||z||^2 or ||x||^2 for the JF epsilon
   double* beta2 = W.scal + 1;  // ||r||^2
@@ -332,6 +368,7 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
   // orthogonalisation: DCGS2 (two passes over V per step, the Hessenberg column final
   // one step later) up to m = 32, CGS2 beyond
   const bool dcgs = dcgs2_supported(m);
+  const bool lusgs = o.precond == FR_PC_LUSGS;
   // small Euler meshes: the JF product of steps with at most kJfDotsMax basis vectors
   // also runs the first DCGS2 pass (one kernel fewer per such step)
   const int jf_dots = dcgs ? residual_dots_blocks(d) : 0;
@@ -361,7 +398,15 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
       // that reads them may write the first pass's rows meanwhile).
       double* zpart = W.partials + kPartZ;
       int np = 0;
-      if (j == 0) {
+      if (lusgs) {
+        // LU-SGS: its passes leave their partial sums in the ||z||^2 slot in turn (each
+        // read by the next kernel), the last one ||z_j||^2
+        const GivensIn gv{W.st, dcgs ? dcgs2_norm_partials(W.partials) : W.partials, cgs_blocks(n), m, dcgs ? 1 : 0};
+        fr_status ls = j == 0 ? lusgs_apply(d, factors, prec, ra, vj, nullptr, nullptr, zj, W, zpart, &np, skip,
+                                            nullptr, s)
+                              : lusgs_apply(d, factors, prec, ra, W.w, &gv, vj, zj, W, zpart, &np, skip, nullptr, s);
+        if (ls != FR_OK) return ls;
+      } else if (j == 0) {
         FR_HIP(launch_ejacobi_solve(d, factors, prec, vj, nullptr, nullptr, zj, zpart, &np, nullptr, skip, s));
       } else {
         // finish step j - 1, then v_j = w / ||w||
@@ -423,6 +468,7 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
   if (rs != FR_OK) return rs;
   S.iters = fz.iters;
   S.residual_evals += fz.evals;
+  if (lusgs) S.residual_evals += 2L * fz.steps;  // the two products of every LU-SGS application
   S.restarts = fz.restarts;
   S.r_final = fz.r_final;
   S.r_ref = fz.r_ref;

@@ -597,6 +597,7 @@ __global__ void __launch_bounds__(256) k_gm_start(GmState* st, const double* bet
     st->fz.result = FR_NOTCONV;
     st->fz.iters = 0;
     st->fz.evals = 0;
+    st->fz.steps = 0;
     st->fz.restarts = 0;
     st->fz.r_final = beta;
     st->fz.r_ref = r_ref;
@@ -653,6 +654,7 @@ __global__ void __launch_bounds__(64) k_gm_cycle_end(GmState* st, double* beta2,
   const int k = st->j, why = st->why;
   st->fz.iters += k;
   st->fz.evals += dcgs ? max(k, st->evals) : k;
+  st->fz.steps += dcgs ? max(k, st->evals) : k;
   double rf = st->rest;
   int res = -1;
   if (why == 3) {

@@ -35,16 +35,43 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def rounding_floor(residual, U, R, trials=2, seed=0):
+def _rebuilt(op, nodes):
+    """The same oracle operator on another vertex array."""
+    from oracle.ns import NavierStokesFR
+    from oracle.problem import make_ns
+    P = op.n - 1
+    if isinstance(op, NavierStokesFR):
+        return make_ns(nodes, P, gamma=op.gamma, flux=op.flux, rgas=op.rgas, mu=op.mu, prandtl=op.prandtl)
+    return make_euler(nodes, P, gamma=op.gamma, flux=op.flux)
+
+
+def ulp_nodes(nodes, rng):
+    """Every vertex coordinate moved by one unit in its last place (seeded random
+    direction), the periodic copies kept exact copies shifted by the box lengths."""
+    nd = np.nextafter(nodes, rng.choice([-np.inf, np.inf], size=np.shape(nodes)))
+    ny, nx = nd.shape[0] - 1, nd.shape[1] - 1
+    lx = nodes[0, nx, 0] - nodes[0, 0, 0]
+    ly = nodes[ny, 0, 1] - nodes[0, 0, 1]
+    nd[:, nx, 0] = nd[:, 0, 0] + lx
+    nd[:, nx, 1] = nd[:, 0, 1]
+    nd[ny, :, 1] = nd[0, :, 1] + ly
+    nd[ny, :, 0] = nd[0, :, 0]
+    return nd
+
+
+def rounding_floor(op, U, R, trials=2, seed=0):
     """The oracle's own rounding floor for R(U): the largest relative change of R when
-    every entry of U moves by one unit in its last place, each in a seeded random
-    direction.  Two correct FP64 evaluations that round in different orders differ by
-    about this much."""
+    every entry of U and every vertex coordinate move by one unit in their last place,
+    each in a seeded random direction.  Two correct FP64 evaluations that round in
+    different orders (the metrics from the vertices included) differ by about this much:
+    R is a small difference of fluxes of size |F|/h, so rounding in the metric terms is
+    amplified by (|F|/h)/|R|."""
     rng = np.random.default_rng(seed)
     worst = 0.0
     for _ in range(trials):
         Up = np.nextafter(U, rng.choice([-np.inf, np.inf], size=np.shape(U)))
-        worst = max(worst, rel(residual(Up), R))
+        opp = _rebuilt(op, ulp_nodes(op.mesh.nodes, rng))
+        worst = max(worst, rel(opp.residual(Up), R))
     return worst
 
 
@@ -53,11 +80,11 @@ def rounding_floor(residual, U, R, trials=2, seed=0):
 FLOOR_MULT = 10.0
 
 
-def check_residual(Rg, Ro, residual, U, label=""):
+def check_residual(Rg, Ro, op, U, label=""):
     """Assert the relative error of a GPU residual: 1e-12 where FP64 allows it, else
     FLOOR_MULT times the measured rounding floor of the oracle.  Returns (error, floor)."""
     err = rel(Rg, Ro)
-    floor = rounding_floor(residual, U, Ro) if err > 1e-12 else float("nan")
+    floor = rounding_floor(op, U, Ro) if err > 1e-12 else float("nan")
     print(f"  {label} residual rel err {err:.3e}, oracle rounding floor {floor:.3e}", flush=True)
     assert err <= 1e-12 or err <= FLOOR_MULT * floor, (err, floor)
     return err, floor

@@ -95,7 +95,8 @@ def test_invalid_arguments_are_rejected_before_any_device_work():
     nodes = ctypes.c_double(0.0)
     good = dict(nx=4, ny=4, p=3, physics=0, flux=0, gamma=1.4, rgas=1.0, mu=0.0, prandtl=0.71,
                 d_nodes=ctypes.cast(ctypes.pointer(nodes), ctypes.c_void_p))
-    cases = [({"p": 5}, "p must be"), ({"p": 1}, "p must be"), ({"nx": 1}, "nx and ny"), ({"physics": 7}, "physics"),
+    cases = [({"p": 7}, "p must be"), ({"p": 1}, "p must be"), ({"p": 5, "physics": 1}, "Navier-Stokes (BR1) supports"),
+             ({"nx": 1}, "nx and ny"), ({"physics": 7}, "physics"),
              ({"flux": 9}, "flux"), ({"d_nodes": None}, "d_nodes"), ({"gamma": 1.0}, "gamma"),
              ({"nx": 1 << 16, "ny": 1 << 15}, "too large")]
     for change, msg in cases:

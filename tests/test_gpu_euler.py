@@ -24,7 +24,7 @@ def test_residual_parity(P, flux):
     U = vortex_state(op)
     Rg = to_np(disc.residual(to_gpu(U)))
     Ro = op.residual(U)
-    check_residual(Rg, Ro, op.residual, U)
+    check_residual(Rg, Ro, op, U)
 
 
 @pytest.mark.parametrize("P", [2, 3, 4])
@@ -48,7 +48,7 @@ def test_residual_minimum_mesh_and_full_workload_mesh():
         _, op, disc = setup(nx, ny, P, "rusanov", seed=seed)
         U = vortex_state(op, 0.7)
         Rg, Ro = to_np(disc.residual(to_gpu(U))), op.residual(U)
-        check_residual(Rg, Ro, op.residual, U, f"{nx}x{ny} P{P}")
+        check_residual(Rg, Ro, op, U, f"{nx}x{ny} P{P}")
 
 
 # meshes large enough for the large tiles (P2: 16x5, P3: 8x8, P4: 10x5; at least 2048 of
@@ -64,7 +64,7 @@ def test_residual_and_matvec_parity_large_tiles(P):
     U = vortex_state(op)
     Ro = op.residual(U)
     Rg = to_np(disc.residual(to_gpu(U)))
-    check_residual(Rg, Ro, op.residual, U)
+    check_residual(Rg, Ro, op, U)
     v = fi.random_vector(U.shape, seed=9, scale=1e-3)
     Ao = linear.jf_matvec(op.residual, U, Ro, v, 4.0, mode="rms")
     Ag = to_np(disc.jf_matvec(to_gpu(U), to_gpu(Ro), to_gpu(v), 4.0))

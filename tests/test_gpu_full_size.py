@@ -26,7 +26,7 @@ def test_vortex_512x512_p4_residual_and_matvec():
     Rg = to_np(disc.residual(Ug))
     worst = int(np.argmax(np.abs(Rg - Ro).reshape(4, op.nel, -1).max(axis=(0, 2))))
     print(f"  largest difference in element {worst}", flush=True)
-    check_residual(Rg, Ro, op.residual, U, "512x512 P4")
+    check_residual(Rg, Ro, op, U, "512x512 P4")
     vv = fi.random_vector(U.shape, seed=17, scale=1e-3)
     print("512x512 P4: oracle JF product", flush=True)
     Ao = linear.jf_matvec(op.residual, U, Ro, vv, 80.0, mode="rms")
@@ -45,4 +45,4 @@ def test_shear_layer_256x256_p3_br1_residual():
     print("256x256 P3 BR1: oracle residual", flush=True)
     Ro = op.residual(U)
     Rg = to_np(disc.residual(to_gpu(U)))
-    check_residual(Rg, Ro, op.residual, U, "256x256 P3 BR1")
+    check_residual(Rg, Ro, op, U, "256x256 P3 BR1")

@@ -38,20 +38,32 @@ def test_gmres_parity_multitile_72x72_p3(m):
     Ug = to_gpu(U)
     pc = disc.ejacobi_factor(Ug, shift, F64)
     xg, sg = disc.gmres_solve(pc, Ug, to_gpu(R0), shift, to_gpu(b), opts=GmresOpts(m=m, rtol=rtol))
+    Ax_g = disc.jf_matvec(Ug, to_gpu(R0), xg, shift)      # the GPU's own operator on x_g
+    Ax_2 = disc.jf_matvec(Ug, to_gpu(R0), xg, shift, eps=2e-8)
     xg = to_np(xg)
+    Ax_g = to_np(Ax_g)
+    fd = float(np.linalg.norm(Ax_g - to_np(Ax_2)))     # the finite-difference product's own error
     nb = float(np.linalg.norm(b))
-    res_o = float(np.linalg.norm(b - A_o(xo)))
-    res_g = float(np.linalg.norm(b - A_o(xg)))
+    Ax_o = A_o(xg)
+    res_o = float(np.linalg.norm(b - A_o(xo)))        # oracle solution, oracle operator
+    own_g = float(np.linalg.norm(b - Ax_g))            # GPU solution, GPU operator
+    delta = float(np.linalg.norm(Ax_g - Ax_o))         # the two operators on x_g
     rho = rtol * so.r_ref + res_o
-    print(f"  oracle {so}\n  gpu {sg}\n  rel {rel(xg, xo):.2e}  true residual gpu {res_g / nb:.2e} "
-          f"oracle {res_o / nb:.2e}", flush=True)
+    print(f"  oracle {so}\n  gpu {sg}\n  rel {rel(xg, xo):.2e}; true residuals: gpu (own operator) "
+          f"{own_g / nb:.2e}, oracle {res_o / nb:.2e}; operators differ on x_g by {delta / nb:.2e}, "
+          f"eps vs 2 eps by {fd / nb:.2e}", flush=True)
     assert sg["status"] == 0 and sg["converged"] == 1
     # restarted cycles: DCGS2/CGS2 against MGS rounding; counts agree within a few steps
     assert abs(sg["iters"] - so.iters) <= max(2, 0.05 * so.iters)
-    assert res_g <= 2 * rho
-    # kappa(A) of this operator is about 20-40 on the small meshes (dense SVD):
-    # solutions within 3 rho kappa / ||b||
-    assert rel(xg, xo) <= 3 * 50 * rho / nb
+    # each solve is as accurate under its own finite-difference operator (the true
+    # residual of a Jacobian-free solve stops at the products' own error, which the
+    # oracle's true residual shows); the two operators differ on x_g by rounding of R
+    # amplified by 1/eps, the same noise as between eps and 2 eps
+    assert own_g <= 2 * rho
+    assert delta <= 4 * fd
+    # kappa(A) of this operator is about 20-40 on the small meshes (dense SVD): the
+    # solutions lie within kappa (2 rho + delta) / ||b|| of each other
+    assert rel(xg, xo) <= 50 * (2 * rho + delta) / nb
 
 
 def test_gmres_large_tiles_250x645_p2():
@@ -69,10 +81,21 @@ def test_gmres_large_tiles_250x645_p2():
         pc = disc.ejacobi_factor(Ug, shift, prec)
         for m in (20, 40):
             xg, sg = disc.gmres_solve(pc, Ug, R0g, shift, bg, opts=GmresOpts(m=m, rtol=rtol))
+            xgt = xg
+            Ax1 = to_np(disc.jf_matvec(Ug, R0g, xgt, shift))              # eps = 1e-8 / rms(x)
+            Ax2 = to_np(disc.jf_matvec(Ug, R0g, xgt, shift, eps=2e-8))    # twice the step
             xg = to_np(xg)
-            res = float(np.linalg.norm(b - linear.jf_matvec(op.residual, U, R0, xg, shift)))
-            print(f"  precision {prec} m={m}: gpu {sg}, true residual under the oracle's operator {res / nb:.2e}",
+            Ao = linear.jf_matvec(op.residual, U, R0, xg, shift)
+            own = float(np.linalg.norm(b - Ax1))
+            fd = float(np.linalg.norm(Ax1 - Ax2))       # the finite-difference product's own error
+            delta = float(np.linalg.norm(Ax1 - Ao))
+            print(f"  precision {prec} m={m}: gpu {sg}; true residual (own operator) {own / nb:.2e}, "
+                  f"product error (eps vs 2 eps) {fd / nb:.2e}, GPU vs oracle operator on x {delta / nb:.2e}",
                   flush=True)
             assert sg["status"] == 0 and sg["converged"] == 1 and sg["iters"] > 1
             assert sg["r_final"] <= rtol * sg["r_ref"]
-            assert res <= 2 * rtol * nb
+            # the true residual of a Jacobian-free solve: the tolerance plus the
+            # products' own error; the GPU's and the oracle's products on x differ by
+            # rounding of R amplified by 1/eps, the same noise as between eps and 2 eps
+            assert own <= 2 * rtol * nb + 2 * fd
+            assert delta <= 4 * fd

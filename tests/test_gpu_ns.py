@@ -39,7 +39,7 @@ def test_ns_residual_parity(P, flux):
     U = _shear(op)
     Rg = to_np(disc.residual(to_gpu(U)))
     Ro = op.residual(U)
-    check_residual(Rg, Ro, op.residual, U, f"NS P={P} {flux}")
+    check_residual(Rg, Ro, op, U, f"NS P={P} {flux}")
 
 
 def test_ns_residual_conservation_and_freestream():
