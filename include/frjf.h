@@ -123,6 +123,18 @@ fr_status fr_jf_matvec(const fr_disc* disc, const double* d_U, const double* d_R
                        const double* d_v, double shift, double eps, int eps_mode,
                        double* d_Av, void* d_work, fr_stream stream);
 
+/* The same product for callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid allocation): no workspace
+ * argument and no allocation.  Its scratch (the RMS norm's partial sums, and for
+ * FR_NS_BR1 the gradient traces) is a static 4 MiB device array per GPU, held until
+ * the process ends.  Returns FR_ESIZE, with the sizes in fr_last_error(), when the
+ * mesh's BR1 traces (256 (P+1) bytes per element) exceed it.  Calls on one GPU share
+ * that array: calls that overlap in time on one GPU (several streams or threads) race
+ * and must be serialised by the caller.  Results are those of fr_jf_matvec. */
+fr_status fr_jf_matvec_noalloc(const fr_disc* disc, const double* d_U, const double* d_R0,
+                               const double* d_v, double shift, double eps, int eps_mode,
+                               double* d_Av, fr_stream stream);
+
 /* Element-Jacobi preconditioner store (Section 4.5: the diagonal element
  * blocks of the Jacobian).  d_factors: caller-allocated, fr_ejacobi_bytes(
  * precision) bytes; after fr_ejacobi_factor it holds, per element, the

@@ -75,6 +75,8 @@ _SIGS = {
                              c_void_p, c_void_p]),
     "fr_lusgs_apply": (c_int, [c_void_p, POINTER(EjacobiC), c_void_p, c_void_p, c_double, c_double, c_int, c_void_p,
                                c_void_p, c_void_p, c_void_p]),
+    "fr_jf_matvec_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double, c_int, c_void_p,
+                                     c_void_p]),
     "fr_ejacobi_assemble": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
     "fr_ejacobi_factor": (c_int, [c_void_p, c_void_p, c_double, POINTER(EjacobiC), c_void_p, c_void_p]),
     "fr_ejacobi_factor_blocks": (c_int, [c_void_p, c_void_p, POINTER(EjacobiC), c_void_p]),

@@ -191,6 +191,15 @@ class Disc:
                                                      _ptr(out), _ptr(ws), _stream()))
         return out
 
+    def jf_matvec_noalloc(self, U, R0, v, shift, eps=1e-8, eps_mode=EPS_RMS, out=None):
+        """fr_jf_matvec_noalloc: the JF product with the library's static scratch (no workspace)."""
+        for t, nm in ((U, "U"), (R0, "R0"), (v, "v")):
+            self._vec(t, nm)
+        out = self.empty() if out is None else self._vec(out, "out")
+        _check("fr_jf_matvec_noalloc", self.lib.fr_jf_matvec_noalloc(self.handle, _ptr(U), _ptr(R0), _ptr(v), shift,
+                                                                     eps, eps_mode, _ptr(out), _stream()))
+        return out
+
     def ejacobi_assemble(self, U, shift):
         """Raw FP64 blocks P_e = shift I - dR_e/dq_e as a [nel, Nb, Nb] (row, col) tensor."""
         self._vec(U, "U")

@@ -6,6 +6,7 @@
 #include <string>
 #include <vector>
 #include <algorithm>
+#include <mutex>
 
 #include "internal.h"
 #include "solvers.h"
@@ -23,6 +24,35 @@ void clear_error() { g_err.clear(); }
 }  // namespace frjf
 
 using namespace frjf;
+
+// ---------------------------------------------------------------- static scratch
+// Device memory of fr_jf_matvec_noalloc: the RMS norm's partial sums and its finished
+// value, then (Navier-Stokes) the BR1 gradient traces.  Every GPU the library runs on
+// holds its own copy until the process ends; calls on one GPU share it.  In host code
+// the array's name is only a stand-in: its device address comes from
+// hipGetSymbolAddress, once per device (scratch_address).
+constexpr size_t kScratchBytes = size_t(4) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr size_t kScratchScalBytes = 256;                              // ||v||^2
+constexpr size_t kScratchPartBytes = sizeof(double) * kRedBlocks;     // its partial sums
+constexpr size_t kScratchTraceOff = kScratchScalBytes + kScratchPartBytes;
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[256];
+
+// Device address of `scratch` on `device` (current when called), looked up on first use.
+static hipError_t scratch_address(int device, void** out) {
+  if (device < 0 || device >= 256) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_addr[device] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[device] = p;
+  }
+  *out = g_scratch_addr[device];
+  return hipSuccess;
+}
 
 #define CHECK(cond, msg)                                   \
   do {                                                     \
@@ -72,6 +102,7 @@ fr_status fr_disc_create(const fr_disc_desc* desc, fr_disc** out) {
   if (e == hipSuccess) e = hipHostMalloc(&d->h_pinned, 4096, hipHostMallocMapped | hipHostMallocCoherent);
   if (e == hipSuccess) e = hipHostGetDevicePointer(&d->d_pinned, d->h_pinned, 0);
   for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&d->ev[i], hipEventDisableTiming);
+  if (e == hipSuccess) e = scratch_address(d->device, &d->d_scratch);
   if (e != hipSuccess) {
     delete d;
     return set_error(FR_EHIP, std::string("fr_disc_create: ") + hipGetErrorString(e));
@@ -155,6 +186,37 @@ fr_status fr_jf_matvec(const fr_disc* d, const double* U, const double* R0, cons
   a.eps_mode = eps_mode;
   a.shift = shift;
   a.grad = d->physics == FR_NS_BR1 ? tr : nullptr;
+  FR_HIP(launch_residual(d, 1, a, S(s)));
+  return FR_OK;
+}
+
+fr_status fr_jf_matvec_noalloc(const fr_disc* d, const double* U, const double* R0, const double* v, double shift,
+                               double eps, int eps_mode, double* Av, fr_stream s) {
+  clear_error();
+  CHECK(d && U && R0 && v && Av, "fr_jf_matvec_noalloc: null argument");
+  CHECK(Av != U && Av != R0 && Av != v, "fr_jf_matvec_noalloc: output aliases an input");
+  CHECK(eps_mode == FR_EPS_ABS || eps_mode == FR_EPS_RMS, "fr_jf_matvec_noalloc: bad eps_mode");
+  CHECK(eps > 0.0, "fr_jf_matvec_noalloc: eps must be positive");
+  if (d->d_scratch == nullptr) return set_error(FR_EHIP, "fr_jf_matvec_noalloc: no scratch address for the device");
+  const size_t tr = ns_trace_bytes(d);
+  if (kScratchTraceOff + tr > kScratchBytes)
+    return set_error(FR_ESIZE, "fr_jf_matvec_noalloc: the mesh's BR1 gradient traces (" + std::to_string(tr) +
+                                   " bytes) exceed the static scratch (" +
+                                   std::to_string(kScratchBytes - kScratchTraceOff) + " bytes)");
+  char* base = (char*)d->d_scratch;
+  double* scal = (double*)base;
+  double* partials = (double*)(base + kScratchScalBytes);
+  if (eps_mode == FR_EPS_RMS) FR_HIP(launch_norm2(v, d->ndof, partials, scal, nullptr, S(s)));
+  ResArgs a{};
+  a.U = U;
+  a.V = v;
+  a.R0 = R0;
+  a.out = Av;
+  a.nrm2 = scal;
+  a.eps = eps;
+  a.eps_mode = eps_mode;
+  a.shift = shift;
+  a.grad = d->physics == FR_NS_BR1 ? (double*)(base + kScratchTraceOff) : nullptr;
   FR_HIP(launch_residual(d, 1, a, S(s)));
   return FR_OK;
 }

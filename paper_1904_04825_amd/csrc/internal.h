@@ -47,6 +47,9 @@ struct fr_disc {
   // [1 KiB, 4 KiB) staging of synchronous device-to-host reads
   void* h_pinned;
   void* d_pinned;  // device-side address of h_pinned
+  // device address of the library's static scratch array on this disc's device (looked
+  // up once per device by fr_disc_create; used by fr_jf_matvec_noalloc)
+  void* d_scratch;
   hipEvent_t ev[4];
 };
 
