@@ -74,11 +74,18 @@ def parse():
                          "list of SCHEME/STEPS entries of tests/golden/paper_vortex_tables.json, or 'all'")
     ap.add_argument("--mach-reading", default="magnitude", choices=["magnitude", "u"],
                     help="velocity of the paper's Mach number: |V| or u")
-    ap.add_argument("--study-eps", default="abs", choices=["abs", "rms"],
+    ap.add_argument("--study-eps", default="rms", choices=["abs", "rms"],
                     help="JF perturbation of the paper-vortex study: the literal eps (abs) or eps / rms(v)")
+    ap.add_argument("--study-precond", default="f64", choices=["f64", "f32"],
+                    help="element-Jacobi precision of the paper-vortex study")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy (counter calibration for rocprofv3 --pmc runs)")
     return ap.parse_args()
+
+
+def progress(msg):
+    """A progress line on stderr (stdout carries only the JSON result line)."""
+    print(f"# bench: {msg} ({time.strftime('%H:%M:%S')})", file=sys.stderr, flush=True)
 
 
 def source_sha(rel):
@@ -86,6 +93,18 @@ def source_sha(rel):
     the kernel is unchanged since the counters were taken."""
     with open(os.path.join(ROOT, rel), "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def calib_copy(dev):
+    """Three 1 GiB device-to-device copies: the counter readings of a plain copy of known
+    size, to scale FETCH_SIZE / WRITE_SIZE of the kernels to bytes."""
+    import torch
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return src.numel() * 8
 
 
 def time_kernel(fn, reps=50, warm=5):
@@ -303,7 +322,7 @@ def order_study(disc, U0, vortex):
     return res
 
 
-def paper_vortex_study(select, speed, eps_mode="abs", progress=True):
+def paper_vortex_study(select, speed, eps_mode="abs", pc_prec="f64", verbose=True):
     """The paper's own vortex study (Section 5.1): 50x50 uniform quads on [-10,10]^2, P6,
     Roe flux, GMRES(60) with the literal eps = 1e-8, FP64 element-Jacobi, one period
     (T = 20) at the table's step counts and tolerances; E(rho) and E(u) against the exact
@@ -311,8 +330,9 @@ def paper_vortex_study(select, speed, eps_mode="abs", progress=True):
     import torch
 
     import fr_inputs as fi
-    from paper_1904_04825_amd import EPS_ABS, EPS_RMS, Disc, GmresOpts, SolverOpts
+    from paper_1904_04825_amd import EPS_ABS, EPS_RMS, F32, F64, Disc, GmresOpts, SolverOpts
     em = EPS_ABS if eps_mode == "abs" else EPS_RMS
+    pp = F32 if pc_prec == "f32" else F64
     with open(os.path.join(ROOT, "tests", "golden", "paper_vortex_tables.json")) as fh:
         golden = json.load(fh)
     T = golden["workload"]["period"]
@@ -333,14 +353,15 @@ def paper_vortex_study(select, speed, eps_mode="abs", progress=True):
         t0 = time.perf_counter()
         status = 0
         if sch.startswith("ROW"):
-            o = SolverOpts(lin=GmresOpts(m=60, rtol=ent["tol_lin"], eps_mode=em))
+            o = SolverOpts(lin=GmresOpts(m=60, rtol=ent["tol_lin"], eps_mode=em), precond_precision=pp)
             for _ in range(n):
                 st = disc.row_step(U, int(sch[3]), dt, o)
                 status = status or st["status"]
                 tot["gmres_iters"] += st["gmres_iters"]
                 tot["residual_evals"] += st["residual_evals"]
         else:
-            o = SolverOpts(lin=GmresOpts(m=60, rtol=ent["tol_lin"], eps_mode=em), tol_nl=ent["tol_nl"])
+            o = SolverOpts(lin=GmresOpts(m=60, rtol=ent["tol_lin"], eps_mode=em), tol_nl=ent["tol_nl"],
+                           precond_precision=pp)
             Um1 = None
             for _ in range(n):
                 if sch.startswith("ESDIRK"):
@@ -362,11 +383,42 @@ def paper_vortex_study(select, speed, eps_mode="abs", progress=True):
         if ent.get("note"):
             row["paper_scheme"] = ent["note"]
         rows.append(row)
-        if progress:
+        if verbose:
             print(f"# {sch} T/{n}: E(rho) {e_rho:.4e} (paper {ent['e_rho']:.4e}, ratio {e_rho / ent['e_rho']:.3f}), "
                   f"E(u) {e_u:.4e} (paper {ent['e_u']:.4e}), {wall:.1f} s", flush=True)
-    return {"mode": "paper-vortex", "mach_reading": speed, "eps_mode": eps_mode, "workload": golden["workload"],
-            "rows": rows}
+    return {"mode": "paper-vortex", "mach_reading": speed, "eps_mode": eps_mode, "precond_precision": pc_prec,
+            "workload": golden["workload"], "rows": rows}
+
+
+def precond_study(disc, W, U, dt, scheme, lin):
+    """The first ROW stage's linear system at the timed legs' start state, solved to the
+    same tolerance with each preconditioner on FP32 blocks: element-Jacobi (the paper's),
+    LU-SGS and p-multigrid (coarse level P - 2, one pre-, one post- and one coarse sweep):
+    GMRES iterations, Jacobian-free products and wall time of the factor + solve."""
+    import torch
+    from paper_1904_04825_amd import F32, PC_EJACOBI, PC_LUSGS, PC_PMG, GmresOpts, Pmg
+    from paper_1904_04825_amd.api import scheme_table
+    gam = scheme_table(0, scheme)[3]
+    shift = 1.0 / (gam * dt)
+    R0 = disc.residual(U)
+    res = {}
+    kinds = [("element-Jacobi", PC_EJACOBI), ("LU-SGS", PC_LUSGS)]
+    if disc.p >= 4:
+        kinds.append((f"p-multigrid P{disc.p}->P{disc.p - 2}", PC_PMG))
+    mg = Pmg(disc, disc.p - 2, 1, 1, 1, F32) if disc.p >= 4 else None
+    for name, pck in kinds:
+        for rep in range(2):   # the second run is timed
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            pc = disc.pmg_factor(U, shift, mg, F32) if pck == PC_PMG else disc.ejacobi_factor(U, shift, F32)
+            x, st = disc.gmres_solve(pc, U, R0, shift, R0, opts=GmresOpts(m=lin.m, rtol=lin.rtol, precond=pck))
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            del pc
+        res[name] = {"gmres_iters": st["iters"], "jf_products": st["residual_evals"], "status": st["status"],
+                     "wall_s": wall}
+    return {"system": f"ROW{scheme} stage 1 at the legs' start, FGMRES({lin.m}) rtol {lin.rtol}, FP32 blocks",
+            **res}
 
 
 def run_leg(disc, U, steps, scheme, dt, opts, allow_unconverged=False):
@@ -396,7 +448,7 @@ def main():
         return
     if args.paper_vortex is not None:
         sel = "all" if args.paper_vortex == "all" else set(args.paper_vortex.split(","))
-        print(json.dumps(paper_vortex_study(sel, args.mach_reading, args.study_eps)), flush=True)
+        print(json.dumps(paper_vortex_study(sel, args.mach_reading, args.study_eps, args.study_precond)), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -405,8 +457,8 @@ def main():
     import torch
 
     import fr_inputs as fi
-    from paper_1904_04825_amd import (F32, F64, Disc, GmresOpts, MlpTrainer, SolverOpts, StageLog, StageLogs,
-                                      WarmStart)
+    from paper_1904_04825_amd import (F32, F64, PC_LUSGS, Disc, GmresOpts, MlpTrainer, SolverOpts, StageLog,
+                                      StageLogs, WarmStart, fit_group)
     from paper_1904_04825_amd.api import scheme_table
 
     W = WORKLOADS[args.workload]
@@ -446,10 +498,13 @@ def main():
 
     if args.kernels_only:
         kernels, roof = kernel_block(disc, U0, dt, scheme, ndof, args.workload)
-        print(json.dumps({"mode": "kernels-only", "config": out["config"], "kernels": kernels, "roofline": roof}),
-              flush=True)
+        res = {"mode": "kernels-only", "config": out["config"], "kernels": kernels, "roofline": roof}
+        if args.calib_copy:
+            res["calib_copy_bytes"] = calib_copy(dev)
+        print(json.dumps(res), flush=True)
         return
 
+    progress("warm-up / logging steps")
     # ---- (1) warm-up steps, logging the stage solves
     rng = np.random.default_rng(40)
     learned = not args.no_learned
@@ -472,26 +527,46 @@ def main():
     t_start = args.warmup * dt
     Ustart, hstart = U.clone(), yhist.clone()
 
+    progress("training")
     # ---- (2) train one network per stage on the GPU
     def train(stage_logs, seed0):
-        """One network per stage, trained on the GPU from the stage's log (cosine-decayed Adam)."""
+        """One network per stage, all trained together on the GPU (fr_mlp_train_group: one
+        launch per kernel for every network, cosine-decayed Adam), each from its stage's log.
+        For reference, one more network is then trained alone through the per-step call
+        (MlpTrainer.fit, the same arithmetic) and timed."""
         t_tr = time.perf_counter()
-        trainers, final_loss = [], []
+        trainers = []
         for i, lg in enumerate(stage_logs.logs):
             tr = MlpTrainer(disc, n_hidden=256, seed=seed0 + i, lr=1e-3)
             tr.fit_stats(lg)
-            ls = tr.fit(lg, args.adam_steps, args.batch, lr=1e-3, seed=seed0 + 100 + i, report_every=250)
             trainers.append(tr)
-            final_loss.append(float(ls[-1][1]))
+        final_loss = []
+        for g0 in range(0, len(trainers), 8):
+            ls = fit_group(trainers[g0:g0 + 8], stage_logs.logs[g0:g0 + 8], args.adam_steps, args.batch, lr=1e-3,
+                           seeds=[seed0 + 100 + i for i in range(g0, min(g0 + 8, len(trainers)))], report_every=250)
+            final_loss += [float(l[-1][1]) for l in ls]
         torch.cuda.synchronize()
+        train_s = time.perf_counter() - t_tr
+        t_ref = time.perf_counter()
+        ref = MlpTrainer(disc, n_hidden=256, seed=seed0, lr=1e-3)
+        ref.fit_stats(stage_logs.logs[0])
+        ref.fit(stage_logs.logs[0], args.adam_steps, args.batch, lr=1e-3, seed=seed0 + 100, report_every=250)
+        torch.cuda.synchronize()
+        ref_s = time.perf_counter() - t_ref
+        del ref
+        n = len(trainers)
         info = {"samples_per_stage": stage_logs.logs[0].count, "adam_steps_per_stage": args.adam_steps,
-                "batch": args.batch, "final_mse_normalised": final_loss, "train_s": time.perf_counter() - t_tr}
+                "batch": args.batch, "networks": n, "final_mse_normalised": final_loss, "train_s": train_s,
+                "train_s_per_network": train_s / n, "single_network_fit_s": ref_s,
+                "note": "the networks are trained together (one launch per kernel for all of them); "
+                        "single_network_fit_s is one network trained alone through the per-step call"}
         return WarmStart([t.net for t in trainers]), info
 
     warm = None
     if learned and args.warmup > 0:
         warm, out["extra"]["learned_training"] = train(logs, 4)
 
+    progress("timed legs")
     # ---- (3) timed legs from the same state
     t_phys = args.steps * dt
 
@@ -537,7 +612,25 @@ def main():
                 "break_even_steps_vs_fp64": (tr_s / save64) if save64 > 0 else None,
                 "note": "the logging steps are ordinary time steps of the run (FP32 element-Jacobi) that also "
                         "store training samples; training is the extra cost"}
+        # the same steps with the matrix-free LU-SGS preconditioner on the FP32 blocks
+        # (Section 4.5 names it beside element-Jacobi), and with the learned start on top
+        if W["physics"] == "euler" and disc.nx % 2 == 0 and disc.ny % 2 == 0:
+            lin_l = GmresOpts(m=lin.m, rtol=lin.rtol, precond=PC_LUSGS)
+            for name, wnet in (("fp32_lusgs", None), ("fp32_lusgs_learned", warm)):
+                if name.endswith("learned") and wnet is None:
+                    continue
+                U = Ustart.clone()
+                w4, e4, i4, x4 = run_leg(disc, U, args.steps, scheme, dt,
+                                         SolverOpts(lin=lin_l, precond_precision=F32, warm=wnet, yhist=hstart.clone()))
+                legs[name] = {"wall_s_per_time_unit": w4 / t_phys, "ms_per_step": w4 / args.steps * 1e3,
+                              "gmres_iters_per_step": i4 / args.steps, "residual_evals_per_step": e4 / args.steps,
+                              "l2_err_rho": err(U), "speedup_vs_plain_fp64": wall / w4,
+                              "rel_diff_vs_fp64": float(torch.linalg.norm(U - U_fp64) / torch.linalg.norm(U_fp64)),
+                              **({k: x4[k] for k in ("warm_used", "warm_rejected")} if wnet is not None else {})}
     out["extra"]["legs"] = legs
+    if not args.no_fp32_leg and W["physics"] == "euler":
+        progress("preconditioner study")
+        out["extra"]["preconditioners"] = precond_study(disc, W, Ustart, dt, scheme, lin)
 
     # ---- (4) the other implicit schemes of the same workload, FP64 element-Jacobi:
     # ESDIRK3 (ESDIRK4 beside ROW4) and BDF2 (BDF1 start), each also with the FP32
@@ -629,19 +722,16 @@ def main():
                 schemes[f"{name}, FP32 element-Jacobi + learned start"] = leg
         out["extra"]["schemes"] = schemes
 
+    progress("kernel timing block")
     if not args.no_kernels:
         kernels, roof = kernel_block(disc, Ustart, dt, scheme, ndof, args.workload)
         out["extra"]["kernels"] = kernels
         out["roofline"] = roof
 
     if args.calib_copy:
-        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        out["extra"]["calib_copy_bytes"] = src.numel() * 8
+        out["extra"]["calib_copy_bytes"] = calib_copy(dev)
 
+    progress("CPU baseline")
     if not args.no_cpu_baseline and W["physics"] == "euler":
         out["cpu_baseline"] = cpu_baseline(W, dt, scheme)
     print(json.dumps(out), flush=True)

@@ -140,10 +140,12 @@ fr_status fr_jf_matvec_noalloc(const fr_disc* disc, const double* d_U, const dou
  * precision) bytes; after fr_ejacobi_factor it holds, per element, the
  * explicit inverse of P_e = shift I - dR_e/dq_e, column-major, in
  * `precision`. */
+struct fr_pmg;
 typedef struct {
   void* d_factors;
   int precision; /* FR_F64 or FR_F32 */
   double shift;  /* set by fr_ejacobi_factor */
+  const struct fr_pmg* mg;  /* FR_PC_PMG: the coarse level (fr_pmg_factor), else NULL */
 } fr_ejacobi;
 
 /* Assemble the raw blocks P_e = shift I - dR_e/dq_e by one-sided finite
@@ -194,7 +196,8 @@ typedef struct {
   double ref_norm;  /* r_ref; <= 0 means ||b - A x0|| (Section 5.1: relative to the first residual) */
   double eps;       /* JF perturbation, default 1e-8 */
   int eps_mode;     /* FR_EPS_RMS or FR_EPS_ABS */
-  int precond;      /* FR_PC_EJACOBI (the paper's element-Jacobi) or FR_PC_LUSGS */
+  int precond;      /* FR_PC_EJACOBI (the paper's element-Jacobi), FR_PC_LUSGS or FR_PC_PMG
+                       (fr_gmres_solve only: the coarse level comes with the pc) */
 } fr_gmres_opts;
 
 /* Preconditioners of the linear solves (Section 4.5 names matrix-free LU-SGS as the
@@ -203,7 +206,40 @@ typedef struct {
  * (ex + ey even / odd; Euler meshes with even nx and ny), the element blocks of the
  * fr_ejacobi store as its diagonal and the couplings between colours applied through
  * Jacobian-free products (two per application, counted in residual_evals). */
-enum { FR_PC_EJACOBI = 0, FR_PC_LUSGS = 1 };
+enum { FR_PC_EJACOBI = 0, FR_PC_LUSGS = 1, FR_PC_PMG = 2 };
+
+/* p-multigrid (FR_PC_PMG; Section 4.5 names it beside element-Jacobi): a coarse
+ * discretisation of the same mesh at degree pc < p (its own handle, Euler, same flux)
+ * with its own residual and element blocks, and a V-cycle preconditioner:
+ *   z = D^{-1} r, nu1 - 1 more sweeps z += D^{-1}(r - A z);
+ *   rc = Pi (r - A z), zc = Dc^{-1} rc, nc - 1 sweeps zc += Dc^{-1}(rc - Ac zc);
+ *   z += I zc; nu2 sweeps z += D^{-1}(r - A z);
+ * Pi the L2 projection onto degree pc and I the interpolation of the coarse polynomial
+ * at the fine points (per element and variable, tensor products of 1D operators), A and
+ * Ac the Jacobian-free products of the two levels (the coarse one at Uc = Pi U).
+ * Caller-allocated buffers; set by fr_pmg_factor. */
+typedef struct fr_pmg {
+  const fr_disc* coarse;
+  fr_ejacobi coarse_pc;  /* fr_ejacobi_bytes(coarse, precision) bytes at d_factors */
+  double* d_Uc;          /* coarse ndof: Pi U */
+  double* d_R0c;         /* coarse ndof: R_c(Uc) */
+  double* d_work_c;      /* 4 coarse ndof + 32 doubles */
+  int nu1, nu2, nc;      /* smoothing sweeps: nu1 >= 1, nu2 >= 0, nc >= 1 */
+} fr_pmg;
+
+/* Fine element-Jacobi at (d_U, shift) into pc (as fr_ejacobi_factor), Uc = Pi U,
+ * R_c(Uc) and the coarse element-Jacobi at (Uc, shift) into mg->coarse_pc; sets
+ * pc->mg = mg.  d_work: FR_WS_RESIDUAL bytes of the fine disc.  FR_EINVAL when the
+ * levels do not match (mesh, flux, physics Euler, pc < p). */
+fr_status fr_pmg_factor(const fr_disc* fine, const double* d_U, double shift, fr_ejacobi* pc, fr_pmg* mg,
+                        void* d_work, fr_stream stream);
+
+/* z = M^{-1} r for the p-multigrid preconditioner of pc (pc->mg set by fr_pmg_factor at
+ * d_U with d_R0 = R(d_U)).  d_work: fr_workspace_bytes(FR_WS_GMRES, m = 1) bytes of the
+ * fine disc.  r and z may not alias. */
+fr_status fr_pmg_apply(const fr_disc* fine, const fr_ejacobi* pc, const double* d_U, const double* d_R0,
+                       double shift, double eps, int eps_mode, const double* d_r, double* d_z, void* d_work,
+                       fr_stream stream);
 
 typedef struct {
   int iters;         /* Arnoldi iterations */
@@ -370,6 +406,20 @@ fr_status fr_mlp_sync(fr_mlp_trainer* tr, fr_stream stream);
  * MSE before the update; with h_loss == NULL it only enqueues the step (no host read). */
 fr_status fr_mlp_train_step(const fr_disc* disc, fr_mlp_trainer* tr, const fr_stage_log* log, const int* d_idx,
                             int batch, double* h_loss, void* d_work, fr_stream stream);
+
+/* Several networks of equal sizes (one per stage, say) trained together: `steps` training
+ * steps of each of the `count` (1..8) trainers trs[q] on its own log logs[q], every kernel
+ * of a step launched once for all networks.  d_idx: device int32 [count][steps][batch]
+ * logged-row indices (each below its log's count; not checked, device data).  h_lr: host
+ * [steps] learning rates, written to every trs[q].lr before step k (NULL: each keeps its
+ * own).  Network q's arithmetic is that of fr_mlp_train_step, in the same order, so it
+ * ends bitwise where `steps` calls of fr_mlp_train_step would have left it.  h_loss:
+ * host [count], the batch MSE of each network's last step before its update (the call
+ * then synchronises), or NULL (enqueue only).  d_work: fr_mlp_group_work_bytes bytes. */
+size_t fr_mlp_group_work_bytes(const fr_disc* disc, int n_hidden, int batch, int count);
+fr_status fr_mlp_train_group(const fr_disc* disc, fr_mlp_trainer* trs, const fr_stage_log* logs, int count,
+                             const int* d_idx, int steps, int batch, const float* h_lr, double* h_loss,
+                             void* d_work, fr_stream stream);
 
 /* Coefficients of the built-in schemes, for inspection: kind 0 = ROW
  * (transformed a_ij, c_ij, m_j, gamma), kind 1 = ESDIRK (a_ij, b_i).

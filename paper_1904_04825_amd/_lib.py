@@ -21,7 +21,12 @@ class DiscDesc(Structure):
 
 
 class EjacobiC(Structure):
-    _fields_ = [("d_factors", c_void_p), ("precision", c_int), ("shift", c_double)]
+    _fields_ = [("d_factors", c_void_p), ("precision", c_int), ("shift", c_double), ("mg", c_void_p)]
+
+
+class PmgC(Structure):
+    _fields_ = [("coarse", c_void_p), ("coarse_pc", EjacobiC), ("d_Uc", c_void_p), ("d_R0c", c_void_p),
+                ("d_work_c", c_void_p), ("nu1", c_int), ("nu2", c_int), ("nc", c_int)]
 
 
 class GmresOptsC(Structure):
@@ -75,6 +80,9 @@ _SIGS = {
                              c_void_p, c_void_p]),
     "fr_lusgs_apply": (c_int, [c_void_p, POINTER(EjacobiC), c_void_p, c_void_p, c_double, c_double, c_int, c_void_p,
                                c_void_p, c_void_p, c_void_p]),
+    "fr_pmg_factor": (c_int, [c_void_p, c_void_p, c_double, POINTER(EjacobiC), POINTER(PmgC), c_void_p, c_void_p]),
+    "fr_pmg_apply": (c_int, [c_void_p, POINTER(EjacobiC), c_void_p, c_void_p, c_double, c_double, c_int, c_void_p,
+                             c_void_p, c_void_p, c_void_p]),
     "fr_jf_matvec_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double, c_int, c_void_p,
                                      c_void_p]),
     "fr_ejacobi_assemble": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
@@ -103,6 +111,9 @@ _SIGS = {
     "fr_mlp_sync": (c_int, [POINTER(MlpTrainerC), c_void_p]),
     "fr_mlp_train_step": (c_int, [c_void_p, POINTER(MlpTrainerC), POINTER(StageLogC), c_void_p, c_int,
                                   POINTER(c_double), c_void_p, c_void_p]),
+    "fr_mlp_group_work_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int]),
+    "fr_mlp_train_group": (c_int, [c_void_p, POINTER(MlpTrainerC), POINTER(StageLogC), c_int, c_void_p, c_int, c_int,
+                                   POINTER(ctypes.c_float), POINTER(c_double), c_void_p, c_void_p]),
     "fr_last_error": (ctypes.c_char_p, []),
 }
 

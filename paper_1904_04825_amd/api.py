@@ -16,7 +16,7 @@ EULER, NS_BR1 = 0, 1
 RUSANOV, ROE = 0, 1
 F64, F32 = 0, 1
 EPS_ABS, EPS_RMS = 0, 1
-PC_EJACOBI, PC_LUSGS = 0, 1
+PC_EJACOBI, PC_LUSGS, PC_PMG = 0, 1, 2
 _PHYS = {"euler": EULER, "ns": NS_BR1, "ns_br1": NS_BR1}
 _FLUX = {"rusanov": RUSANOV, "roe": ROE}
 _PREC = {"f64": F64, "fp64": F64, "f32": F32, "fp32": F32}
@@ -97,13 +97,29 @@ class Ejacobi:
         self.precision = _PREC.get(precision, precision)
         nbytes = L.lib().fr_ejacobi_bytes(disc.handle, self.precision)
         self.buf = torch.empty(nbytes, dtype=torch.uint8, device=disc.device)
-        self.c = L.EjacobiC(self.buf.data_ptr(), self.precision, 0.0)
+        self.c = L.EjacobiC(self.buf.data_ptr(), self.precision, 0.0, None)
 
     def inverse_blocks(self):
         dt = torch.float32 if self.precision == F32 else torch.float64
         nb = self.disc.nb
         # column-major per element: [e][col][row] -> return [e][row][col]
         return self.buf.view(dt).view(self.disc.nel, nb, nb).transpose(1, 2)
+
+
+class Pmg:
+    """The coarse level of a p-multigrid preconditioner: a discretisation of the same mesh
+    at a lower degree, its element-Jacobi store and buffers (torch-owned)."""
+
+    def __init__(self, fine, pc_coarse, nu1=1, nu2=1, nc=1, precision=F64):
+        self.fine = fine
+        self.coarse = fine.__class__(fine.nodes.cpu().numpy(), pc_coarse, flux={0: "rusanov", 1: "roe"}[fine.flux],
+                                     gamma=fine.gamma, device=fine.device)
+        self.cpc = Ejacobi(self.coarse, precision)
+        self.Uc = self.coarse.empty()
+        self.R0c = self.coarse.empty()
+        self.work = torch.empty(4 * self.coarse.ndof + 32, dtype=torch.float64, device=fine.device)
+        self.c = L.PmgC(self.coarse.handle, self.cpc.c, self.Uc.data_ptr(), self.R0c.data_ptr(),
+                        self.work.data_ptr(), nu1, nu2, nc)
 
 
 class Disc:
@@ -231,6 +247,27 @@ class Disc:
         z = self.empty() if z is None else self._vec(z, "z")
         _check("fr_ejacobi_solve", self.lib.fr_ejacobi_solve(self.handle, ctypes.byref(pc.c), _ptr(r), _ptr(z),
                                                              _stream()))
+        return z
+
+    def pmg_factor(self, U, shift, mg, precision=F64, pc=None):
+        """Fine element-Jacobi at (U, shift) plus the coarse level of mg (Pmg): returns the
+        fine store, which carries mg for FR_PC_PMG solves."""
+        self._vec(U, "U")
+        pc = Ejacobi(self, precision) if pc is None else pc
+        ws = self.workspace(L.WS_RESIDUAL)
+        _check("fr_pmg_factor", self.lib.fr_pmg_factor(self.handle, _ptr(U), shift, ctypes.byref(pc.c),
+                                                       ctypes.byref(mg.c), _ptr(ws), _stream()))
+        pc.mg = mg   # keep the coarse level alive with the store
+        return pc
+
+    def pmg_apply(self, pc, U, R0, shift, r, eps=1e-8, eps_mode=EPS_RMS, z=None):
+        """z = M^{-1} r for the p-multigrid preconditioner of pc (from pmg_factor)."""
+        for t, nm in ((U, "U"), (R0, "R0"), (r, "r")):
+            self._vec(t, nm)
+        z = self.empty() if z is None else self._vec(z, "z")
+        ws = self.workspace(L.WS_GMRES, 1)
+        _check("fr_pmg_apply", self.lib.fr_pmg_apply(self.handle, ctypes.byref(pc.c), _ptr(U), _ptr(R0), shift, eps,
+                                                     eps_mode, _ptr(r), _ptr(z), _ptr(ws), _stream()))
         return z
 
     def lusgs_apply(self, pc, U, R0, shift, r, eps=1e-8, eps_mode=EPS_RMS, z=None):
@@ -406,19 +443,67 @@ class MlpTrainer:
         log (each batch drawn without replacement, seeded; all batches copied to the device
         at once).  The loss is read back only every `report_every` steps and at the end:
         returns the list of those (step, loss) pairs."""
-        import numpy as np
-        rng = np.random.default_rng(seed)
-        n = log.count
-        b = min(batch, n)
-        idx = np.stack([rng.choice(n, b, replace=False) for _ in range(steps)]).astype(np.int32)
+        idx = _fit_batches(log.count, steps, batch, seed)
+        lrs = _cosine_lr(lr, steps)
         didx = torch.as_tensor(idx, device=self.net.disc.device)
         out = []
         for it in range(steps):
             rd = (it + 1) % report_every == 0 or it + 1 == steps or it == 0
-            l = self.step(log, didx[it], lr=lr * 0.5 * (1 + np.cos(np.pi * it / steps)), read_loss=rd)
+            l = self.step(log, didx[it], lr=lrs[it], read_loss=rd)
             if rd:
                 out.append((it, l))
         return out
+
+
+def _fit_batches(n, steps, batch, seed):
+    """The batches of MlpTrainer.fit: per step `batch` logged rows drawn without replacement."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    b = min(batch, n)
+    return np.stack([rng.choice(n, b, replace=False) for _ in range(steps)]).astype(np.int32)
+
+
+def _cosine_lr(lr, steps):
+    import numpy as np
+    return [lr * 0.5 * (1 + np.cos(np.pi * it / steps)) for it in range(steps)]
+
+
+def fit_group(trainers, logs, steps, batch, lr=1e-3, seeds=None, report_every=100):
+    """Train several networks of equal sizes together (fr_mlp_train_group): `steps` Adam
+    steps of trainers[q] on logs[q], with the batches and cosine-decayed learning rate that
+    MlpTrainer.fit draws from seeds[q], so every network ends bitwise where its own fit
+    would have left it.  The step loop runs in the library; the losses are read after the
+    first step, every report_every steps and at the end: returns per trainer the list of
+    those (step, loss) pairs."""
+    import numpy as np
+    count = len(trainers)
+    if count != len(logs) or not 1 <= count <= 8:
+        raise ValueError("fit_group: one log per trainer, 1..8 trainers")
+    seeds = list(seeds) if seeds is not None else [0] * count
+    disc = trainers[0].net.disc
+    idx = np.stack([_fit_batches(lg.count, steps, batch, sd) for lg, sd in zip(logs, seeds)])  # [count][steps][b]
+    b = idx.shape[2]
+    didx = torch.as_tensor(idx, device=disc.device)
+    lrs = np.asarray(_cosine_lr(lr, steps), dtype=np.float32)
+    nbytes = int(L.lib().fr_mlp_group_work_bytes(disc.handle, trainers[0].net.n_hidden, b, count))
+    if nbytes == 0:
+        raise ValueError("fit_group: invalid sizes")
+    work = torch.empty(nbytes, dtype=torch.uint8, device=disc.device)
+    arr = (L.MlpTrainerC * count)(*[t.c for t in trainers])
+    larr = (L.StageLogC * count)(*[lg.c for lg in logs])
+    bounds = sorted({0, 1, steps} | set(range(report_every, steps, report_every)))
+    out = [[] for _ in range(count)]
+    loss = (ctypes.c_double * count)()
+    for a, e in zip(bounds[:-1], bounds[1:]):
+        chunk = didx[:, a:e, :].contiguous()
+        lr_c = (ctypes.c_float * (e - a))(*lrs[a:e])
+        _check("fr_mlp_train_group", L.lib().fr_mlp_train_group(disc.handle, arr, larr, count, _ptr(chunk), e - a, b,
+                                                                lr_c, loss, _ptr(work), _stream()))
+        for q in range(count):
+            out[q].append((e - 1, loss[q]))
+    for q, t in enumerate(trainers):
+        t.c.t, t.c.lr = arr[q].t, arr[q].lr
+    return out
 
 
 class StageLog:

@@ -266,7 +266,7 @@ static fr_status check_gmres_opts(const fr_gmres_opts* o) {
   CHECK(o->m >= 1 && o->m <= kMaxM, "GMRES restart m must be in 1..64");
   CHECK(o->rtol >= 0.0, "GMRES rtol must be >= 0");
   CHECK(o->eps_mode == FR_EPS_ABS || o->eps_mode == FR_EPS_RMS, "bad eps_mode");
-  CHECK(o->precond == FR_PC_EJACOBI || o->precond == FR_PC_LUSGS, "bad precond");
+  CHECK(o->precond == FR_PC_EJACOBI || o->precond == FR_PC_LUSGS || o->precond == FR_PC_PMG, "bad precond");
   return FR_OK;
 }
 
@@ -304,7 +304,44 @@ fr_status fr_gmres_solve(const fr_disc* d, const fr_ejacobi* pc, const double* U
   CHECK(x != b && x != U && x != R0, "fr_gmres_solve: x aliases an input");
   Carver cv(work);
   GmWork W = carve_gmres(cv, d, opts->m);
-  return gmres_core(d, pc->d_factors, pc->precision, U, R0, shift, b, x, false, *opts, stats, W, S(s));
+  return gmres_core(d, pc->d_factors, pc->precision, U, R0, shift, b, x, false, *opts, stats, W, S(s), false,
+                    nullptr, pc->mg);
+}
+
+fr_status fr_pmg_factor(const fr_disc* d, const double* U, double shift, fr_ejacobi* pc, fr_pmg* mg, void* work,
+                        fr_stream s) {
+  clear_error();
+  CHECK(d && U && pc && pc->d_factors && mg, "fr_pmg_factor: null argument");
+  CHECK(pc->precision == FR_F64 || pc->precision == FR_F32, "fr_pmg_factor: bad precision");
+  CHECK(mg->coarse_pc.precision == FR_F64 || mg->coarse_pc.precision == FR_F32, "fr_pmg_factor: bad coarse precision");
+  CHECK(pmg_compatible(d, mg), "fr_pmg_factor: levels do not match (same mesh and flux, Euler, coarse p < fine p, "
+                               "buffers set, nu1 >= 1, nu2 >= 0, nc >= 1)");
+  (void)work;
+  fr_status st = pmg_factor(d, U, shift, pc, mg, nullptr, S(s));
+  if (st == FR_OK) pc->mg = mg;
+  return st;
+}
+
+fr_status fr_pmg_apply(const fr_disc* d, const fr_ejacobi* pc, const double* U, const double* R0, double shift,
+                       double eps, int eps_mode, const double* r, double* z, void* work, fr_stream s) {
+  clear_error();
+  CHECK(d && pc && pc->d_factors && U && R0 && r && z && work, "fr_pmg_apply: null argument");
+  CHECK(z != r && z != U && z != R0, "fr_pmg_apply: z aliases an input");
+  CHECK(pmg_compatible(d, pc->mg), "fr_pmg_apply: pc has no matching coarse level (fr_pmg_factor)");
+  CHECK(eps_mode == FR_EPS_ABS || eps_mode == FR_EPS_RMS, "fr_pmg_apply: bad eps_mode");
+  CHECK(eps > 0.0, "fr_pmg_apply: eps must be positive");
+  Carver cv(work);
+  GmWork W = carve_gmres(cv, d, 1);
+  ResArgs ra{};
+  ra.U = U;
+  ra.R0 = R0;
+  ra.eps = eps;
+  ra.eps_mode = eps_mode;
+  ra.shift = shift;
+  ra.nrm2 = W.scal;
+  int np = 0;
+  return pmg_apply(d, pc->d_factors, pc->precision, pc->mg, ra, r, nullptr, nullptr, z, W, W.partials + kPartZ, &np,
+                   nullptr, S(s));
 }
 
 static fr_status check_step(const fr_disc* d, const fr_solver_opts* o, fr_step_stats* st, void* work) {
@@ -312,6 +349,8 @@ static fr_status check_step(const fr_disc* d, const fr_solver_opts* o, fr_step_s
   fr_status c = check_gmres_opts(&o->lin);
   if (c != FR_OK) return c;
   CHECK(o->precond_precision == FR_F64 || o->precond_precision == FR_F32, "step: bad precond_precision");
+  CHECK(o->lin.precond != FR_PC_PMG, "step: the time steps take element-Jacobi or LU-SGS (p-multigrid: "
+                                     "fr_gmres_solve with fr_pmg_factor)");
   return FR_OK;
 }
 
@@ -401,7 +440,7 @@ fr_status fr_mlp_forward(const fr_mlp* net, const uint16_t* x, int batch, float*
   char* p = (char*)work;
   uint16_t* H1 = (uint16_t*)p;
   uint16_t* H2 = (uint16_t*)(p + (((size_t)batch * net->n_hidden * 2 + 255) / 256) * 256);
-  FR_HIP(mlp_forward(net, x, batch, y, nullptr, H1, nullptr, nullptr, H2, nullptr, S(s)));
+  FR_HIP(mlp_forward(net, x, batch, y, H1, H2, S(s)));
   return FR_OK;
 }
 
@@ -426,21 +465,58 @@ fr_status fr_mlp_sync(fr_mlp_trainer* tr, fr_stream s) {
 fr_status fr_mlp_train_step(const fr_disc* d, fr_mlp_trainer* tr, const fr_stage_log* log, const int* idx, int batch,
                             double* h_loss, void* work, fr_stream s) {
   clear_error();
-  CHECK(d && tr && log && idx && work && batch > 0, "fr_mlp_train_step: null argument");
+  CHECK(d && tr && log && log->d_samples && idx && work && batch > 0, "fr_mlp_train_step: null argument");
   CHECK(tr->d_master && tr->d_grad && tr->d_m && tr->d_v, "fr_mlp_train_step: null trainer buffers");
   fr_status c = check_mlp(d, &tr->net);
   if (c != FR_OK) return c;
-  const size_t tb = mlp_train_bytes(batch, tr->net.n_in, tr->net.n_hidden, tr->net.n_out);
-  double* partials = (double*)((char*)work + tb - sizeof(double) * 4096);
+  const float* raw = log->d_samples;
+  void* w = work;
   int np = 0;
-  FR_HIP(mlp_train_step(tr, log->d_samples, idx, batch, d->np, partials, &np, work, S(s)));
+  FR_HIP(mlp_train_group(&tr, &raw, &idx, 1, batch, d->np, &w, &np, S(s)));
   if (h_loss == nullptr) return FR_OK;  // asynchronous: no loss read-back
-  std::vector<double> h(np);
-  FR_HIP(hipMemcpyAsync(h.data(), partials, sizeof(double) * np, hipMemcpyDeviceToHost, S(s)));
-  FR_HIP(hipStreamSynchronize(S(s)));
-  double sum = 0.0;
-  for (double v : h) sum += v;
-  *h_loss = sum / ((double)batch * tr->net.n_out);
+  FR_HIP(mlp_group_loss(&w, 1, batch, tr->net.n_in, tr->net.n_hidden, tr->net.n_out, np, h_loss, S(s)));
+  return FR_OK;
+}
+
+size_t fr_mlp_group_work_bytes(const fr_disc* d, int n_hidden, int batch, int count) {
+  if (d == nullptr || batch < 1 || count < 1 || count > kMlpGroupMax) return 0;
+  return (size_t)count * mlp_train_bytes(batch, 16 * d->np, n_hidden, 4 * d->np);
+}
+
+fr_status fr_mlp_train_group(const fr_disc* d, fr_mlp_trainer* trs, const fr_stage_log* logs, int count,
+                             const int* idx, int steps, int batch, const float* h_lr, double* h_loss, void* work,
+                             fr_stream s) {
+  clear_error();
+  CHECK(d && trs && logs && idx && work, "fr_mlp_train_group: null argument");
+  CHECK(batch > 0 && steps > 0, "fr_mlp_train_group: empty batch or no steps");
+  CHECK(count >= 1 && count <= kMlpGroupMax, "fr_mlp_train_group: count must be in 1..8");
+  for (int q = 0; q < count; ++q) {
+    CHECK(trs[q].d_master && trs[q].d_grad && trs[q].d_m && trs[q].d_v, "fr_mlp_train_group: null trainer buffers");
+    fr_status c = check_mlp(d, &trs[q].net);
+    if (c != FR_OK) return c;
+    CHECK(trs[q].net.n_hidden == trs[0].net.n_hidden, "fr_mlp_train_group: networks of different sizes");
+    CHECK(logs[q].d_samples && logs[q].count > 0, "fr_mlp_train_group: empty log");
+  }
+  const int In = trs[0].net.n_in, H = trs[0].net.n_hidden, Out = trs[0].net.n_out;
+  const size_t tb = mlp_train_bytes(batch, In, H, Out);
+  fr_mlp_trainer* tp[kMlpGroupMax];
+  const float* raws[kMlpGroupMax];
+  const int* ip[kMlpGroupMax];
+  void* works[kMlpGroupMax];
+  for (int q = 0; q < count; ++q) {
+    tp[q] = &trs[q];
+    raws[q] = logs[q].d_samples;
+    works[q] = (char*)work + (size_t)q * tb;
+  }
+  int np = 0;
+  for (int k = 0; k < steps; ++k) {
+    for (int q = 0; q < count; ++q) {
+      ip[q] = idx + ((size_t)q * steps + k) * batch;
+      if (h_lr != nullptr) trs[q].lr = h_lr[k];
+    }
+    FR_HIP(mlp_train_group(tp, raws, ip, count, batch, d->np, works, &np, S(s)));
+  }
+  if (h_loss != nullptr) FR_HIP(mlp_group_loss(works, count, batch, In, H, Out, np, h_loss, S(s)));
   return FR_OK;
 }
 

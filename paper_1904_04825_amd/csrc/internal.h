@@ -107,6 +107,8 @@ int residual_dots_blocks(const fr_disc* d);
 // Sum of squares with a deterministic two-level reduction; result in *out (device).
 hipError_t launch_norm2(const double* x, size_t n, double* partials, double* out,
                         const int* skip, hipStream_t s);
+// Partial sums of ||x||^2 only: *nb <= kRedBlocks of them into partials.
+hipError_t launch_norm2_parts(const double* x, size_t n, double* partials, int* nb, const int* skip, hipStream_t s);
 // y = sum_i c[i] * x[i] (k <= 8); pointers and coefficients passed by value
 hipError_t launch_lincomb(double* y, int k, const double* const* x, const double* c, size_t n,
                           hipStream_t s);
@@ -271,15 +273,18 @@ size_t mlp_weight_elems(int In, int H, int Out);
 size_t mlp_param_elems(int In, int H, int Out);
 size_t mlp_infer_bytes(int nel, int In, int H, int Out);
 size_t mlp_train_bytes(int B, int In, int H, int Out);
-hipError_t mlp_forward(const fr_mlp* net, const uint16_t* X, int B, float* Y, float* Z1, uint16_t* H1, uint16_t* H1t,
-                       float* Z2, uint16_t* H2, uint16_t* H2t, hipStream_t s);
+hipError_t mlp_forward(const fr_mlp* net, const uint16_t* X, int B, float* Y, uint16_t* H1, uint16_t* H2,
+                       hipStream_t s);
 hipError_t mlp_infer(const fr_disc* d, const fr_mlp* net, const double* U, const double* R, const double* Y1,
                      const double* Y2, double dt, double* x0, void* work, hipStream_t s);
 hipError_t mlp_log(const fr_disc* d, fr_stage_log* log, const double* U, const double* R, const double* Y1,
                    const double* Y2, const double* Y, double dt, hipStream_t s);
 hipError_t mlp_stats(const float* raw, int count, int Np, float* norm, hipStream_t s);
-hipError_t mlp_train_step(fr_mlp_trainer* tr, const float* raw, const int* idx, int B, int Np, double* loss_partials,
-                          int* nparts, void* work, hipStream_t s);
+constexpr int kMlpGroupMax = 8;  // networks trained together (mlp_train_group)
+hipError_t mlp_train_group(fr_mlp_trainer* const* trs, const float* const* raws, const int* const* idx, int count,
+                           int B, int Np, void* const* works, int* nparts, hipStream_t s);
+hipError_t mlp_group_loss(void* const* works, int count, int B, int In, int H, int Out, int nparts, double* h_loss,
+                          hipStream_t s);
 hipError_t mlp_sync_weights(fr_mlp_trainer* tr, hipStream_t s);
 
 

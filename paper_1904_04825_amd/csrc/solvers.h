@@ -50,10 +50,20 @@ fr_status device_norm(const fr_disc* d, const double* x, double* partials, doubl
 fr_status lusgs_apply(const fr_disc* d, const void* factors, int prec, const ResArgs& ra, const double* r,
                       const GivensIn* gv, double* r_store, double* z, GmWork& W, double* zpart, int* np,
                       const int* skip, long* evals, hipStream_t s);
+// p-multigrid (pmg.hip): compatibility of the two levels, their factorisation, and one
+// V-cycle z = M^{-1} r with the same conventions as lusgs_apply; pmg_products: the
+// Jacobian-free products of one application.
+bool pmg_compatible(const fr_disc* fine, const fr_pmg* mg);
+fr_status pmg_factor(const fr_disc* fine, const double* U, double shift, fr_ejacobi* pc, fr_pmg* mg, double* grad,
+                     hipStream_t s);
+fr_status pmg_apply(const fr_disc* fine, const void* factors, int prec, const fr_pmg* mg, const ResArgs& ra,
+                    const double* r, const GivensIn* gv, double* r_store, double* z, GmWork& W, double* zpart,
+                    int* np, const int* skip, hipStream_t s);
+int pmg_products(const fr_pmg* mg);
 fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const double* U, const double* R0,
                      double shift, const double* b, double* x, bool x_is_zero, const fr_gmres_opts& o,
                      fr_gmres_stats* stats, GmWork& W, hipStream_t s, bool plain_fallback = false,
-                     int* fell_back = nullptr);
+                     int* fell_back = nullptr, const fr_pmg* mg = nullptr);
 fr_status row_step_impl(const fr_disc* d, int scheme, double dt, double* U, const fr_solver_opts& o,
                         fr_step_stats* st, void* work, hipStream_t s);
 fr_status esdirk_step_impl(const fr_disc* d, int scheme, double dt, double* U, const fr_solver_opts& o,

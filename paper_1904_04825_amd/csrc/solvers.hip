@@ -291,12 +291,15 @@ fr_status lusgs_apply(const fr_disc* d, const void* factors, int prec, const Res
 // ---------------------------------------------------------------- FGMRES
 fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const double* U, const double* R0,
                      double shift, const double* b, double* x, bool x_is_zero, const fr_gmres_opts& o,
-                     fr_gmres_stats* stats, GmWork& W, hipStream_t s, bool plain_fallback, int* fell_back) {
+                     fr_gmres_stats* stats, GmWork& W, hipStream_t s, bool plain_fallback, int* fell_back,
+                     const fr_pmg* mg) {
   const size_t n = d->ndof;
   const int m = o.m;
   const int max_iters = o.max_iters > 0 ? o.max_iters : 50 * m;
   if (o.precond == FR_PC_LUSGS && (d->physics != FR_EULER || (d->nx & 1) || (d->ny & 1)))
     return set_error(FR_EINVAL, "LU-SGS preconditioner: Euler meshes with even nx and ny only");
+  if (o.precond == FR_PC_PMG && !pmg_compatible(d, mg))
+    return set_error(FR_EINVAL, "p-multigrid preconditioner: no matching coarse level (fr_pmg_factor)");
   fr_gmres_stats S{};
   double* nz = W.scal + 0;     // ||z||^2 or ||x||^2 for the JF epsilon
   double* beta2 = W.scal + 1;  // ||r||^2
@@ -369,6 +372,7 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
   // one step later) up to m = 32, CGS2 beyond
   const bool dcgs = dcgs2_supported(m);
   const bool lusgs = o.precond == FR_PC_LUSGS;
+  const bool pmg = o.precond == FR_PC_PMG;
   // small Euler meshes: the JF product of steps with at most kJfDotsMax basis vectors
   // also runs the first DCGS2 pass (one kernel fewer per such step)
   const int jf_dots = dcgs ? residual_dots_blocks(d) : 0;
@@ -398,7 +402,12 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
       // that reads them may write the first pass's rows meanwhile).
       double* zpart = W.partials + kPartZ;
       int np = 0;
-      if (lusgs) {
+      if (pmg) {
+        const GivensIn gv{W.st, dcgs ? dcgs2_norm_partials(W.partials) : W.partials, cgs_blocks(n), m, dcgs ? 1 : 0};
+        fr_status ps = j == 0 ? pmg_apply(d, factors, prec, mg, ra, vj, nullptr, nullptr, zj, W, zpart, &np, skip, s)
+                              : pmg_apply(d, factors, prec, mg, ra, W.w, &gv, vj, zj, W, zpart, &np, skip, s);
+        if (ps != FR_OK) return ps;
+      } else if (lusgs) {
         // LU-SGS: its passes leave their partial sums in the ||z||^2 slot in turn (each
         // read by the next kernel), the last one ||z_j||^2
         const GivensIn gv{W.st, dcgs ? dcgs2_norm_partials(W.partials) : W.partials, cgs_blocks(n), m, dcgs ? 1 : 0};
@@ -469,6 +478,7 @@ fr_status gmres_core(const fr_disc* d, const void* factors, int prec, const doub
   S.iters = fz.iters;
   S.residual_evals += fz.evals;
   if (lusgs) S.residual_evals += 2L * fz.steps;  // the two products of every LU-SGS application
+  if (pmg) S.residual_evals += (long)pmg_products(mg) * fz.steps;
   S.restarts = fz.restarts;
   S.r_final = fz.r_final;
   S.r_ref = fz.r_ref;
@@ -574,7 +584,7 @@ fr_status ptc_solve(const fr_disc* d, const double* cst, double omega_dt, double
   const int max_ptc = o.max_ptc > 0 ? o.max_ptc : 200;
   const int max_rej = o.max_reject > 0 ? o.max_reject : 30;
   int k = 0, rejects = 0;
-  fr_ejacobi pc{B.pc, o.precond_precision, 0.0};
+  fr_ejacobi pc{B.pc, o.precond_precision, 0.0, nullptr};
   while (nF > o.tol_nl * nF0) {
     if (!std::isfinite(nF)) return FR_ENAN;
     if (k >= max_ptc) return FR_NOTCONV;

@@ -77,6 +77,12 @@ __global__ void __launch_bounds__(kRedThreads) k_norm2_part(const double* __rest
   if (threadIdx.x == 0) partials[blockIdx.x] = acc;
 }
 
+hipError_t launch_norm2_parts(const double* x, size_t n, double* partials, int* nb, const int* skip, hipStream_t s) {
+  *nb = red_blocks(n);
+  hipLaunchKernelGGL(k_norm2_part, dim3(*nb), dim3(kRedThreads), 0, s, x, n, partials, skip);
+  return hipGetLastError();
+}
+
 hipError_t launch_norm2(const double* x, size_t n, double* partials, double* out, const int* skip,
                         hipStream_t s) {
   const int nb = red_blocks(n);

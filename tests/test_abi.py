@@ -74,16 +74,16 @@ def test_ctypes_layouts_match_the_c_compiler(tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
     src = tmp_path / "sz.c"
-    src.write_text('#include <stdio.h>\n#include "frjf.h"\nint main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+    src.write_text('#include <stdio.h>\n#include "frjf.h"\nint main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
                    'sizeof(fr_disc_desc),sizeof(fr_ejacobi),sizeof(fr_gmres_opts),sizeof(fr_gmres_stats),'
                    'sizeof(fr_solver_opts),sizeof(fr_step_stats),sizeof(fr_mlp),sizeof(fr_mlp_trainer),'
-                   'sizeof(fr_stage_log));}\n')
+                   'sizeof(fr_stage_log),sizeof(fr_pmg));}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [ctypes.sizeof(t) for t in (_lib.DiscDesc, _lib.EjacobiC, _lib.GmresOptsC, _lib.GmresStatsC,
                                        _lib.SolverOptsC, _lib.StepStatsC, _lib.MlpC, _lib.MlpTrainerC,
-                                       _lib.StageLogC)]
+                                       _lib.StageLogC, _lib.PmgC)]
     assert got == want
 
 

@@ -291,3 +291,34 @@ def test_ptc_learned_start(kind):
     assert used >= 3
     assert ptc_w <= ptc_p
     assert rel(to_np(Uw), to_np(Up)) <= 1e-6
+
+
+def test_group_training_matches_single():
+    """fr_mlp_train_group: three P4 networks (400 -> 256 -> 256 -> 100) trained together on
+    their own logs end bitwise where MlpTrainer.fit leaves each one alone (same batches,
+    same learning-rate schedule): master weights, Adam moments, bf16 weights, biases and
+    the losses read along the way.  Batch 1024 takes the split-K weight-gradient path."""
+    from paper_1904_04825_amd import MlpTrainer, fit_group
+    _, op, disc = setup(6, 5, 4, "rusanov")
+    logs = [_synthetic_log(disc, 3000, 20 + q)[0] for q in range(3)]
+    steps, batch = 25, 1024
+    single, group = [], []
+    for q in range(3):
+        a = MlpTrainer(disc, n_hidden=256, seed=30 + q)
+        b = MlpTrainer(disc, n_hidden=256, seed=30 + q)
+        for tr in (a, b):
+            tr.fit_stats(logs[q])
+        single.append((a, a.fit(logs[q], steps, batch, lr=2e-3, seed=50 + q, report_every=10)))
+        group.append(b)
+    out = fit_group(group, logs, steps, batch, lr=2e-3, seeds=[50, 51, 52], report_every=10)
+    torch.cuda.synchronize()
+    for q in range(3):
+        a, la = single[q]
+        b = group[q]
+        assert [s for s, _ in la] == [s for s, _ in out[q]]
+        assert [l for _, l in la] == [l for _, l in out[q]], (la, out[q])
+        assert la[-1][1] < 0.8 * la[0][1]
+        for name in ("master", "m", "v"):
+            assert torch.equal(getattr(a, name), getattr(b, name)), (q, name)
+        assert torch.equal(a.net.w, b.net.w) and torch.equal(a.net.b, b.net.b), q
+        assert a.c.t == b.c.t == steps
