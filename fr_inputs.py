@@ -142,6 +142,67 @@ class ShearLayer:
         return np.stack([rho, rho * u, rho * v, p / (self.gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
 
 
+def ogrid_nodes(nx: int, ny: int, r0: float = 0.5, r1: float = 100.0, first: float | None = None) -> np.ndarray:
+    """O-grid of straight-sided quads around the circle of radius r0 (a cylinder of diameter
+    2 r0) out to radius r1: i runs along the angle theta_i = -2 pi i / nx (clockwise, so the
+    map from (xi, eta) = (angle index, radius index) has a positive Jacobian), j along the
+    radius.  Radii r_j = r0 + first (s^j - 1)/(s - 1) with the ratio s > 1 chosen so that
+    r_ny = r1 (bisection); first = None spaces the radii evenly.  Column nx repeats column 0
+    exactly (the periodic seam); row 0 lies on the circle (the wall), row ny on the outer
+    circle (the far field)."""
+    if first is None:
+        r = r0 + (r1 - r0) * np.arange(ny + 1) / ny
+    else:
+        span = r1 - r0
+        if first * ny >= span:
+            raise ValueError("first layer too thick for a growing spacing")
+        lo, hi = 1.0 + 1e-12, 2.0
+        while first * (hi ** ny - 1.0) / (hi - 1.0) < span:
+            hi *= 2.0
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if first * (mid ** ny - 1.0) / (mid - 1.0) < span:
+                lo = mid
+            else:
+                hi = mid
+        s = 0.5 * (lo + hi)
+        r = r0 + first * (s ** np.arange(ny + 1) - 1.0) / (s - 1.0)
+        r[ny] = r1
+    th = -2.0 * math.pi * np.arange(nx + 1) / nx
+    c, sn = np.cos(th), np.sin(th)
+    c[nx], sn[nx] = c[0], sn[0]
+    nodes = np.empty((ny + 1, nx + 1, 2))
+    nodes[:, :, 0] = r[:, None] * c[None, :]
+    nodes[:, :, 1] = r[:, None] * sn[None, :]
+    return nodes
+
+
+@dataclass(frozen=True)
+class Cylinder:
+    """Laminar flow past a circular cylinder of diameter 1 (Section 5.2): Ma = 0.1 and
+    Re = 1200 on the diameter and the free stream; rho = 1, c = 1 (p = 1/gamma), u = Ma,
+    v = 0, mu = rho u D / Re.  The far-field state is the free stream."""
+    gamma: float = GAMMA
+    rgas: float = 1.0
+    mach: float = 0.1
+    reynolds: float = 1200.0
+    prandtl: float = 0.71
+
+    @property
+    def mu(self) -> float:
+        return self.mach / self.reynolds
+
+    def far_state(self) -> np.ndarray:
+        rho, u, p = 1.0, self.mach, 1.0 / self.gamma
+        return np.array([rho, rho * u, 0.0, p / (self.gamma - 1.0) + 0.5 * rho * u * u])
+
+    def conservative(self, x, y):
+        """The free stream everywhere (an impulsive start)."""
+        x = np.asarray(x, dtype=np.float64)
+        q = self.far_state()
+        return np.stack([np.full_like(x, q[v]) for v in range(4)])
+
+
 def random_vector(shape, seed: int, scale: float = 1.0) -> np.ndarray:
     """Seeded standard-normal array (GMRES right-hand sides, Krylov test vectors)."""
     return scale * np.random.default_rng(seed).standard_normal(size=shape)
@@ -155,11 +216,16 @@ WORKLOADS = {
     "vortex512_p4_perturbed": dict(nx=512, ny=512, p=4, x0=-5.0, y0=-5.0, lx=10.0, ly=10.0, perturb=0.1, seed=5),
     # the paper's own vortex study (Section 5.1)
     "vortex50_p6_paper": dict(nx=50, ny=50, p=6, x0=-10.0, y0=-10.0, lx=20.0, ly=20.0, perturb=0.0, seed=None),
+    # cylinder O-grids (Section 5.2 sizes: about 5,700 P3 elements, first layer 0.0033, far field at 100)
+    "cylinder120x48_p3": dict(ogrid=True, nx=120, ny=48, p=3, r0=0.5, r1=100.0, first=0.0033),
+    "cylinder480x192_p3": dict(ogrid=True, nx=480, ny=192, p=3, r0=0.5, r1=100.0, first=0.0033 / 4),
 }
 
 
 def workload_nodes(name: str) -> np.ndarray:
     w = WORKLOADS[name]
+    if w.get("ogrid"):
+        return ogrid_nodes(w["nx"], w["ny"], w["r0"], w["r1"], w["first"])
     if w["perturb"] > 0.0:
         return perturbed_nodes(w["nx"], w["ny"], w["x0"], w["y0"], w["lx"], w["ly"], w["perturb"], w["seed"])
     return uniform_nodes(w["nx"], w["ny"], w["x0"], w["y0"], w["lx"], w["ly"])

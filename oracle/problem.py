@@ -35,3 +35,11 @@ def l2_error(op, s_num, s_exact):
     vol = np.sum(wk[None, :] * Jk)
     d = np.asarray(s_num) - np.asarray(s_exact)
     return float(np.sqrt(np.sum(wk[None, :] * Jk * d * d) / vol))
+
+
+def make_ns_bc(nodes, P, gamma=1.4, flux="rusanov", rgas=1.0, mu=1e-4, prandtl=0.71, viscous="br1",
+               bc_south=None, bc_north=None, q_far=None):
+    from .ns_bc import NavierStokesBC
+    geo = Geometry(Mesh(nodes), Basis(P))
+    return NavierStokesBC(geo, gamma=gamma, flux=flux, rgas=rgas, mu=mu, prandtl=prandtl, viscous=viscous,
+                          bc_south=bc_south, bc_north=bc_north, q_far=q_far)
