@@ -57,7 +57,9 @@ typedef enum {
   FR_REJECTED = 4  /* PTC: too many rejected pseudo-steps */
 } fr_status;
 
-enum { FR_EULER = 0, FR_NS_BR1 = 1 };            /* physics */
+enum { FR_EULER = 0, FR_NS_BR1 = 1 };            /* physics (FR_NS_BR1: Navier-Stokes, viscous scheme below) */
+enum { FR_BR1 = 0, FR_BR2 = 1 };                 /* common gradient of the viscous flux */
+enum { FR_BC_PERIODIC = 0, FR_BC_WALL = 1, FR_BC_FARFIELD = 2 };  /* eta-boundaries */
 enum { FR_RUSANOV = 0, FR_ROE = 1 };             /* inviscid common flux */
 enum { FR_F64 = 0, FR_F32 = 1 };                 /* element-Jacobi precision */
 enum { FR_EPS_ABS = 0, FR_EPS_RMS = 1 };         /* JF perturbation rule */
@@ -77,12 +79,26 @@ typedef struct {
   double mu;        /* dynamic viscosity (FR_NS_BR1), constant */
   double prandtl;   /* Prandtl number (FR_NS_BR1), kappa = mu Cp / Pr */
   const double* d_nodes; /* device vertex array, see above; borrowed, must outlive the disc */
+  /* Navier-Stokes only; all zero = BR1 on a doubly periodic mesh. */
+  int viscous;      /* FR_BR1 (mean of the corrected gradients), or FR_BR2: each side's raw gradient
+                       plus its face lifting c_P (q^com - q) n |grad xi| with c_P = (P+1)(P+2)/2
+                       (Section 3, eq. com_grad_q and the lifting after it) */
+  int bc_south;     /* FR_BC_* of the eta = -1 side of element row 0 */
+  int bc_north;     /* FR_BC_* of the eta = +1 side of element row ny-1.  With either one not
+                       periodic, vertex row ny is the outer boundary, not a copy of row 0; xi stays
+                       periodic (column nx repeats column 0, e.g. the seam of an O-grid).
+                       FR_BC_WALL: no-slip adiabatic wall (outside trace (rho, -rho u, -rho v,
+                       E - rho|u|^2), pressure flux, viscous flux at zero velocity without heat flux);
+                       FR_BC_FARFIELD: outside trace q_far through the Riemann solver. */
+  double q_far[4];  /* far-field conservative state (rho, rho u, rho v, E) for FR_BC_FARFIELD */
 } fr_disc_desc;
 
 /* Create / destroy a discretisation handle.  Computes the Gauss points,
  * Lagrange extrapolation rows, differentiation matrix and Radau correction
  * derivatives of degree p (Section 3).  Returns FR_EINVAL for p outside 2..6
- * (2..4 for FR_NS_BR1), nx or ny < 2, physics/flux out of range or a null d_nodes. */
+ * (2..4 for FR_NS_BR1), nx or ny < 2, physics/flux out of range or a null d_nodes, and for
+ * a viscous scheme or boundary out of range, a non-periodic side with FR_EULER, or a
+ * far-field state with rho <= 0 or p <= 0. */
 fr_status fr_disc_create(const fr_disc_desc* desc, fr_disc** out);
 void fr_disc_destroy(fr_disc* disc);
 
@@ -426,6 +442,14 @@ fr_status fr_mlp_train_group(const fr_disc* disc, fr_mlp_trainer* trs, const fr_
  * h_a and h_c: s*s row-major (c unused for ESDIRK), h_b: s.  Returns the
  * number of stages s, or a negative status. */
 int fr_scheme_table(int kind, int scheme, double* h_a, double* h_c, double* h_b, double* h_gamma);
+
+/* Force of the fluid on the wall at the eta = -1 side of row 0 (bc_south = FR_BC_WALL),
+ * per unit depth: minus the momentum part of the common flux F^num on the wall faces
+ * (pressure minus viscous stress, the wall's reading of the boundary above), integrated
+ * with the Gauss weights along each face; the drag and lift coefficients of the cylinder
+ * case (Section 5.2) are h_force / (rho u^2 D / 2).  d_work: fr_workspace_bytes(disc,
+ * FR_WS_RESIDUAL, 0, 0) bytes.  Synchronises; FR_EINVAL without a wall. */
+fr_status fr_wall_force(const fr_disc* disc, const double* d_U, double* h_force, void* d_work, fr_stream stream);
 
 /* Last error message of this thread ("" if none). */
 const char* fr_last_error(void);

@@ -17,7 +17,8 @@ WS_RESIDUAL, WS_MATVEC, WS_GMRES, WS_STEP = 0, 1, 2, 3
 class DiscDesc(Structure):
     _fields_ = [("nx", c_int), ("ny", c_int), ("p", c_int), ("physics", c_int), ("flux", c_int),
                 ("gamma", c_double), ("rgas", c_double), ("mu", c_double), ("prandtl", c_double),
-                ("d_nodes", c_void_p)]
+                ("d_nodes", c_void_p), ("viscous", c_int), ("bc_south", c_int), ("bc_north", c_int),
+                ("q_far", c_double * 4)]
 
 
 class EjacobiC(Structure):
@@ -114,6 +115,7 @@ _SIGS = {
     "fr_mlp_group_work_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int]),
     "fr_mlp_train_group": (c_int, [c_void_p, POINTER(MlpTrainerC), POINTER(StageLogC), c_int, c_void_p, c_int, c_int,
                                    POINTER(ctypes.c_float), POINTER(c_double), c_void_p, c_void_p]),
+    "fr_wall_force": (c_int, [c_void_p, c_void_p, POINTER(c_double), c_void_p, c_void_p]),
     "fr_last_error": (ctypes.c_char_p, []),
 }
 

@@ -19,6 +19,10 @@ EPS_ABS, EPS_RMS = 0, 1
 PC_EJACOBI, PC_LUSGS, PC_PMG = 0, 1, 2
 _PHYS = {"euler": EULER, "ns": NS_BR1, "ns_br1": NS_BR1}
 _FLUX = {"rusanov": RUSANOV, "roe": ROE}
+BR1, BR2 = 0, 1
+BC_PERIODIC, BC_WALL, BC_FARFIELD = 0, 1, 2
+_VISC = {"br1": BR1, "br2": BR2}
+_BC = {None: BC_PERIODIC, "periodic": BC_PERIODIC, "wall": BC_WALL, "farfield": BC_FARFIELD}
 _PREC = {"f64": F64, "fp64": F64, "f32": F32, "fp32": F32}
 
 
@@ -123,10 +127,11 @@ class Pmg:
 
 
 class Disc:
-    """A periodic structured quad mesh with FR degree p, bound to one GPU."""
+    """A structured quad mesh with FR degree p, bound to one GPU: doubly periodic, or (with
+    Navier-Stokes) periodic in xi with a wall or far field on the eta = -1 / +1 sides."""
 
     def __init__(self, nodes, p, physics="euler", flux="rusanov", gamma=1.4, rgas=1.0, mu=0.0, prandtl=0.71,
-                 device="cuda"):
+                 device="cuda", viscous="br1", bc_south=None, bc_north=None, q_far=None):
         self.lib = L.lib()
         self.device = torch.device(device)
         self.nodes = torch.as_tensor(nodes, dtype=torch.float64).to(self.device).contiguous()
@@ -139,8 +144,11 @@ class Disc:
         self.physics = _PHYS.get(physics, physics)
         self.flux = _FLUX.get(flux, flux)
         self.gamma, self.rgas, self.mu, self.prandtl = gamma, rgas, mu, prandtl
+        self.viscous = _VISC.get(viscous, viscous)
+        self.bc_south, self.bc_north = _BC.get(bc_south, bc_south), _BC.get(bc_north, bc_north)
+        qf = (ctypes.c_double * 4)(*([0.0] * 4 if q_far is None else [float(x) for x in q_far]))
         desc = L.DiscDesc(self.nx, self.ny, p, self.physics, self.flux, gamma, rgas, mu, prandtl,
-                          self.nodes.data_ptr())
+                          self.nodes.data_ptr(), self.viscous, self.bc_south, self.bc_north, qf)
         h = ctypes.c_void_p()
         _check("fr_disc_create", self.lib.fr_disc_create(ctypes.byref(desc), ctypes.byref(h)))
         self.handle = h
@@ -356,6 +364,14 @@ class Disc:
         _check("fr_l2_error_vortex", self.lib.fr_l2_error_vortex(self.handle, _ptr(U), var, t, prm,
                                                                  ctypes.byref(err), _ptr(ws), _stream()))
         return err.value
+
+    def wall_force(self, U):
+        """(F_x, F_y): force of the fluid on the wall of the eta = -1 side (fr_wall_force)."""
+        self._vec(U, "U")
+        f = (ctypes.c_double * 2)()
+        ws = self.workspace(L.WS_RESIDUAL)
+        _check("fr_wall_force", self.lib.fr_wall_force(self.handle, _ptr(U), f, _ptr(ws), _stream()))
+        return f[0], f[1]
 
 
 # ---------------------------------------------------------------- learned warm start

@@ -76,8 +76,19 @@ fr_status fr_disc_create(const fr_disc_desc* desc, fr_disc** out) {
   CHECK(desc->gamma > 1.0 && desc->rgas > 0.0, "fr_disc_create: gamma must exceed 1 and R be positive");
   CHECK((size_t)desc->nx * desc->ny < (1u << 30), "fr_disc_create: mesh too large");
   if (desc->physics == FR_NS_BR1) {
-    CHECK(desc->p <= 4, "fr_disc_create: Navier-Stokes (BR1) supports p = 2, 3, 4");
+    CHECK(desc->p <= 4, "fr_disc_create: Navier-Stokes supports p = 2, 3, 4");
     CHECK(desc->mu >= 0.0 && desc->prandtl > 0.0, "fr_disc_create: mu >= 0 and Pr > 0 required");
+  }
+  CHECK(desc->viscous == FR_BR1 || desc->viscous == FR_BR2, "fr_disc_create: bad viscous scheme");
+  for (int b : {desc->bc_south, desc->bc_north}) {
+    CHECK(b == FR_BC_PERIODIC || b == FR_BC_WALL || b == FR_BC_FARFIELD, "fr_disc_create: bad boundary");
+    CHECK(b == FR_BC_PERIODIC || desc->physics == FR_NS_BR1,
+          "fr_disc_create: wall and far-field boundaries need the Navier-Stokes physics");
+  }
+  if (desc->bc_south == FR_BC_FARFIELD || desc->bc_north == FR_BC_FARFIELD) {
+    const double* q = desc->q_far;
+    const double pf = (desc->gamma - 1.0) * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) / q[0]);
+    CHECK(q[0] > 0.0 && pf > 0.0, "fr_disc_create: far-field state needs rho > 0 and p > 0");
   }
   fr_disc* d = new fr_disc{};
   d->nx = desc->nx;
@@ -89,6 +100,10 @@ fr_status fr_disc_create(const fr_disc_desc* desc, fr_disc** out) {
   d->nel = desc->nx * desc->ny;
   d->physics = desc->physics;
   d->flux = desc->flux;
+  d->visc = desc->viscous;
+  d->bc_south = desc->bc_south;
+  d->bc_north = desc->bc_north;
+  for (int v = 0; v < 4; ++v) d->qfar[v] = desc->q_far[v];
   d->ndof = (size_t)4 * d->nel * d->np;
   d->phys.gamma = desc->gamma;
   d->phys.rgas = desc->rgas;
@@ -385,6 +400,25 @@ fr_status fr_bdf2_step(const fr_disc* d, double dt, const double* Unm1, const do
   CHECK(Unp1 != Un && Unp1 != Unm1, "fr_bdf2_step: output aliases an input");
   *st = fr_step_stats{};
   return bdf2_step_impl(d, dt, Unm1, Un, Unp1, *o, st, work, S(s));
+}
+
+fr_status fr_wall_force(const fr_disc* d, const double* U, double* h_force, void* work, fr_stream s) {
+  clear_error();
+  CHECK(d && U && h_force && work, "fr_wall_force: null argument");
+  CHECK(d->physics == FR_NS_BR1 && d->bc_south == FR_BC_WALL, "fr_wall_force: no wall on the eta = -1 side");
+  double* part = (double*)work;
+  FR_HIP(launch_ns_wall_flux(d, U, part, S(s)));
+  std::vector<double> h(2 * (size_t)d->nx);
+  FR_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, S(s)));
+  FR_HIP(hipStreamSynchronize(S(s)));
+  double fx = 0.0, fy = 0.0;
+  for (int e = 0; e < d->nx; ++e) {
+    fx += h[2 * e];
+    fy += h[2 * e + 1];
+  }
+  h_force[0] = -fx;
+  h_force[1] = -fy;
+  return FR_OK;
 }
 
 fr_status fr_l2_error_vortex(const fr_disc* d, const double* U, int var, double t, const double* h_params,

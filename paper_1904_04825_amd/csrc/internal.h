@@ -37,6 +37,8 @@ struct Phys {
 struct fr_disc {
   int nx, ny, p, n, np, nb, nel;
   int physics, flux;
+  int visc, bc_south, bc_north;  // Navier-Stokes: FR_BR1 / FR_BR2, FR_BC_* of the eta-sides
+  double qfar[4];                // far-field state
   size_t ndof;
   frjf::Phys phys;
   frjf::Basis basis;
@@ -149,6 +151,8 @@ hipError_t launch_ejacobi_solve(const fr_disc* d, const void* factors, int preci
                                 const int* skip, hipStream_t s);
 
 hipError_t launch_solution_points(const fr_disc* d, double* xy, hipStream_t s);
+// force of the fluid on the wall (ns.hip): per element of row 0, its wall face's momentum flux
+hipError_t launch_ns_wall_flux(const fr_disc* d, const double* U, double* part, hipStream_t s);
 hipError_t launch_l2_vortex(const fr_disc* d, const double* U, int var, double t, const double* prm,
                             double* partials, double* out, hipStream_t s);
 

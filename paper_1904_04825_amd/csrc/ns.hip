@@ -18,6 +18,19 @@
 // grad_nbr = grad_nbr(base) + c_f (q^com - q^com(base)), with c_f computed
 // from the neighbour's metrics.
 //
+// BR2 (Section 3, eq. com_grad_q and the lifting after it): an element's gradient on a
+// face is the raw gradient of its solution polynomial (no corrections), extrapolated to
+// the face, plus the lifting r = c_P (q^com - q_local) S_out / |J| of that face alone,
+// c_P = (P+1)(P+2)/2 (the paper's g'(+-1)), S_out the outward area-weighted normal and
+// |J| at the face point; the common gradient averages the two sides'.  The gradient
+// inside the element stays the FR-corrected one.
+// Boundaries (the eta = -1 side of row 0, the eta = +1 side of row ny-1; xi periodic):
+//   far field: outside trace q_far, Riemann-solver flux, common state (q + q_far)/2;
+//   wall (no slip, adiabatic): outside trace (rho, -rho u, -rho v, E - rho |u|^2), so the
+//   common state has zero velocity and the inside internal energy; pressure flux
+//   (0, p S_x, p S_y, 0); viscous flux at the common state, energy component zero.
+// A boundary side's common gradient is its own face gradient.
+//
 // All three kernels run the same per-slot steps below; a slot is one element
 // evaluation whose threads cover its solution points or face points.
 #include <algorithm>
@@ -50,8 +63,31 @@ struct NSArgs {
   int eps_mode;
   const double* nodes;
   int nx, ny, nel;
+  int visc;      // FR_BR1 or FR_BR2
+  int bcS, bcN;  // FR_BC_* of the eta = -1 side of row 0 and the eta = +1 side of row ny-1
+  double qfar[4];
   Phys ph;
 };
+
+// boundary condition of face f (W, E, S, N) of an element in row ey (0: interior face)
+__device__ __forceinline__ int face_bc(const NSArgs& a, int f, int ey) {
+  if (f == 2 && ey == 0) return a.bcS;
+  if (f == 3 && ey == a.ny - 1) return a.bcN;
+  return FR_BC_PERIODIC;
+}
+
+// outside trace of a boundary face
+__device__ __forceinline__ void ghost_state(int bc, const double qo[4], const double qfar[4], double qn[4]) {
+  if (bc == FR_BC_WALL) {
+    qn[0] = qo[0];
+    qn[1] = -qo[1];
+    qn[2] = -qo[2];
+    qn[3] = qo[3] - (qo[1] * qo[1] + qo[2] * qo[2]) / qo[0];
+  } else {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) qn[v] = qfar[v];
+  }
+}
 
 // viscous flux f_v, g_v of Section 2 (2D) from q and its gradient
 __device__ __forceinline__ void viscous_fluxes(const double q[4], const double qx[4], const double qy[4],
@@ -111,9 +147,11 @@ template <int P>
 struct ElemGeo {
   static constexpr int n = P + 1, Np = n * n;
   double met[Np][5];      // x_xi, x_eta, y_xi, y_eta, 1/|J|
-  double S[4][2];         // area-weighted face normals
+  double S[4][2];         // area-weighted face normals (+xi / +eta)
+  double Jf[4][n];        // |J| at the face points (BR2 lifting)
   double nb[4][4][n];     // neighbours' solution traces on the shared faces
-  int nbr[4];             // neighbour element indices
+  int nbr[4];             // neighbour element indices (-1 on a boundary side)
+  int bc[4];              // FR_BC_* of each face
 };
 
 __device__ __forceinline__ void face_neighbour(int f, int ex, int ey, int nx, int ny, int* nex, int* ney) {
@@ -152,46 +190,66 @@ __device__ void load_elem_geo(ElemGeo<P>& g, const NSArgs& a, const Basis& B, in
   }
   if (t < 4) {
     double Sx, Sy;
+    const int bc = face_bc(a, t, ey);
     if (t == 0) xi_face_normal(a.nodes, a.nx, ex, ey, &Sx, &Sy);
     else if (t == 1) xi_face_normal(a.nodes, a.nx, (ex + 1 == a.nx) ? 0 : ex + 1, ey, &Sx, &Sy);
     else if (t == 2) eta_face_normal(a.nodes, a.nx, ex, ey, &Sx, &Sy);
-    else eta_face_normal(a.nodes, a.nx, ex, (ey + 1 == a.ny) ? 0 : ey + 1, &Sx, &Sy);
+    else eta_face_normal(a.nodes, a.nx, ex, (ey + 1 == a.ny && bc == FR_BC_PERIODIC) ? 0 : ey + 1, &Sx, &Sy);
     g.S[t][0] = Sx;
     g.S[t][1] = Sy;
     int nex, ney;
     face_neighbour(t, ex, ey, a.nx, a.ny, &nex, &ney);
-    g.nbr[t] = ney * a.nx + nex;
+    g.nbr[t] = bc == FR_BC_PERIODIC ? ney * a.nx + nex : -1;
+    g.bc[t] = bc;
   }
   for (int idx = t; idx < 4 * n; idx += nthreads) {
     const int f = idx / n, j = idx % n;
+    double c[8];
+    load_corners(a.nodes, a.nx, ex, ey, c);
+    const double xi = f == 0 ? -1.0 : (f == 1 ? 1.0 : B.x[j]);
+    const double eta = f == 2 ? -1.0 : (f == 3 ? 1.0 : B.x[j]);
+    g.Jf[f][j] = bilinear_metric(c, xi, eta).J;
+    if (face_bc(a, f, ey) != FR_BC_PERIODIC) continue;  // outside trace from the own one, per slot
     int nex, ney;
     face_neighbour(f, ex, ey, a.nx, a.ny, &nex, &ney);
     const size_t ne = (size_t)ney * a.nx + nex;
     const double* lo = (f == 0 || f == 2) ? B.lp : B.lm;
     double qn[4] = {0, 0, 0, 0};
-    for (int c = 0; c < n; ++c) {
-      const int kk = (f < 2) ? j * n + c : c * n + j;
+    for (int c2 = 0; c2 < n; ++c2) {
+      const int kk = (f < 2) ? j * n + c2 : c2 * n + j;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) qn[v] = fma(lo[c], ns_state<MODE>(a, ((size_t)v * nel + ne) * Np + kk, e), qn[v]);
+      for (int v = 0; v < 4; ++v) qn[v] = fma(lo[c2], ns_state<MODE>(a, ((size_t)v * nel + ne) * Np + kk, e), qn[v]);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) g.nb[f][v][j] = qn[v];
   }
 }
 
-// step 2: own traces and common solution on the faces
+// step 2: own traces and common solution on the faces (a boundary side's outside trace
+// from the own one)
 template <int P>
-__device__ void slot_traces(Slot<P>& s, const ElemGeo<P>& g, const Basis& B, int t) {
+__device__ void slot_traces(Slot<P>& s, const ElemGeo<P>& g, const Basis& B, const double qfar[4], int t) {
   constexpr int n = P + 1;
   for (int idx = t; idx < 4 * n; idx += NS<P>::ST) {
     const int f = idx / n, j = idx % n;
     const double* lw = (f == 0 || f == 2) ? B.lm : B.lp;
+    double qo[4], qn[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      double qo = 0.0;
-      for (int c = 0; c < n; ++c) qo = fma(lw[c], s.q[v][(f < 2) ? j * n + c : c * n + j], qo);
-      s.tr[f][v][j] = qo;
-      s.qc[f][v][j] = 0.5 * (qo + g.nb[f][v][j]);
+      double x = 0.0;
+      for (int c = 0; c < n; ++c) x = fma(lw[c], s.q[v][(f < 2) ? j * n + c : c * n + j], x);
+      qo[v] = x;
+    }
+    if (g.bc[f] == FR_BC_PERIODIC) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) qn[v] = g.nb[f][v][j];
+    } else {
+      ghost_state(g.bc[f], qo, qfar, qn);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      s.tr[f][v][j] = qo[v];
+      s.qc[f][v][j] = 0.5 * (qo[v] + qn[v]);
     }
   }
 }
@@ -220,17 +278,38 @@ __device__ void slot_gradient(Slot<P>& s, const ElemGeo<P>& g, const Basis& B, i
   }
 }
 
-// own face gradient of face point (f, j), variable v
+// own face gradient of face point (f, j), variable v: BR1 the corrected gradient
+// extrapolated; BR2 the raw gradient extrapolated plus the face's lifting
 template <int P>
-__device__ __forceinline__ void own_face_gradient(const Slot<P>& s, const Basis& B, int f, int j, int v, double* gx,
-                                                  double* gy) {
+__device__ __forceinline__ void own_face_gradient(const Slot<P>& s, const ElemGeo<P>& g, const Basis& B, int visc,
+                                                  int f, int j, int v, double* gx, double* gy) {
   constexpr int n = P + 1;
   const double* lw = (f == 0 || f == 2) ? B.lm : B.lp;
   double x = 0.0, y = 0.0;
-  for (int c = 0; c < n; ++c) {
-    const int kk = (f < 2) ? j * n + c : c * n + j;
-    x = fma(lw[c], s.qx[v][kk], x);
-    y = fma(lw[c], s.qy[v][kk], y);
+  if (visc == FR_BR1) {
+    for (int c = 0; c < n; ++c) {
+      const int kk = (f < 2) ? j * n + c : c * n + j;
+      x = fma(lw[c], s.qx[v][kk], x);
+      y = fma(lw[c], s.qy[v][kk], y);
+    }
+  } else {
+    for (int c = 0; c < n; ++c) {
+      const int kk = (f < 2) ? j * n + c : c * n + j;
+      const int ia = kk % n, ib = kk / n;
+      double dxi = 0.0, deta = 0.0;
+      for (int d = 0; d < n; ++d) {
+        dxi = fma(B.D[ia][d], s.q[v][ib * n + d], dxi);
+        deta = fma(B.D[ib][d], s.q[v][d * n + ia], deta);
+      }
+      const double* m = g.met[kk];
+      x = fma(lw[c], (m[3] * dxi - m[2] * deta) * m[4], x);
+      y = fma(lw[c], (-m[1] * dxi + m[0] * deta) * m[4], y);
+    }
+    constexpr double cP = 0.5 * (P + 1) * (P + 2);
+    const double sg = (f == 0 || f == 2) ? -1.0 : 1.0;  // outward normal = sg S
+    const double lift = cP * (s.qc[f][v][j] - s.tr[f][v][j]) / g.Jf[f][j];
+    x = fma(lift * sg, g.S[f][0], x);
+    y = fma(lift * sg, g.S[f][1], y);
   }
   *gx = x;
   *gy = y;
@@ -260,9 +339,39 @@ __device__ void slot_fluxes(Slot<P>& s, const ElemGeo<P>& g, const Phys& ph, int
   }
 }
 
+// common flux F^num (inviscid minus viscous, along S) of face point (f, j) from the own
+// trace qo, the common state qc and the common gradient (gx, gy)
+template <int FLUX>
+__device__ __forceinline__ void face_common_flux(int f, int bc, const double qo[4], const double qnb[4],
+                                                 const double qfar[4], const double qc[4], const double gx[4],
+                                                 const double gy[4], double Sx, double Sy, const Phys& ph,
+                                                 double Fn[4]) {
+  double Fi[4], fv[4], gv[4];
+  if (bc == FR_BC_WALL) {
+    const double p = pressure_of(qo, ph.gamma);
+    Fi[0] = 0.0;
+    Fi[1] = p * Sx;
+    Fi[2] = p * Sy;
+    Fi[3] = 0.0;
+  } else {
+    const double* qn = bc == FR_BC_FARFIELD ? qfar : qnb;
+    if (f == 0 || f == 2)
+      common_flux<FLUX>(qn, qo, Sx, Sy, ph.gamma, Fi);
+    else
+      common_flux<FLUX>(qo, qn, Sx, Sy, ph.gamma, Fi);
+  }
+  viscous_fluxes(qc, gx, gy, ph, fv, gv);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double vis = (bc == FR_BC_WALL && v == 3) ? 0.0 : fv[v] * Sx + gv[v] * Sy;
+    Fn[v] = Fi[v] - vis;
+  }
+}
+
 // step 6: common fluxes and jumps on the faces (gc holds the common gradient)
 template <int P, int FLUX>
-__device__ void slot_face_fluxes(Slot<P>& s, const ElemGeo<P>& g, const Basis& B, const Phys& ph, int t) {
+__device__ void slot_face_fluxes(Slot<P>& s, const ElemGeo<P>& g, const Basis& B, const Phys& ph,
+                                 const double qfar[4], int t) {
   constexpr int n = P + 1;
   for (int idx = t; idx < 4 * n; idx += NS<P>::ST) {
     const int f = idx / n, j = idx % n;
@@ -279,14 +388,10 @@ __device__ void slot_face_fluxes(Slot<P>& s, const ElemGeo<P>& g, const Basis& B
       for (int c = 0; c < n; ++c) fl = fma(lw[c], (f < 2) ? s.F[v][j * n + c] : s.G[v][c * n + j], fl);
       Fl[v] = fl;
     }
-    double Fi[4], fv[4], gv[4];
-    if (f == 0 || f == 2)
-      common_flux<FLUX>(qn, qo, g.S[f][0], g.S[f][1], ph.gamma, Fi);
-    else
-      common_flux<FLUX>(qo, qn, g.S[f][0], g.S[f][1], ph.gamma, Fi);
-    viscous_fluxes(qc, gx, gy, ph, fv, gv);
+    double Fn[4];
+    face_common_flux<FLUX>(f, g.bc[f], qo, qn, qfar, qc, gx, gy, g.S[f][0], g.S[f][1], ph, Fn);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) s.jmp[f][v][j] = (Fi[v] - (fv[v] * g.S[f][0] + gv[v] * g.S[f][1])) - Fl[v];
+    for (int v = 0; v < 4; ++v) s.jmp[f][v][j] = Fn[v] - Fl[v];
   }
 }
 
@@ -340,7 +445,7 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_grad(const NSArgs a, const Bas
       for (int v = 0; v < 4; ++v) S[sl].q[v][k] = ns_state<MODE>(a, ((size_t)v * nel + el) * Np + k, e);
   }
   __syncthreads();
-  if (live) slot_traces<P>(S[sl], Gm[sl], B, t);
+  if (live) slot_traces<P>(S[sl], Gm[sl], B, a.qfar, t);
   __syncthreads();
   if (live) slot_gradient<P>(S[sl], Gm[sl], B, t);
   __syncthreads();
@@ -350,7 +455,7 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_grad(const NSArgs a, const Bas
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         double gx, gy;
-        own_face_gradient<P>(S[sl], B, f, j, v, &gx, &gy);
+        own_face_gradient<P>(S[sl], Gm[sl], B, a.visc, f, j, v, &gx, &gy);
         const size_t gi = grad_index(el, f, v, j, n);
         a.grad[gi] = gx;
         a.grad[gi + 1] = gy;
@@ -391,7 +496,7 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_res(const NSArgs a, const Basi
       for (int v = 0; v < 4; ++v) S[sl].q[v][k] = ns_state<MODE>(a, ((size_t)v * nel + el) * Np + k, e);
   }
   __syncthreads();
-  if (live) slot_traces<P>(S[sl], Gm[sl], B, t);
+  if (live) slot_traces<P>(S[sl], Gm[sl], B, a.qfar, t);
   __syncthreads();
   if (live) slot_gradient<P>(S[sl], Gm[sl], B, t);
   __syncthreads();
@@ -403,16 +508,21 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_res(const NSArgs a, const Basi
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         double gx, gy;
-        own_face_gradient<P>(S[sl], B, f, j, v, &gx, &gy);
-        const size_t gi = grad_index(ne, o, v, j, n);
-        S[sl].gc[f][v][j][0] = 0.5 * (gx + a.grad[gi]);
-        S[sl].gc[f][v][j][1] = 0.5 * (gy + a.grad[gi + 1]);
+        own_face_gradient<P>(S[sl], Gm[sl], B, a.visc, f, j, v, &gx, &gy);
+        if (ne < 0) {  // boundary side: its own face gradient
+          S[sl].gc[f][v][j][0] = gx;
+          S[sl].gc[f][v][j][1] = gy;
+        } else {
+          const size_t gi = grad_index(ne, o, v, j, n);
+          S[sl].gc[f][v][j][0] = 0.5 * (gx + a.grad[gi]);
+          S[sl].gc[f][v][j][1] = 0.5 * (gy + a.grad[gi + 1]);
+        }
       }
     }
   __syncthreads();
   if (live) slot_fluxes<P>(S[sl], Gm[sl], a.ph, t);
   __syncthreads();
-  if (live) slot_face_fluxes<P, FLUX>(S[sl], Gm[sl], B, a.ph, t);
+  if (live) slot_face_fluxes<P, FLUX>(S[sl], Gm[sl], B, a.ph, a.qfar, t);
   __syncthreads();
   if (live)
     for (int k = t; k < Np; k += ST)
@@ -460,6 +570,7 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const 
     const int f = idx / n, j = idx % n;
     const int o = f ^ 1;
     const int ne = Gm.nbr[f];
+    if (ne < 0) continue;  // boundary side: no neighbour
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const size_t gi = grad_index(ne, o, v, j, n);
@@ -468,21 +579,33 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const 
     }
     double c8[8];
     load_corners(a.nodes, a.nx, ne % a.nx, ne / a.nx, c8);
-    // neighbour face o: E(1) -> its xi = +1 lifted with g_R'; W(0) -> xi = -1 with g_L'
-    // (likewise N(3)/S(2) in eta); the neighbour's face values extrapolate with l(+-1)
     double cx = 0.0, cy = 0.0;
-    for (int c = 0; c < n; ++c) {
-      const bool xi_dir = (o < 2);
-      const int ia = xi_dir ? c : j, ib = xi_dir ? j : c;
-      const Metric m = bilinear_metric(c8, B.x[ia], B.x[ib]);
-      const double lift = (o == 0 || o == 2) ? B.gL[c] : B.gR[c];
-      const double ext = (o == 0 || o == 2) ? B.lm[c] : B.lp[c];
-      if (xi_dir) {
-        cx += ext * lift * m.yeta / m.J;
-        cy += ext * lift * (-m.xeta) / m.J;
-      } else {
-        cx += ext * lift * (-m.yxi) / m.J;
-        cy += ext * lift * m.xxi / m.J;
+    if (a.visc == FR_BR2) {
+      // the neighbour's lifting c_P (q^com - q_nbr) S_out,nbr / |J_nbr| on the shared face;
+      // its outward normal there is +S on this element's W and S faces, -S on E and N
+      const double xi = o == 0 ? -1.0 : (o == 1 ? 1.0 : B.x[j]);
+      const double eta = o == 2 ? -1.0 : (o == 3 ? 1.0 : B.x[j]);
+      const double Jn = bilinear_metric(c8, xi, eta).J;
+      const double sg = (f == 0 || f == 2) ? 1.0 : -1.0;
+      constexpr double cP = 0.5 * (P + 1) * (P + 2);
+      cx = cP * sg * Gm.S[f][0] / Jn;
+      cy = cP * sg * Gm.S[f][1] / Jn;
+    } else {
+      // neighbour face o: E(1) -> its xi = +1 lifted with g_R'; W(0) -> xi = -1 with g_L'
+      // (likewise N(3)/S(2) in eta); the neighbour's face values extrapolate with l(+-1)
+      for (int c = 0; c < n; ++c) {
+        const bool xi_dir = (o < 2);
+        const int ia = xi_dir ? c : j, ib = xi_dir ? j : c;
+        const Metric m = bilinear_metric(c8, B.x[ia], B.x[ib]);
+        const double lift = (o == 0 || o == 2) ? B.gL[c] : B.gR[c];
+        const double ext = (o == 0 || o == 2) ? B.lm[c] : B.lp[c];
+        if (xi_dir) {
+          cx += ext * lift * m.yeta / m.J;
+          cy += ext * lift * (-m.xeta) / m.J;
+        } else {
+          cx += ext * lift * (-m.yxi) / m.J;
+          cy += ext * lift * m.xxi / m.J;
+        }
       }
     }
     cg[f][j][0] = cx;
@@ -503,7 +626,7 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const 
 #pragma unroll
         for (int v = 0; v < 4; ++v) S[sl].q[v][k] = q0[v][k] + ((v == pv && k == pk) ? delta : 0.0);
     __syncthreads();
-    if (active) slot_traces<P>(S[sl], Gm, B, t);
+    if (active) slot_traces<P>(S[sl], Gm, B, a.qfar, t);
     __syncthreads();
     if (active) slot_gradient<P>(S[sl], Gm, B, t);
     if (base && active)
@@ -519,7 +642,12 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const 
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           double gx, gy;
-          own_face_gradient<P>(S[sl], B, f, jj, v, &gx, &gy);
+          own_face_gradient<P>(S[sl], Gm, B, a.visc, f, jj, v, &gx, &gy);
+          if (Gm.nbr[f] < 0) {  // boundary side: its own face gradient
+            S[sl].gc[f][v][jj][0] = gx;
+            S[sl].gc[f][v][jj][1] = gy;
+            continue;
+          }
           const double dqc = S[sl].qc[f][v][jj] - qc0[f][v][jj];
           const double nx_ = gnb[f][v][jj][0] + cg[f][jj][0] * dqc;
           const double ny_ = gnb[f][v][jj][1] + cg[f][jj][1] * dqc;
@@ -530,7 +658,7 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const 
     __syncthreads();
     if (active) slot_fluxes<P>(S[sl], Gm, a.ph, t);
     __syncthreads();
-    if (active) slot_face_fluxes<P, FLUX>(S[sl], Gm, B, a.ph, t);
+    if (active) slot_face_fluxes<P, FLUX>(S[sl], Gm, B, a.ph, a.qfar, t);
     __syncthreads();
     if (active)
       for (int k = t; k < Np; k += ST)
@@ -551,6 +679,51 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const 
   for (int idx = tid; idx < Nb * Nb; idx += NT) out[idx] = A[(idx / Nb) * LD + idx % Nb];
 }
 
+// ---------------------------------------------------------------- wall momentum flux
+// One slot per element of row 0 (its eta = -1 side a wall): the element's own steps up to
+// its face gradients, then sum_j w_j F^num(j) of the momentum on the wall face (S per unit
+// reference length) into part[2 ex], part[2 ex + 1].  A boundary side needs no neighbour
+// gradient, so no gradient traces are formed.
+template <int P, int FLUX>
+__global__ void __launch_bounds__(NS<P>::NT) k_ns_wall_flux(const NSArgs a, const Basis B, double* part) {
+  using C = NS<P>;
+  constexpr int n = C::n, Np = C::Np, ST = C::ST, SL = C::SLOTS;
+  __shared__ Slot<P> S[SL];
+  __shared__ ElemGeo<P> Gm[SL];
+  const int sl = threadIdx.x / ST, t = threadIdx.x % ST;
+  const int el = blockIdx.x * SL + sl;  // row 0: element index = ex
+  const bool live = sl < SL && el < a.nx;
+  const size_t nel = (size_t)a.nel;
+  if (live) {
+    load_elem_geo<P, 0>(Gm[sl], a, B, el, 0, 0.0, t, ST);
+    for (int k = t; k < Np; k += ST)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) S[sl].q[v][k] = a.U[((size_t)v * nel + el) * Np + k];
+  }
+  __syncthreads();
+  if (live) slot_traces<P>(S[sl], Gm[sl], B, a.qfar, t);
+  __syncthreads();
+  if (live) slot_gradient<P>(S[sl], Gm[sl], B, t);
+  __syncthreads();
+  if (live && t == 0) {
+    double fx = 0.0, fy = 0.0;
+    for (int j = 0; j < n; ++j) {
+      double qo[4], qc[4], gx[4], gy[4], Fn[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        qo[v] = S[sl].tr[2][v][j];
+        qc[v] = S[sl].qc[2][v][j];
+        own_face_gradient<P>(S[sl], Gm[sl], B, a.visc, 2, j, v, &gx[v], &gy[v]);
+      }
+      face_common_flux<FLUX>(2, FR_BC_WALL, qo, qo, a.qfar, qc, gx, gy, Gm[sl].S[2][0], Gm[sl].S[2][1], a.ph, Fn);
+      fx = fma(B.w[j], Fn[1], fx);
+      fy = fma(B.w[j], Fn[2], fy);
+    }
+    part[2 * el] = fx;
+    part[2 * el + 1] = fy;
+  }
+}
+
 // ---------------------------------------------------------------- launchers
 static NSArgs ns_args(const fr_disc* d, const ResArgs& r) {
   NSArgs a{};
@@ -569,6 +742,10 @@ static NSArgs ns_args(const fr_disc* d, const ResArgs& r) {
   a.nx = d->nx;
   a.ny = d->ny;
   a.nel = d->nel;
+  a.visc = d->visc;
+  a.bcS = d->bc_south;
+  a.bcN = d->bc_north;
+  for (int v = 0; v < 4; ++v) a.qfar[v] = d->qfar[v];
   a.ph = d->phys;
   return a;
 }
@@ -602,6 +779,27 @@ hipError_t launch_ns_residual(const fr_disc* d, int mode, const ResArgs& r, hipS
     case 2: return ns_res_p<2>(d, mode, a, s);
     case 3: return ns_res_p<3>(d, mode, a, s);
     case 4: return ns_res_p<4>(d, mode, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int P, int FLUX>
+static hipError_t ns_wall_pf(const fr_disc* d, const NSArgs& a, double* part, hipStream_t s) {
+  using C = NS<P>;
+  hipLaunchKernelGGL((k_ns_wall_flux<P, FLUX>), dim3((d->nx + C::SLOTS - 1) / C::SLOTS), dim3(C::NT), 0, s, a,
+                     d->basis, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_ns_wall_flux(const fr_disc* d, const double* U, double* part, hipStream_t s) {
+  ResArgs r{};
+  r.U = U;
+  const NSArgs a = ns_args(d, r);
+  const bool roe = d->flux == FR_ROE;
+  switch (d->p) {
+    case 2: return roe ? ns_wall_pf<2, 1>(d, a, part, s) : ns_wall_pf<2, 0>(d, a, part, s);
+    case 3: return roe ? ns_wall_pf<3, 1>(d, a, part, s) : ns_wall_pf<3, 0>(d, a, part, s);
+    case 4: return roe ? ns_wall_pf<4, 1>(d, a, part, s) : ns_wall_pf<4, 0>(d, a, part, s);
   }
   return hipErrorInvalidValue;
 }

@@ -38,24 +38,30 @@ def rel(a, b):
 def _rebuilt(op, nodes):
     """The same oracle operator on another vertex array."""
     from oracle.ns import NavierStokesFR
-    from oracle.problem import make_ns
+    from oracle.ns_bc import NavierStokesBC
+    from oracle.problem import make_ns, make_ns_bc
     P = op.n - 1
+    if isinstance(op, NavierStokesBC):
+        return make_ns_bc(nodes, P, gamma=op.gamma, flux=op.flux, rgas=op.rgas, mu=op.mu, prandtl=op.prandtl,
+                          viscous=op.viscous, bc_south=op.bc["S"], bc_north=op.bc["N"], q_far=op.q_far)
     if isinstance(op, NavierStokesFR):
         return make_ns(nodes, P, gamma=op.gamma, flux=op.flux, rgas=op.rgas, mu=op.mu, prandtl=op.prandtl)
     return make_euler(nodes, P, gamma=op.gamma, flux=op.flux)
 
 
-def ulp_nodes(nodes, rng):
+def ulp_nodes(nodes, rng, periodic_y=True):
     """Every vertex coordinate moved by one unit in its last place (seeded random
-    direction), the periodic copies kept exact copies shifted by the box lengths."""
+    direction), the periodic copies kept exact copies shifted by the box lengths (in y
+    only on doubly periodic meshes)."""
     nd = np.nextafter(nodes, rng.choice([-np.inf, np.inf], size=np.shape(nodes)))
     ny, nx = nd.shape[0] - 1, nd.shape[1] - 1
     lx = nodes[0, nx, 0] - nodes[0, 0, 0]
     ly = nodes[ny, 0, 1] - nodes[0, 0, 1]
     nd[:, nx, 0] = nd[:, 0, 0] + lx
     nd[:, nx, 1] = nd[:, 0, 1]
-    nd[ny, :, 1] = nd[0, :, 1] + ly
-    nd[ny, :, 0] = nd[0, :, 0]
+    if periodic_y:
+        nd[ny, :, 1] = nd[0, :, 1] + ly
+        nd[ny, :, 0] = nd[0, :, 0]
     return nd
 
 
@@ -70,7 +76,8 @@ def rounding_floor(op, U, R, trials=2, seed=0):
     worst = 0.0
     for _ in range(trials):
         Up = np.nextafter(U, rng.choice([-np.inf, np.inf], size=np.shape(U)))
-        opp = _rebuilt(op, ulp_nodes(op.mesh.nodes, rng))
+        bounded = getattr(op, "bc", {}).get("S") is not None or getattr(op, "bc", {}).get("N") is not None
+        opp = _rebuilt(op, ulp_nodes(op.mesh.nodes, rng, periodic_y=not bounded))
         worst = max(worst, rel(opp.residual(Up), R))
     return worst
 

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_function():
 
 def test_binding_struct_sizes_match_header_layout():
     from paper_1904_04825_amd import _lib
-    assert ctypes.sizeof(_lib.DiscDesc) == 5 * 4 + 4 + 4 * 8 + 8
+    assert ctypes.sizeof(_lib.DiscDesc) == 5 * 4 + 4 + 4 * 8 + 8 + 3 * 4 + 4 + 4 * 8
     assert ctypes.sizeof(_lib.GmresOptsC) == 2 * 4 + 3 * 8 + 8
     assert ctypes.sizeof(_lib.SolverOptsC) == ctypes.sizeof(_lib.GmresOptsC) + 3 * 8 + 4 * 4 + 4 * 8
     assert ctypes.sizeof(_lib.StepStatsC) == 7 * 4 + 4 + 8 + 8
@@ -95,7 +95,10 @@ def test_invalid_arguments_are_rejected_before_any_device_work():
     nodes = ctypes.c_double(0.0)
     good = dict(nx=4, ny=4, p=3, physics=0, flux=0, gamma=1.4, rgas=1.0, mu=0.0, prandtl=0.71,
                 d_nodes=ctypes.cast(ctypes.pointer(nodes), ctypes.c_void_p))
-    cases = [({"p": 7}, "p must be"), ({"p": 1}, "p must be"), ({"p": 5, "physics": 1}, "Navier-Stokes (BR1) supports"),
+    cases = [({"p": 7}, "p must be"), ({"p": 1}, "p must be"), ({"p": 5, "physics": 1}, "Navier-Stokes supports"),
+             ({"viscous": 2}, "viscous scheme"), ({"bc_south": 3}, "bad boundary"),
+             ({"bc_north": 1}, "need the Navier-Stokes physics"),
+             ({"physics": 1, "bc_north": 2}, "far-field state"),
              ({"nx": 1}, "nx and ny"), ({"physics": 7}, "physics"),
              ({"flux": 9}, "flux"), ({"d_nodes": None}, "d_nodes"), ({"gamma": 1.0}, "gamma"),
              ({"nx": 1 << 16, "ny": 1 << 15}, "too large")]

@@ -1,0 +1,142 @@
+"""GPU parity of the BR2 common gradient and the wall / far-field boundaries (Section 3
+lifting; the cylinder case of Section 5.2) against the FP64 oracle: residual, Jacobian-free
+product, element blocks, wall force, and ROW / ESDIRK / BDF2 steps on a cylinder O-grid
+with the paper's pseudo-time settings (dtau_init = 0.01, dtau_max = 1), including steps
+whose pseudo-iterations get rejected."""
+import numpy as np
+import pytest
+
+import fr_inputs as fi
+from oracle import integrators as I
+from oracle import linear
+from oracle.problem import make_ns_bc, sample_state
+from oracle.tableaux import ESDIRK, ROW
+from tests.gpu_common import check_residual, rel, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+GAM = 1.4
+CYL = fi.Cylinder()
+QF = CYL.far_state()
+
+
+def _mesh(kind, nx, ny):
+    if kind == "ogrid":
+        return fi.ogrid_nodes(nx, ny, 0.5, 6.0, 0.05)
+    return fi.perturbed_nodes(nx, ny, -5, -3, 10, 6, 0.1, 7)
+
+
+def _pair(nodes, P, visc, bcs, mu=0.01, flux="roe"):
+    from paper_1904_04825_amd import Disc
+    op = make_ns_bc(nodes, P, mu=mu, flux=flux, viscous=visc, bc_south=bcs[0], bc_north=bcs[1], q_far=QF)
+    disc = Disc(nodes, P, physics="ns", flux=flux, mu=mu, prandtl=0.71, viscous=visc, bc_south=bcs[0],
+                bc_north=bcs[1], q_far=QF)
+    return op, disc
+
+
+def _state(op):
+    """Smooth, non-uniform, with velocity at the walls."""
+    def fn(x, y):
+        rho = 1.0 + 0.05 * np.sin(0.8 * x + 0.2) * np.cos(0.6 * y)
+        u = 0.1 + 0.05 * np.cos(0.7 * y + 0.3 * x)
+        v = 0.03 * np.sin(0.5 * x) * np.cos(0.4 * y)
+        p = 1.0 / GAM + 0.01 * np.cos(0.5 * x - 0.4 * y)
+        return np.stack([rho, rho * u, rho * v, p / (GAM - 1) + 0.5 * rho * (u * u + v * v)])
+    return sample_state(op, fn)
+
+
+CASES = [("ogrid", ("wall", "farfield")), ("channel", ("farfield", "farfield")), ("channel", ("wall", "wall")),
+         ("channel", (None, None))]
+
+
+@pytest.mark.parametrize("P", [2, 3, 4])
+@pytest.mark.parametrize("visc", ["br1", "br2"])
+@pytest.mark.parametrize("kind,bcs", CASES)
+def test_residual_parity(P, visc, kind, bcs):
+    nodes = _mesh(kind, 10, 5) if bcs[0] is not None else fi.perturbed_nodes(9, 7, -5, -5, 10, 10, 0.1, 7)
+    op, disc = _pair(nodes, P, visc, bcs)
+    U = _state(op)
+    check_residual(to_np(disc.residual(to_gpu(U))), op.residual(U), op, U, f"P={P} {visc} {kind} {bcs}")
+
+
+@pytest.mark.parametrize("visc", ["br1", "br2"])
+def test_jf_product_blocks_and_wall_force(visc):
+    op, disc = _pair(_mesh("ogrid", 8, 4), 2, visc, ("wall", "farfield"), mu=0.02)
+    U = _state(op)
+    R0 = op.residual(U)
+    v = fi.random_vector(U.shape, seed=7, scale=1e-2)
+    Ao = linear.jf_matvec(op.residual, U, R0, v, 9.0)
+    Ag = to_np(disc.jf_matvec(to_gpu(U), to_gpu(R0), to_gpu(v), 9.0))
+    assert rel(Ag, Ao) <= 1e-6
+    Bo = linear.ejacobi_blocks(op, U, 5.0)
+    Bg = to_np(disc.ejacobi_assemble(to_gpu(U), 5.0))
+    for e in range(op.nel):
+        assert np.linalg.norm(Bg[e] - Bo[e]) <= 1e-6 * np.linalg.norm(Bo[e]), e
+    fo = op.wall_force(U)
+    fg = np.array(disc.wall_force(to_gpu(U)))
+    print(f"{visc} wall force gpu {fg}, oracle {fo}", flush=True)
+    assert np.linalg.norm(fg - fo) <= 1e-11 * (1.0 + np.linalg.norm(fo))
+
+
+def test_wall_force_needs_a_wall():
+    from paper_1904_04825_amd import FrError
+    op, disc = _pair(_mesh("channel", 6, 4), 2, "br2", ("farfield", "farfield"))
+    with pytest.raises(FrError):
+        disc.wall_force(to_gpu(_state(op)))
+
+
+def test_paper_size_cylinder_residual():
+    """The cylinder O-grid at the paper's size (120 x 48 P3 = 5,760 elements, first layer
+    0.0033, far field at 100), BR2 with the paper's Re = 1200, M = 0.1."""
+    nodes = fi.workload_nodes("cylinder120x48_p3")
+    op, disc = _pair(nodes, 3, "br2", ("wall", "farfield"), mu=CYL.mu)
+    U = _state(op)
+    check_residual(to_np(disc.residual(to_gpu(U))), op.residual(U), op, U, "cylinder 120x48 P3 BR2")
+    fo = op.wall_force(U)
+    fg = np.array(disc.wall_force(to_gpu(U)))
+    assert np.linalg.norm(fg - fo) <= 1e-10 * (1.0 + np.linalg.norm(fo))
+
+
+def _cyl(visc="br2", nx=12, ny=4):
+    op, disc = _pair(fi.ogrid_nodes(nx, ny, 0.5, 6.0, 0.05), 2, visc, ("wall", "farfield"))
+    return op, disc, sample_state(op, CYL.conservative)
+
+
+def test_esdirk3_with_rejected_pseudo_iterations():
+    """Impulsive start of the cylinder flow, one ESDIRK3 step of dt = 1 with the paper's
+    dtau_init = 0.01, dtau_max = 1 and GMRES(5) capped at 5 iterations: pseudo-iterations
+    are rejected (GMRES cannot gain an order of magnitude), dtau_max halves and PTC goes on.
+    Both sides solve each stage to 1e-10, so they end at the same state whatever their
+    pseudo-time paths."""
+    from paper_1904_04825_amd import GmresOpts, SolverOpts
+    op, disc, U = _cyl()
+    Ug = to_gpu(U)
+    opts = SolverOpts(lin=GmresOpts(m=5, max_iters=5, rtol=1e-1), tol_nl=1e-10, dtau_init=0.01, dtau_max=1.0,
+                      max_ptc=2000)
+    st = disc.esdirk_step(Ug, 3, 1.0, opts)
+    Uo, so = I.esdirk_step(op, ESDIRK["ESDIRK3"], 1.0, U, I.LinOpts(m=5, rtol=1e-1, max_iters=5),
+                           I.NlOpts(tol_nl=1e-10, dtau_init=0.01, dtau_max=1.0, max_ptc=2000))
+    print("gpu", st, "oracle ptc", so.ptc_iters, "rejections", so.rejections, flush=True)
+    assert st["status"] == 0 and so.converged
+    assert st["rejections"] > 0 and so.rejections > 0
+    assert rel(to_np(Ug), Uo) <= 1e-8
+
+
+@pytest.mark.parametrize("visc", ["br1", "br2"])
+def test_row3_and_bdf2_steps(visc):
+    from paper_1904_04825_amd import GmresOpts, SolverOpts
+    op, disc, U = _cyl(visc, 10, 4)
+    dt = 0.2
+    Ug = to_gpu(U)
+    st = disc.row_step(Ug, 3, dt, SolverOpts(lin=GmresOpts(m=20, rtol=1e-10)))
+    Uo, _ = I.row_step(op, ROW["ROW3"], dt, U, I.LinOpts(m=20, rtol=1e-10))
+    assert st["status"] == 0 and rel(to_np(Ug), Uo) <= 1e-8
+    opts = SolverOpts(lin=GmresOpts(m=20, rtol=1e-1), tol_nl=1e-10, dtau_init=0.01, dtau_max=1.0)
+    lin, nl = I.LinOpts(m=20, rtol=1e-1), I.NlOpts(tol_nl=1e-10, dtau_init=0.01, dtau_max=1.0)
+    U1o, _ = I.bdf2_step(op, dt, None, U, lin, nl)
+    U2o, _ = I.bdf2_step(op, dt, U, U1o, lin, nl)
+    U0g = to_gpu(U)
+    U1g, s1 = disc.bdf2_step(None, U0g, dt, opts)
+    U2g, s2 = disc.bdf2_step(U0g, U1g, dt, opts)
+    assert s1["status"] == 0 and s2["status"] == 0
+    assert rel(to_np(U2g), U2o) <= 1e-8
