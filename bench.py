@@ -72,6 +72,14 @@ def parse():
     ap.add_argument("--paper-vortex", default=None,
                     help="instead of the bench line: the paper's vortex study (50x50 P6, Roe, GMRES(60)); a comma "
                          "list of SCHEME/STEPS entries of tests/golden/paper_vortex_tables.json, or 'all'")
+    ap.add_argument("--cylinder", action="store_true",
+                    help="instead of the bench line: the cylinder case's scheme comparison (120x48 P3 O-grid, "
+                         "BR2, wall and far field, Re 1200, M 0.1)")
+    ap.add_argument("--cyl-schemes", default="ROW3,ROW4,ESDIRK3,ESDIRK4,BDF2")
+    ap.add_argument("--cyl-dts", default="0.2,0.1,0.05")
+    ap.add_argument("--cyl-tdev", type=float, default=2.0)
+    ap.add_argument("--cyl-trun", type=float, default=1.0)
+    ap.add_argument("--cyl-dtref", type=float, default=0.00625)
     ap.add_argument("--mach-reading", default="magnitude", choices=["magnitude", "u"],
                     help="velocity of the paper's Mach number: |V| or u")
     ap.add_argument("--study-eps", default="rms", choices=["abs", "rms"],
@@ -390,6 +398,98 @@ def paper_vortex_study(select, speed, eps_mode="abs", pc_prec="f64", verbose=Tru
             "workload": golden["workload"], "rows": rows}
 
 
+def cylinder_study(schemes, dts, t_dev, t_run, dt_ref, pc_prec="f32", verbose=True):
+    """The cylinder case's scheme comparison (Section 5.2) on a self-generated O-grid (the
+    paper's 5,690-element mesh is not available): 120 x 48 P3 quads, first layer 0.0033,
+    far field at radius 100; Re = 1200, M = 0.1, BR2, Roe, element-Jacobi.  From an
+    impulsive start the flow is developed for t_dev time units by ESDIRK4 at dt = 0.01;
+    from there every scheme runs t_run time units at each dt with the paper's tolerances
+    (ROW: linear 1e-6; ESDIRK and BDF2: nonlinear 1e-6, linear 1e-1) and pseudo-time
+    settings (dtau_init = 0.01, dtau_max = 1); Error(C_d) is the paper's root mean square
+    of the drag-coefficient differences over the run's steps, against an ESDIRK4 run at
+    dt_ref (in place of the paper's explicit SSPRK3 reference)."""
+    import numpy as np
+    import torch
+
+    import fr_inputs as fi
+    from paper_1904_04825_amd import F32, F64, Disc, GmresOpts, SolverOpts
+    pp = F32 if pc_prec == "f32" else F64
+    cyl = fi.Cylinder()
+    disc = Disc(fi.workload_nodes("cylinder120x48_p3"), 3, physics="ns", flux="roe", mu=cyl.mu,
+                prandtl=cyl.prandtl, viscous="br2", bc_south="wall", bc_north="farfield", q_far=cyl.far_state())
+    xy = disc.solution_points().cpu().numpy()
+    U0 = torch.as_tensor(cyl.conservative(xy[0], xy[1]), device=disc.device).contiguous()
+    qinf = 0.5 * cyl.mach ** 2          # rho u^2 / 2 with rho = 1, D = 1
+
+    def cd(U):
+        return disc.wall_force(U)[0] / qinf
+
+    def run(sch, dt, nsteps, U, record):
+        """nsteps of scheme sch from U (in place); per-step totals and the C_d history."""
+        tot = {"gmres_iters": 0, "ptc_iters": 0, "rejections": 0, "residual_evals": 0, "failed_steps": 0}
+        hist = []
+        lin_row = GmresOpts(m=20, rtol=1e-6)
+        o_row = SolverOpts(lin=lin_row, precond_precision=pp)
+        o_imp = SolverOpts(lin=GmresOpts(m=20, rtol=1e-1), tol_nl=1e-6, dtau_init=0.01, dtau_max=1.0,
+                           precond_precision=pp)
+        Um1 = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            if sch.startswith("ROW"):
+                st = disc.row_step(U, int(sch[3]), dt, o_row)
+            elif sch.startswith("ESDIRK"):
+                st = disc.esdirk_step(U, int(sch[6]), dt, o_imp)
+            else:
+                Un, st = disc.bdf2_step(Um1, U, dt, o_imp)
+                Um1 = U.clone()
+                U.copy_(Un)
+            if st["status"] != 0:
+                tot["failed_steps"] += 1
+                break
+            for k in ("gmres_iters", "ptc_iters", "rejections", "residual_evals"):
+                tot[k] += st.get(k, 0)
+            if record:
+                hist.append(cd(U))
+        torch.cuda.synchronize()
+        return tot, hist, time.perf_counter() - t0
+
+    progress("cylinder: development run")
+    U = U0.clone()
+    dev_tot, _, dev_s = run("ESDIRK4", 0.01, int(round(t_dev / 0.01)), U, False)
+    Ustart = U.clone()
+    progress("cylinder: reference run")
+    Ur = Ustart.clone()
+    nref = int(round(t_run / dt_ref))
+    ref_tot, ref_hist, ref_s = run("ESDIRK4", dt_ref, nref, Ur, True)
+    rows = []
+    for sch in schemes:
+        for dt in dts:
+            n = int(round(t_run / dt))
+            stride = int(round(dt / dt_ref))
+            Uc = Ustart.clone()
+            tot, hist, wall = run(sch, dt, n, Uc, True)
+            ok = tot["failed_steps"] == 0 and len(hist) == n
+            err = float(np.sqrt(np.mean([(hist[i] - ref_hist[(i + 1) * stride - 1]) ** 2 for i in range(n)]))) \
+                if ok else None
+            row = {"scheme": sch, "dt": dt, "steps": n, "completed": len(hist), "error_cd": err, "wall_s": wall,
+                   "cd_end": hist[-1] if hist else None,
+                   **{k: v / max(len(hist), 1) for k, v in tot.items() if k not in ("rejections", "failed_steps")},
+                   "rejections": tot["rejections"], "failed": not ok}
+            rows.append(row)
+            if verbose:
+                print(f"# {sch} dt={dt}: Error(Cd) {err if err is None else f'{err:.3e}'}, {wall:.2f} s, "
+                      f"GMRES/step {row['gmres_iters']:.1f}, PTC/step {row['ptc_iters']:.1f}, "
+                      f"rejections {tot['rejections']}{' FAILED' if not ok else ''}", flush=True)
+    return {"mode": "cylinder", "mesh": "O-grid 120x48, P3 (5760 elements, 368,640 DOFs)", "reynolds": cyl.reynolds,
+            "mach": cyl.mach, "viscous": "BR2", "precond_precision": pc_prec,
+            "development": {"scheme": "ESDIRK4", "dt": 0.01, "t": t_dev, "wall_s": dev_s,
+                            "rejections": dev_tot["rejections"]},
+            "reference": {"scheme": "ESDIRK4", "dt": dt_ref, "steps": nref, "wall_s": ref_s,
+                          "cd_start": ref_hist[0] if ref_hist else None, "cd_end": ref_hist[-1] if ref_hist else None},
+            "rows": rows}
+
+
 def precond_study(disc, W, U, dt, scheme, lin):
     """The first ROW stage's linear system at the timed legs' start state, solved to the
     same tolerance with each preconditioner on FP32 blocks: element-Jacobi (the paper's),
@@ -449,6 +549,10 @@ def main():
     if args.paper_vortex is not None:
         sel = "all" if args.paper_vortex == "all" else set(args.paper_vortex.split(","))
         print(json.dumps(paper_vortex_study(sel, args.mach_reading, args.study_eps, args.study_precond)), flush=True)
+        return
+    if args.cylinder:
+        print(json.dumps(cylinder_study(args.cyl_schemes.split(","), [float(x) for x in args.cyl_dts.split(",")],
+                                        args.cyl_tdev, args.cyl_trun, args.cyl_dtref, args.study_precond)), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
