@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--cyl-tdev", type=float, default=2.0)
     ap.add_argument("--cyl-trun", type=float, default=1.0)
     ap.add_argument("--cyl-dtref", type=float, default=0.00625)
+    ap.add_argument("--cyl-tolnl", type=float, default=1e-6, help="ESDIRK / BDF2 nonlinear tolerance (the paper's 1e-6)")
+    ap.add_argument("--cyl-tollin", type=float, default=1e-6, help="ROW linear tolerance (the paper's 1e-6)")
     ap.add_argument("--mach-reading", default="magnitude", choices=["magnitude", "u"],
                     help="velocity of the paper's Mach number: |V| or u")
     ap.add_argument("--study-eps", default="rms", choices=["abs", "rms"],
@@ -398,7 +400,7 @@ def paper_vortex_study(select, speed, eps_mode="abs", pc_prec="f64", verbose=Tru
             "workload": golden["workload"], "rows": rows}
 
 
-def cylinder_study(schemes, dts, t_dev, t_run, dt_ref, pc_prec="f32", verbose=True):
+def cylinder_study(schemes, dts, t_dev, t_run, dt_ref, pc_prec="f32", tol_nl=1e-6, tol_lin_row=1e-6, verbose=True):
     """The cylinder case's scheme comparison (Section 5.2) on a self-generated O-grid (the
     paper's 5,690-element mesh is not available): 120 x 48 P3 quads, first layer 0.0033,
     far field at radius 100; Re = 1200, M = 0.1, BR2, Roe, element-Jacobi.  From an
@@ -428,9 +430,9 @@ def cylinder_study(schemes, dts, t_dev, t_run, dt_ref, pc_prec="f32", verbose=Tr
         """nsteps of scheme sch from U (in place); per-step totals and the C_d history."""
         tot = {"gmres_iters": 0, "ptc_iters": 0, "rejections": 0, "residual_evals": 0, "failed_steps": 0}
         hist = []
-        lin_row = GmresOpts(m=20, rtol=1e-6)
+        lin_row = GmresOpts(m=20, rtol=tol_lin_row)
         o_row = SolverOpts(lin=lin_row, precond_precision=pp)
-        o_imp = SolverOpts(lin=GmresOpts(m=20, rtol=1e-1), tol_nl=1e-6, dtau_init=0.01, dtau_max=1.0,
+        o_imp = SolverOpts(lin=GmresOpts(m=20, rtol=1e-1), tol_nl=tol_nl, dtau_init=0.01, dtau_max=1.0,
                            precond_precision=pp)
         Um1 = None
         torch.cuda.synchronize()
@@ -482,7 +484,8 @@ def cylinder_study(schemes, dts, t_dev, t_run, dt_ref, pc_prec="f32", verbose=Tr
                       f"GMRES/step {row['gmres_iters']:.1f}, PTC/step {row['ptc_iters']:.1f}, "
                       f"rejections {tot['rejections']}{' FAILED' if not ok else ''}", flush=True)
     return {"mode": "cylinder", "mesh": "O-grid 120x48, P3 (5760 elements, 368,640 DOFs)", "reynolds": cyl.reynolds,
-            "mach": cyl.mach, "viscous": "BR2", "precond_precision": pc_prec,
+            "mach": cyl.mach, "viscous": "BR2", "precond_precision": pc_prec, "tol_nl": tol_nl,
+            "tol_lin_row": tol_lin_row,
             "development": {"scheme": "ESDIRK4", "dt": 0.01, "t": t_dev, "wall_s": dev_s,
                             "rejections": dev_tot["rejections"]},
             "reference": {"scheme": "ESDIRK4", "dt": dt_ref, "steps": nref, "wall_s": ref_s,
@@ -552,7 +555,8 @@ def main():
         return
     if args.cylinder:
         print(json.dumps(cylinder_study(args.cyl_schemes.split(","), [float(x) for x in args.cyl_dts.split(",")],
-                                        args.cyl_tdev, args.cyl_trun, args.cyl_dtref, args.study_precond)), flush=True)
+                                        args.cyl_tdev, args.cyl_trun, args.cyl_dtref, args.study_precond,
+                                        args.cyl_tolnl, args.cyl_tollin)), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))

@@ -122,7 +122,7 @@ __device__ __forceinline__ void viscous_fluxes(const double q[4], const double q
 // The point fluxes F, G replace the gradient qx, qy in place: each point's fluxes
 // need only that point's gradient, and the face gradients are taken before.
 template <int P>
-struct Slot {
+struct SlotData {
   static constexpr int n = P + 1, Np = n * n;
   double q[4][Np];
   union {
@@ -141,6 +141,9 @@ struct Slot {
   };
   double qc[4][4][n], gc[4][4][n][2];
 };
+
+template <int P>
+using Slot = SlotData<P>;
 
 // Per-element geometry and neighbour data in LDS.
 template <int P>
@@ -173,7 +176,11 @@ __device__ __forceinline__ double ns_state(const NSArgs& a, size_t gi, double e)
 
 // geometry of element (ex, ey): metrics at the points, face normals, neighbour indices and
 // the neighbours' solution traces (for state U or U + e V); t indexes the slot's threads
-template <int P, int MODE>
+// V: compile-time variant, bit 0 = BR2 (else BR1), bit 1 = boundaries on the eta sides
+// (else doubly periodic); the BR1 periodic kernels carry none of the other code.
+enum { kVarBR2 = 1, kVarBnd = 2 };
+
+template <int P, int MODE, int V>
 __device__ void load_elem_geo(ElemGeo<P>& g, const NSArgs& a, const Basis& B, int ex, int ey, double e, int t,
                               int nthreads) {
   constexpr int n = P + 1, Np = n * n;
@@ -190,7 +197,7 @@ __device__ void load_elem_geo(ElemGeo<P>& g, const NSArgs& a, const Basis& B, in
   }
   if (t < 4) {
     double Sx, Sy;
-    const int bc = face_bc(a, t, ey);
+    const int bc = (V & kVarBnd) ? face_bc(a, t, ey) : FR_BC_PERIODIC;
     if (t == 0) xi_face_normal(a.nodes, a.nx, ex, ey, &Sx, &Sy);
     else if (t == 1) xi_face_normal(a.nodes, a.nx, (ex + 1 == a.nx) ? 0 : ex + 1, ey, &Sx, &Sy);
     else if (t == 2) eta_face_normal(a.nodes, a.nx, ex, ey, &Sx, &Sy);
@@ -204,12 +211,14 @@ __device__ void load_elem_geo(ElemGeo<P>& g, const NSArgs& a, const Basis& B, in
   }
   for (int idx = t; idx < 4 * n; idx += nthreads) {
     const int f = idx / n, j = idx % n;
-    double c[8];
-    load_corners(a.nodes, a.nx, ex, ey, c);
-    const double xi = f == 0 ? -1.0 : (f == 1 ? 1.0 : B.x[j]);
-    const double eta = f == 2 ? -1.0 : (f == 3 ? 1.0 : B.x[j]);
-    g.Jf[f][j] = bilinear_metric(c, xi, eta).J;
-    if (face_bc(a, f, ey) != FR_BC_PERIODIC) continue;  // outside trace from the own one, per slot
+    if constexpr ((V & kVarBR2) != 0) {
+      double c[8];
+      load_corners(a.nodes, a.nx, ex, ey, c);
+      const double xi = f == 0 ? -1.0 : (f == 1 ? 1.0 : B.x[j]);
+      const double eta = f == 2 ? -1.0 : (f == 3 ? 1.0 : B.x[j]);
+      g.Jf[f][j] = bilinear_metric(c, xi, eta).J;
+    }
+    if ((V & kVarBnd) && face_bc(a, f, ey) != FR_BC_PERIODIC) continue;  // outside trace from the own one
     int nex, ney;
     face_neighbour(f, ex, ey, a.nx, a.ny, &nex, &ney);
     const size_t ne = (size_t)ney * a.nx + nex;
@@ -227,7 +236,7 @@ __device__ void load_elem_geo(ElemGeo<P>& g, const NSArgs& a, const Basis& B, in
 
 // step 2: own traces and common solution on the faces (a boundary side's outside trace
 // from the own one)
-template <int P>
+template <int P, int V>
 __device__ void slot_traces(Slot<P>& s, const ElemGeo<P>& g, const Basis& B, const double qfar[4], int t) {
   constexpr int n = P + 1;
   for (int idx = t; idx < 4 * n; idx += NS<P>::ST) {
@@ -240,7 +249,7 @@ __device__ void slot_traces(Slot<P>& s, const ElemGeo<P>& g, const Basis& B, con
       for (int c = 0; c < n; ++c) x = fma(lw[c], s.q[v][(f < 2) ? j * n + c : c * n + j], x);
       qo[v] = x;
     }
-    if (g.bc[f] == FR_BC_PERIODIC) {
+    if (!(V & kVarBnd) || g.bc[f] == FR_BC_PERIODIC) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) qn[v] = g.nb[f][v][j];
     } else {
@@ -280,13 +289,13 @@ __device__ void slot_gradient(Slot<P>& s, const ElemGeo<P>& g, const Basis& B, i
 
 // own face gradient of face point (f, j), variable v: BR1 the corrected gradient
 // extrapolated; BR2 the raw gradient extrapolated plus the face's lifting
-template <int P>
-__device__ __forceinline__ void own_face_gradient(const Slot<P>& s, const ElemGeo<P>& g, const Basis& B, int visc,
-                                                  int f, int j, int v, double* gx, double* gy) {
+template <int P, int V>
+__device__ __forceinline__ void own_face_gradient(const Slot<P>& s, const ElemGeo<P>& g, const Basis& B, int f, int j,
+                                                  int v, double* gx, double* gy) {
   constexpr int n = P + 1;
   const double* lw = (f == 0 || f == 2) ? B.lm : B.lp;
   double x = 0.0, y = 0.0;
-  if (visc == FR_BR1) {
+  if constexpr ((V & kVarBR2) == 0) {
     for (int c = 0; c < n; ++c) {
       const int kk = (f < 2) ? j * n + c : c * n + j;
       x = fma(lw[c], s.qx[v][kk], x);
@@ -341,20 +350,20 @@ __device__ void slot_fluxes(Slot<P>& s, const ElemGeo<P>& g, const Phys& ph, int
 
 // common flux F^num (inviscid minus viscous, along S) of face point (f, j) from the own
 // trace qo, the common state qc and the common gradient (gx, gy)
-template <int FLUX>
+template <int FLUX, int V>
 __device__ __forceinline__ void face_common_flux(int f, int bc, const double qo[4], const double qnb[4],
                                                  const double qfar[4], const double qc[4], const double gx[4],
                                                  const double gy[4], double Sx, double Sy, const Phys& ph,
                                                  double Fn[4]) {
   double Fi[4], fv[4], gv[4];
-  if (bc == FR_BC_WALL) {
+  if ((V & kVarBnd) && bc == FR_BC_WALL) {
     const double p = pressure_of(qo, ph.gamma);
     Fi[0] = 0.0;
     Fi[1] = p * Sx;
     Fi[2] = p * Sy;
     Fi[3] = 0.0;
   } else {
-    const double* qn = bc == FR_BC_FARFIELD ? qfar : qnb;
+    const double* qn = ((V & kVarBnd) && bc == FR_BC_FARFIELD) ? qfar : qnb;
     if (f == 0 || f == 2)
       common_flux<FLUX>(qn, qo, Sx, Sy, ph.gamma, Fi);
     else
@@ -363,13 +372,13 @@ __device__ __forceinline__ void face_common_flux(int f, int bc, const double qo[
   viscous_fluxes(qc, gx, gy, ph, fv, gv);
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const double vis = (bc == FR_BC_WALL && v == 3) ? 0.0 : fv[v] * Sx + gv[v] * Sy;
+    const double vis = ((V & kVarBnd) && bc == FR_BC_WALL && v == 3) ? 0.0 : fv[v] * Sx + gv[v] * Sy;
     Fn[v] = Fi[v] - vis;
   }
 }
 
 // step 6: common fluxes and jumps on the faces (gc holds the common gradient)
-template <int P, int FLUX>
+template <int P, int FLUX, int V>
 __device__ void slot_face_fluxes(Slot<P>& s, const ElemGeo<P>& g, const Basis& B, const Phys& ph,
                                  const double qfar[4], int t) {
   constexpr int n = P + 1;
@@ -389,7 +398,8 @@ __device__ void slot_face_fluxes(Slot<P>& s, const ElemGeo<P>& g, const Basis& B
       Fl[v] = fl;
     }
     double Fn[4];
-    face_common_flux<FLUX>(f, g.bc[f], qo, qn, qfar, qc, gx, gy, g.S[f][0], g.S[f][1], ph, Fn);
+    face_common_flux<FLUX, V>(f, (V & kVarBnd) ? g.bc[f] : FR_BC_PERIODIC, qo, qn, qfar, qc, gx, gy, g.S[f][0],
+                              g.S[f][1], ph, Fn);
 #pragma unroll
     for (int v = 0; v < 4; ++v) s.jmp[f][v][j] = Fn[v] - Fl[v];
   }
@@ -417,7 +427,7 @@ __device__ __forceinline__ size_t grad_index(int el, int f, int v, int j, int n)
 }
 
 // ---------------------------------------------------------------- kernel A: face gradient traces
-template <int P, int MODE>
+template <int P, int MODE, int V>
 __global__ void __launch_bounds__(NS<P>::NT) k_ns_grad(const NSArgs a, const Basis B) {
   using C = NS<P>;
   constexpr int n = C::n, Np = C::Np, ST = C::ST, SL = C::SLOTS;
@@ -439,13 +449,13 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_grad(const NSArgs a, const Bas
   }
   const int ex = live ? el % a.nx : 0, ey = live ? el / a.nx : 0;
   if (live) {
-    load_elem_geo<P, MODE>(Gm[sl], a, B, ex, ey, e, t, ST);
+    load_elem_geo<P, MODE, V>(Gm[sl], a, B, ex, ey, e, t, ST);
     for (int k = t; k < Np; k += ST)
 #pragma unroll
       for (int v = 0; v < 4; ++v) S[sl].q[v][k] = ns_state<MODE>(a, ((size_t)v * nel + el) * Np + k, e);
   }
   __syncthreads();
-  if (live) slot_traces<P>(S[sl], Gm[sl], B, a.qfar, t);
+  if (live) slot_traces<P, V>(S[sl], Gm[sl], B, a.qfar, t);
   __syncthreads();
   if (live) slot_gradient<P>(S[sl], Gm[sl], B, t);
   __syncthreads();
@@ -455,7 +465,7 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_grad(const NSArgs a, const Bas
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         double gx, gy;
-        own_face_gradient<P>(S[sl], Gm[sl], B, a.visc, f, j, v, &gx, &gy);
+        own_face_gradient<P, V>(S[sl], Gm[sl], B, f, j, v, &gx, &gy);
         const size_t gi = grad_index(el, f, v, j, n);
         a.grad[gi] = gx;
         a.grad[gi + 1] = gy;
@@ -464,7 +474,7 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_grad(const NSArgs a, const Bas
 }
 
 // ---------------------------------------------------------------- kernel B: residual
-template <int P, int FLUX, int MODE>
+template <int P, int FLUX, int MODE, int V>
 __global__ void __launch_bounds__(NS<P>::NT) k_ns_res(const NSArgs a, const Basis B) {
   using C = NS<P>;
   constexpr int n = C::n, Np = C::Np, ST = C::ST, SL = C::SLOTS;
@@ -490,13 +500,13 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_res(const NSArgs a, const Basi
   }
   const int ex = live ? el % a.nx : 0, ey = live ? el / a.nx : 0;
   if (live) {
-    load_elem_geo<P, MODE>(Gm[sl], a, B, ex, ey, e, t, ST);
+    load_elem_geo<P, MODE, V>(Gm[sl], a, B, ex, ey, e, t, ST);
     for (int k = t; k < Np; k += ST)
 #pragma unroll
       for (int v = 0; v < 4; ++v) S[sl].q[v][k] = ns_state<MODE>(a, ((size_t)v * nel + el) * Np + k, e);
   }
   __syncthreads();
-  if (live) slot_traces<P>(S[sl], Gm[sl], B, a.qfar, t);
+  if (live) slot_traces<P, V>(S[sl], Gm[sl], B, a.qfar, t);
   __syncthreads();
   if (live) slot_gradient<P>(S[sl], Gm[sl], B, t);
   __syncthreads();
@@ -508,8 +518,8 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_res(const NSArgs a, const Basi
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         double gx, gy;
-        own_face_gradient<P>(S[sl], Gm[sl], B, a.visc, f, j, v, &gx, &gy);
-        if (ne < 0) {  // boundary side: its own face gradient
+        own_face_gradient<P, V>(S[sl], Gm[sl], B, f, j, v, &gx, &gy);
+        if ((V & kVarBnd) && ne < 0) {  // boundary side: its own face gradient
           S[sl].gc[f][v][j][0] = gx;
           S[sl].gc[f][v][j][1] = gy;
         } else {
@@ -522,7 +532,7 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_res(const NSArgs a, const Basi
   __syncthreads();
   if (live) slot_fluxes<P>(S[sl], Gm[sl], a.ph, t);
   __syncthreads();
-  if (live) slot_face_fluxes<P, FLUX>(S[sl], Gm[sl], B, a.ph, a.qfar, t);
+  if (live) slot_face_fluxes<P, FLUX, V>(S[sl], Gm[sl], B, a.ph, a.qfar, t);
   __syncthreads();
   if (live)
     for (int k = t; k < Np; k += ST)
@@ -544,7 +554,7 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_res(const NSArgs a, const Basi
 
 // ---------------------------------------------------------------- kernel C: element-Jacobi blocks
 
-template <int P, int FLUX, typename T>
+template <int P, int FLUX, typename T, int V>
 __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const Basis B, void* outp) {
   using C = NS<P>;
   constexpr int n = C::n, Np = C::Np, Nb = C::Nb, ST = C::ST, SL = C::SLOTS, NT = C::NT, LD = C::LD;
@@ -559,7 +569,7 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const 
   const int ex = el % a.nx, ey = el / a.nx;
   const size_t nel = (size_t)a.nel;
 
-  if (tid < ST) load_elem_geo<P, 0>(Gm, a, B, ex, ey, 0.0, tid, ST);
+  if (tid < ST) load_elem_geo<P, 0, V>(Gm, a, B, ex, ey, 0.0, tid, ST);
   for (int k = tid; k < Np; k += NT)
 #pragma unroll
     for (int v = 0; v < 4; ++v) q0[v][k] = a.U[((size_t)v * nel + el) * Np + k];
@@ -570,7 +580,7 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const 
     const int f = idx / n, j = idx % n;
     const int o = f ^ 1;
     const int ne = Gm.nbr[f];
-    if (ne < 0) continue;  // boundary side: no neighbour
+    if ((V & kVarBnd) && ne < 0) continue;  // boundary side: no neighbour
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const size_t gi = grad_index(ne, o, v, j, n);
@@ -580,7 +590,7 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const 
     double c8[8];
     load_corners(a.nodes, a.nx, ne % a.nx, ne / a.nx, c8);
     double cx = 0.0, cy = 0.0;
-    if (a.visc == FR_BR2) {
+    if constexpr ((V & kVarBR2) != 0) {
       // the neighbour's lifting c_P (q^com - q_nbr) S_out,nbr / |J_nbr| on the shared face;
       // its outward normal there is +S on this element's W and S faces, -S on E and N
       const double xi = o == 0 ? -1.0 : (o == 1 ? 1.0 : B.x[j]);
@@ -626,7 +636,7 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const 
 #pragma unroll
         for (int v = 0; v < 4; ++v) S[sl].q[v][k] = q0[v][k] + ((v == pv && k == pk) ? delta : 0.0);
     __syncthreads();
-    if (active) slot_traces<P>(S[sl], Gm, B, a.qfar, t);
+    if (active) slot_traces<P, V>(S[sl], Gm, B, a.qfar, t);
     __syncthreads();
     if (active) slot_gradient<P>(S[sl], Gm, B, t);
     if (base && active)
@@ -642,8 +652,8 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const 
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           double gx, gy;
-          own_face_gradient<P>(S[sl], Gm, B, a.visc, f, jj, v, &gx, &gy);
-          if (Gm.nbr[f] < 0) {  // boundary side: its own face gradient
+          own_face_gradient<P, V>(S[sl], Gm, B, f, jj, v, &gx, &gy);
+          if ((V & kVarBnd) && Gm.nbr[f] < 0) {  // boundary side: its own face gradient
             S[sl].gc[f][v][jj][0] = gx;
             S[sl].gc[f][v][jj][1] = gy;
             continue;
@@ -658,7 +668,7 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const 
     __syncthreads();
     if (active) slot_fluxes<P>(S[sl], Gm, a.ph, t);
     __syncthreads();
-    if (active) slot_face_fluxes<P, FLUX>(S[sl], Gm, B, a.ph, a.qfar, t);
+    if (active) slot_face_fluxes<P, FLUX, V>(S[sl], Gm, B, a.ph, a.qfar, t);
     __syncthreads();
     if (active)
       for (int k = t; k < Np; k += ST)
@@ -684,7 +694,7 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_ejacobi(const NSArgs a, const 
 // its face gradients, then sum_j w_j F^num(j) of the momentum on the wall face (S per unit
 // reference length) into part[2 ex], part[2 ex + 1].  A boundary side needs no neighbour
 // gradient, so no gradient traces are formed.
-template <int P, int FLUX>
+template <int P, int FLUX, int V>
 __global__ void __launch_bounds__(NS<P>::NT) k_ns_wall_flux(const NSArgs a, const Basis B, double* part) {
   using C = NS<P>;
   constexpr int n = C::n, Np = C::Np, ST = C::ST, SL = C::SLOTS;
@@ -695,13 +705,13 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_wall_flux(const NSArgs a, cons
   const bool live = sl < SL && el < a.nx;
   const size_t nel = (size_t)a.nel;
   if (live) {
-    load_elem_geo<P, 0>(Gm[sl], a, B, el, 0, 0.0, t, ST);
+    load_elem_geo<P, 0, V>(Gm[sl], a, B, el, 0, 0.0, t, ST);
     for (int k = t; k < Np; k += ST)
 #pragma unroll
       for (int v = 0; v < 4; ++v) S[sl].q[v][k] = a.U[((size_t)v * nel + el) * Np + k];
   }
   __syncthreads();
-  if (live) slot_traces<P>(S[sl], Gm[sl], B, a.qfar, t);
+  if (live) slot_traces<P, V>(S[sl], Gm[sl], B, a.qfar, t);
   __syncthreads();
   if (live) slot_gradient<P>(S[sl], Gm[sl], B, t);
   __syncthreads();
@@ -713,9 +723,9 @@ __global__ void __launch_bounds__(NS<P>::NT) k_ns_wall_flux(const NSArgs a, cons
       for (int v = 0; v < 4; ++v) {
         qo[v] = S[sl].tr[2][v][j];
         qc[v] = S[sl].qc[2][v][j];
-        own_face_gradient<P>(S[sl], Gm[sl], B, a.visc, 2, j, v, &gx[v], &gy[v]);
+        own_face_gradient<P, V>(S[sl], Gm[sl], B, 2, j, v, &gx[v], &gy[v]);
       }
-      face_common_flux<FLUX>(2, FR_BC_WALL, qo, qo, a.qfar, qc, gx, gy, Gm[sl].S[2][0], Gm[sl].S[2][1], a.ph, Fn);
+      face_common_flux<FLUX, V>(2, FR_BC_WALL, qo, qo, a.qfar, qc, gx, gy, Gm[sl].S[2][0], Gm[sl].S[2][1], a.ph, Fn);
       fx = fma(B.w[j], Fn[1], fx);
       fy = fma(B.w[j], Fn[2], fy);
     }
@@ -750,21 +760,37 @@ static NSArgs ns_args(const fr_disc* d, const ResArgs& r) {
   return a;
 }
 
-template <int P, int FLUX>
-static hipError_t ns_res_pf(const fr_disc* d, int mode, const NSArgs& a, hipStream_t s) {
+template <int P, int FLUX, int V>
+static hipError_t ns_res_pfv(const fr_disc* d, int mode, const NSArgs& a, hipStream_t s) {
   using C = NS<P>;
   dim3 grid((d->nel + C::SLOTS - 1) / C::SLOTS), block(C::NT);
   if (mode == 0) {
-    hipLaunchKernelGGL((k_ns_grad<P, 0>), grid, block, 0, s, a, d->basis);
-    hipLaunchKernelGGL((k_ns_res<P, FLUX, 0>), grid, block, 0, s, a, d->basis);
+    hipLaunchKernelGGL((k_ns_grad<P, 0, V>), grid, block, 0, s, a, d->basis);
+    hipLaunchKernelGGL((k_ns_res<P, FLUX, 0, V>), grid, block, 0, s, a, d->basis);
   } else if (mode == 1) {
-    hipLaunchKernelGGL((k_ns_grad<P, 1>), grid, block, 0, s, a, d->basis);
-    hipLaunchKernelGGL((k_ns_res<P, FLUX, 1>), grid, block, 0, s, a, d->basis);
+    hipLaunchKernelGGL((k_ns_grad<P, 1, V>), grid, block, 0, s, a, d->basis);
+    hipLaunchKernelGGL((k_ns_res<P, FLUX, 1, V>), grid, block, 0, s, a, d->basis);
   } else {
-    hipLaunchKernelGGL((k_ns_grad<P, 2>), grid, block, 0, s, a, d->basis);
-    hipLaunchKernelGGL((k_ns_res<P, FLUX, 2>), grid, block, 0, s, a, d->basis);
+    hipLaunchKernelGGL((k_ns_grad<P, 2, V>), grid, block, 0, s, a, d->basis);
+    hipLaunchKernelGGL((k_ns_res<P, FLUX, 2, V>), grid, block, 0, s, a, d->basis);
   }
   return hipGetLastError();
+}
+
+// the compile-time variant of a disc: BR2 and / or boundaries
+static int ns_variant(const fr_disc* d) {
+  return (d->visc == FR_BR2 ? kVarBR2 : 0) |
+         ((d->bc_south != FR_BC_PERIODIC || d->bc_north != FR_BC_PERIODIC) ? kVarBnd : 0);
+}
+
+template <int P, int FLUX>
+static hipError_t ns_res_pf(const fr_disc* d, int mode, const NSArgs& a, hipStream_t s) {
+  switch (ns_variant(d)) {
+    case 0: return ns_res_pfv<P, FLUX, 0>(d, mode, a, s);
+    case 1: return ns_res_pfv<P, FLUX, 1>(d, mode, a, s);
+    case 2: return ns_res_pfv<P, FLUX, 2>(d, mode, a, s);
+    default: return ns_res_pfv<P, FLUX, 3>(d, mode, a, s);
+  }
 }
 
 template <int P>
@@ -786,8 +812,11 @@ hipError_t launch_ns_residual(const fr_disc* d, int mode, const ResArgs& r, hipS
 template <int P, int FLUX>
 static hipError_t ns_wall_pf(const fr_disc* d, const NSArgs& a, double* part, hipStream_t s) {
   using C = NS<P>;
-  hipLaunchKernelGGL((k_ns_wall_flux<P, FLUX>), dim3((d->nx + C::SLOTS - 1) / C::SLOTS), dim3(C::NT), 0, s, a,
-                     d->basis, part);
+  const dim3 grid((d->nx + C::SLOTS - 1) / C::SLOTS), block(C::NT);
+  if (d->visc == FR_BR2)
+    hipLaunchKernelGGL((k_ns_wall_flux<P, FLUX, kVarBnd | kVarBR2>), grid, block, 0, s, a, d->basis, part);
+  else
+    hipLaunchKernelGGL((k_ns_wall_flux<P, FLUX, kVarBnd>), grid, block, 0, s, a, d->basis, part);
   return hipGetLastError();
 }
 
@@ -804,22 +833,22 @@ hipError_t launch_ns_wall_flux(const fr_disc* d, const double* U, double* part, 
   return hipErrorInvalidValue;
 }
 
-template <int P, int FLUX>
-static hipError_t ns_asm_pf(const fr_disc* d, const NSArgs& a, void* out, int precision, int invert, hipStream_t s) {
+template <int P, int FLUX, int V>
+static hipError_t ns_asm_pfv(const fr_disc* d, const NSArgs& a, void* out, int precision, int invert, hipStream_t s) {
   using C = NS<P>;
   dim3 grid((d->nel + C::SLOTS - 1) / C::SLOTS), block(C::NT);
-  hipLaunchKernelGGL((k_ns_grad<P, 0>), grid, block, 0, s, a, d->basis);
+  hipLaunchKernelGGL((k_ns_grad<P, 0, V>), grid, block, 0, s, a, d->basis);
   dim3 g2(d->nel);
   if (precision == FR_F32) {
     // FP32: the FP64 blocks rounded on the way out, then inverted in place on MFMA
     if (!invert) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_ns_ejacobi<P, FLUX, float>), g2, block, 0, s, a, d->basis, out);
+    hipLaunchKernelGGL((k_ns_ejacobi<P, FLUX, float, V>), g2, block, 0, s, a, d->basis, out);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_gj_mfma_f32(4 * (P + 1) * (P + 1), static_cast<float*>(out), d->nel, s);
   } else {
     // FP64: the raw blocks, then their inverses in place
-    hipLaunchKernelGGL((k_ns_ejacobi<P, FLUX, double>), g2, block, 0, s, a, d->basis, out);
+    hipLaunchKernelGGL((k_ns_ejacobi<P, FLUX, double, V>), g2, block, 0, s, a, d->basis, out);
     if (invert) {
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
@@ -827,6 +856,16 @@ static hipError_t ns_asm_pf(const fr_disc* d, const NSArgs& a, void* out, int pr
     }
   }
   return hipGetLastError();
+}
+
+template <int P, int FLUX>
+static hipError_t ns_asm_pf(const fr_disc* d, const NSArgs& a, void* out, int precision, int invert, hipStream_t s) {
+  switch (ns_variant(d)) {
+    case 0: return ns_asm_pfv<P, FLUX, 0>(d, a, out, precision, invert, s);
+    case 1: return ns_asm_pfv<P, FLUX, 1>(d, a, out, precision, invert, s);
+    case 2: return ns_asm_pfv<P, FLUX, 2>(d, a, out, precision, invert, s);
+    default: return ns_asm_pfv<P, FLUX, 3>(d, a, out, precision, invert, s);
+  }
 }
 
 hipError_t launch_ns_ejacobi_assemble(const fr_disc* d, const double* U, double shift, void* out, int precision,
