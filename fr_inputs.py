@@ -196,11 +196,18 @@ class Cylinder:
         rho, u, p = 1.0, self.mach, 1.0 / self.gamma
         return np.array([rho, rho * u, 0.0, p / (self.gamma - 1.0) + 0.5 * rho * u * u])
 
-    def conservative(self, x, y):
-        """The free stream everywhere (an impulsive start)."""
+    def conservative(self, x, y, perturb: float = 0.0):
+        """The free stream everywhere (an impulsive start); perturb > 0 adds a small
+        cross-stream velocity bump behind the cylinder, v = perturb u exp(-((x - 1.5)^2 + y^2) / 0.5),
+        which breaks the mesh's symmetry so that vortex shedding sets in."""
         x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
         q = self.far_state()
-        return np.stack([np.full_like(x, q[v]) for v in range(4)])
+        rho, u = q[0], q[1] / q[0]
+        v = perturb * u * np.exp(-((x - 1.5) ** 2 + y ** 2) / 0.5)
+        p = 1.0 / self.gamma
+        return np.stack([np.full_like(x, rho), np.full_like(x, rho * u), rho * v,
+                         p / (self.gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
 
 
 def random_vector(shape, seed: int, scale: float = 1.0) -> np.ndarray:

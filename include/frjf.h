@@ -451,6 +451,49 @@ int fr_scheme_table(int kind, int scheme, double* h_a, double* h_c, double* h_b,
  * FR_WS_RESIDUAL, 0, 0) bytes.  Synchronises; FR_EINVAL without a wall. */
 fr_status fr_wall_force(const fr_disc* disc, const double* d_U, double* h_force, void* d_work, fr_stream stream);
 
+/* ---- 3D hexahedral FR (Section 3's hexahedral forms; the Taylor-Green vortex of
+ * Section 5.3) ---------------------------------------------------------------
+ * Uniform hexahedra of a triply periodic box, nx x ny x nz elements of size
+ * len / (nx, ny, nz); Gauss solution points; state q = (rho, rho u, rho v, rho w, E)
+ * stored [v][e][k] with e = (ez ny + ey) nx + ex and k = (c n + b) n + a (a along x,
+ * c along z), n = p + 1.  mu > 0: Navier-Stokes with the BR2 common gradient (as
+ * FR_BR2 above: each side's raw gradient plus its lifting with (P+1)(P+2)/2), zero
+ * bulk viscosity; mu = 0: Euler.  Common inviscid flux FR_RUSANOV or FR_ROE. */
+typedef struct fr3d_disc fr3d_disc;  /* opaque */
+typedef struct {
+  int nx, ny, nz;   /* elements per direction, >= 2 */
+  int p;            /* 2 .. 4 */
+  int flux;         /* FR_RUSANOV or FR_ROE */
+  double lo[3];     /* box corner */
+  double len[3];    /* box side lengths, > 0 */
+  double gamma, rgas, mu, prandtl;
+} fr3d_desc;
+
+/* FR_EINVAL for sizes or parameters out of range. */
+fr_status fr3d_create(const fr3d_desc* desc, fr3d_disc** out);
+void fr3d_destroy(fr3d_disc* disc);
+/* 5 * nel * (p+1)^3. */
+size_t fr3d_ndof(const fr3d_disc* disc);
+/* Workspace of every fr3d_ call below: the face traces (and raw face gradients with
+ * mu > 0), reduction partials and two state vectors (SSPRK3 stages). */
+size_t fr3d_workspace_bytes(const fr3d_disc* disc);
+/* Physical coordinates of the solution points: h_xyz[3][nel (p+1)^3] on the host. */
+fr_status fr3d_solution_points(const fr3d_disc* disc, double* h_xyz);
+/* R(q): -sum_d (2/h_d)(D f_d + correction terms), f_d inviscid minus viscous flux. */
+fr_status fr3d_residual(const fr3d_disc* disc, const double* d_U, double* d_R, void* d_work, fr_stream stream);
+/* w = shift v - [R(U + e v) - R0] / e, e = eps / rms(v) (FR_EPS_RMS) or eps (Section 4.5). */
+fr_status fr3d_jf_matvec(const fr3d_disc* disc, const double* d_U, const double* d_R0, const double* d_v,
+                         double shift, double eps, int eps_mode, double* d_w, void* d_work, fr_stream stream);
+/* One SSPRK3 step in place (the paper's explicit reference integrator, Section 5.3):
+ * U1 = U + dt R(U), U2 = 3/4 U + 1/4 (U1 + dt R(U1)), U = 1/3 U + 2/3 (U2 + dt R(U2)). */
+fr_status fr3d_ssprk3_step(const fr3d_disc* disc, double* d_U, double dt, void* d_work, fr_stream stream);
+/* Kinetic energy and dissipation rates of Section 5.3 (h_out = E_k, eps1, eps3; eps2 = 0
+ * at zero bulk viscosity): E_k = int rho |u|^2/2 dV / (rho0 V), eps1 = 2 mu int S^d:S^d dV /
+ * (rho0 V), eps3 = -int p div u dV / (rho0 V), the velocity gradient from the raw gradient
+ * of each element's solution polynomial, Gauss quadrature.  Synchronises. */
+fr_status fr3d_dissipation(const fr3d_disc* disc, const double* d_U, double rho0, double* h_out, void* d_work,
+                           fr_stream stream);
+
 /* Last error message of this thread ("" if none). */
 const char* fr_last_error(void);
 

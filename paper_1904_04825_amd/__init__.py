@@ -5,8 +5,8 @@ include/frjf.h; this package is a thin binding that marshals torch tensors
 (device memory, streams) into those calls.
 """
 from .api import (Disc, Ejacobi, GmresOpts, SolverOpts, FrError, Mlp, MlpTrainer, StageLog, StageLogs, WarmStart,
-                  EULER, NS_BR1, RUSANOV, ROE, F64, F32, EPS_ABS, EPS_RMS, PC_EJACOBI, PC_LUSGS, PC_PMG, Pmg, fit_group)
+                  EULER, NS_BR1, RUSANOV, ROE, F64, F32, EPS_ABS, EPS_RMS, PC_EJACOBI, PC_LUSGS, PC_PMG, Pmg, fit_group, Disc3D)
 
 __all__ = ["Disc", "Ejacobi", "GmresOpts", "SolverOpts", "FrError", "Mlp", "MlpTrainer", "StageLog", "StageLogs",
            "WarmStart", "EULER", "NS_BR1", "RUSANOV", "ROE",
-           "F64", "F32", "EPS_ABS", "EPS_RMS", "PC_EJACOBI", "PC_LUSGS", "PC_PMG", "Pmg", "fit_group"]
+           "F64", "F32", "EPS_ABS", "EPS_RMS", "PC_EJACOBI", "PC_LUSGS", "PC_PMG", "Pmg", "fit_group", "Disc3D"]

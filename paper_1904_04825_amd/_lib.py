@@ -21,6 +21,12 @@ class DiscDesc(Structure):
                 ("q_far", c_double * 4)]
 
 
+class Desc3C(Structure):
+    _fields_ = [("nx", c_int), ("ny", c_int), ("nz", c_int), ("p", c_int), ("flux", c_int),
+                ("lo", c_double * 3), ("len", c_double * 3), ("gamma", c_double), ("rgas", c_double),
+                ("mu", c_double), ("prandtl", c_double)]
+
+
 class EjacobiC(Structure):
     _fields_ = [("d_factors", c_void_p), ("precision", c_int), ("shift", c_double), ("mg", c_void_p)]
 
@@ -116,6 +122,16 @@ _SIGS = {
     "fr_mlp_train_group": (c_int, [c_void_p, POINTER(MlpTrainerC), POINTER(StageLogC), c_int, c_void_p, c_int, c_int,
                                    POINTER(ctypes.c_float), POINTER(c_double), c_void_p, c_void_p]),
     "fr_wall_force": (c_int, [c_void_p, c_void_p, POINTER(c_double), c_void_p, c_void_p]),
+    "fr3d_create": (c_int, [POINTER(Desc3C), POINTER(c_void_p)]),
+    "fr3d_destroy": (None, [c_void_p]),
+    "fr3d_ndof": (c_size_t, [c_void_p]),
+    "fr3d_workspace_bytes": (c_size_t, [c_void_p]),
+    "fr3d_solution_points": (c_int, [c_void_p, c_void_p]),
+    "fr3d_residual": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "fr3d_jf_matvec": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double, c_int, c_void_p,
+                               c_void_p, c_void_p]),
+    "fr3d_ssprk3_step": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_void_p]),
+    "fr3d_dissipation": (c_int, [c_void_p, c_void_p, c_double, POINTER(c_double), c_void_p, c_void_p]),
     "fr_last_error": (ctypes.c_char_p, []),
 }
 

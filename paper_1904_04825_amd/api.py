@@ -374,6 +374,75 @@ class Disc:
         return f[0], f[1]
 
 
+# ---------------------------------------------------------------- 3D hexahedra
+class Disc3D:
+    """Uniform hexahedra of a triply periodic box with FR degree p, bound to one GPU
+    (fr3d_* of the C ABI); mu > 0 gives Navier-Stokes with the BR2 gradient, mu = 0 Euler."""
+
+    def __init__(self, nx, ny, nz, p, lo, length, flux="roe", gamma=1.4, rgas=1.0, mu=0.0, prandtl=0.71,
+                 device="cuda"):
+        self.lib = L.lib()
+        self.device = torch.device(device)
+        self.nx, self.ny, self.nz, self.p, self.n = nx, ny, nz, p, p + 1
+        self.np_ = self.n ** 3
+        self.nel = nx * ny * nz
+        desc = L.Desc3C(nx, ny, nz, p, _FLUX.get(flux, flux), (ctypes.c_double * 3)(*lo),
+                        (ctypes.c_double * 3)(*length), gamma, rgas, mu, prandtl)
+        h = ctypes.c_void_p()
+        _check("fr3d_create", self.lib.fr3d_create(ctypes.byref(desc), ctypes.byref(h)))
+        self.handle = h
+        self.ndof = int(self.lib.fr3d_ndof(h))
+        self.shape = (5, self.nel, self.np_)
+        self.work = torch.empty(int(self.lib.fr3d_workspace_bytes(h)), dtype=torch.uint8, device=self.device)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self.lib.fr3d_destroy(h)
+            self.handle = None
+
+    def _vec(self, t, name):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_contiguous() \
+                or t.device != self.device or t.numel() != self.ndof:
+            raise ValueError(f"{name}: expected a contiguous float64 {self.device} tensor with {self.ndof} entries")
+        return t
+
+    def empty(self):
+        return torch.empty(self.shape, dtype=torch.float64, device=self.device)
+
+    def solution_points(self):
+        import numpy as np
+        xyz = np.empty((3, self.nel * self.np_))
+        _check("fr3d_solution_points", self.lib.fr3d_solution_points(self.handle, xyz.ctypes.data))
+        return xyz
+
+    def residual(self, U, out=None):
+        self._vec(U, "U")
+        out = self.empty() if out is None else out
+        _check("fr3d_residual", self.lib.fr3d_residual(self.handle, _ptr(U), _ptr(out), _ptr(self.work), _stream()))
+        return out
+
+    def jf_matvec(self, U, R0, v, shift, eps=1e-8, eps_mode=EPS_RMS, out=None):
+        for t, nm in ((U, "U"), (R0, "R0"), (v, "v")):
+            self._vec(t, nm)
+        out = self.empty() if out is None else out
+        _check("fr3d_jf_matvec", self.lib.fr3d_jf_matvec(self.handle, _ptr(U), _ptr(R0), _ptr(v), shift, eps, eps_mode,
+                                                         _ptr(out), _ptr(self.work), _stream()))
+        return out
+
+    def ssprk3_step(self, U, dt):
+        self._vec(U, "U")
+        _check("fr3d_ssprk3_step", self.lib.fr3d_ssprk3_step(self.handle, _ptr(U), dt, _ptr(self.work), _stream()))
+
+    def dissipation(self, U, rho0=1.0):
+        """(E_k, eps1, eps3) of the Taylor-Green diagnostics."""
+        self._vec(U, "U")
+        h = (ctypes.c_double * 3)()
+        _check("fr3d_dissipation", self.lib.fr3d_dissipation(self.handle, _ptr(U), rho0, h, _ptr(self.work),
+                                                             _stream()))
+        return h[0], h[1], h[2]
+
+
 # ---------------------------------------------------------------- learned warm start
 class Mlp:
     """Per-element MLP (BF16 weights) on the device; sizes fixed by the disc's degree."""

@@ -554,6 +554,144 @@ fr_status fr_mlp_train_group(const fr_disc* d, fr_mlp_trainer* trs, const fr_sta
   return FR_OK;
 }
 
+// ---------------------------------------------------------------- 3D hexahedral FR
+struct Work3 {
+  void* traces;
+  double* scal;
+  double* partials;
+  double* R;
+  double* U1;
+};
+static size_t r256(size_t b) { return (b + 255) & ~(size_t)255; }
+static Work3 carve3(const fr3d_disc* d, void* work) {
+  char* p = (char*)work;
+  Work3 w;
+  w.traces = p;
+  p += r256(fr3d_trace_bytes(d));
+  w.scal = (double*)p;
+  p += 256;
+  w.partials = (double*)p;
+  p += r256(sizeof(double) * std::max<size_t>(kRedBlocks, 3 * (size_t)d->nel));
+  w.R = (double*)p;
+  p += r256(sizeof(double) * d->ndof);
+  w.U1 = (double*)p;
+  return w;
+}
+
+fr_status fr3d_create(const fr3d_desc* desc, fr3d_disc** out) {
+  clear_error();
+  CHECK(desc != nullptr && out != nullptr, "fr3d_create: null argument");
+  CHECK(desc->p >= 2 && desc->p <= 4, "fr3d_create: p must be 2 .. 4");
+  CHECK(desc->nx >= 2 && desc->ny >= 2 && desc->nz >= 2, "fr3d_create: nx, ny and nz must be >= 2");
+  CHECK((size_t)desc->nx * desc->ny * desc->nz < (1u << 28), "fr3d_create: mesh too large");
+  CHECK(desc->flux == FR_RUSANOV || desc->flux == FR_ROE, "fr3d_create: bad flux");
+  CHECK(desc->len[0] > 0.0 && desc->len[1] > 0.0 && desc->len[2] > 0.0, "fr3d_create: box lengths must be positive");
+  CHECK(desc->gamma > 1.0 && desc->rgas > 0.0 && desc->mu >= 0.0 && desc->prandtl > 0.0,
+        "fr3d_create: gamma > 1, R > 0, mu >= 0 and Pr > 0 required");
+  fr3d_disc* d = new fr3d_disc{};
+  d->nx = desc->nx;
+  d->ny = desc->ny;
+  d->nz = desc->nz;
+  d->p = desc->p;
+  d->n = desc->p + 1;
+  d->np = d->n * d->n * d->n;
+  d->nel = desc->nx * desc->ny * desc->nz;
+  d->flux = desc->flux;
+  d->ndof = (size_t)5 * d->nel * d->np;
+  const int ne[3] = {desc->nx, desc->ny, desc->nz};
+  for (int i = 0; i < 3; ++i) {
+    d->lo[i] = desc->lo[i];
+    d->h[i] = desc->len[i] / ne[i];
+  }
+  d->gamma = desc->gamma;
+  d->rgas = desc->rgas;
+  d->mu = desc->mu;
+  d->prandtl = desc->prandtl;
+  d->basis = make_basis(desc->p);
+  *out = d;
+  return FR_OK;
+}
+
+void fr3d_destroy(fr3d_disc* d) { delete d; }
+
+size_t fr3d_ndof(const fr3d_disc* d) { return d ? d->ndof : 0; }
+
+size_t fr3d_workspace_bytes(const fr3d_disc* d) {
+  if (d == nullptr) return 0;
+  return r256(fr3d_trace_bytes(d)) + 256 + r256(sizeof(double) * std::max<size_t>(kRedBlocks, 3 * (size_t)d->nel)) +
+         2 * r256(sizeof(double) * d->ndof);
+}
+
+fr_status fr3d_solution_points(const fr3d_disc* d, double* xyz) {
+  clear_error();
+  CHECK(d && xyz, "fr3d_solution_points: null argument");
+  const int n = d->n;
+  const size_t per = (size_t)d->nel * d->np;
+  for (int e = 0; e < d->nel; ++e) {
+    const int ex = e % d->nx, ey = (e / d->nx) % d->ny, ez = e / (d->nx * d->ny);
+    for (int k = 0; k < d->np; ++k) {
+      const int a = k % n, b = (k / n) % n, c = k / (n * n);
+      const size_t i = (size_t)e * d->np + k;
+      xyz[i] = d->lo[0] + d->h[0] * (ex + 0.5 * (d->basis.x[a] + 1.0));
+      xyz[per + i] = d->lo[1] + d->h[1] * (ey + 0.5 * (d->basis.x[b] + 1.0));
+      xyz[2 * per + i] = d->lo[2] + d->h[2] * (ez + 0.5 * (d->basis.x[c] + 1.0));
+    }
+  }
+  return FR_OK;
+}
+
+fr_status fr3d_residual(const fr3d_disc* d, const double* U, double* R, void* work, fr_stream s) {
+  clear_error();
+  CHECK(d && U && R && work, "fr3d_residual: null argument");
+  CHECK(U != R, "fr3d_residual: U and R alias");
+  FR_HIP(launch_fr3d_residual(d, 0, U, nullptr, nullptr, 0.0, 0.0, FR_EPS_ABS, nullptr, R, work, S(s)));
+  return FR_OK;
+}
+
+fr_status fr3d_jf_matvec(const fr3d_disc* d, const double* U, const double* R0, const double* v, double shift,
+                         double eps, int eps_mode, double* w, void* work, fr_stream s) {
+  clear_error();
+  CHECK(d && U && R0 && v && w && work, "fr3d_jf_matvec: null argument");
+  CHECK(w != U && w != R0 && w != v, "fr3d_jf_matvec: the output aliases an input");
+  CHECK(eps_mode == FR_EPS_ABS || eps_mode == FR_EPS_RMS, "fr3d_jf_matvec: bad eps_mode");
+  CHECK(eps > 0.0, "fr3d_jf_matvec: eps must be positive");
+  Work3 k = carve3(d, work);
+  if (eps_mode == FR_EPS_RMS) FR_HIP(launch_norm2(v, d->ndof, k.partials, k.scal, nullptr, S(s)));
+  FR_HIP(launch_fr3d_residual(d, 1, U, v, R0, shift, eps, eps_mode, k.scal, w, k.traces, S(s)));
+  return FR_OK;
+}
+
+fr_status fr3d_ssprk3_step(const fr3d_disc* d, double* U, double dt, void* work, fr_stream s) {
+  clear_error();
+  CHECK(d && U && work, "fr3d_ssprk3_step: null argument");
+  CHECK(dt > 0.0, "fr3d_ssprk3_step: dt must be positive");
+  Work3 k = carve3(d, work);
+  const size_t n = d->ndof;
+  FR_HIP(launch_fr3d_residual(d, 0, U, nullptr, nullptr, 0.0, 0.0, FR_EPS_ABS, nullptr, k.R, k.traces, S(s)));
+  FR_HIP(launch_fr3d_combine(k.U1, U, U, k.R, 0.0, 1.0, dt, n, S(s)));          // U1 = U + dt R(U)
+  FR_HIP(launch_fr3d_residual(d, 0, k.U1, nullptr, nullptr, 0.0, 0.0, FR_EPS_ABS, nullptr, k.R, k.traces, S(s)));
+  FR_HIP(launch_fr3d_combine(k.U1, U, k.U1, k.R, 0.75, 0.25, dt, n, S(s)));     // U2 = 3/4 U + 1/4 (U1 + dt R(U1))
+  FR_HIP(launch_fr3d_residual(d, 0, k.U1, nullptr, nullptr, 0.0, 0.0, FR_EPS_ABS, nullptr, k.R, k.traces, S(s)));
+  FR_HIP(launch_fr3d_combine(U, U, k.U1, k.R, 1.0 / 3.0, 2.0 / 3.0, dt, n, S(s)));  // U = 1/3 U + 2/3 (U2 + dt R(U2))
+  return FR_OK;
+}
+
+fr_status fr3d_dissipation(const fr3d_disc* d, const double* U, double rho0, double* h_out, void* work, fr_stream s) {
+  clear_error();
+  CHECK(d && U && h_out && work && rho0 > 0.0, "fr3d_dissipation: null argument or rho0 <= 0");
+  Work3 k = carve3(d, work);
+  FR_HIP(launch_fr3d_dissipation(d, U, k.partials, S(s)));
+  FR_HIP(launch_finalize(k.partials, d->nel, 3, 3, k.scal, nullptr, S(s)));
+  double h[3];
+  FR_HIP(hipMemcpyAsync(h, k.scal, sizeof(h), hipMemcpyDeviceToHost, S(s)));
+  FR_HIP(hipStreamSynchronize(S(s)));
+  const double V = d->h[0] * d->h[1] * d->h[2] * d->nel;
+  h_out[0] = h[0] / (rho0 * V);
+  h_out[1] = 2.0 * d->mu * h[1] / (rho0 * V);
+  h_out[2] = -h[2] / (rho0 * V);
+  return FR_OK;
+}
+
 int fr_scheme_table(int kind, int scheme, double* a, double* c, double* b, double* gamma) {
   if (!a || !b || !gamma) return FR_EINVAL;
   if (kind == 0) {

@@ -55,6 +55,15 @@ struct fr_disc {
   hipEvent_t ev[4];
 };
 
+// 3D hexahedral discretisation (uniform elements of a triply periodic box)
+struct fr3d_disc {
+  int nx, ny, nz, p, n, np, nel, flux;
+  size_t ndof;
+  double lo[3], h[3];
+  double gamma, rgas, mu, prandtl;
+  frjf::Basis basis;
+};
+
 namespace frjf {
 
 // error reporting (thread-local message)
@@ -153,6 +162,14 @@ hipError_t launch_ejacobi_solve(const fr_disc* d, const void* factors, int preci
 hipError_t launch_solution_points(const fr_disc* d, double* xy, hipStream_t s);
 // force of the fluid on the wall (ns.hip): per element of row 0, its wall face's momentum flux
 hipError_t launch_ns_wall_flux(const fr_disc* d, const double* U, double* part, hipStream_t s);
+// 3D hexahedral FR (fr3d.hip)
+size_t fr3d_trace_bytes(const fr3d_disc* d);
+hipError_t launch_fr3d_residual(const fr3d_disc* d, int mode, const double* U, const double* V, const double* R0,
+                                double shift, double eps, int eps_mode, const double* nrm2, double* out, void* work,
+                                hipStream_t s);
+hipError_t launch_fr3d_combine(double* out, const double* A, const double* Bv, const double* R, double alpha,
+                               double beta, double dt, size_t n, hipStream_t s);
+hipError_t launch_fr3d_dissipation(const fr3d_disc* d, const double* U, double* part, hipStream_t s);
 hipError_t launch_l2_vortex(const fr_disc* d, const double* U, int var, double t, const double* prm,
                             double* partials, double* out, hipStream_t s);
 
