@@ -83,6 +83,14 @@ def parse():
     ap.add_argument("--cyl-dtref", type=float, default=0.00625)
     ap.add_argument("--cyl-tolnl", type=float, default=1e-6, help="ESDIRK / BDF2 nonlinear tolerance (the paper's 1e-6)")
     ap.add_argument("--cyl-tollin", type=float, default=1e-6, help="ROW linear tolerance (the paper's 1e-6)")
+    ap.add_argument("--tgv", action="store_true",
+                    help="instead of the bench line: the Taylor-Green vortex on 3D hexahedra (residual timing, "
+                         "SSPRK3 steps with the dissipation diagnostics)")
+    ap.add_argument("--tgv-n", type=int, default=64)
+    ap.add_argument("--tgv-p", type=int, default=3)
+    ap.add_argument("--tgv-steps", type=int, default=50)
+    ap.add_argument("--tgv-dt", type=float, default=2e-4, help="SSPRK3 step in units of t_c (the paper's 2e-4)")
+    ap.add_argument("--tgv-sample", type=int, default=10)
     ap.add_argument("--mach-reading", default="magnitude", choices=["magnitude", "u"],
                     help="velocity of the paper's Mach number: |V| or u")
     ap.add_argument("--study-eps", default="rms", choices=["abs", "rms"],
@@ -505,6 +513,65 @@ def cylinder_study(schemes, dts, t_dev, t_run, dt_ref, pc_prec="f32", tol_nl=1e-
             "rows": rows}
 
 
+def tgv_study(n_el, P, steps, dt_tc, sample_every, verbose=True):
+    """The Taylor-Green vortex of Section 5.3 on n_el^3 uniform P hexahedra (the paper's
+    mesh is 64^3 P3: 83.9M DOFs), Re 1600, Ma 0.1, BR2, Roe.  Times the 3D residual with
+    HIP events (DOF-residuals/s, and algorithmic bytes per second: the state in and the
+    residual out, plus the face traces and raw face gradients the first kernel writes and
+    the second reads), then runs `steps` SSPRK3 steps of dt_tc t_c (the paper's explicit
+    reference integrator) from t = 0 with E_k, eps1 and eps3 every sample_every steps."""
+    import math
+
+    import torch
+
+    import fr_inputs as fi
+    from paper_1904_04825_amd import Disc3D
+    tg = fi.TaylorGreen()
+    L = tg.L
+    disc = Disc3D(n_el, n_el, n_el, P, (-math.pi * L,) * 3, (2 * math.pi * L,) * 3, flux="roe", mu=tg.mu,
+                  prandtl=tg.prandtl, gamma=tg.gamma, rgas=tg.rgas)
+    xyz = disc.solution_points()
+    U = torch.as_tensor(tg.conservative(xyz[0], xyz[1], xyz[2]), device=disc.device).reshape(disc.shape).contiguous()
+    R = disc.empty()
+    progress("tgv: residual timing")
+    for _ in range(3):
+        disc.residual(U, R)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record(s)
+    for _ in range(reps):
+        disc.residual(U, R)
+    e1.record(s)
+    e1.synchronize()
+    t_res = e0.elapsed_time(e1) / 1e3 / reps
+    n2 = (P + 1) ** 2
+    face = disc.nel * 6 * 5 * n2 * 8
+    alg = 2 * 8 * disc.ndof + 2 * 4 * face          # state in, R out; traces and gradients (x, y, z) written and read
+    tc = L / tg.V0
+    dt = dt_tc * tc
+    hist = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in range(steps + 1):
+        if it % sample_every == 0:
+            ek, e1_, e3 = disc.dissipation(U, tg.rho0)
+            hist.append({"t_tc": it * dt_tc, "E_k": ek, "eps1": e1_, "eps3": e3})
+            if verbose:
+                print(f"# t/t_c {it * dt_tc:.4f}: E_k {ek:.6e}, eps1 {e1_:.6e}, eps3 {e3:.3e}", flush=True)
+        if it < steps:
+            disc.ssprk3_step(U, dt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return {"mode": "tgv", "mesh": f"{n_el}^3 hexahedra, P{P}", "ndof": disc.ndof, "reynolds": 1600, "mach": 0.1,
+            "viscous": "BR2", "flux": "Roe",
+            "residual": {"us": t_res * 1e6, "dof_res_per_s": disc.ndof / t_res, "alg_bytes": alg,
+                         "GBs": alg / t_res / 1e9},
+            "ssprk3": {"dt_tc": dt_tc, "steps": steps, "wall_s": wall,
+                       "ms_per_step": 1e3 * wall / max(steps, 1)},
+            "history": hist}
+
+
 def precond_study(disc, W, U, dt, scheme, lin):
     """The first ROW stage's linear system at the timed legs' start state, solved to the
     same tolerance with each preconditioner on FP32 blocks: element-Jacobi (the paper's),
@@ -564,6 +631,9 @@ def main():
     if args.paper_vortex is not None:
         sel = "all" if args.paper_vortex == "all" else set(args.paper_vortex.split(","))
         print(json.dumps(paper_vortex_study(sel, args.mach_reading, args.study_eps, args.study_precond)), flush=True)
+        return
+    if args.tgv:
+        print(json.dumps(tgv_study(args.tgv_n, args.tgv_p, args.tgv_steps, args.tgv_dt, args.tgv_sample)), flush=True)
         return
     if args.cylinder:
         print(json.dumps(cylinder_study(args.cyl_schemes.split(","), [float(x) for x in args.cyl_dts.split(",")],

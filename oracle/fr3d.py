@@ -251,29 +251,6 @@ class NavierStokes3D:
         return R.reshape(np.shape(U))
 
 
-class TaylorGreen:
-    """Taylor-Green vortex (Section 5.3): u = V0 sin(x/L) cos(y/L) cos(z/L),
-    v = -V0 cos(x/L) sin(y/L) cos(z/L), w = 0,
-    p = p0 + rho0 V0^2 / 16 (cos(2x/L) + cos(2y/L)) (cos(2z/L) + 2), on [-pi L, pi L]^3,
-    Re = rho0 V0 L / mu = 1600, Pr = 0.71, Ma = V0 / c0 = 0.1 (c0 from p0 and rho0),
-    density rho = p / (R T0) at the uniform temperature T0 = p0 / (rho0 R)."""
-
-    def __init__(self, L=1.0, V0=1.0, rho0=1.0, mach=0.1, reynolds=1600.0, gamma=1.4, rgas=1.0, prandtl=0.71):
-        self.L, self.V0, self.rho0, self.gamma, self.rgas, self.prandtl = L, V0, rho0, gamma, rgas, prandtl
-        c0 = V0 / mach
-        self.p0 = rho0 * c0 * c0 / gamma
-        self.mu = rho0 * V0 * L / reynolds
-
-    def conservative(self, x, y, z):
-        L, V0 = self.L, self.V0
-        u = V0 * np.sin(x / L) * np.cos(y / L) * np.cos(z / L)
-        v = -V0 * np.cos(x / L) * np.sin(y / L) * np.cos(z / L)
-        w = np.zeros_like(u)
-        p = self.p0 + self.rho0 * V0 * V0 / 16.0 * (np.cos(2 * x / L) + np.cos(2 * y / L)) * (np.cos(2 * z / L) + 2.0)
-        rho = p / self.p0 * self.rho0
-        return np.stack([rho, rho * u, rho * v, rho * w, p / (self.gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
-
-
 def dissipation(op, U, rho0):
     """Kinetic energy E_k = (1/(rho0 V)) int rho |u|^2 / 2 dV and the dissipation rates of
     Section 5.3: eps1 = 2 mu / (rho0 V) int S^d : S^d dV and eps3 = -(1/(rho0 V)) int p div u dV

@@ -394,6 +394,7 @@ class Disc3D:
         self.ndof = int(self.lib.fr3d_ndof(h))
         self.shape = (5, self.nel, self.np_)
         self.work = torch.empty(int(self.lib.fr3d_workspace_bytes(h)), dtype=torch.uint8, device=self.device)
+        self.device = self.work.device        # with its index (cuda:0)
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -7,7 +7,8 @@ import numpy as np
 import pytest
 import torch
 
-from oracle.fr3d import Box3D, NavierStokes3D, TaylorGreen, dissipation, ssprk3_step
+import fr_inputs as fi
+from oracle.fr3d import Box3D, NavierStokes3D, dissipation, ssprk3_step
 from tests.gpu_common import rel, to_gpu, to_np
 from tests.test_oracle_fr3d import _state3d
 
@@ -72,7 +73,7 @@ def test_jf_product_parity(mu):
 def test_taylor_green_ssprk3_and_dissipation():
     """The Taylor-Green vortex on 4^3 P3: three SSPRK3 steps of dt = 0.02 t_c agree with the
     oracle's, and so do E_k, eps1 and eps3 before and after."""
-    tg = TaylorGreen()
+    tg = fi.TaylorGreen()
     box, op, disc = _pair(4, 4, 4, 3, tg.mu, "roe", lo=(-math.pi,) * 3, L=(2 * math.pi,) * 3)
     x, y, z = box.points()
     U = tg.conservative(x, y, z).reshape(5, box.nel, -1)

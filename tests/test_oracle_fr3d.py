@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import fr_inputs as fi
-from oracle.fr3d import Box3D, NavierStokes3D, TaylorGreen, dissipation, inviscid_flux, ssprk3_step, viscous_flux
+from oracle.fr3d import Box3D, NavierStokes3D, dissipation, inviscid_flux, ssprk3_step, viscous_flux
 from oracle.problem import make_ns_bc
 
 GAM = 1.4
@@ -131,7 +131,7 @@ def test_residual_converges_to_pde_rhs(P):
 def test_taylor_green_initial_energy_and_dissipation():
     """E_k(0) = V0^2 / 8 up to the O(M^2) density variation, eps3(0) = 0 (div u = 0) and
     eps1(0) = 2 mu <S:S> / rho0 = 3 mu V0^2 / (4 rho0 L^2), approached as the mesh refines."""
-    tg = TaylorGreen()
+    tg = fi.TaylorGreen()
     errs = []
     for n in (4, 8):
         box = Box3D(n, n, n, [-math.pi] * 3, [2 * math.pi] * 3, 3)
