@@ -432,7 +432,7 @@ def cylinder_study(schemes, dts, t_dev, t_run, dt_ref, pc_prec="f32", tol_nl=1e-
                 prandtl=cyl.prandtl, viscous="br2", bc_south="wall", bc_north="farfield", q_far=cyl.far_state())
     xy = disc.solution_points().cpu().numpy()
     U0 = torch.as_tensor(cyl.conservative(xy[0], xy[1], perturb=0.05), device=disc.device).contiguous()
-    qinf = 0.5 * cyl.mach ** 2          # rho u^2 / 2 with rho = 1, D = 1
+    qinf = 0.5 * cyl.speed ** 2         # rho u^2 / 2 with rho = 1, D = 1
 
     def cd(U):
         return disc.wall_force(U)[0] / qinf

@@ -180,20 +180,27 @@ def ogrid_nodes(nx: int, ny: int, r0: float = 0.5, r1: float = 100.0, first: flo
 @dataclass(frozen=True)
 class Cylinder:
     """Laminar flow past a circular cylinder of diameter 1 (Section 5.2): Ma = 0.1 and
-    Re = 1200 on the diameter and the free stream; rho = 1, c = 1 (p = 1/gamma), u = Ma,
-    v = 0, mu = rho u D / Re.  The far-field state is the free stream."""
+    Re = 1200 on the diameter and the free stream.  Velocity scale (not stated by the paper):
+    the free stream u = 1, so the convective time D/u is the time unit; rho = 1, c = u/Ma = 10,
+    p = rho c^2 / gamma, v = 0, mu = rho u D / Re.  The far-field state is the free stream."""
     gamma: float = GAMMA
     rgas: float = 1.0
     mach: float = 0.1
     reynolds: float = 1200.0
     prandtl: float = 0.71
+    speed: float = 1.0
 
     @property
     def mu(self) -> float:
-        return self.mach / self.reynolds
+        return self.speed / self.reynolds
+
+    @property
+    def p_inf(self) -> float:
+        c = self.speed / self.mach
+        return c * c / self.gamma
 
     def far_state(self) -> np.ndarray:
-        rho, u, p = 1.0, self.mach, 1.0 / self.gamma
+        rho, u, p = 1.0, self.speed, self.p_inf
         return np.array([rho, rho * u, 0.0, p / (self.gamma - 1.0) + 0.5 * rho * u * u])
 
     def conservative(self, x, y, perturb: float = 0.0):
@@ -205,7 +212,7 @@ class Cylinder:
         q = self.far_state()
         rho, u = q[0], q[1] / q[0]
         v = perturb * u * np.exp(-((x - 1.5) ** 2 + y ** 2) / 0.5)
-        p = 1.0 / self.gamma
+        p = self.p_inf
         return np.stack([np.full_like(x, rho), np.full_like(x, rho * u), rho * v,
                          p / (self.gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
 
