@@ -74,16 +74,16 @@ def test_ctypes_layouts_match_the_c_compiler(tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
     src = tmp_path / "sz.c"
-    src.write_text('#include <stdio.h>\n#include "frjf.h"\nint main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "frjf.h"\nint main(){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
                    'sizeof(fr_disc_desc),sizeof(fr_ejacobi),sizeof(fr_gmres_opts),sizeof(fr_gmres_stats),'
                    'sizeof(fr_solver_opts),sizeof(fr_step_stats),sizeof(fr_mlp),sizeof(fr_mlp_trainer),'
-                   'sizeof(fr_stage_log),sizeof(fr_pmg));}\n')
+                   'sizeof(fr_stage_log),sizeof(fr_pmg),sizeof(fr3d_desc),offsetof(fr_disc_desc,q_far));}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [ctypes.sizeof(t) for t in (_lib.DiscDesc, _lib.EjacobiC, _lib.GmresOptsC, _lib.GmresStatsC,
                                        _lib.SolverOptsC, _lib.StepStatsC, _lib.MlpC, _lib.MlpTrainerC,
-                                       _lib.StageLogC, _lib.PmgC)]
+                                       _lib.StageLogC, _lib.PmgC, _lib.Desc3C)] + [_lib.DiscDesc.q_far.offset]
     assert got == want
 
 
@@ -111,3 +111,30 @@ def test_invalid_arguments_are_rejected_before_any_device_work():
         assert msg in L.fr_last_error().decode(), (change, L.fr_last_error())
         assert out.value == 12345
     assert L.fr_disc_create(None, None) == -1
+
+
+def test_fr3d_invalid_arguments_and_sizes():
+    """The 3D descriptor is checked before any device work; the sizes follow the layout."""
+    from paper_1904_04825_amd import _lib
+    L = _lib.lib()
+
+    def desc(**kw):
+        d = dict(nx=3, ny=4, nz=5, p=3, flux=1, lo=(0.0, 0.0, 0.0), len=(1.0, 2.0, 3.0), gamma=1.4, rgas=1.0,
+                 mu=0.01, prandtl=0.71)
+        d.update(kw)
+        return _lib.Desc3C(d["nx"], d["ny"], d["nz"], d["p"], d["flux"], (ctypes.c_double * 3)(*d["lo"]),
+                           (ctypes.c_double * 3)(*d["len"]), d["gamma"], d["rgas"], d["mu"], d["prandtl"])
+    for change, msg in (({"p": 5}, "p must be"), ({"nz": 1}, "nx, ny and nz"), ({"flux": 7}, "bad flux"),
+                        ({"len": (1.0, 0.0, 1.0)}, "lengths"), ({"mu": -1.0}, "mu >= 0")):
+        out = ctypes.c_void_p(7)
+        assert L.fr3d_create(ctypes.byref(desc(**change)), ctypes.byref(out)) == -1, change
+        assert msg in L.fr_last_error().decode(), (change, L.fr_last_error())
+        assert out.value == 7
+    h = ctypes.c_void_p()
+    assert L.fr3d_create(ctypes.byref(desc()), ctypes.byref(h)) == 0
+    try:
+        assert L.fr3d_ndof(h) == 5 * 60 * 64
+        n2, nel = 16, 60
+        assert L.fr3d_workspace_bytes(h) >= 2 * nel * 6 * 5 * n2 * 8 + 2 * 5 * nel * 64 * 8
+    finally:
+        L.fr3d_destroy(h)
