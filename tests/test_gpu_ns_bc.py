@@ -129,7 +129,10 @@ def test_row3_and_bdf2_steps(visc):
     # at dt = 0.2 the ROW stage systems of the impulsive start do not converge to 1e-10 within
     # the iteration cap, for the oracle and the GPU alike (the paper's ROW methods fail at
     # dt = 0.2 on its cylinder too); at dt = 0.02 (acoustic Courant number c dt / h = 4 at
-    # the first layer) they do, and the two runs agree to 1e-8
+    # the first layer) they do.  At Mach 0.1 the pressure (71) dwarfs the dynamic terms (1),
+    # so R loses about two digits to rounding and the Jacobian-free products with it: a ROW
+    # step (three linear solves, no nonlinear iteration to pull it back) is held to 1e-8 or
+    # to 10x the oracle's own spread under a one-ulp change of the state, whichever is larger
     Ug = to_gpu(U)
     st = disc.row_step(Ug, 3, 0.2, SolverOpts(lin=GmresOpts(m=20, rtol=1e-10)))
     _, so = I.row_step(op, ROW["ROW3"], 0.2, U, I.LinOpts(m=20, rtol=1e-10))
@@ -138,7 +141,12 @@ def test_row3_and_bdf2_steps(visc):
     Ug = to_gpu(U)
     st = disc.row_step(Ug, 3, dt, SolverOpts(lin=GmresOpts(m=20, rtol=1e-10)))
     Uo, _ = I.row_step(op, ROW["ROW3"], dt, U, I.LinOpts(m=20, rtol=1e-10))
-    assert st["status"] == 0 and rel(to_np(Ug), Uo) <= 1e-8
+    rng = np.random.default_rng(5)
+    Uo2, _ = I.row_step(op, ROW["ROW3"], dt, np.nextafter(U, rng.choice([-np.inf, np.inf], size=U.shape)),
+                        I.LinOpts(m=20, rtol=1e-10))
+    err, spread = rel(to_np(Ug), Uo), rel(Uo2, Uo)
+    print(f"{visc} ROW3 dt={dt}: gpu vs oracle {err:.2e}, oracle spread under one ulp {spread:.2e}", flush=True)
+    assert st["status"] == 0 and err <= max(1e-8, 10 * spread)
     opts = SolverOpts(lin=GmresOpts(m=20, rtol=1e-1), tol_nl=1e-10, dtau_init=0.01, dtau_max=1.0)
     lin, nl = I.LinOpts(m=20, rtol=1e-1), I.NlOpts(tol_nl=1e-10, dtau_init=0.01, dtau_max=1.0)
     U1o, _ = I.bdf2_step(op, dt, None, U, lin, nl)
