@@ -12,17 +12,13 @@
 // with f_d the inviscid minus viscous flux along axis d.
 //
 // Kernel A (k3_faces): per element, its solution traces on the six faces and, with
-//   viscosity, the component along the face's axis of the raw gradient of its solution
-//   polynomial (no corrections) extrapolated there: T[e][f][v][j], Gn[e][f][v][j].  The
-//   two components along the face are the derivatives of the trace itself (the raw
-//   gradient is polynomial, so extrapolating its tangential part to the face and
-//   differentiating the face trace give the same values), so they are not stored.
-// Kernel B (k3_res): per element, its own traces and normal face gradients from its own
-//   state, the neighbours' from T and Gn; the common states (q_own + q_nbr)/2, the
+//   viscosity, the raw gradient of its solution polynomial (no corrections) extrapolated
+//   there: T[e][f][v][j], G[e][f][v][j][x|y|z].
+// Kernel B (k3_res): per element, the common states (q_own + q_nbr)/2 from T, the
 //   FR-corrected gradient at the solution points, the total fluxes there, the common
 //   fluxes on the faces (Riemann solver between the traces; viscous flux at the common
-//   state with the BR2 common gradient: the mean of the two sides' raw face gradients
-//   plus their liftings r = c_P (q^com - q_side) (2/h_d) n_out), and R.
+//   state with the BR2 common gradient: the mean of each side's G plus its lifting
+//   r = c_P (q^com - q_side) (2/h_d) n_out), and R.
 // MODE 0: out = R(U); MODE 1: out = shift v - (R(U + e v) - R0) / e (Jacobian-free product).
 #include <cmath>
 #include <vector>
@@ -38,7 +34,7 @@ struct Args3 {
   const double* R0;
   double* out;
   double* T;  // traces [nel][6][5][n^2]
-  double* G;  // raw face gradients along the face's axis [nel][6][5][n^2]
+  double* G;  // raw face gradients [nel][6][5][n^2][3]
   const double* nrm2;
   double eps, shift;
   int eps_mode;
@@ -202,24 +198,12 @@ __device__ __forceinline__ double eps3(const Args3& a, size_t ndof, bool* zero_v
 }
 
 // ---------------------------------------------------------------- kernel A: traces and raw face gradients
-// dl[s][m] = sum_i l_i(+-1) D[i][m]: the derivative of the interpolant at the face s
-template <int n>
-__device__ __forceinline__ void face_derivative_rows(const Basis& B, double dl[2][kMaxN], int tid) {
-  if (tid < 2 * n) {
-    const int side = tid / n, m = tid % n;
-    const double* lw = side ? B.lp : B.lm;
-    double x = 0.0;
-    for (int i = 0; i < n; ++i) x = fma(lw[i], B.D[i][m], x);
-    dl[side][m] = x;
-  }
-}
-
 template <int P, int MODE, bool VISC>
 __global__ void __launch_bounds__(C3<P>::NT) k3_faces(const Args3 a, const Basis B) {
   using C = C3<P>;
   constexpr int n = C::n, n2 = C::n2, Np = C::Np, NF = C::NF, NT = C::NT;
   __shared__ double q[5][Np];
-  __shared__ double dl[2][kMaxN];
+  __shared__ double gr[VISC ? 3 : 1][5][VISC ? Np : 1];
   const int el = blockIdx.x, tid = threadIdx.x;
   const size_t nel = (size_t)a.nel, ndof = 5 * nel * Np;
   bool zv = false;
@@ -227,21 +211,40 @@ __global__ void __launch_bounds__(C3<P>::NT) k3_faces(const Args3 a, const Basis
   for (int k = tid; k < Np; k += NT)
 #pragma unroll
     for (int v = 0; v < 5; ++v) q[v][k] = state3<MODE>(a, ((size_t)v * nel + el) * Np + k, e);
-  if constexpr (VISC) face_derivative_rows<n>(B, dl, tid);
   __syncthreads();
+  if constexpr (VISC) {
+    for (int k = tid; k < Np; k += NT) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        int j, t;
+        point_on_line<n>(k, d, &j, &t);
+        const double s = 2.0 / a.h[d];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          double x = 0.0;
+          for (int m = 0; m < n; ++m) x = fma(B.D[t][m], q[v][line_pt<n>(d, j, m)], x);
+          gr[d][v][k] = s * x;
+        }
+      }
+    }
+    __syncthreads();
+  }
   for (int idx = tid; idx < NF; idx += NT) {
     const int f = idx / n2, j = idx % n2, d = f >> 1;
     const double* lw = (f & 1) ? B.lp : B.lm;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      double x = 0.0, y = 0.0;
-      for (int m = 0; m < n; ++m) {
-        const double qm = q[v][line_pt<n>(d, j, m)];
-        x = fma(lw[m], qm, x);
-        if constexpr (VISC) y = fma(dl[f & 1][m], qm, y);
-      }
+      double x = 0.0;
+      for (int m = 0; m < n; ++m) x = fma(lw[m], q[v][line_pt<n>(d, j, m)], x);
       a.T[t_index(el, f, v, j, n2)] = x;
-      if constexpr (VISC) a.G[t_index(el, f, v, j, n2)] = (2.0 / a.h[d]) * y;
+      if constexpr (VISC) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          double y = 0.0;
+          for (int m = 0; m < n; ++m) y = fma(lw[m], gr[c][v][line_pt<n>(d, j, m)], y);
+          a.G[t_index(el, f, v, j, n2) * 3 + c] = y;
+        }
+      }
     }
   }
 }
@@ -253,12 +256,10 @@ __global__ void __launch_bounds__(C3<P>::NT) k3_res(const Args3 a, const Basis B
   constexpr int n = C::n, n2 = C::n2, Np = C::Np, NF = C::NF, NT = C::NT;
   constexpr double cP = 0.5 * (P + 1) * (P + 2);
   __shared__ double q[5][Np];
-  __shared__ double tr[6][5][n2];   // own traces
+  __shared__ double tr[6][5][n2];   // own traces, then the face jumps f^com - f^l
   __shared__ double tn[6][5][n2];   // neighbours' traces on the shared faces
   __shared__ double qc[6][5][n2];   // common states
-  __shared__ double jm[6][5][n2];   // face jumps f^com - f^l
   __shared__ double F[3][5][Np];    // corrected gradient, then the total fluxes
-  __shared__ double dl[2][kMaxN];
   const int el = blockIdx.x, tid = threadIdx.x;
   const size_t nel = (size_t)a.nel, ndof = 5 * nel * Np;
   bool zero_v = false;
@@ -266,23 +267,16 @@ __global__ void __launch_bounds__(C3<P>::NT) k3_res(const Args3 a, const Basis B
   for (int k = tid; k < Np; k += NT)
 #pragma unroll
     for (int v = 0; v < 5; ++v) q[v][k] = state3<MODE>(a, ((size_t)v * nel + el) * Np + k, e);
-  if constexpr (VISC) face_derivative_rows<n>(B, dl, tid);
-  for (int idx = tid; idx < NF; idx += NT) {  // the neighbours' traces, while the state lands
+  for (int idx = tid; idx < NF; idx += NT) {
     const int f = idx / n2, j = idx % n2, d = f >> 1, s = f & 1;
     const int ne = nbr3(a, el, d, s);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) tn[f][v][j] = a.T[t_index(ne, f ^ 1, v, j, n2)];
-  }
-  __syncthreads();
-  for (int idx = tid; idx < NF; idx += NT) {
-    const int f = idx / n2, j = idx % n2, d = f >> 1;
-    const double* lw = (f & 1) ? B.lp : B.lm;
-#pragma unroll
     for (int v = 0; v < 5; ++v) {
-      double x = 0.0;
-      for (int m = 0; m < n; ++m) x = fma(lw[m], q[v][line_pt<n>(d, j, m)], x);
-      tr[f][v][j] = x;
-      qc[f][v][j] = 0.5 * (x + tn[f][v][j]);
+      const double o = a.T[t_index(el, f, v, j, n2)];
+      const double m = a.T[t_index(ne, f ^ 1, v, j, n2)];
+      tr[f][v][j] = o;
+      tn[f][v][j] = m;
+      qc[f][v][j] = 0.5 * (o + m);
     }
   }
   __syncthreads();
@@ -339,40 +333,17 @@ __global__ void __launch_bounds__(C3<P>::NT) k3_res(const Args3 a, const Basis B
       riemann3<FLUX>(qo, qn, d, a.gamma, fc);
     if constexpr (VISC) {
       const int ne = nbr3(a, el, d, s);
-      const int d1 = d == 0 ? 1 : 0, d2 = d == 2 ? 1 : 2;  // the face's axes (j = i1 n + i0)
-      const int i0 = j % n, i1 = j / n;
       double gc[3][5], qcv[5];
       const double sg = s ? 1.0 : -1.0;  // own outward normal along axis d; the neighbour's is opposite
       const double lift = cP * 2.0 / a.h[d];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         qcv[v] = qc[f][v][j];
-        // along the face: the mean of the two traces' derivatives
-        double t0 = 0.0, t1 = 0.0;
-        for (int m = 0; m < n; ++m) {
-          t0 = fma(B.D[i0][m], tr[f][v][i1 * n + m] + tn[f][v][i1 * n + m], t0);
-          t1 = fma(B.D[i1][m], tr[f][v][m * n + i0] + tn[f][v][m * n + i0], t1);
-        }
-        const double ga = (1.0 / a.h[d1]) * t0, gb = (1.0 / a.h[d2]) * t1;
-        // across it: the mean of the two raw normal gradients and the two liftings
-        double gn = 0.0;
-        for (int m = 0; m < n; ++m) gn = fma(dl[s][m], q[v][line_pt<n>(d, j, m)], gn);
-        gn = 0.5 * ((2.0 / a.h[d]) * gn + a.G[t_index(ne, f ^ 1, v, j, n2)]) +
-             0.5 * lift * sg * ((qcv[v] - qo[v]) - (qcv[v] - qn[v]));
-        // (the axes by branches, so the gradient stays in registers)
-        if (d == 0) {
-          gc[0][v] = gn;
-          gc[1][v] = ga;
-          gc[2][v] = gb;
-        } else if (d == 1) {
-          gc[0][v] = ga;
-          gc[1][v] = gn;
-          gc[2][v] = gb;
-        } else {
-          gc[0][v] = ga;
-          gc[1][v] = gb;
-          gc[2][v] = gn;
-        }
+        const size_t io = t_index(el, f, v, j, n2) * 3, in = t_index(ne, f ^ 1, v, j, n2) * 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gc[c][v] = 0.5 * (a.G[io + c] + a.G[in + c]);
+        // the two liftings: c_P (q^com - q_own) (2/h) n_own + c_P (q^com - q_nbr) (2/h) n_nbr
+        gc[d][v] += 0.5 * lift * sg * ((qcv[v] - qo[v]) - (qcv[v] - qn[v]));
       }
       double fv[5];
       vis3(qcv, gc, d, a, fv);
@@ -383,7 +354,7 @@ __global__ void __launch_bounds__(C3<P>::NT) k3_res(const Args3 a, const Basis B
     for (int v = 0; v < 5; ++v) {
       double fl = 0.0;
       for (int m = 0; m < n; ++m) fl = fma(lw[m], F[d][v][line_pt<n>(d, j, m)], fl);
-      jm[f][v][j] = fc[v] - fl;
+      tr[f][v][j] = fc[v] - fl;
     }
   }
   __syncthreads();
@@ -397,8 +368,8 @@ __global__ void __launch_bounds__(C3<P>::NT) k3_res(const Args3 a, const Basis B
         point_on_line<n>(k, d, &j, &t);
         double x = 0.0;
         for (int m = 0; m < n; ++m) x = fma(B.D[t][m], F[d][v][line_pt<n>(d, j, m)], x);
-        x = fma(jm[2 * d][v][j], B.gL[t], x);
-        x = fma(jm[2 * d + 1][v][j], B.gR[t], x);
+        x = fma(tr[2 * d][v][j], B.gL[t], x);
+        x = fma(tr[2 * d + 1][v][j], B.gR[t], x);
         R = fma(-2.0 / a.h[d], x, R);
       }
       const size_t gi = ((size_t)v * nel + el) * Np + k;
@@ -531,7 +502,7 @@ static Args3 args3(const fr3d_disc* d) {
 size_t fr3d_trace_bytes(const fr3d_disc* d) {
   const size_t n2 = (size_t)d->n * d->n;
   const size_t t = (size_t)d->nel * 6 * 5 * n2 * sizeof(double);
-  return ((t + 255) & ~(size_t)255) + ((d->mu != 0.0) ? ((t + 255) & ~(size_t)255) : 0);
+  return ((t + 255) & ~(size_t)255) + ((d->mu != 0.0) ? ((3 * t + 255) & ~(size_t)255) : 0);
 }
 
 hipError_t launch_fr3d_residual(const fr3d_disc* d, int mode, const double* U, const double* V, const double* R0,
