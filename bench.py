@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--cyl-dts", default="0.2,0.1,0.05")
     ap.add_argument("--cyl-tdev", type=float, default=2.0)
     ap.add_argument("--cyl-devdt", type=float, default=0.05)
+    ap.add_argument("--cyl-save", default=None, help="save the developed state (.npy)")
+    ap.add_argument("--cyl-load", default=None, help="start from a saved developed state instead of developing")
     ap.add_argument("--cyl-trun", type=float, default=1.0)
     ap.add_argument("--cyl-dtref", type=float, default=0.00625)
     ap.add_argument("--cyl-tolnl", type=float, default=1e-6, help="ESDIRK / BDF2 nonlinear tolerance (the paper's 1e-6)")
@@ -410,13 +412,14 @@ def paper_vortex_study(select, speed, eps_mode="abs", pc_prec="f64", verbose=Tru
 
 
 def cylinder_study(schemes, dts, t_dev, t_run, dt_ref, pc_prec="f32", tol_nl=1e-6, tol_lin_row=1e-6, dev_dt=0.01,
-                   verbose=True):
+                   save=None, load=None, verbose=True):
     """The cylinder case's scheme comparison (Section 5.2) on a self-generated O-grid (the
     paper's 5,690-element mesh is not available): 120 x 48 P3 quads, first layer 0.0033,
     far field at radius 100; Re = 1200, M = 0.1, BR2, Roe, element-Jacobi.  From an
     impulsive start (with a small cross-stream bump that breaks the symmetry) the flow is
-    developed for t_dev time units by ESDIRK3 at dev_dt (ROW steps fail on the impulsive
-    start's acoustic transient at these step sizes);
+    developed for t_dev time units by ESDIRK3 at dev_dt with uncapped pseudo-time steps (ROW
+    steps fail on the impulsive start's acoustic transient at these step sizes; the state can
+    be saved and loaded so that the study itself runs separately);
     from there every scheme runs t_run time units at each dt with the paper's tolerances
     (ROW: linear 1e-6; ESDIRK and BDF2: nonlinear 1e-6, linear 1e-1) and pseudo-time
     settings (dtau_init = 0.01, dtau_max = 1); Error(C_d) is the paper's root mean square
@@ -438,19 +441,20 @@ def cylinder_study(schemes, dts, t_dev, t_run, dt_ref, pc_prec="f32", tol_nl=1e-
     def cd(U):
         return disc.wall_force(U)[0] / qinf
 
-    def run(sch, dt, nsteps, U, record):
-        """nsteps of scheme sch from U (in place); per-step totals and the C_d history."""
+    def run(sch, dt, nsteps, U, record, dev=False):
+        """nsteps of scheme sch from U (in place); per-step totals and the C_d history.  dev:
+        the development run's settings (pseudo-time steps not capped, dtau_init = dt)."""
         tot = {"gmres_iters": 0, "ptc_iters": 0, "rejections": 0, "residual_evals": 0, "failed_steps": 0}
         hist = []
         lin_row = GmresOpts(m=20, rtol=tol_lin_row)
         o_row = SolverOpts(lin=lin_row, precond_precision=pp)
-        o_imp = SolverOpts(lin=GmresOpts(m=20, rtol=1e-1), tol_nl=tol_nl, dtau_init=0.01, dtau_max=1.0,
-                           precond_precision=pp)
+        o_imp = SolverOpts(lin=GmresOpts(m=20, rtol=1e-1), tol_nl=tol_nl, dtau_init=0.0 if dev else 0.01,
+                           dtau_max=1e20 if dev else 1.0, precond_precision=pp)
         Um1 = None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for it in range(nsteps):
-            if (it + 1) % (50 if not record else 20) == 0:
+            if (it + 1) % 10 == 0:
                 progress(f"cylinder: {sch} dt={dt} step {it + 1}/{nsteps}")
             if sch.startswith("ROW"):
                 st = disc.row_step(U, int(sch[3]), dt, o_row)
@@ -470,9 +474,16 @@ def cylinder_study(schemes, dts, t_dev, t_run, dt_ref, pc_prec="f32", tol_nl=1e-
         torch.cuda.synchronize()
         return tot, hist, time.perf_counter() - t0
 
-    progress("cylinder: development run")
     U = U0.clone()
-    dev_tot, _, dev_s = run("ESDIRK3", dev_dt, int(round(t_dev / dev_dt)), U, False)
+    if load is not None:
+        U.copy_(torch.as_tensor(np.load(load), device=disc.device).reshape(U.shape))
+        dev_tot, dev_s = {"rejections": 0, "failed_steps": 0}, 0.0
+        progress(f"cylinder: developed state loaded from {load}")
+    else:
+        progress("cylinder: development run")
+        dev_tot, _, dev_s = run("ESDIRK3", dev_dt, int(round(t_dev / dev_dt)), U, False, dev=True)
+        if save is not None:
+            np.save(save, U.cpu().numpy())
     progress(f"cylinder: developed to t = {t_dev}, C_d = {cd(U):.4f}")
     Ustart = U.clone()
     progress("cylinder: reference run")
@@ -501,7 +512,7 @@ def cylinder_study(schemes, dts, t_dev, t_run, dt_ref, pc_prec="f32", tol_nl=1e-
     return {"mode": "cylinder", "mesh": "O-grid 120x48, P3 (5760 elements, 368,640 DOFs)", "reynolds": cyl.reynolds,
             "mach": cyl.mach, "viscous": "BR2", "precond_precision": pc_prec, "tol_nl": tol_nl,
             "tol_lin_row": tol_lin_row,
-            "development": {"scheme": f"ESDIRK3 at dt {dev_dt}",
+            "development": {"scheme": f"ESDIRK3 at dt {dev_dt}", "loaded_from": load,
                             "t": t_dev, "wall_s": dev_s, "rejections": dev_tot["rejections"],
                             "failed_steps": dev_tot["failed_steps"]},
             "reference": {"scheme": "ESDIRK4", "dt": dt_ref, "steps": nref, "wall_s": ref_s,
@@ -634,7 +645,8 @@ def main():
     if args.cylinder:
         print(json.dumps(cylinder_study(args.cyl_schemes.split(","), [float(x) for x in args.cyl_dts.split(",")],
                                         args.cyl_tdev, args.cyl_trun, args.cyl_dtref, args.study_precond,
-                                        args.cyl_tolnl, args.cyl_tollin, args.cyl_devdt)), flush=True)
+                                        args.cyl_tolnl, args.cyl_tollin, args.cyl_devdt, args.cyl_save,
+                                        args.cyl_load)), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
