@@ -113,7 +113,8 @@ def ptc_solve(op, R, const, omega_dt, q0, Rq0, lin: LinOpts, nl: NlOpts, dt, st:
     dtau follows SER: dtau^{k+1} = min(dtau^k ||F^k|| / ||F^{k+1}||, dtau_max).
     If GMRES does not reduce the linear residual by a factor of ten, the
     iteration is rejected and dtau_max is halved (Section 4.4).
-    Stops when ||F|| <= tol_nl * ||F(q0)||.  Returns (q, R(q), converged).
+    Stops when ||F|| <= tol_nl * ||F(q0)||; a non-finite ||F|| ends it unconverged.
+    Returns (q, R(q), converged).
     """
     q = q0.copy()
     Rq = Rq0 if Rq0 is not None else R(q)
@@ -124,8 +125,8 @@ def ptc_solve(op, R, const, omega_dt, q0, Rq0, lin: LinOpts, nl: NlOpts, dt, st:
     dtau_max = nl.dtau_max
     rejects = 0
     k = 0
-    while nF > nl.tol_nl * nF0:
-        if k >= nl.max_ptc or rejects > nl.max_reject:
+    while not nF <= nl.tol_nl * nF0:       # a NaN norm enters the loop and fails the solve
+        if not np.isfinite(nF) or k >= nl.max_ptc or rejects > nl.max_reject:
             return q, Rq, False
         shift = 1.0 / dtau + 1.0 / omega_dt
         dq, gs = linear_solve(op, R, q, Rq, shift, -F, lin, st)

@@ -585,7 +585,9 @@ fr_status ptc_solve(const fr_disc* d, const double* cst, double omega_dt, double
   const int max_rej = o.max_reject > 0 ? o.max_reject : 30;
   int k = 0, rejects = 0;
   fr_ejacobi pc{B.pc, o.precond_precision, 0.0, nullptr};
-  while (nF > o.tol_nl * nF0) {
+  // written so that a NaN norm enters the loop and ends it as FR_ENAN rather than
+  // passing the test as converged
+  while (!(nF <= o.tol_nl * nF0)) {
     if (!std::isfinite(nF)) return FR_ENAN;
     if (k >= max_ptc) return FR_NOTCONV;
     if (rejects > max_rej) return FR_REJECTED;

@@ -172,6 +172,20 @@ def test_gmres_reports_nan():
     assert sg["status"] == 3   # FR_ENAN
 
 
+def test_implicit_steps_report_nan_state():
+    """A NaN in the state makes the stage residual norm NaN: the PTC loop must end with
+    FR_ENAN, not take the failed comparison with the tolerance as convergence."""
+    from paper_1904_04825_amd import GmresOpts, SolverOpts
+    _, op, disc = setup(4, 4, 2, "rusanov", seed=14)
+    U = vortex_state(op)
+    U[0, 3, 1] = np.nan
+    opts = SolverOpts(lin=GmresOpts(m=5, rtol=1e-1), tol_nl=1e-6)
+    st = disc.esdirk_step(to_gpu(U), 3, 0.5, opts)
+    assert st["status"] == 3
+    _, sb = disc.bdf2_step(None, to_gpu(U), 0.5, opts)
+    assert sb["status"] == 3
+
+
 def test_row2_vortex_8x8_p2_twenty_steps():
     """The 8x8 P=2 vortex workload: ROW2, dt = 0.05, 20 steps, GMRES(20) rtol 1e-8."""
     from paper_1904_04825_amd import GmresOpts, SolverOpts

@@ -218,3 +218,19 @@ def test_ptc_rejection_halves_dtau_max():
     q, _, ok = I.ptc_solve(op, I.Counted(op), U + 0.01, 0.5, U, None, I.LinOpts(m=1, rtol=1e-3, max_iters=1),
                            I.NlOpts(tol_nl=1e-8, max_reject=5, dtau_init=1e3), 1.0, st)
     assert not ok and st.rejections == 6 and np.array_equal(q, U)
+
+
+def test_ptc_nan_state_is_not_converged():
+    # a NaN anywhere in the state makes ||F|| NaN, which compares false with the tolerance:
+    # the solve must end unconverged instead of taking the comparison as convergence
+    nodes = fi.uniform_nodes(2, 2, -5, -5, 10, 10)
+    op = make_euler(nodes, 2)
+    v = fi.Vortex()
+    U = sample_state(op, lambda x, y: v.conservative(x, y))
+    U[0, 1, 2] = np.nan
+    st = I.StepStats()
+    _, _, ok = I.ptc_solve(op, I.Counted(op), U, 0.5, U, None, I.LinOpts(m=5, rtol=1e-1), I.NlOpts(tol_nl=1e-6),
+                           1.0, st)
+    assert not ok and st.ptc_iters == 0
+    _, so = I.esdirk_step(op, ESDIRK["ESDIRK3"], 0.5, U)
+    assert not so.converged
