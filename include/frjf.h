@@ -489,8 +489,11 @@ fr_status fr3d_jf_matvec(const fr3d_disc* disc, const double* d_U, const double*
 fr_status fr3d_ssprk3_step(const fr3d_disc* disc, double* d_U, double dt, void* d_work, fr_stream stream);
 /* Kinetic energy and dissipation rates of Section 5.3 (h_out = E_k, eps1, eps3; eps2 = 0
  * at zero bulk viscosity): E_k = int rho |u|^2/2 dV / (rho0 V), eps1 = 2 mu int S^d:S^d dV /
- * (rho0 V), eps3 = -int p div u dV / (rho0 V), the velocity gradient from the raw gradient
- * of each element's solution polynomial, Gauss quadrature.  Synchronises. */
+ * (rho0 V), eps3 = -int (p - <p>) div u dV / (rho0 V), the velocity gradient from the raw
+ * gradient of each element's solution polynomial, Gauss quadrature.  <p> is the volume mean
+ * of p: int div u dV = 0 on the periodic box for the exact field, and taking p about its
+ * mean drops <p> times the inter-element velocity jumps that the element-local gradient
+ * leaves in that integral.  Synchronises. */
 fr_status fr3d_dissipation(const fr3d_disc* disc, const double* d_U, double rho0, double* h_out, void* d_work,
                            fr_stream stream);
 

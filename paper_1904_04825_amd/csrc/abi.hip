@@ -571,7 +571,7 @@ static Work3 carve3(const fr3d_disc* d, void* work) {
   w.scal = (double*)p;
   p += 256;
   w.partials = (double*)p;
-  p += r256(sizeof(double) * std::max<size_t>(kRedBlocks, 3 * (size_t)d->nel));
+  p += r256(sizeof(double) * std::max<size_t>(kRedBlocks, 5 * (size_t)d->nel));
   w.R = (double*)p;
   p += r256(sizeof(double) * d->ndof);
   w.U1 = (double*)p;
@@ -618,7 +618,7 @@ size_t fr3d_ndof(const fr3d_disc* d) { return d ? d->ndof : 0; }
 
 size_t fr3d_workspace_bytes(const fr3d_disc* d) {
   if (d == nullptr) return 0;
-  return r256(fr3d_trace_bytes(d)) + 256 + r256(sizeof(double) * std::max<size_t>(kRedBlocks, 3 * (size_t)d->nel)) +
+  return r256(fr3d_trace_bytes(d)) + 256 + r256(sizeof(double) * std::max<size_t>(kRedBlocks, 5 * (size_t)d->nel)) +
          2 * r256(sizeof(double) * d->ndof);
 }
 
@@ -681,14 +681,15 @@ fr_status fr3d_dissipation(const fr3d_disc* d, const double* U, double rho0, dou
   CHECK(d && U && h_out && work && rho0 > 0.0, "fr3d_dissipation: null argument or rho0 <= 0");
   Work3 k = carve3(d, work);
   FR_HIP(launch_fr3d_dissipation(d, U, k.partials, S(s)));
-  FR_HIP(launch_finalize(k.partials, d->nel, 3, 3, k.scal, nullptr, S(s)));
-  double h[3];
+  FR_HIP(launch_finalize(k.partials, d->nel, 5, 5, k.scal, nullptr, S(s)));
+  double h[5];  // int rho|u|^2/2, int S^d:S^d, int p div u, int p, int div u
   FR_HIP(hipMemcpyAsync(h, k.scal, sizeof(h), hipMemcpyDeviceToHost, S(s)));
   FR_HIP(hipStreamSynchronize(S(s)));
   const double V = d->h[0] * d->h[1] * d->h[2] * d->nel;
   h_out[0] = h[0] / (rho0 * V);
   h_out[1] = 2.0 * d->mu * h[1] / (rho0 * V);
-  h_out[2] = -h[2] / (rho0 * V);
+  // int (p - <p>) div u = int p div u - <p> int div u (see the declaration)
+  h_out[2] = -(h[2] - (h[3] / V) * h[4]) / (rho0 * V);
   return FR_OK;
 }
 

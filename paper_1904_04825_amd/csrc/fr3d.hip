@@ -397,7 +397,7 @@ __global__ void __launch_bounds__(C3<P>::NT) k3_dissip(const Args3 a, const Basi
   using C = C3<P>;
   constexpr int n = C::n, Np = C::Np, NT = C::NT;
   __shared__ double q[5][Np];
-  __shared__ double red[3][NT / 64];
+  __shared__ double red[5][NT / 64];
   const int el = blockIdx.x, tid = threadIdx.x;
   const size_t nel = (size_t)a.nel;
   for (int k = tid; k < Np; k += NT)
@@ -405,7 +405,7 @@ __global__ void __launch_bounds__(C3<P>::NT) k3_dissip(const Args3 a, const Basi
     for (int v = 0; v < 5; ++v) q[v][k] = a.U[((size_t)v * nel + el) * Np + k];
   __syncthreads();
   const double J = a.h[0] * a.h[1] * a.h[2] / 8.0;
-  double ek = 0.0, ss = 0.0, pd = 0.0;
+  double ek = 0.0, ss = 0.0, pd = 0.0, ps = 0.0, ds = 0.0;
   for (int k = tid; k < Np; k += NT) {
     double g[3][5];
 #pragma unroll
@@ -440,21 +440,28 @@ __global__ void __launch_bounds__(C3<P>::NT) k3_dissip(const Args3 a, const Basi
     double qk[5] = {q[0][k], q[1][k], q[2][k], q[3][k], q[4][k]};
     ek = fma(w, 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]), ek);
     ss = fma(w, s2, ss);
-    pd = fma(w, p3(qk, a.gamma) * div, pd);
+    const double p = p3(qk, a.gamma);
+    pd = fma(w, p * div, pd);
+    ps = fma(w, p, ps);
+    ds = fma(w, div, ds);
   }
   ek = wave_sum(ek);
   ss = wave_sum(ss);
   pd = wave_sum(pd);
+  ps = wave_sum(ps);
+  ds = wave_sum(ds);
   if ((tid & 63) == 0) {
     red[0][tid >> 6] = ek;
     red[1][tid >> 6] = ss;
     red[2][tid >> 6] = pd;
+    red[3][tid >> 6] = ps;
+    red[4][tid >> 6] = ds;
   }
   __syncthreads();
-  if (tid < 3) {
+  if (tid < 5) {
     double t = 0.0;
     for (int w = 0; w < NT / 64; ++w) t += red[tid][w];
-    part[(size_t)el * 3 + tid] = t;
+    part[(size_t)el * 5 + tid] = t;
   }
 }
 

@@ -143,6 +143,46 @@ def test_taylor_green_initial_energy_and_dissipation():
     assert errs[1] < errs[0] / 8 and errs[1] < 1e-3 * 0.75 * tg.mu
 
 
+def test_eps3_closed_form_and_constant_pressure():
+    """u = a sin x, v = w = 0, rho = 1, p = p0 + b cos x: int p div u dV = a b V / 2, so
+    eps3 = -a b / 2, approached as the mesh refines whatever p0 (here the Mach-0.1 size).
+    Adding a constant to p does not move eps3 even when the velocity jumps between
+    elements (a per-element slope), where int div u dV over the elements is not zero."""
+    a, b, gam = 0.01, 0.5, 1.4
+
+    def state(x, p0):
+        rho = np.ones_like(x)
+        u = a * np.sin(x)
+        p = p0 + b * np.cos(x)
+        zero = np.zeros_like(x)
+        return np.stack([rho, rho * u, zero, zero, p / (gam - 1) + 0.5 * rho * u * u])
+    errs = []
+    for n in (3, 6):
+        box = Box3D(n, 2, 2, [0.0] * 3, [2 * math.pi] * 3, 3)
+        op = NavierStokes3D(box, mu=0.0)
+        x, _, _ = box.points()
+        _, _, e3 = dissipation(op, state(x, 1.0 / (gam * 0.01)), 1.0)
+        errs.append(abs(e3 + a * b / 2))
+    assert errs[1] < errs[0] / 8 and errs[1] < 1e-3 * a * b / 2
+    rng = np.random.default_rng(4)
+    box = Box3D(3, 3, 2, [0.0] * 3, [2 * math.pi] * 3, 2)
+    op = NavierStokes3D(box, mu=0.0)
+    x, _, _ = box.points()
+    U = state(x, 1.0)
+    U[1] += 0.02 * rng.standard_normal((box.nel, 1, 1, 1)) * x     # u jumps between elements (not
+                                                                    # by per-element constants, which telescope)
+    _, _, e3 = dissipation(op, U, 1.0)
+    U2 = U.copy()
+    U2[4] += 70.0 / (gam - 1)                                      # p -> p + 70
+    _, _, e3b = dissipation(op, U2, 1.0)
+    assert abs(e3b - e3) <= 1e-12 * 70
+    # the jumps make int div u dV non-zero: the literal form would move by 70 times it
+    w = box.weights()
+    raw = op.raw_gradient(U)
+    div = (raw[0][1] - U[1] / U[0] * raw[0][0]) / U[0]
+    assert abs(70.0 * np.sum(w * div) / np.sum(w)) > 1e3 * abs(e3b - e3) + 1e-6
+
+
 def test_ssprk3_amplification():
     """On dU/dt = lambda U one step multiplies by 1 + z + z^2/2 + z^3/6, z = lambda dt."""
     class Lin:
