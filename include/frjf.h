@@ -497,6 +497,52 @@ fr_status fr3d_ssprk3_step(const fr3d_disc* disc, double* d_U, double dt, void* 
 fr_status fr3d_dissipation(const fr3d_disc* disc, const double* d_U, double rho0, double* h_out, void* d_work,
                            fr_stream stream);
 
+/* ---- implicit steps on the 3D path (Sections 4.1-4.5 on the hexahedral
+ * discretisation; the implicit comparison of Section 5.3) --------------------------
+ * Element-Jacobi blocks P_e = shift I - dR_e/dq_e of Nb = 5 (p+1)^3 rows (p = 2: 135,
+ * p = 3: 320; other p: FR_EINVAL), FP64, column-major per element: the entry in row i,
+ * column j of block e at [(e Nb + j) Nb + i], rows and columns ordered v (p+1)^3 + k.
+ * Column j is the one-sided difference -(R_e(q + delta u_j) - R_e(q)) / delta with
+ * delta = 1e-8 max(1, |q_j|) and every neighbour's state unchanged (the elements are
+ * coloured so that face neighbours differ, and one residual evaluation gives column j of
+ * every element of a colour: c Nb evaluations per assembly, c = 2 when nx, ny, nz are
+ * even).  The inverses come from Gauss-Jordan with partial pivoting, same layout. */
+size_t fr3d_ejacobi_bytes(const fr3d_disc* disc);  /* nel Nb^2 doubles */
+/* Workspace of the calls below for restart length m (1 .. 64): the residual's face data,
+ * the steps' assembled blocks and inverses (2 fr3d_ejacobi_bytes), m + 1 Krylov and m
+ * preconditioned vectors, and 16 more state vectors; 0 for a bad m. */
+size_t fr3d_step_workspace_bytes(const fr3d_disc* disc, int m);
+/* The blocks at (d_U, shift) into d_blocks (fr3d_ejacobi_bytes bytes).  d_work:
+ * fr3d_step_workspace_bytes(disc, 1) bytes. */
+fr_status fr3d_ejacobi_assemble(const fr3d_disc* disc, const double* d_U, double shift, double* d_blocks,
+                                void* d_work, fr_stream stream);
+/* The inverse blocks at (d_U, shift) into d_inv (fr3d_ejacobi_bytes bytes).  d_work as above. */
+fr_status fr3d_ejacobi_factor(const fr3d_disc* disc, const double* d_U, double shift, double* d_inv,
+                              void* d_work, fr_stream stream);
+/* z = P^{-1} r element by element (ndof doubles each, not aliased). */
+fr_status fr3d_ejacobi_apply(const fr3d_disc* disc, const double* d_inv, const double* d_r, double* d_z,
+                             fr_stream stream);
+/* (shift I - dR/dq(U)) x = b by restarted flexible GMRES(m) (classical Gram-Schmidt
+ * applied twice), right-preconditioned by d_inv (factored with the same shift), with the
+ * Jacobian-free product about (d_U, d_R0 = R(d_U)); options, statistics and returns as
+ * fr_gmres_solve (element-Jacobi only; a breakdown counts as converged).  d_x: in the
+ * initial guess, out the solution.  d_work: fr3d_step_workspace_bytes(disc, opts->m)
+ * bytes.  Synchronises. */
+fr_status fr3d_gmres_solve(const fr3d_disc* disc, const double* d_inv, const double* d_U, const double* d_R0,
+                           double shift, const double* d_b, double* d_x, const fr_gmres_opts* opts,
+                           fr_gmres_stats* stats, void* d_work, fr_stream stream);
+/* One ROW, ESDIRK or BDF2 step as fr_row_step, fr_esdirk_step and fr_bdf2_step (same
+ * schemes, options, statistics and returns): element-Jacobi (FP64 only) formed once per
+ * ROW step and at every PTC iterate; no learned starts (opts->warm, log and d_yhist must
+ * be NULL); residual_evals includes the c Nb evaluations of every assembly.  d_work:
+ * fr3d_step_workspace_bytes(disc, opts->lin.m) bytes.  Synchronises. */
+fr_status fr3d_row_step(const fr3d_disc* disc, int scheme, double dt, double* d_U, const fr_solver_opts* opts,
+                        fr_step_stats* stats, void* d_work, fr_stream stream);
+fr_status fr3d_esdirk_step(const fr3d_disc* disc, int scheme, double dt, double* d_U, const fr_solver_opts* opts,
+                           fr_step_stats* stats, void* d_work, fr_stream stream);
+fr_status fr3d_bdf2_step(const fr3d_disc* disc, double dt, const double* d_Unm1, const double* d_Un, double* d_Unp1,
+                         const fr_solver_opts* opts, fr_step_stats* stats, void* d_work, fr_stream stream);
+
 /* Last error message of this thread ("" if none). */
 const char* fr_last_error(void);
 

@@ -222,11 +222,50 @@ class NavierStokes3D:
                 out[(d, s)] = g
         return out
 
+    def _other_side(self, q):
+        """For each face (d, s) of every element, the neighbour's trace there and, with
+        viscosity, the neighbour's raw gradient extrapolated to that face."""
+        tr = self.traces(q)
+        other = {(d, s): self.neighbour(tr[(d, 1 - s)], d, s) for d in range(3) for s in (0, 1)}
+        raw_other = None
+        if self.mu != 0.0:
+            raw = self.raw_gradient(q)
+            raw_other = {}
+            for d in range(3):
+                for s in (0, 1):
+                    vec = self.b.lp if s == 0 else self.b.lm      # the neighbour's face (d, 1 - s)
+                    raw_other[(d, s)] = [self.neighbour(_face(raw[k], vec, d), d, s) for k in range(3)]
+        return other, raw_other
+
     def residual(self, U):
         q = self.shape(U)
+        other, raw_other = self._other_side(q)
+        return self._residual(q, other, raw_other).reshape(np.shape(U))
+
+    def local_residual_factory(self, U):
+        """R as a function of each element's own state with every neighbour frozen at U,
+        all elements at once (what the element-Jacobi blocks differentiate): the other
+        side of each face (trace, raw gradient) comes from U; the common state and both
+        sides' BR2 liftings use the element's own trace."""
+        other, raw_other = self._other_side(self.shape(U))
+
+        def local(V):
+            q = self.shape(V)
+            return self._residual(q, other, raw_other).reshape(np.shape(V))
+        return local
+
+    @property
+    def nvar(self):
+        return 5
+
+    @property
+    def npts(self):
+        return self.n ** 3
+
+    def _residual(self, q, other, raw_other):
         b, gam = self.b, self.gamma
         tr = self.traces(q)
-        qc = self.common_states(tr)
+        qc = {(d, s): 0.5 * (tr[(d, s)] + other[(d, s)]) for d in range(3) for s in (0, 1)}
         viscous = self.mu != 0.0
         if viscous:
             grad = self.corrected_gradient(q, tr, qc)
@@ -239,16 +278,20 @@ class NavierStokes3D:
             div = _apply(b.D, f, d)
             for s in (0, 1):
                 fl = _face(f, b.lm if s == 0 else b.lp, d)
-                mine, other = tr[(d, s)], self.neighbour(tr[(d, 1 - s)], d, s)
-                qL, qR = (other, mine) if s == 0 else (mine, other)
+                mine = tr[(d, s)]
+                qL, qR = (other[(d, s)], mine) if s == 0 else (mine, other[(d, s)])
                 fc = FLUXES[self.flux](qL, qR, d, gam)
                 if viscous:
-                    gn = [self.neighbour(g, d, s) for g in fg[(d, 1 - s)]]
+                    # the neighbour's BR2 gradient on this face: its raw gradient plus its
+                    # lifting (q^com - its trace) on its face (d, 1 - s)
+                    gn = list(raw_other[(d, s)])
+                    sign_nb = -1.0 if s == 1 else 1.0
+                    gn[d] = gn[d] + self.cP * (qc[(d, s)] - other[(d, s)]) * (2.0 / self.box.h[d]) * sign_nb
                     gcom = [0.5 * (fg[(d, s)][k] + gn[k]) for k in range(3)]
                     fc = fc - viscous_flux(qc[(d, s)], gcom, d, gam, self.rgas, self.mu, self.prandtl)
                 div = div + _lift(fc - fl, b.gLp if s == 0 else b.gRp, d)
             R -= (2.0 / self.box.h[d]) * div
-        return R.reshape(np.shape(U))
+        return R
 
 
 def dissipation(op, U, rho0):

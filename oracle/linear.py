@@ -50,34 +50,39 @@ def ejacobi_blocks(op, U, shift):
     Returns blocks[e, row, col] with row/col index j = v * Np + k.
     """
     q = op.shape(U)
-    nel, n = op.nel, op.n
-    Np = n * n
-    Nb = 4 * Np
+    nel = op.nel
+    nv, Np = _layout(op)
+    Nb = nv * Np
     local = op.local_residual_factory(U)
-    R0 = local(q).reshape(4, nel, Np)
-    qf = q.reshape(4, nel, Np)
+    R0 = local(q).reshape(nv, nel, Np)
+    qf = q.reshape(nv, nel, Np)
     blocks = np.zeros((nel, Nb, Nb))
-    for v in range(4):
+    for v in range(nv):
         for k in range(Np):
             delta = BLOCK_FD_REL * np.maximum(1.0, np.abs(qf[v, :, k]))
             qp = qf.copy()
             qp[v, :, k] += delta
-            Rp = local(qp.reshape(q.shape)).reshape(4, nel, Np)
+            Rp = local(qp.reshape(q.shape)).reshape(nv, nel, Np)
             col = -(Rp - R0) / delta[None, :, None]          # -dR/dq_j, [v', e, k']
             blocks[:, :, v * Np + k] = col.transpose(1, 0, 2).reshape(nel, Nb)
     blocks += shift * np.eye(Nb)[None]
     return blocks
 
 
+def _layout(op):
+    """(variables, points per element): 2D operators (4, n^2); others state theirs."""
+    return getattr(op, "nvar", 4), getattr(op, "npts", op.n * op.n)
+
+
 def to_blocks(op, r):
     """[v, e, k] vector -> per-element vectors [e, v*Np + k]."""
-    Np = op.n * op.n
-    return np.asarray(r).reshape(4, op.nel, Np).transpose(1, 0, 2).reshape(op.nel, 4 * Np)
+    nv, Np = _layout(op)
+    return np.asarray(r).reshape(nv, op.nel, Np).transpose(1, 0, 2).reshape(op.nel, nv * Np)
 
 
 def from_blocks(op, z, shape):
-    Np = op.n * op.n
-    return z.reshape(op.nel, 4, Np).transpose(1, 0, 2).reshape(shape)
+    nv, Np = _layout(op)
+    return z.reshape(op.nel, nv, Np).transpose(1, 0, 2).reshape(shape)
 
 
 def ejacobi_apply(op, blocks, r):

@@ -132,6 +132,19 @@ _SIGS = {
                                c_void_p, c_void_p]),
     "fr3d_ssprk3_step": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_void_p]),
     "fr3d_dissipation": (c_int, [c_void_p, c_void_p, c_double, POINTER(c_double), c_void_p, c_void_p]),
+    "fr3d_ejacobi_bytes": (c_size_t, [c_void_p]),
+    "fr3d_step_workspace_bytes": (c_size_t, [c_void_p, c_int]),
+    "fr3d_ejacobi_assemble": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
+    "fr3d_ejacobi_factor": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_void_p, c_void_p]),
+    "fr3d_ejacobi_apply": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "fr3d_gmres_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_void_p, c_void_p,
+                                 POINTER(GmresOptsC), POINTER(GmresStatsC), c_void_p, c_void_p]),
+    "fr3d_row_step": (c_int, [c_void_p, c_int, c_double, c_void_p, POINTER(SolverOptsC), POINTER(StepStatsC),
+                              c_void_p, c_void_p]),
+    "fr3d_esdirk_step": (c_int, [c_void_p, c_int, c_double, c_void_p, POINTER(SolverOptsC), POINTER(StepStatsC),
+                                 c_void_p, c_void_p]),
+    "fr3d_bdf2_step": (c_int, [c_void_p, c_double, c_void_p, c_void_p, c_void_p, POINTER(SolverOptsC),
+                               POINTER(StepStatsC), c_void_p, c_void_p]),
     "fr_last_error": (ctypes.c_char_p, []),
 }
 

@@ -435,6 +435,85 @@ class Disc3D:
         self._vec(U, "U")
         _check("fr3d_ssprk3_step", self.lib.fr3d_ssprk3_step(self.handle, _ptr(U), dt, _ptr(self.work), _stream()))
 
+    # ---- implicit steps (FP64 element-Jacobi on 5 (p+1)^3-row blocks, p = 2 or 3)
+    @property
+    def nb(self):
+        return 5 * self.np_
+
+    def step_workspace(self, m):
+        """The workspace of the implicit calls for restart length m, kept between calls."""
+        ws = getattr(self, "_ws3", {})
+        self._ws3 = ws
+        if m not in ws:
+            nbytes = int(self.lib.fr3d_step_workspace_bytes(self.handle, m))
+            if nbytes == 0:
+                raise ValueError("fr3d_step_workspace_bytes: m must be 1 .. 64")
+            ws.clear()      # one workspace at a time: they hold two block stores each
+            ws[m] = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return ws[m]
+
+    def ejacobi_assemble(self, U, shift):
+        """The element blocks shift I - dR_e/dq_e, returned as [nel, Nb, Nb] (row, column)."""
+        self._vec(U, "U")
+        B = torch.empty((self.nel, self.nb, self.nb), dtype=torch.float64, device=self.device)
+        _check("fr3d_ejacobi_assemble", self.lib.fr3d_ejacobi_assemble(self.handle, _ptr(U), shift, _ptr(B),
+                                                                       _ptr(self.step_workspace(1)), _stream()))
+        return B.transpose(1, 2)        # stored column-major per element
+
+    def ejacobi_factor(self, U, shift):
+        """The inverse blocks (the library's column-major store) at (U, shift)."""
+        self._vec(U, "U")
+        inv = torch.empty((self.nel, self.nb, self.nb), dtype=torch.float64, device=self.device)
+        _check("fr3d_ejacobi_factor", self.lib.fr3d_ejacobi_factor(self.handle, _ptr(U), shift, _ptr(inv),
+                                                                   _ptr(self.step_workspace(1)), _stream()))
+        return inv
+
+    def ejacobi_apply(self, inv, r, out=None):
+        self._vec(r, "r")
+        out = self.empty() if out is None else self._vec(out, "out")
+        _check("fr3d_ejacobi_apply", self.lib.fr3d_ejacobi_apply(self.handle, _ptr(inv), _ptr(r), _ptr(out),
+                                                                 _stream()))
+        return out
+
+    def gmres_solve(self, inv, U, R0, shift, b, x=None, opts=None):
+        opts = opts or GmresOpts()
+        for t, nm in ((U, "U"), (R0, "R0"), (b, "b")):
+            self._vec(t, nm)
+        x = torch.zeros(self.shape, dtype=torch.float64, device=self.device) if x is None else self._vec(x, "x")
+        st = L.GmresStatsC()
+        oc = opts.c()
+        status = self.lib.fr3d_gmres_solve(self.handle, _ptr(inv), _ptr(U), _ptr(R0), shift, _ptr(b), _ptr(x),
+                                           ctypes.byref(oc), ctypes.byref(st), _ptr(self.step_workspace(opts.m)),
+                                           _stream())
+        _check("fr3d_gmres_solve", status, allow_numerical=True)
+        return x, dict(_stats(st), status=status)
+
+    def _step(self, name, opts, *args):
+        st = L.StepStatsC()
+        oc = opts.c()
+        ws = self.step_workspace((opts.lin or GmresOpts()).m)
+        status = getattr(self.lib, name)(self.handle, *args, ctypes.byref(oc), ctypes.byref(st), _ptr(ws), _stream())
+        _check(name, status, allow_numerical=True)
+        return dict(_stats(st), status=status)
+
+    def row_step(self, U, scheme, dt, opts=None):
+        opts = opts or SolverOpts(lin=GmresOpts())
+        self._vec(U, "U")
+        return self._step("fr3d_row_step", opts, int(scheme), dt, _ptr(U))
+
+    def esdirk_step(self, U, scheme, dt, opts=None):
+        opts = opts or SolverOpts(lin=GmresOpts(rtol=1e-1))
+        self._vec(U, "U")
+        return self._step("fr3d_esdirk_step", opts, int(scheme), dt, _ptr(U))
+
+    def bdf2_step(self, Unm1, Un, dt, opts=None, out=None):
+        opts = opts or SolverOpts(lin=GmresOpts(rtol=1e-1))
+        self._vec(Un, "Un")
+        if Unm1 is not None:
+            self._vec(Unm1, "Unm1")
+        out = self.empty() if out is None else self._vec(out, "out")
+        return out, self._step("fr3d_bdf2_step", opts, dt, _ptr(Unm1), _ptr(Un), _ptr(out))
+
     def dissipation(self, U, rho0=1.0):
         """(E_k, eps1, eps3) of the Taylor-Green diagnostics."""
         self._vec(U, "U")

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libfrjf.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["basis.hip", "residual.hip", "ns.hip", "vecops.hip", "ejacobi.hip", "gj_rows.hip", "gj_mfma.hip", "gj_wide.hip", "mlp.hip", "pmg.hip", "fr3d.hip", "solvers.hip", "abi.hip"]
+SOURCES = ["basis.hip", "residual.hip", "ns.hip", "vecops.hip", "ejacobi.hip", "gj_rows.hip", "gj_mfma.hip", "gj_wide.hip", "mlp.hip", "pmg.hip", "fr3d.hip", "solvers.hip", "implicit3d.hip", "abi.hip"]
 ARCH = "gfx950"
 
 

@@ -693,6 +693,79 @@ fr_status fr3d_dissipation(const fr3d_disc* d, const double* U, double rho0, dou
   return FR_OK;
 }
 
+size_t fr3d_ejacobi_bytes(const fr3d_disc* d) { return d ? fr3d_block_bytes(d) : 0; }
+
+size_t fr3d_step_workspace_bytes(const fr3d_disc* d, int m) {
+  if (d == nullptr || m < 1 || m > kMaxM) return 0;
+  return fr3d_step_bytes(d, m);
+}
+
+fr_status fr3d_ejacobi_assemble(const fr3d_disc* d, const double* U, double shift, double* blocks, void* work,
+                                fr_stream s) {
+  clear_error();
+  CHECK(d && U && blocks && work, "fr3d_ejacobi_assemble: null argument");
+  return fr3d_assemble_impl(d, U, shift, blocks, work, S(s));
+}
+
+fr_status fr3d_ejacobi_factor(const fr3d_disc* d, const double* U, double shift, double* inv, void* work,
+                              fr_stream s) {
+  clear_error();
+  CHECK(d && U && inv && work, "fr3d_ejacobi_factor: null argument");
+  return fr3d_factor_impl(d, U, shift, inv, work, S(s));
+}
+
+fr_status fr3d_ejacobi_apply(const fr3d_disc* d, const double* inv, const double* r, double* z, fr_stream s) {
+  clear_error();
+  CHECK(d && inv && r && z, "fr3d_ejacobi_apply: null argument");
+  CHECK(r != z, "fr3d_ejacobi_apply: r and z alias");
+  return fr3d_apply_impl(d, inv, r, z, S(s));
+}
+
+fr_status fr3d_gmres_solve(const fr3d_disc* d, const double* inv, const double* U, const double* R0, double shift,
+                           const double* b, double* x, const fr_gmres_opts* o, fr_gmres_stats* st, void* work,
+                           fr_stream s) {
+  clear_error();
+  CHECK(d && inv && U && R0 && b && x && o && st && work, "fr3d_gmres_solve: null argument");
+  CHECK(x != b && x != U && x != R0, "fr3d_gmres_solve: x aliases an input");
+  CHECK(o->rtol > 0.0, "fr3d_gmres_solve: rtol must be positive");
+  *st = fr_gmres_stats{};
+  return fr3d_gmres_impl(d, inv, U, R0, shift, b, x, *o, st, work, S(s));
+}
+
+static fr_status check3_step(const fr3d_disc* d, const void* U, double dt, const fr_solver_opts* o,
+                             fr_step_stats* st, void* work, const char* who) {
+  if (!(d && U && o && st && work)) return set_error(FR_EINVAL, std::string(who) + ": null argument");
+  if (!(dt > 0.0)) return set_error(FR_EINVAL, std::string(who) + ": dt must be positive");
+  if (!(o->lin.rtol > 0.0)) return set_error(FR_EINVAL, std::string(who) + ": lin.rtol must be positive");
+  *st = fr_step_stats{};
+  return FR_OK;
+}
+
+fr_status fr3d_row_step(const fr3d_disc* d, int scheme, double dt, double* U, const fr_solver_opts* o,
+                        fr_step_stats* st, void* work, fr_stream s) {
+  clear_error();
+  fr_status c = check3_step(d, U, dt, o, st, work, "fr3d_row_step");
+  if (c != FR_OK) return c;
+  return fr3d_row_impl(d, scheme, dt, U, *o, st, work, S(s));
+}
+
+fr_status fr3d_esdirk_step(const fr3d_disc* d, int scheme, double dt, double* U, const fr_solver_opts* o,
+                           fr_step_stats* st, void* work, fr_stream s) {
+  clear_error();
+  fr_status c = check3_step(d, U, dt, o, st, work, "fr3d_esdirk_step");
+  if (c != FR_OK) return c;
+  return fr3d_esdirk_impl(d, scheme, dt, U, *o, st, work, S(s));
+}
+
+fr_status fr3d_bdf2_step(const fr3d_disc* d, double dt, const double* Unm1, const double* Un, double* Unp1,
+                         const fr_solver_opts* o, fr_step_stats* st, void* work, fr_stream s) {
+  clear_error();
+  fr_status c = check3_step(d, Un, dt, o, st, work, "fr3d_bdf2_step");
+  if (c != FR_OK) return c;
+  CHECK(Unp1 != nullptr && Unp1 != Un && Unp1 != Unm1, "fr3d_bdf2_step: Unp1 null or aliasing an input");
+  return fr3d_bdf2_impl(d, dt, Unm1, Un, Unp1, *o, st, work, S(s));
+}
+
 int fr_scheme_table(int kind, int scheme, double* a, double* c, double* b, double* gamma) {
   if (!a || !b || !gamma) return FR_EINVAL;
   if (kind == 0) {

@@ -71,4 +71,22 @@ fr_status esdirk_step_impl(const fr_disc* d, int scheme, double dt, double* U, c
 fr_status bdf2_step_impl(const fr_disc* d, double dt, const double* Unm1, const double* Un, double* Unp1,
                          const fr_solver_opts& o, fr_step_stats* st, void* work, hipStream_t s);
 
+// Implicit steps on the 3D path (implicit3d.hip).
+size_t fr3d_step_bytes(const fr3d_disc* d, int m);
+size_t fr3d_block_bytes(const fr3d_disc* d);
+fr_status fr3d_assemble_impl(const fr3d_disc* d, const double* U, double shift, double* blocks, void* work,
+                             hipStream_t s);
+fr_status fr3d_factor_impl(const fr3d_disc* d, const double* U, double shift, double* inv, void* work,
+                           hipStream_t s);
+fr_status fr3d_apply_impl(const fr3d_disc* d, const double* inv, const double* r, double* z, hipStream_t s);
+fr_status fr3d_gmres_impl(const fr3d_disc* d, const double* inv, const double* U, const double* R0, double shift,
+                          const double* b, double* x, const fr_gmres_opts& o, fr_gmres_stats* st, void* work,
+                          hipStream_t s);
+fr_status fr3d_row_impl(const fr3d_disc* d, int scheme, double dt, double* U, const fr_solver_opts& o,
+                        fr_step_stats* st, void* work, hipStream_t s);
+fr_status fr3d_esdirk_impl(const fr3d_disc* d, int scheme, double dt, double* U, const fr_solver_opts& o,
+                           fr_step_stats* st, void* work, hipStream_t s);
+fr_status fr3d_bdf2_impl(const fr3d_disc* d, double dt, const double* Unm1, const double* Un, double* Unp1,
+                         const fr_solver_opts& o, fr_step_stats* st, void* work, hipStream_t s);
+
 }  // namespace frjf

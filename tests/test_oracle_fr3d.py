@@ -191,3 +191,54 @@ def test_ssprk3_amplification():
     U = np.array([1.0, -2.0])
     z = -0.7 * 0.3
     assert np.allclose(ssprk3_step(Lin(), U, 0.3), U * (1 + z + z * z / 2 + z ** 3 / 6), rtol=1e-15)
+
+
+def _ns_small(nx, ny, nz, P, mu=0.05):
+    box = Box3D(nx, ny, nz, [0.0] * 3, [2 * math.pi] * 3, P)
+    op = NavierStokes3D(box, mu=mu)
+    x, y, z = box.points()
+    return box, op, _state3d(x, y, z)
+
+
+def test_local_residual_and_element_blocks_by_definition():
+    """The frozen-neighbour residual at U is R(U), and columns of the element-Jacobi blocks
+    (Section 4.5) match the definition: perturb one entry of one element only, evaluate
+    the full residual, take that element's rows (one-sided, step 1e-8 max(1, |q|))."""
+    from oracle import linear
+    box, op, U = _ns_small(3, 2, 2, 2)
+    assert np.array_equal(op.local_residual_factory(U)(U), op.residual(U))
+    shift = 3.0
+    B = linear.ejacobi_blocks(op, U, shift)
+    nb = 5 * 27
+    assert B.shape == (box.nel, nb, nb)
+    q = op.shape(U).reshape(5, box.nel, 27)
+    R0 = op.residual(U).reshape(5, box.nel, 27)
+    rng = np.random.default_rng(2)
+    for j in rng.choice(nb, size=8, replace=False):
+        v, k = divmod(int(j), 27)
+        for e in range(box.nel):
+            qp = q.copy()
+            delta = 1e-8 * max(1.0, abs(qp[v, e, k]))
+            qp[v, e, k] += delta
+            Rp = op.residual(qp.reshape(U.shape)).reshape(5, box.nel, 27)
+            col = -(Rp[:, e, :] - R0[:, e, :]).reshape(-1) / delta
+            col[j] += shift
+            assert np.linalg.norm(B[e, :, j] - col) <= 1e-6 * np.linalg.norm(col), (j, e)
+
+
+def test_row3_step_local_order_3d():
+    """One ROW3 step on the 3D Navier-Stokes residual (generic integrators with the 3D
+    element-Jacobi): against SSPRK3 with 50 substeps the local error, relative to the
+    step's own change (itself O(dt)), falls like dt^3 (local error dt^4)."""
+    from oracle import integrators as I
+    from oracle.tableaux import ROW
+    box, op, U = _ns_small(2, 2, 2, 2)
+    errs = []
+    for dt in (0.02, 0.01):
+        Ur, _ = I.row_step(op, ROW["ROW3"], dt, U, I.LinOpts(m=30, rtol=1e-12))
+        Us = U.copy()
+        for _ in range(50):
+            Us = ssprk3_step(op, Us, dt / 50)
+        errs.append(np.linalg.norm(Ur - Us) / np.linalg.norm(Us - U))
+    rate = math.log2(errs[0] / errs[1])
+    assert 2.7 < rate < 3.3, (errs, rate)
