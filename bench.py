@@ -97,6 +97,16 @@ def parse():
     ap.add_argument("--tgv-steps", type=int, default=50)
     ap.add_argument("--tgv-dt", type=float, default=2e-4, help="SSPRK3 step in units of t_c (the paper's 2e-4)")
     ap.add_argument("--tgv-sample", type=int, default=10)
+    ap.add_argument("--tgv-implicit", action="store_true",
+                    help="instead of the bench line: the implicit schemes on the Taylor-Green vortex (Section 5.3), "
+                         "Error(eps) against SSPRK3 over a window of t / t_c")
+    ap.add_argument("--tgvi-n", type=int, default=16)
+    ap.add_argument("--tgvi-schemes", default="ROW2,ROW3,ROW4,ESDIRK2,ESDIRK3,ESDIRK4,BDF2")
+    ap.add_argument("--tgvi-steps-per-tc", default="25,50,100", help="dt = t_c / k for each k")
+    ap.add_argument("--tgvi-t0", type=float, default=8.0)
+    ap.add_argument("--tgvi-t1", type=float, default=9.0)
+    ap.add_argument("--tgvi-ref-save", default=None, help="save the SSPRK3 reference (state at t0 and eps) (.npz)")
+    ap.add_argument("--tgvi-ref-load", default=None)
     ap.add_argument("--mach-reading", default="magnitude", choices=["magnitude", "u"],
                     help="velocity of the paper's Mach number: |V| or u")
     ap.add_argument("--study-eps", default="rms", choices=["abs", "rms"],
@@ -627,6 +637,116 @@ def tgv_study(n_el, P, steps, dt_tc, sample_every, verbose=True):
             "history": hist}
 
 
+def tgv_implicit_study(n_el, P, schemes, per_tc, t0, t1, dt_ref_tc, ref_save=None, ref_load=None, verbose=True):
+    """The implicit schemes on the Taylor-Green vortex (Section 5.3) on n_el^3 P hexahedra:
+    the reference is SSPRK3 at dt_ref_tc t_c from t = 0 (the paper's 2e-4 t_c), which also
+    gives the state at t0; each scheme then runs from t0 to t1 at dt = t_c / k and
+    Error(eps) is the paper's root mean square over its steps of eps - eps_ref, eps = eps1 +
+    eps3 (eps2 = 0).  Tolerances as the paper's: ROW linear 1e-6; ESDIRK and BDF2 nonlinear
+    1e-6 with linear 1e-1, dtau_init = dt, dtau_max = 1e20; GMRES(30), FP64 element-Jacobi."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import fr_inputs as fi
+    from paper_1904_04825_amd import Disc3D, GmresOpts, SolverOpts
+    tg = fi.TaylorGreen()
+    L = tg.L
+    tc = L / tg.V0
+    disc = Disc3D(n_el, n_el, n_el, P, (-math.pi * L,) * 3, (2 * math.pi * L,) * 3, flux="roe", mu=tg.mu,
+                  prandtl=tg.prandtl, gamma=tg.gamma, rgas=tg.rgas)
+    kmax = max(per_tc)
+    stride = int(round(1.0 / (kmax * dt_ref_tc)))        # reference steps per finest implicit step
+    if abs(stride * kmax * dt_ref_tc - 1.0) > 1e-9 or any(kmax % k for k in per_tc):
+        raise SystemExit("tgv-implicit: every t_c / k must be a whole number of reference steps of the finest")
+
+    def eps_of(U):
+        _, e1, e3 = disc.dissipation(U, tg.rho0)
+        return e1 + e3
+
+    if ref_load is not None:
+        z = np.load(ref_load)
+        U0 = torch.as_tensor(z["U0"], device=disc.device).reshape(disc.shape).contiguous()
+        ref_eps, ref_s = z["eps"], float(z["wall_s"])
+        progress(f"tgv-implicit: reference loaded from {ref_load}")
+    else:
+        xyz = disc.solution_points()
+        U = torch.as_tensor(tg.conservative(xyz[0], xyz[1], xyz[2]), device=disc.device).reshape(
+            disc.shape).contiguous()
+        n0 = int(round(t0 / dt_ref_tc))
+        n1 = int(round(t1 / dt_ref_tc))
+        ref_eps = []
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        U0 = None
+        for it in range(n1 + 1):
+            if it == n0:
+                U0 = U.clone()
+            if it >= n0 and (it - n0) % stride == 0:
+                ref_eps.append(eps_of(U))
+            if it % 5000 == 0:
+                progress(f"tgv-implicit: reference step {it}/{n1}")
+            if it < n1:
+                disc.ssprk3_step(U, dt_ref_tc * tc)
+        torch.cuda.synchronize()
+        ref_s = time.perf_counter() - w0
+        ref_eps = np.array(ref_eps)
+        if ref_save is not None:
+            np.savez(ref_save, U0=U0.cpu().numpy(), eps=ref_eps, wall_s=ref_s)
+    rows = []
+    for sch in schemes:
+        for k in per_tc:
+            dt = tc / k
+            n = int(round((t1 - t0) * k))
+            o = SolverOpts(lin=GmresOpts(m=30, rtol=1e-6)) if sch.startswith("ROW") else \
+                SolverOpts(lin=GmresOpts(m=30, rtol=1e-1), tol_nl=1e-6, dtau_init=0.0, dtau_max=1e20)
+            U = U0.clone()
+            Um1 = None
+            tot = {"gmres_iters": 0, "ptc_iters": 0, "rejections": 0, "residual_evals": 0}
+            eps = []
+            failed = None
+            torch.cuda.synchronize()
+            w0 = time.perf_counter()
+            for it in range(n):
+                if sch.startswith("ROW"):
+                    st = disc.row_step(U, int(sch[3]), dt, o)
+                elif sch.startswith("ESDIRK"):
+                    st = disc.esdirk_step(U, int(sch[6]), dt, o)
+                else:
+                    Un, st = disc.bdf2_step(Um1, U, dt, o)
+                    Um1 = U.clone()
+                    U.copy_(Un)
+                if st["status"] != 0:
+                    failed = st["status"]
+                    break
+                for key in tot:
+                    tot[key] += st[key]
+                eps.append(eps_of(U))
+                if (it + 1) % 10 == 0:
+                    progress(f"tgv-implicit: {sch} t_c/{k} step {it + 1}/{n}")
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - w0
+            err = None
+            if failed is None:
+                r = ref_eps[[(i + 1) * (kmax // k) for i in range(n)]]
+                err = float(np.sqrt(np.mean((np.array(eps) - r) ** 2)))
+            row = {"scheme": sch, "dt_tc": 1.0 / k, "steps": n, "error_eps": err, "wall_s": wall,
+                   "fail_status": failed, **{key: v / max(len(eps), 1) for key, v in tot.items()},
+                   "eps_end": eps[-1] if eps else None}
+            rows.append(row)
+            if verbose:
+                print(f"# {sch} dt=t_c/{k}: Error(eps) {err if err is None else f'{err:.3e}'}, {wall:.1f} s, "
+                      f"GMRES/step {row['gmres_iters']:.1f}, PTC/step {row['ptc_iters']:.1f}, "
+                      f"rejections {tot['rejections']}{'' if failed is None else f' FAILED ({failed})'}", flush=True)
+    return {"mode": "tgv-implicit", "mesh": f"{n_el}^3 hexahedra, P{P}", "ndof": disc.ndof, "reynolds": 1600,
+            "mach": 0.1, "window_tc": [t0, t1], "reference": {"scheme": "SSPRK3", "dt_tc": dt_ref_tc, "wall_s": ref_s,
+                                                               "loaded_from": ref_load,
+                                                               "eps_t0": float(ref_eps[0]),
+                                                               "eps_t1": float(ref_eps[-1])},
+            "rows": rows}
+
+
 def precond_study(disc, W, U, dt, scheme, lin):
     """The first ROW stage's linear system at the timed legs' start state, solved to the
     same tolerance with each preconditioner on FP32 blocks: element-Jacobi (the paper's),
@@ -689,6 +809,12 @@ def main():
         return
     if args.tgv:
         print(json.dumps(tgv_study(args.tgv_n, args.tgv_p, args.tgv_steps, args.tgv_dt, args.tgv_sample)), flush=True)
+        return
+    if args.tgv_implicit:
+        print(json.dumps(tgv_implicit_study(args.tgvi_n, args.tgv_p, args.tgvi_schemes.split(","),
+                                            [int(k) for k in args.tgvi_steps_per_tc.split(",")], args.tgvi_t0,
+                                            args.tgvi_t1, args.tgv_dt, args.tgvi_ref_save, args.tgvi_ref_load)),
+              flush=True)
         return
     if args.cylinder:
         print(json.dumps(cylinder_study(args.cyl_schemes.split(","), [float(x) for x in args.cyl_dts.split(",")],
