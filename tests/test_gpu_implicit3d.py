@@ -132,3 +132,56 @@ def test_nan_state_and_invalid_calls():
     d4 = Disc3D(2, 2, 2, 4, (0.0,) * 3, (1.0,) * 3, mu=0.01)
     with pytest.raises(FrError):
         d4.row_step(d4.empty().fill_(1.0), 3, 0.1, SolverOpts(lin=GmresOpts(m=4)))
+
+
+def test_tgv16_p3_blocks_and_inverses_sampled():
+    """At the size the Taylor-Green implicit study runs (16^3 P3, 4,096 blocks of 320 rows,
+    shift 1/(gamma dt) of ROW4 at dt = t_c/25): three block columns of every element against
+    the oracle's frozen-neighbour differences, and inverse x block = I on sampled elements.
+    At Ma = 0.1 the pressure (about 71) dwarfs the residual, so a difference quotient with
+    step 1e-8 |q| carries rounding near 1e-6 of the column; the columns are held to 1e-6 or
+    to 3x the oracle's own spread under a one-ulp change of the state, whichever is larger."""
+    import fr_inputs as fi
+    import torch
+    from paper_1904_04825_amd import Disc3D
+    tg = fi.TaylorGreen()
+    L = tg.L
+    box = Box3D(16, 16, 16, [-math.pi * L] * 3, [2 * math.pi * L] * 3, 3)
+    op = NavierStokes3D(box, mu=tg.mu, prandtl=tg.prandtl, gamma=tg.gamma, rgas=tg.rgas)
+    disc = Disc3D(16, 16, 16, 3, (-math.pi * L,) * 3, (2 * math.pi * L,) * 3, flux="roe", mu=tg.mu,
+                  prandtl=tg.prandtl, gamma=tg.gamma, rgas=tg.rgas)
+    x, y, z = box.points()
+    U = tg.conservative(x, y, z).reshape(5, box.nel, -1)
+    shift = 1.0 / (0.25 * 0.04 * L / tg.V0)
+    Ug = to_gpu(U)
+    B = disc.ejacobi_assemble(Ug, shift)                 # [e, row, col] view
+    rng = np.random.default_rng(6)
+    U2 = np.nextafter(U, rng.choice([-np.inf, np.inf], size=U.shape))
+
+    def column(Us, j):
+        local = op.local_residual_factory(Us)
+        v, k = divmod(j, 64)
+        qp = Us.copy()
+        delta = 1e-8 * np.maximum(1.0, np.abs(qp[v, :, k]))
+        qp[v, :, k] += delta
+        col = -(local(qp).reshape(5, box.nel, 64) - local(Us).reshape(5, box.nel, 64)) / delta[None, :, None]
+        col = col.transpose(1, 0, 2).reshape(box.nel, 320)
+        col[:, j] += shift
+        return col
+
+    def rel_rows(a, b):
+        return float(np.max(np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)))
+    for j in (0, 137, 319):
+        col = column(U, j)
+        err = rel_rows(B[:, :, j].cpu().numpy(), col)
+        spread = rel_rows(column(U2, j), col)
+        print(f"16^3 P3 block column {j}: gpu vs oracle {err:.2e}, oracle spread under one ulp {spread:.2e}",
+              flush=True)
+        assert err <= max(1e-6, 3 * spread)
+    Bs = {e: B[e].cpu().numpy() for e in (0, 1234, 4095)}
+    del B
+    torch.cuda.empty_cache()
+    inv = disc.ejacobi_factor(Ug, shift)
+    for e, Be in Bs.items():
+        Ie = inv[e].cpu().numpy().T
+        assert np.abs(Ie @ Be - np.eye(320)).max() <= 1e-13 * np.linalg.cond(Be), e
