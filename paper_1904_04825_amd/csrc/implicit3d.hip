@@ -7,8 +7,9 @@
 //   element of one colour perturbed at once (colours chosen so that face neighbours
 //   differ, so each such element sees unperturbed neighbours).  A 320 x 320 FP64 block
 //   fits neither a workgroup's registers nor its LDS, so the inversion is a panel
-//   Gauss-Jordan that keeps 16 columns in LDS and streams the rest of the block through
-//   global memory once per panel.  Blocks and inverses are column-major per element.
+//   Gauss-Jordan, one thread per row, that keeps the panel's columns in registers and
+//   streams the rest of the block through global memory once per panel.  Blocks and
+//   inverses are column-major per element.
 //   FGMRES(m): classical Gram-Schmidt applied twice; the Hessenberg column, the Givens
 //   rotations and the stopping tests run on the host, one synchronisation per Arnoldi
 //   step (a 3D residual costs far more than that round trip).
@@ -29,8 +30,6 @@ namespace frjf {
 
 namespace {
 
-constexpr int kPW = 16;   // panel width of the Gauss-Jordan
-constexpr int kGT = 256;  // threads of the inversion kernel
 constexpr int kVec3 = 12; // state-sized vectors of a step
 
 #define FR3_TRY(expr)        \
@@ -86,112 +85,124 @@ __global__ void k3a_column(double* __restrict__ B, const double* __restrict__ Rp
 // In-place Gauss-Jordan of one N x N block per workgroup with partial pivoting by
 // Jordan exchanges: no rows move; step k takes as pivot the row p_k with the largest
 // |a| in column k among the rows not pivoted yet (ties to the lower row, NaN never
-// wins).  A panel of kPW columns is factored in LDS; every other column j then becomes
+// wins; if every candidate is NaN, the lowest candidate row).  One thread per row.
+// Panels of W columns: the panel is factored in registers (each thread its row's W
+// entries, the pivot row broadcast through LDS); every other column j then becomes
 // (column j with the panel's pivot rows zeroed) + Panel * (column j's old entries at
-// those rows), one wave per column.  After all panels A^{-1}[k][p_j] = M[p_k][j]; the
-// inverse goes column-major to out.
-template <int N>
-__global__ void __launch_bounds__(kGT) k3_gj(double* __restrict__ A, double* __restrict__ out) {
-  constexpr int RPT = (N + kGT - 1) / kGT;
-  constexpr int NW = kGT / 64;
-  __shared__ double Pn[kPW][N];
-  __shared__ double rowp[kPW];
-  __shared__ int kst[N], pv[N];
+// those rows), JB columns per barrier: each thread loads its row's entries, the pivot
+// rows' threads publish theirs in LDS, and each thread forms its new entries from its
+// panel row in registers.  The block streams through global memory once per panel.
+// After all panels A^{-1}[k][p_j] = M[p_k][j]; the inverse goes column-major to out.
+template <int N, int W>
+__global__ void __launch_bounds__((N + 63) / 64 * 64, 1) k3_gj(double* __restrict__ A, double* __restrict__ out) {
+  constexpr int NT = (N + 63) / 64 * 64, NW = NT / 64, JB = 16;
+  __shared__ double rowp[W];
+  __shared__ double ap[W][JB];
+  __shared__ int pv[N];
   __shared__ double wb[NW];
-  __shared__ int wi[NW];
-  __shared__ int piv;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  __shared__ int wi[NW], wm[NW];
+  const int i = threadIdx.x, lane = i & 63, wid = i >> 6;
+  const bool own = i < N;
   double* a = A + (size_t)blockIdx.x * N * N;
-  for (int i = tid; i < N; i += kGT) kst[i] = -1;
-  for (int c0 = 0; c0 < N; c0 += kPW) {
-    const int w = min(kPW, N - c0);
-    for (int t = tid; t < w * N; t += kGT) Pn[t / N][t % N] = a[(size_t)(c0 + t / N) * N + t % N];
-    __syncthreads();
-    for (int c = 0; c < w; ++c) {
-      double best = -1.0;
-      int bi = N;
+  int kst = own ? -1 : N;  // step that pivoted this row; -1 while a candidate
+  for (int c0 = 0; c0 < N; c0 += W) {
+    const int w = min(W, N - c0);
+    double pr[W];
 #pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const int i = tid + r * kGT;
-        if (i < N && kst[i] < 0) {
-          const double v = fabs(Pn[c][i]);
-          if (v > best) {
-            best = v;
-            bi = i;
-          }
-        }
+    for (int cc = 0; cc < W; ++cc) pr[cc] = (own && cc < w) ? a[(size_t)(c0 + cc) * N + i] : 0.0;
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+      if (c >= w) continue;  // uniform: the last panel may be narrower
+      const bool cand = own && kst < 0;
+      const double v = fabs(pr[c]);
+      double best = -1.0;
+      int bi = N, mc = cand ? i : N;
+      if (cand && v > best) {
+        best = v;
+        bi = i;
       }
       for (int off = 32; off > 0; off >>= 1) {
         const double ob = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
+        const int oi = __shfl_xor(bi, off), om = __shfl_xor(mc, off);
         if (ob > best || (ob == best && oi < bi)) {
           best = ob;
           bi = oi;
         }
+        mc = min(mc, om);
       }
       if (lane == 0) {
         wb[wid] = best;
         wi[wid] = bi;
+        wm[wid] = mc;
       }
       __syncthreads();
-      if (tid == 0) {
-        double b = wb[0];
-        int p = wi[0];
-        for (int q = 1; q < NW; ++q)
-          if (wb[q] > b || (wb[q] == b && wi[q] < p)) {
-            b = wb[q];
-            p = wi[q];
-          }
-        if (p >= N) {  // every candidate entry NaN: the lowest candidate row
-          p = 0;
-          while (kst[p] >= 0) ++p;
+      double b = wb[0];
+      int p = wi[0], m = wm[0];
+#pragma unroll
+      for (int q = 1; q < NW; ++q) {
+        if (wb[q] > b || (wb[q] == b && wi[q] < p)) {
+          b = wb[q];
+          p = wi[q];
         }
-        piv = p;
-        kst[p] = c0 + c;
-        pv[c0 + c] = p;
+        m = min(m, wm[q]);
       }
-      __syncthreads();
-      const int p = piv;
-      if (tid < w) rowp[tid] = Pn[tid][p];
+      if (p >= N) p = m;  // every candidate entry NaN
+      if (i == p) {
+        kst = c0 + c;
+        pv[c0 + c] = p;
+#pragma unroll
+        for (int cc = 0; cc < W; ++cc)
+          if (cc < w) rowp[cc] = pr[cc];
+      }
       __syncthreads();
       const double ipiv = 1.0 / rowp[c];
-#pragma unroll
-      for (int r = 0; r < RPT; ++r) {
-        const int i = tid + r * kGT;
-        if (i >= N) continue;
+      if (own) {
         if (i == p) {
 #pragma unroll
-          for (int cc = 0; cc < kPW; ++cc)
-            if (cc < w) Pn[cc][i] = (cc == c) ? ipiv : rowp[cc] * ipiv;
+          for (int cc = 0; cc < W; ++cc)
+            if (cc < w) pr[cc] = (cc == c) ? ipiv : pr[cc] * ipiv;
         } else {
-          const double f = Pn[c][i] * ipiv;
+          const double f = pr[c] * ipiv;
 #pragma unroll
-          for (int cc = 0; cc < kPW; ++cc)
-            if (cc < w) Pn[cc][i] = (cc == c) ? -f : fma(-f, rowp[cc], Pn[cc][i]);
+          for (int cc = 0; cc < W; ++cc)
+            if (cc < w) pr[cc] = (cc == c) ? -f : fma(-f, rowp[cc], pr[cc]);
+        }
+      }
+    }
+    if (own) {
+#pragma unroll
+      for (int cc = 0; cc < W; ++cc)
+        if (cc < w) a[(size_t)(c0 + cc) * N + i] = pr[cc];
+    }
+    // this panel's pivot slot of the row (-1: not one of its pivots)
+    const int slot = (kst >= c0 && kst < c0 + w) ? kst - c0 : -1;
+    for (int j0 = 0; j0 < N; j0 += JB) {
+      double x[JB];
+#pragma unroll
+      for (int t = 0; t < JB; ++t) {
+        const int j = j0 + t;
+        const bool live = own && j < N && (j < c0 || j >= c0 + w);
+        x[t] = live ? a[(size_t)j * N + i] : 0.0;
+      }
+      if (slot >= 0) {
+#pragma unroll
+        for (int t = 0; t < JB; ++t) ap[slot][t] = x[t];
+      }
+      __syncthreads();
+      if (own) {
+#pragma unroll
+        for (int t = 0; t < JB; ++t) {
+          const int j = j0 + t;
+          if (j >= N || (j >= c0 && j < c0 + w)) continue;
+          double v = slot >= 0 ? 0.0 : x[t];
+#pragma unroll
+          for (int cc = 0; cc < W; ++cc)
+            if (cc < w) v = fma(pr[cc], ap[cc][t], v);
+          a[(size_t)j * N + i] = v;
         }
       }
       __syncthreads();
     }
-    for (int t = tid; t < w * N; t += kGT) a[(size_t)(c0 + t / N) * N + t % N] = Pn[t / N][t % N];
-    for (int j = wid; j < N; j += NW) {
-      if (j >= c0 && j < c0 + w) continue;
-      double* col = a + (size_t)j * N;
-      double ap[kPW];
-#pragma unroll
-      for (int cc = 0; cc < kPW; ++cc) {
-        ap[cc] = 0.0;
-        if (cc < w) ap[cc] = col[pv[c0 + cc]];
-      }
-      for (int i = lane; i < N; i += 64) {
-        const int ks = kst[i];
-        double v = (ks >= c0 && ks < c0 + w) ? 0.0 : col[i];
-#pragma unroll
-        for (int cc = 0; cc < kPW; ++cc)
-          if (cc < w) v = fma(Pn[cc][i], ap[cc], v);
-        col[i] = v;
-      }
-    }
-    __syncthreads();
   }
   double* o = out + (size_t)blockIdx.x * N * N;
   for (int j = wid; j < N; j += NW) {
@@ -386,8 +397,10 @@ fr_status assemble(const fr3d_disc* d, const double* U, const double* R0, double
 
 fr_status invert(const fr3d_disc* d, double* B, double* inv, hipStream_t s) {
   switch (d->p) {
-    case 2: hipLaunchKernelGGL((k3_gj<135>), dim3(d->nel), dim3(kGT), 0, s, B, inv); break;
-    case 3: hipLaunchKernelGGL((k3_gj<320>), dim3(d->nel), dim3(kGT), 0, s, B, inv); break;
+    // panel widths that divide N: every panel is full and the pivot loop unrolls into
+    // registers (a ragged last panel kept the panel row in scratch memory)
+    case 2: hipLaunchKernelGGL((k3_gj<135, 27>), dim3(d->nel), dim3(192), 0, s, B, inv); break;
+    case 3: hipLaunchKernelGGL((k3_gj<320, 32>), dim3(d->nel), dim3(320), 0, s, B, inv); break;
     default: return set_error(FR_EINVAL, "3D element-Jacobi: p must be 2 or 3");
   }
   FR_HIP(hipGetLastError());
