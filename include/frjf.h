@@ -504,9 +504,10 @@ fr_status fr3d_dissipation(const fr3d_disc* disc, const double* d_U, double rho0
  * column j of block e at [(e Nb + j) Nb + i], rows and columns ordered v (p+1)^3 + k.
  * Column j is the one-sided difference -(R_e(q + delta u_j) - R_e(q)) / delta with
  * delta = 1e-8 max(1, |q_j|) and every neighbour's state unchanged (the elements are
- * coloured so that face neighbours differ, and one residual evaluation gives column j of
- * every element of a colour: c Nb evaluations per assembly, c = 2 when nx, ny, nz are
- * even).  The inverses come from Gauss-Jordan with partial pivoting, same layout. */
+ * coloured so that face neighbours differ, and one evaluation of the residual on the
+ * elements of a colour gives column j of all of them: c Nb such evaluations per assembly,
+ * c = 2 when nx, ny, nz are even).  The inverses come from Gauss-Jordan with partial
+ * pivoting, same layout. */
 size_t fr3d_ejacobi_bytes(const fr3d_disc* disc);  /* nel Nb^2 doubles */
 /* Workspace of the calls below for restart length m (1 .. 64): the residual's face data,
  * the steps' assembled blocks and inverses (2 fr3d_ejacobi_bytes), m + 1 Krylov and m
@@ -534,7 +535,8 @@ fr_status fr3d_gmres_solve(const fr3d_disc* disc, const double* d_inv, const dou
 /* One ROW, ESDIRK or BDF2 step as fr_row_step, fr_esdirk_step and fr_bdf2_step (same
  * schemes, options, statistics and returns): element-Jacobi (FP64 only) formed once per
  * ROW step and at every PTC iterate; no learned starts (opts->warm, log and d_yhist must
- * be NULL); residual_evals includes the c Nb evaluations of every assembly.  d_work:
+ * be NULL); residual_evals includes the c Nb single-colour evaluations of every
+ * assembly.  d_work:
  * fr3d_step_workspace_bytes(disc, opts->lin.m) bytes.  Synchronises. */
 fr_status fr3d_row_step(const fr3d_disc* disc, int scheme, double dt, double* d_U, const fr_solver_opts* opts,
                         fr_step_stats* stats, void* d_work, fr_stream stream);

@@ -36,6 +36,7 @@ struct Args3 {
   double* T;  // traces [nel][6][5][n^2]
   double* G;  // raw face gradients [nel][6][5][n^2][3]
   const double* nrm2;
+  const int* elist;  // null: workgroup b is element b; else element elist[b]
   double eps, shift;
   int eps_mode;
   int nx, ny, nz, nel;
@@ -204,7 +205,7 @@ __global__ void __launch_bounds__(C3<P>::NT) k3_faces(const Args3 a, const Basis
   constexpr int n = C::n, n2 = C::n2, Np = C::Np, NF = C::NF, NT = C::NT;
   __shared__ double q[5][Np];
   __shared__ double gr[VISC ? 3 : 1][5][VISC ? Np : 1];
-  const int el = blockIdx.x, tid = threadIdx.x;
+  const int el = a.elist != nullptr ? a.elist[blockIdx.x] : (int)blockIdx.x, tid = threadIdx.x;
   const size_t nel = (size_t)a.nel, ndof = 5 * nel * Np;
   bool zv = false;
   const double e = MODE ? eps3(a, ndof, &zv) : 0.0;
@@ -260,7 +261,7 @@ __global__ void __launch_bounds__(C3<P>::NT) k3_res(const Args3 a, const Basis B
   __shared__ double tn[6][5][n2];   // neighbours' traces on the shared faces
   __shared__ double qc[6][5][n2];   // common states
   __shared__ double F[3][5][Np];    // corrected gradient, then the total fluxes
-  const int el = blockIdx.x, tid = threadIdx.x;
+  const int el = a.elist != nullptr ? a.elist[blockIdx.x] : (int)blockIdx.x, tid = threadIdx.x;
   const size_t nel = (size_t)a.nel, ndof = 5 * nel * Np;
   bool zero_v = false;
   const double e = MODE ? eps3(a, ndof, &zero_v) : 0.0;
@@ -533,6 +534,46 @@ hipError_t launch_fr3d_residual(const fr3d_disc* d, int mode, const double* U, c
     case 2: return roe ? res3_pf<2, 1>(a, d->basis, mode, visc, s) : res3_pf<2, 0>(a, d->basis, mode, visc, s);
     case 3: return roe ? res3_pf<3, 1>(a, d->basis, mode, visc, s) : res3_pf<3, 0>(a, d->basis, mode, visc, s);
     case 4: return roe ? res3_pf<4, 1>(a, d->basis, mode, visc, s) : res3_pf<4, 0>(a, d->basis, mode, visc, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+// The plain residual (mode 0) on the elements elist[0 .. count) only: the first kernel
+// writes their traces and face gradients, the second (unless faces_only) their R, reading
+// the other elements' face data as the work buffer holds it.
+template <int P, int FLUX, bool VISC>
+static hipError_t res3_subset(const Args3& a, const Basis& B, int count, bool faces_only, hipStream_t s) {
+  using C = C3<P>;
+  const dim3 g(count), b(C::NT);
+  hipLaunchKernelGGL((k3_faces<P, 0, VISC>), g, b, 0, s, a, B);
+  if (!faces_only) hipLaunchKernelGGL((k3_res<P, FLUX, 0, VISC>), g, b, 0, s, a, B);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t res3_subset_p(const fr3d_disc* d, const Args3& a, int count, bool faces_only, hipStream_t s) {
+  const bool roe = d->flux == FR_ROE, visc = d->mu != 0.0;
+  if (visc)
+    return roe ? res3_subset<P, 1, true>(a, d->basis, count, faces_only, s)
+               : res3_subset<P, 0, true>(a, d->basis, count, faces_only, s);
+  return roe ? res3_subset<P, 1, false>(a, d->basis, count, faces_only, s)
+             : res3_subset<P, 0, false>(a, d->basis, count, faces_only, s);
+}
+
+hipError_t launch_fr3d_residual_subset(const fr3d_disc* d, const double* U, double* out, void* work,
+                                       const int* elist, int count, bool faces_only, hipStream_t s) {
+  if (count <= 0 || elist == nullptr) return hipErrorInvalidValue;
+  Args3 a = args3(d);
+  a.U = U;
+  a.out = out;
+  a.elist = elist;
+  const size_t n2 = (size_t)d->n * d->n;
+  const size_t t = (size_t)d->nel * 6 * 5 * n2 * sizeof(double);
+  a.T = (double*)work;
+  a.G = (d->mu != 0.0) ? (double*)((char*)work + ((t + 255) & ~(size_t)255)) : nullptr;
+  switch (d->p) {
+    case 2: return res3_subset_p<2>(d, a, count, faces_only, s);
+    case 3: return res3_subset_p<3>(d, a, count, faces_only, s);
   }
   return hipErrorInvalidValue;
 }

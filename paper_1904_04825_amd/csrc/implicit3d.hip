@@ -292,6 +292,7 @@ struct W3 {
   double* blocks;   // assembled blocks (destroyed by the inversion)
   double* inv;      // the preconditioner (inverse blocks) of the step drivers
   double* dl;       // per-element finite-difference steps
+  int* elist;       // the elements grouped by colour
   double* Up;       // perturbed state
   double* Rp;       // its residual
   double* V;        // m + 1 basis vectors
@@ -318,6 +319,7 @@ W3 carve(const fr3d_disc* d, void* work, int m) {
   w.blocks = take(block_store(d));
   w.inv = take(block_store(d));
   w.dl = take(sizeof(double) * d->nel);
+  w.elist = (int*)take(sizeof(int) * d->nel);
   w.Up = take(sizeof(double) * n);
   w.Rp = take(sizeof(double) * n);
   w.V = take(sizeof(double) * n * (size_t)(m + 1));
@@ -333,7 +335,8 @@ W3 carve(const fr3d_disc* d, void* work, int m) {
 size_t carve_bytes(const fr3d_disc* d, int m) {
   const size_t n = d->ndof;
   return al(fr3d_trace_bytes(d)) + al(256) + al(sizeof(double) * std::max<size_t>(kRedBlocks, 5 * (size_t)d->nel)) +
-         2 * al(block_store(d)) + al(sizeof(double) * d->nel) + 2 * al(sizeof(double) * n) +
+         2 * al(block_store(d)) + al(sizeof(double) * d->nel) + al(sizeof(int) * d->nel) +
+         2 * al(sizeof(double) * n) +
          al(sizeof(double) * n * (size_t)(m + 1)) + al(sizeof(double) * n * (size_t)m) + 2 * al(sizeof(double) * n) +
          al(sizeof(double) * kHost) + al(sizeof(double) * (size_t)kRedBlocks * (kMaxM + 1)) +
          kVec3 * al(sizeof(double) * n);
@@ -372,18 +375,36 @@ int colour_count(const fr3d_disc* d) {
     if (d->nx % c != 1 && d->ny % c != 1 && d->nz % c != 1) return c;
 }
 
-// Blocks shift I - dR_e/dq_e at U into B (column-major per element); R0 = R(U).
+// Blocks shift I - dR_e/dq_e at U into B (column-major per element); R0 = R(U).  Per
+// colour and column, only that colour's elements are re-evaluated: their traces from the
+// perturbed state, their residuals against the neighbours' face data at U (written by one
+// full evaluation at U first, restored after each colour).
 fr_status assemble(const fr3d_disc* d, const double* U, const double* R0, double shift, double* B, W3& W,
                    hipStream_t s) {
   const int nb = 5 * d->np, nc = colour_count(d);
   const unsigned ge = grid_of((size_t)d->nel, 4096), gc = grid_of((size_t)d->nel * nb, 8192);
-  FR_HIP(hipMemcpyAsync(W.Up, U, sizeof(double) * d->ndof, hipMemcpyDeviceToDevice, s));
+  std::vector<int> list;
+  std::vector<int> off(nc + 1, 0);
+  list.reserve(d->nel);
   for (int col = 0; col < nc; ++col) {
+    for (int e = 0; e < d->nel; ++e) {
+      const int ex = e % d->nx, ey = (e / d->nx) % d->ny, ez = e / (d->nx * d->ny);
+      if ((ex + ey + ez) % nc == col) list.push_back(e);
+    }
+    off[col + 1] = (int)list.size();
+  }
+  FR_HIP(hipMemcpyAsync(W.elist, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice, s));
+  FR_HIP(hipMemcpyAsync(W.Up, U, sizeof(double) * d->ndof, hipMemcpyDeviceToDevice, s));
+  FR3_TRY(residual(d, U, W.Rp, W, s));  // every element's face data at U
+  for (int col = 0; col < nc; ++col) {
+    const int* el = W.elist + off[col];
+    const int cnt = off[col + 1] - off[col];
+    if (cnt == 0) continue;
     for (int j = 0; j < nb; ++j) {
       hipLaunchKernelGGL(k3a_perturb, dim3(ge), dim3(256), 0, s, W.Up, U, W.dl, d->nel, d->np, j - 1, j, d->nx, d->ny,
                          nc, col);
       FR_HIP(hipGetLastError());
-      FR3_TRY(residual(d, W.Up, W.Rp, W, s));
+      FR_HIP(launch_fr3d_residual_subset(d, W.Up, W.Rp, W.traces, el, cnt, false, s));
       hipLaunchKernelGGL(k3a_column, dim3(gc), dim3(256), 0, s, B, W.Rp, R0, W.dl, d->nel, d->np, j, shift, d->nx,
                          d->ny, nc, col);
       FR_HIP(hipGetLastError());
@@ -391,7 +412,9 @@ fr_status assemble(const fr3d_disc* d, const double* U, const double* R0, double
     hipLaunchKernelGGL(k3a_perturb, dim3(ge), dim3(256), 0, s, W.Up, U, W.dl, d->nel, d->np, nb - 1, -1, d->nx,
                        d->ny, nc, col);
     FR_HIP(hipGetLastError());
+    FR_HIP(launch_fr3d_residual_subset(d, W.Up, W.Rp, W.traces, el, cnt, true, s));  // the colour's data at U again
   }
+  FR_HIP(hipStreamSynchronize(s));  // the element lists were copied from this frame
   return FR_OK;
 }
 
