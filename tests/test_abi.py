@@ -136,5 +136,20 @@ def test_fr3d_invalid_arguments_and_sizes():
         assert L.fr3d_ndof(h) == 5 * 60 * 64
         n2, nel = 16, 60
         assert L.fr3d_workspace_bytes(h) >= 2 * nel * 6 * 5 * n2 * 8 + 2 * 5 * nel * 64 * 8
+        # implicit steps: 320-row blocks at P3, two block stores in the step workspace
+        nb = 5 * 64
+        assert L.fr3d_ejacobi_bytes(h) == nel * nb * nb * 8
+        assert L.fr3d_step_workspace_bytes(h, 0) == 0 and L.fr3d_step_workspace_bytes(h, 65) == 0
+        w20, w30 = L.fr3d_step_workspace_bytes(h, 20), L.fr3d_step_workspace_bytes(h, 30)
+        assert w20 >= 2 * nel * nb * nb * 8 + (41 + 16) * 5 * nel * 64 * 8
+        assert w30 - w20 >= 20 * 5 * nel * 64 * 8           # ten more V and ten more Z vectors
+        null = ctypes.c_void_p()
+        assert L.fr3d_ejacobi_factor(h, null, 1.0, null, null, null) == -1
+        assert L.fr3d_ejacobi_apply(h, null, null, null, null) == -1
+        assert L.fr3d_gmres_solve(h, null, null, null, 1.0, null, null, None, None, null, null) == -1
+        assert "null argument" in L.fr_last_error().decode()
+        st = _lib.StepStatsC()
+        assert L.fr3d_row_step(h, 3, 0.1, null, None, ctypes.byref(st), null, null) == -1
+        assert L.fr3d_bdf2_step(h, 0.1, null, null, null, None, ctypes.byref(st), null, null) == -1
     finally:
         L.fr3d_destroy(h)
