@@ -185,3 +185,33 @@ def test_tgv16_p3_blocks_and_inverses_sampled():
     for e, Be in Bs.items():
         Ie = inv[e].cpu().numpy().T
         assert np.abs(Ie @ Be - np.eye(320)).max() <= 1e-13 * np.linalg.cond(Be), e
+
+
+def test_runs_of_several_steps():
+    """Run-level parity: four ROW3 steps and three BDF2 steps (BDF1 start) on 3 x 2 x 2 P2
+    against the oracle, the stage solves to 1e-10 (ROW) and 1e-10 nonlinear (BDF2)."""
+    from paper_1904_04825_amd import GmresOpts, SolverOpts
+    box, op, disc, U = _pair(3, 2, 2, 2)
+    dt = 0.05
+    Uo = U.copy()
+    Ug = to_gpu(U)
+    for _ in range(4):
+        Uo, so = I.row_step(op, ROW["ROW3"], dt, Uo, I.LinOpts(m=20, rtol=1e-10))
+        st = disc.row_step(Ug, 3, dt, SolverOpts(lin=GmresOpts(m=20, rtol=1e-10)))
+        assert st["status"] == 0 and so.converged
+    err = rel(to_np(Ug), Uo)
+    print(f"4 ROW3 steps: {err:.2e}", flush=True)
+    assert err <= 1e-8
+    lin, nl = I.LinOpts(m=20, rtol=1e-1), I.NlOpts(tol_nl=1e-10)
+    opts = SolverOpts(lin=GmresOpts(m=20, rtol=1e-1), tol_nl=1e-10)
+    prev_o, cur_o = None, U.copy()
+    prev_g, cur_g = None, to_gpu(U)
+    for _ in range(3):
+        nxt_o, so = I.bdf2_step(op, dt, prev_o, cur_o, lin, nl)
+        nxt_g, sg = disc.bdf2_step(prev_g, cur_g, dt, opts)
+        assert sg["status"] == 0 and so.converged
+        prev_o, cur_o = cur_o, nxt_o
+        prev_g, cur_g = cur_g, nxt_g
+    err = rel(to_np(cur_g), cur_o)
+    print(f"3 BDF2 steps: {err:.2e}", flush=True)
+    assert err <= 1e-8
