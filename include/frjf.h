@@ -510,8 +510,10 @@ fr_status fr3d_dissipation(const fr3d_disc* disc, const double* d_U, double rho0
  * pivoting, same layout. */
 size_t fr3d_ejacobi_bytes(const fr3d_disc* disc);  /* nel Nb^2 doubles */
 /* Workspace of the calls below for restart length m (1 .. 64): the residual's face data,
- * the steps' assembled blocks and inverses (2 fr3d_ejacobi_bytes), m + 1 Krylov and m
- * preconditioned vectors, and 16 more state vectors; 0 for a bad m. */
+ * the steps' assembled blocks and inverses (2 fr3d_ejacobi_bytes), eight copies of the
+ * state, its residual and its face data (the assembly evaluates eight block columns per
+ * launch), m + 1 Krylov and m preconditioned vectors, and 14 more state vectors; 0 for a
+ * bad m. */
 size_t fr3d_step_workspace_bytes(const fr3d_disc* disc, int m);
 /* The blocks at (d_U, shift) into d_blocks (fr3d_ejacobi_bytes bytes).  d_work:
  * fr3d_step_workspace_bytes(disc, 1) bytes. */

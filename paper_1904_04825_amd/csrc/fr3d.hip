@@ -37,6 +37,8 @@ struct Args3 {
   double* G;  // raw face gradients [nel][6][5][n^2][3]
   const double* nrm2;
   const int* elist;  // null: workgroup b is element b; else element elist[b]
+  size_t cs;         // copies (blockIdx.y): state and output stride in doubles,
+  size_t fs;         // and face-data stride in bytes (0 with one copy)
   double eps, shift;
   int eps_mode;
   int nx, ny, nz, nel;
@@ -180,11 +182,11 @@ __device__ __forceinline__ size_t t_index(int e, int f, int v, int j, int n2) {
 }
 
 template <int MODE>
-__device__ __forceinline__ double state3(const Args3& a, size_t gi, double e) {
+__device__ __forceinline__ double state3(const double* U, const double* V, size_t gi, double e) {
   if constexpr (MODE == 0)
-    return a.U[gi];
+    return U[gi];
   else
-    return fma(e, a.V[gi], a.U[gi]);
+    return fma(e, V[gi], U[gi]);
 }
 
 __device__ __forceinline__ double eps3(const Args3& a, size_t ndof, bool* zero_v) {
@@ -201,6 +203,11 @@ __device__ __forceinline__ double eps3(const Args3& a, size_t ndof, bool* zero_v
 // ---------------------------------------------------------------- kernel A: traces and raw face gradients
 template <int P, int MODE, bool VISC>
 __global__ void __launch_bounds__(C3<P>::NT) k3_faces(const Args3 a, const Basis B) {
+  // copy blockIdx.y (one copy unless a.cs, a.fs are set): its state and face data
+  const size_t cy = blockIdx.y;
+  const double* const Uc = a.U + cy * a.cs;
+  double* const Tc = (double*)((char*)a.T + cy * a.fs);
+  double* const Gc = a.G != nullptr ? (double*)((char*)a.G + cy * a.fs) : nullptr;
   using C = C3<P>;
   constexpr int n = C::n, n2 = C::n2, Np = C::Np, NF = C::NF, NT = C::NT;
   __shared__ double q[5][Np];
@@ -211,7 +218,7 @@ __global__ void __launch_bounds__(C3<P>::NT) k3_faces(const Args3 a, const Basis
   const double e = MODE ? eps3(a, ndof, &zv) : 0.0;
   for (int k = tid; k < Np; k += NT)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) q[v][k] = state3<MODE>(a, ((size_t)v * nel + el) * Np + k, e);
+    for (int v = 0; v < 5; ++v) q[v][k] = state3<MODE>(Uc, a.V, ((size_t)v * nel + el) * Np + k, e);
   __syncthreads();
   if constexpr (VISC) {
     for (int k = tid; k < Np; k += NT) {
@@ -237,13 +244,13 @@ __global__ void __launch_bounds__(C3<P>::NT) k3_faces(const Args3 a, const Basis
     for (int v = 0; v < 5; ++v) {
       double x = 0.0;
       for (int m = 0; m < n; ++m) x = fma(lw[m], q[v][line_pt<n>(d, j, m)], x);
-      a.T[t_index(el, f, v, j, n2)] = x;
+      Tc[t_index(el, f, v, j, n2)] = x;
       if constexpr (VISC) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           double y = 0.0;
           for (int m = 0; m < n; ++m) y = fma(lw[m], gr[c][v][line_pt<n>(d, j, m)], y);
-          a.G[t_index(el, f, v, j, n2) * 3 + c] = y;
+          Gc[t_index(el, f, v, j, n2) * 3 + c] = y;
         }
       }
     }
@@ -253,6 +260,12 @@ __global__ void __launch_bounds__(C3<P>::NT) k3_faces(const Args3 a, const Basis
 // ---------------------------------------------------------------- kernel B: residual
 template <int P, int FLUX, int MODE, bool VISC>
 __global__ void __launch_bounds__(C3<P>::NT) k3_res(const Args3 a, const Basis B) {
+  // copy blockIdx.y (one copy unless a.cs, a.fs are set): its state, face data and output
+  const size_t cy = blockIdx.y;
+  const double* const Uc = a.U + cy * a.cs;
+  const double* const Tc = (const double*)((const char*)a.T + cy * a.fs);
+  const double* const Gc = a.G != nullptr ? (const double*)((const char*)a.G + cy * a.fs) : nullptr;
+  double* const outc = a.out + cy * a.cs;
   using C = C3<P>;
   constexpr int n = C::n, n2 = C::n2, Np = C::Np, NF = C::NF, NT = C::NT;
   constexpr double cP = 0.5 * (P + 1) * (P + 2);
@@ -267,14 +280,14 @@ __global__ void __launch_bounds__(C3<P>::NT) k3_res(const Args3 a, const Basis B
   const double e = MODE ? eps3(a, ndof, &zero_v) : 0.0;
   for (int k = tid; k < Np; k += NT)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) q[v][k] = state3<MODE>(a, ((size_t)v * nel + el) * Np + k, e);
+    for (int v = 0; v < 5; ++v) q[v][k] = state3<MODE>(Uc, a.V, ((size_t)v * nel + el) * Np + k, e);
   for (int idx = tid; idx < NF; idx += NT) {
     const int f = idx / n2, j = idx % n2, d = f >> 1, s = f & 1;
     const int ne = nbr3(a, el, d, s);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      const double o = a.T[t_index(el, f, v, j, n2)];
-      const double m = a.T[t_index(ne, f ^ 1, v, j, n2)];
+      const double o = Tc[t_index(el, f, v, j, n2)];
+      const double m = Tc[t_index(ne, f ^ 1, v, j, n2)];
       tr[f][v][j] = o;
       tn[f][v][j] = m;
       qc[f][v][j] = 0.5 * (o + m);
@@ -342,7 +355,7 @@ __global__ void __launch_bounds__(C3<P>::NT) k3_res(const Args3 a, const Basis B
         qcv[v] = qc[f][v][j];
         const size_t io = t_index(el, f, v, j, n2) * 3, in = t_index(ne, f ^ 1, v, j, n2) * 3;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) gc[c][v] = 0.5 * (a.G[io + c] + a.G[in + c]);
+        for (int c = 0; c < 3; ++c) gc[c][v] = 0.5 * (Gc[io + c] + Gc[in + c]);
         // the two liftings: c_P (q^com - q_own) (2/h) n_own + c_P (q^com - q_nbr) (2/h) n_nbr
         gc[d][v] += 0.5 * lift * sg * ((qcv[v] - qo[v]) - (qcv[v] - qn[v]));
       }
@@ -375,9 +388,9 @@ __global__ void __launch_bounds__(C3<P>::NT) k3_res(const Args3 a, const Basis B
       }
       const size_t gi = ((size_t)v * nel + el) * Np + k;
       if constexpr (MODE == 0)
-        a.out[gi] = R;
+        outc[gi] = R;
       else
-        a.out[gi] = zero_v ? 0.0 : a.shift * a.V[gi] - (R - a.R0[gi]) / e;
+        outc[gi] = zero_v ? 0.0 : a.shift * a.V[gi] - (R - a.R0[gi]) / e;
     }
   }
 }
@@ -540,40 +553,47 @@ hipError_t launch_fr3d_residual(const fr3d_disc* d, int mode, const double* U, c
 
 // The plain residual (mode 0) on the elements elist[0 .. count) only: the first kernel
 // writes their traces and face gradients, the second (unless faces_only) their R, reading
-// the other elements' face data as the work buffer holds it.
+// the other elements' face data as the work buffer holds it.  With copies > 1, copy c
+// (blockIdx.y) has its own state U + c ndof, output out + c ndof and face data at
+// work + c face_stride bytes.
 template <int P, int FLUX, bool VISC>
-static hipError_t res3_subset(const Args3& a, const Basis& B, int count, bool faces_only, hipStream_t s) {
+static hipError_t res3_subset(const Args3& a, const Basis& B, int count, int copies, bool faces_only,
+                              hipStream_t s) {
   using C = C3<P>;
-  const dim3 g(count), b(C::NT);
+  const dim3 g(count, copies), b(C::NT);
   hipLaunchKernelGGL((k3_faces<P, 0, VISC>), g, b, 0, s, a, B);
   if (!faces_only) hipLaunchKernelGGL((k3_res<P, FLUX, 0, VISC>), g, b, 0, s, a, B);
   return hipGetLastError();
 }
 
 template <int P>
-static hipError_t res3_subset_p(const fr3d_disc* d, const Args3& a, int count, bool faces_only, hipStream_t s) {
+static hipError_t res3_subset_p(const fr3d_disc* d, const Args3& a, int count, int copies, bool faces_only,
+                                hipStream_t s) {
   const bool roe = d->flux == FR_ROE, visc = d->mu != 0.0;
   if (visc)
-    return roe ? res3_subset<P, 1, true>(a, d->basis, count, faces_only, s)
-               : res3_subset<P, 0, true>(a, d->basis, count, faces_only, s);
-  return roe ? res3_subset<P, 1, false>(a, d->basis, count, faces_only, s)
-             : res3_subset<P, 0, false>(a, d->basis, count, faces_only, s);
+    return roe ? res3_subset<P, 1, true>(a, d->basis, count, copies, faces_only, s)
+               : res3_subset<P, 0, true>(a, d->basis, count, copies, faces_only, s);
+  return roe ? res3_subset<P, 1, false>(a, d->basis, count, copies, faces_only, s)
+             : res3_subset<P, 0, false>(a, d->basis, count, copies, faces_only, s);
 }
 
 hipError_t launch_fr3d_residual_subset(const fr3d_disc* d, const double* U, double* out, void* work,
-                                       const int* elist, int count, bool faces_only, hipStream_t s) {
-  if (count <= 0 || elist == nullptr) return hipErrorInvalidValue;
+                                       const int* elist, int count, int copies, size_t face_stride,
+                                       bool faces_only, hipStream_t s) {
+  if (count <= 0 || copies <= 0 || elist == nullptr) return hipErrorInvalidValue;
   Args3 a = args3(d);
   a.U = U;
   a.out = out;
   a.elist = elist;
+  a.cs = copies > 1 ? d->ndof : 0;
+  a.fs = copies > 1 ? face_stride : 0;
   const size_t n2 = (size_t)d->n * d->n;
   const size_t t = (size_t)d->nel * 6 * 5 * n2 * sizeof(double);
   a.T = (double*)work;
   a.G = (d->mu != 0.0) ? (double*)((char*)work + ((t + 255) & ~(size_t)255)) : nullptr;
   switch (d->p) {
-    case 2: return res3_subset_p<2>(d, a, count, faces_only, s);
-    case 3: return res3_subset_p<3>(d, a, count, faces_only, s);
+    case 2: return res3_subset_p<2>(d, a, count, copies, faces_only, s);
+    case 3: return res3_subset_p<3>(d, a, count, copies, faces_only, s);
   }
   return hipErrorInvalidValue;
 }

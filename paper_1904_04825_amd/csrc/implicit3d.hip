@@ -31,6 +31,7 @@ namespace frjf {
 namespace {
 
 constexpr int kVec3 = 12; // state-sized vectors of a step
+constexpr int kCopies = 8; // block columns evaluated per launch in the assembly
 
 #define FR3_TRY(expr)        \
   do {                       \
@@ -44,38 +45,47 @@ __device__ __forceinline__ int colour_of(int e, int nx, int ny, int c) {
   return (ex + ey + ez) % c;
 }
 
-// Restores entry `prev` (v * np + k, or -1) of Up from U for the elements of colour col,
-// then moves entry `next` by delta_e = 1e-8 max(1, |U|) (kept in dl[e]).
+// Copy c = blockIdx.y of the perturbed states (Up + c ndof, steps dl + c nel): restores
+// entry prev0 + c (v * np + k; none if prev0 < 0 or out of range) from U for the elements
+// of colour col, then moves entry next0 + c (none if next0 < 0 or out of range) by
+// delta_e = 1e-8 max(1, |U|).
 __global__ void k3a_perturb(double* __restrict__ Up, const double* __restrict__ U, double* __restrict__ dl,
-                            int nel, int np, int prev, int next, int nx, int ny, int c, int col) {
+                            int nel, int np, int prev0, int next0, int nx, int ny, int c, int col, size_t ndof) {
+  const int cp = blockIdx.y, nb = 5 * np;
+  const int prev = prev0 < 0 ? -1 : prev0 + cp, next = next0 < 0 ? -1 : next0 + cp;
+  double* u = Up + cp * ndof;
+  double* d = dl + (size_t)cp * nel;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nel; e += gridDim.x * blockDim.x) {
     if (colour_of(e, nx, ny, c) != col) continue;
-    if (prev >= 0) {
+    if (prev >= 0 && prev < nb) {
       const size_t i = ((size_t)(prev / np) * nel + e) * np + prev % np;
-      Up[i] = U[i];
+      u[i] = U[i];
     }
-    if (next >= 0) {
+    if (next >= 0 && next < nb) {
       const size_t i = ((size_t)(next / np) * nel + e) * np + next % np;
       const double x = U[i];
       const double del = 1e-8 * fmax(1.0, fabs(x));
-      dl[e] = del;
-      Up[i] = x + del;
+      d[e] = del;
+      u[i] = x + del;
     }
   }
 }
 
-// Column j of the blocks of the elements of colour col: -(Rp_e - R0_e) / delta_e, plus
-// shift on the diagonal.  B[e][j][row].
+// Column j = j0 + blockIdx.y of the blocks of the elements of colour col, from copy
+// blockIdx.y: -(Rp_e - R0_e) / delta_e, plus shift on the diagonal.  B[e][j][row].
 __global__ void k3a_column(double* __restrict__ B, const double* __restrict__ Rp, const double* __restrict__ R0,
-                           const double* __restrict__ dl, int nel, int np, int j, double shift, int nx, int ny, int c,
-                           int col) {
-  const int nb = 5 * np;
+                           const double* __restrict__ dl, int nel, int np, int j0, double shift, int nx, int ny, int c,
+                           int col, size_t ndof) {
+  const int nb = 5 * np, cp = blockIdx.y, j = j0 + cp;
+  if (j >= nb) return;
+  const double* rp = Rp + cp * ndof;
+  const double* d = dl + (size_t)cp * nel;
   const size_t total = (size_t)nel * nb;
   for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
     const int e = (int)(t / nb), r = (int)(t % nb);
     if (colour_of(e, nx, ny, c) != col) continue;
     const size_t i = ((size_t)(r / np) * nel + e) * np + r % np;
-    double v = -(Rp[i] - R0[i]) / dl[e];
+    double v = -(rp[i] - R0[i]) / d[e];
     if (r == j) v += shift;
     B[((size_t)e * nb + j) * nb + r] = v;
   }
@@ -291,10 +301,11 @@ struct W3 {
   double* partials; // reduction partials
   double* blocks;   // assembled blocks (destroyed by the inversion)
   double* inv;      // the preconditioner (inverse blocks) of the step drivers
-  double* dl;       // per-element finite-difference steps
+  double* dl;       // per-element finite-difference steps, kCopies x nel
   int* elist;       // the elements grouped by colour
-  double* Up;       // perturbed state
-  double* Rp;       // its residual
+  double* Up;       // perturbed states, kCopies x ndof
+  double* Rp;       // their residuals, kCopies x ndof
+  char* Tc;         // their face data, kCopies x fr3d_trace_bytes (256-aligned)
   double* V;        // m + 1 basis vectors
   double* Z;        // m preconditioned vectors
   double* w;
@@ -318,10 +329,11 @@ W3 carve(const fr3d_disc* d, void* work, int m) {
   w.partials = take(sizeof(double) * std::max<size_t>(kRedBlocks, 5 * (size_t)d->nel));
   w.blocks = take(block_store(d));
   w.inv = take(block_store(d));
-  w.dl = take(sizeof(double) * d->nel);
+  w.dl = take(sizeof(double) * d->nel * kCopies);
   w.elist = (int*)take(sizeof(int) * d->nel);
-  w.Up = take(sizeof(double) * n);
-  w.Rp = take(sizeof(double) * n);
+  w.Up = take(sizeof(double) * n * kCopies);
+  w.Rp = take(sizeof(double) * n * kCopies);
+  w.Tc = (char*)take(al(fr3d_trace_bytes(d)) * kCopies);
   w.V = take(sizeof(double) * n * (size_t)(m + 1));
   w.Z = take(sizeof(double) * n * (size_t)m);
   w.w = take(sizeof(double) * n);
@@ -335,8 +347,8 @@ W3 carve(const fr3d_disc* d, void* work, int m) {
 size_t carve_bytes(const fr3d_disc* d, int m) {
   const size_t n = d->ndof;
   return al(fr3d_trace_bytes(d)) + al(256) + al(sizeof(double) * std::max<size_t>(kRedBlocks, 5 * (size_t)d->nel)) +
-         2 * al(block_store(d)) + al(sizeof(double) * d->nel) + al(sizeof(int) * d->nel) +
-         2 * al(sizeof(double) * n) +
+         2 * al(block_store(d)) + al(sizeof(double) * d->nel * kCopies) + al(sizeof(int) * d->nel) +
+         2 * al(sizeof(double) * n * kCopies) + al(al(fr3d_trace_bytes(d)) * kCopies) +
          al(sizeof(double) * n * (size_t)(m + 1)) + al(sizeof(double) * n * (size_t)m) + 2 * al(sizeof(double) * n) +
          al(sizeof(double) * kHost) + al(sizeof(double) * (size_t)kRedBlocks * (kMaxM + 1)) +
          kVec3 * al(sizeof(double) * n);
@@ -376,12 +388,14 @@ int colour_count(const fr3d_disc* d) {
 }
 
 // Blocks shift I - dR_e/dq_e at U into B (column-major per element); R0 = R(U).  Per
-// colour and column, only that colour's elements are re-evaluated: their traces from the
-// perturbed state, their residuals against the neighbours' face data at U (written by one
-// full evaluation at U first, restored after each colour).
+// colour, kCopies block columns at a time, each in its own copy of the state and face
+// data: only that colour's elements are re-evaluated, their traces from the perturbed
+// state, their residuals against the neighbours' face data at U (one full evaluation at U
+// first, copied to every copy; each copy's colour data restored after the colour).
 fr_status assemble(const fr3d_disc* d, const double* U, const double* R0, double shift, double* B, W3& W,
                    hipStream_t s) {
   const int nb = 5 * d->np, nc = colour_count(d);
+  const size_t n = d->ndof, tb = al(fr3d_trace_bytes(d));
   const unsigned ge = grid_of((size_t)d->nel, 4096), gc = grid_of((size_t)d->nel * nb, 8192);
   std::vector<int> list;
   std::vector<int> off(nc + 1, 0);
@@ -394,25 +408,31 @@ fr_status assemble(const fr3d_disc* d, const double* U, const double* R0, double
     off[col + 1] = (int)list.size();
   }
   FR_HIP(hipMemcpyAsync(W.elist, list.data(), sizeof(int) * list.size(), hipMemcpyHostToDevice, s));
-  FR_HIP(hipMemcpyAsync(W.Up, U, sizeof(double) * d->ndof, hipMemcpyDeviceToDevice, s));
   FR3_TRY(residual(d, U, W.Rp, W, s));  // every element's face data at U
+  for (int c = 0; c < kCopies; ++c) {
+    FR_HIP(hipMemcpyAsync(W.Tc + c * tb, W.traces, fr3d_trace_bytes(d), hipMemcpyDeviceToDevice, s));
+    FR_HIP(hipMemcpyAsync(W.Up + c * n, U, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  }
   for (int col = 0; col < nc; ++col) {
     const int* el = W.elist + off[col];
     const int cnt = off[col + 1] - off[col];
     if (cnt == 0) continue;
-    for (int j = 0; j < nb; ++j) {
-      hipLaunchKernelGGL(k3a_perturb, dim3(ge), dim3(256), 0, s, W.Up, U, W.dl, d->nel, d->np, j - 1, j, d->nx, d->ny,
-                         nc, col);
+    int last = -1;
+    for (int j0 = 0; j0 < nb; j0 += kCopies) {
+      const int k = std::min(kCopies, nb - j0);
+      hipLaunchKernelGGL(k3a_perturb, dim3(ge, kCopies), dim3(256), 0, s, W.Up, U, W.dl, d->nel, d->np, last, j0,
+                         d->nx, d->ny, nc, col, n);
       FR_HIP(hipGetLastError());
-      FR_HIP(launch_fr3d_residual_subset(d, W.Up, W.Rp, W.traces, el, cnt, false, s));
-      hipLaunchKernelGGL(k3a_column, dim3(gc), dim3(256), 0, s, B, W.Rp, R0, W.dl, d->nel, d->np, j, shift, d->nx,
-                         d->ny, nc, col);
+      FR_HIP(launch_fr3d_residual_subset(d, W.Up, W.Rp, W.Tc, el, cnt, k, tb, false, s));
+      hipLaunchKernelGGL(k3a_column, dim3(gc, k), dim3(256), 0, s, B, W.Rp, R0, W.dl, d->nel, d->np, j0, shift,
+                         d->nx, d->ny, nc, col, n);
       FR_HIP(hipGetLastError());
+      last = j0;
     }
-    hipLaunchKernelGGL(k3a_perturb, dim3(ge), dim3(256), 0, s, W.Up, U, W.dl, d->nel, d->np, nb - 1, -1, d->nx,
-                       d->ny, nc, col);
+    hipLaunchKernelGGL(k3a_perturb, dim3(ge, kCopies), dim3(256), 0, s, W.Up, U, W.dl, d->nel, d->np, last, -1,
+                       d->nx, d->ny, nc, col, n);
     FR_HIP(hipGetLastError());
-    FR_HIP(launch_fr3d_residual_subset(d, W.Up, W.Rp, W.traces, el, cnt, true, s));  // the colour's data at U again
+    FR_HIP(launch_fr3d_residual_subset(d, W.Up, W.Rp, W.Tc, el, cnt, kCopies, tb, true, s));  // colour data at U
   }
   FR_HIP(hipStreamSynchronize(s));  // the element lists were copied from this frame
   return FR_OK;

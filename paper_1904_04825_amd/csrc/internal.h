@@ -168,7 +168,8 @@ hipError_t launch_fr3d_residual(const fr3d_disc* d, int mode, const double* U, c
                                 double shift, double eps, int eps_mode, const double* nrm2, double* out, void* work,
                                 hipStream_t s);
 hipError_t launch_fr3d_residual_subset(const fr3d_disc* d, const double* U, double* out, void* work,
-                                       const int* elist, int count, bool faces_only, hipStream_t s);
+                                       const int* elist, int count, int copies, size_t face_stride,
+                                       bool faces_only, hipStream_t s);
 hipError_t launch_fr3d_combine(double* out, const double* A, const double* Bv, const double* R, double alpha,
                                double beta, double dt, size_t n, hipStream_t s);
 hipError_t launch_fr3d_dissipation(const fr3d_disc* d, const double* U, double* part, hipStream_t s);
