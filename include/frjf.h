@@ -535,9 +535,9 @@ fr_status fr3d_gmres_solve(const fr3d_disc* disc, const double* d_inv, const dou
                            double shift, const double* d_b, double* d_x, const fr_gmres_opts* opts,
                            fr_gmres_stats* stats, void* d_work, fr_stream stream);
 /* One ROW, ESDIRK or BDF2 step as fr_row_step, fr_esdirk_step and fr_bdf2_step (same
- * schemes, options, statistics and returns): element-Jacobi (FP64 only) formed once per
- * ROW step and at every PTC iterate; no learned starts (opts->warm, log and d_yhist must
- * be NULL); residual_evals includes the c Nb single-colour evaluations of every
+ * schemes, options, statistics and returns): element-Jacobi formed once per ROW step and
+ * at every PTC iterate, in FP64 or (opts->precond_precision = FR_F32) assembled, inverted
+ * and applied in FP32; no learned starts (opts->warm, log and d_yhist must be NULL); residual_evals includes the c Nb single-colour evaluations of every
  * assembly.  d_work:
  * fr3d_step_workspace_bytes(disc, opts->lin.m) bytes.  Synchronises. */
 fr_status fr3d_row_step(const fr3d_disc* disc, int scheme, double dt, double* d_U, const fr_solver_opts* opts,

@@ -72,8 +72,10 @@ __global__ void k3a_perturb(double* __restrict__ Up, const double* __restrict__ 
 }
 
 // Column j = j0 + blockIdx.y of the blocks of the elements of colour col, from copy
-// blockIdx.y: -(Rp_e - R0_e) / delta_e, plus shift on the diagonal.  B[e][j][row].
-__global__ void k3a_column(double* __restrict__ B, const double* __restrict__ Rp, const double* __restrict__ R0,
+// blockIdx.y: -(Rp_e - R0_e) / delta_e, plus shift on the diagonal, rounded to T.
+// B[e][j][row].
+template <typename T>
+__global__ void k3a_column(T* __restrict__ B, const double* __restrict__ Rp, const double* __restrict__ R0,
                            const double* __restrict__ dl, int nel, int np, int j0, double shift, int nx, int ny, int c,
                            int col, size_t ndof) {
   const int nb = 5 * np, cp = blockIdx.y, j = j0 + cp;
@@ -87,7 +89,7 @@ __global__ void k3a_column(double* __restrict__ B, const double* __restrict__ Rp
     const size_t i = ((size_t)(r / np) * nel + e) * np + r % np;
     double v = -(rp[i] - R0[i]) / d[e];
     if (r == j) v += shift;
-    B[((size_t)e * nb + j) * nb + r] = v;
+    B[((size_t)e * nb + j) * nb + r] = (T)v;
   }
 }
 
@@ -103,28 +105,29 @@ __global__ void k3a_column(double* __restrict__ B, const double* __restrict__ Rp
 // rows' threads publish theirs in LDS, and each thread forms its new entries from its
 // panel row in registers.  The block streams through global memory once per panel.
 // After all panels A^{-1}[k][p_j] = M[p_k][j]; the inverse goes column-major to out.
-template <int N, int W>
-__global__ void __launch_bounds__((N + 63) / 64 * 64, 1) k3_gj(double* __restrict__ A, double* __restrict__ out) {
+// T = double, or float for the FP32 preconditioner (arithmetic in T).
+template <int N, int W, typename T>
+__global__ void __launch_bounds__((N + 63) / 64 * 64, 1) k3_gj(T* __restrict__ A, T* __restrict__ out) {
   constexpr int NT = (N + 63) / 64 * 64, NW = NT / 64, JB = 16;
-  __shared__ double rowp[W];
-  __shared__ double ap[W][JB];
+  __shared__ T rowp[W];
+  __shared__ T ap[W][JB];
   __shared__ int pv[N];
   __shared__ double wb[NW];
   __shared__ int wi[NW], wm[NW];
   const int i = threadIdx.x, lane = i & 63, wid = i >> 6;
   const bool own = i < N;
-  double* a = A + (size_t)blockIdx.x * N * N;
+  T* a = A + (size_t)blockIdx.x * N * N;
   int kst = own ? -1 : N;  // step that pivoted this row; -1 while a candidate
   for (int c0 = 0; c0 < N; c0 += W) {
     const int w = min(W, N - c0);
-    double pr[W];
+    T pr[W];
 #pragma unroll
-    for (int cc = 0; cc < W; ++cc) pr[cc] = (own && cc < w) ? a[(size_t)(c0 + cc) * N + i] : 0.0;
+    for (int cc = 0; cc < W; ++cc) pr[cc] = (own && cc < w) ? a[(size_t)(c0 + cc) * N + i] : T(0);
 #pragma unroll
     for (int c = 0; c < W; ++c) {
       if (c >= w) continue;  // uniform: the last panel may be narrower
       const bool cand = own && kst < 0;
-      const double v = fabs(pr[c]);
+      const double v = fabs((double)pr[c]);
       double best = -1.0;
       int bi = N, mc = cand ? i : N;
       if (cand && v > best) {
@@ -165,14 +168,14 @@ __global__ void __launch_bounds__((N + 63) / 64 * 64, 1) k3_gj(double* __restric
           if (cc < w) rowp[cc] = pr[cc];
       }
       __syncthreads();
-      const double ipiv = 1.0 / rowp[c];
+      const T ipiv = T(1) / rowp[c];
       if (own) {
         if (i == p) {
 #pragma unroll
           for (int cc = 0; cc < W; ++cc)
             if (cc < w) pr[cc] = (cc == c) ? ipiv : pr[cc] * ipiv;
         } else {
-          const double f = pr[c] * ipiv;
+          const T f = pr[c] * ipiv;
 #pragma unroll
           for (int cc = 0; cc < W; ++cc)
             if (cc < w) pr[cc] = (cc == c) ? -f : fma(-f, rowp[cc], pr[cc]);
@@ -187,12 +190,12 @@ __global__ void __launch_bounds__((N + 63) / 64 * 64, 1) k3_gj(double* __restric
     // this panel's pivot slot of the row (-1: not one of its pivots)
     const int slot = (kst >= c0 && kst < c0 + w) ? kst - c0 : -1;
     for (int j0 = 0; j0 < N; j0 += JB) {
-      double x[JB];
+      T x[JB];
 #pragma unroll
       for (int t = 0; t < JB; ++t) {
         const int j = j0 + t;
         const bool live = own && j < N && (j < c0 || j >= c0 + w);
-        x[t] = live ? a[(size_t)j * N + i] : 0.0;
+        x[t] = live ? a[(size_t)j * N + i] : T(0);
       }
       if (slot >= 0) {
 #pragma unroll
@@ -204,7 +207,7 @@ __global__ void __launch_bounds__((N + 63) / 64 * 64, 1) k3_gj(double* __restric
         for (int t = 0; t < JB; ++t) {
           const int j = j0 + t;
           if (j >= N || (j >= c0 && j < c0 + w)) continue;
-          double v = slot >= 0 ? 0.0 : x[t];
+          T v = slot >= 0 ? T(0) : x[t];
 #pragma unroll
           for (int cc = 0; cc < W; ++cc)
             if (cc < w) v = fma(pr[cc], ap[cc][t], v);
@@ -214,33 +217,34 @@ __global__ void __launch_bounds__((N + 63) / 64 * 64, 1) k3_gj(double* __restric
       __syncthreads();
     }
   }
-  double* o = out + (size_t)blockIdx.x * N * N;
+  T* o = out + (size_t)blockIdx.x * N * N;
   for (int j = wid; j < N; j += NW) {
-    const double* col = a + (size_t)j * N;
-    double* oc = o + (size_t)pv[j] * N;
+    const T* col = a + (size_t)j * N;
+    T* oc = o + (size_t)pv[j] * N;
     for (int k = lane; k < N; k += 64) oc[k] = col[pv[k]];
   }
 }
 
-// z_e = inv_e r_e, one workgroup per element, one thread per row; inv column-major.
-template <int N>
-__global__ void __launch_bounds__((N + 63) / 64 * 64) k3_ej_apply(const double* __restrict__ inv,
+// z_e = inv_e r_e, one workgroup per element, one thread per row; inv column-major, in T
+// (r rounded to T, the sums in T).
+template <int N, typename T>
+__global__ void __launch_bounds__((N + 63) / 64 * 64) k3_ej_apply(const T* __restrict__ inv,
                                                                  const double* __restrict__ r,
                                                                  double* __restrict__ z, int nel, int np) {
-  __shared__ double rs[N];
+  __shared__ T rs[N];
   const int e = blockIdx.x, i = threadIdx.x;
-  if (i < N) rs[i] = r[((size_t)(i / np) * nel + e) * np + i % np];
+  if (i < N) rs[i] = (T)r[((size_t)(i / np) * nel + e) * np + i % np];
   __syncthreads();
   if (i >= N) return;
-  const double* B = inv + (size_t)e * N * N + i;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const T* B = inv + (size_t)e * N * N + i;
+  T acc[4] = {T(0), T(0), T(0), T(0)};
   int j = 0;
   for (; j + 4 <= N; j += 4) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[q] = fma(B[(size_t)(j + q) * N], rs[j + q], acc[q]);
   }
   for (; j < N; ++j) acc[0] = fma(B[(size_t)j * N], rs[j], acc[0]);
-  z[((size_t)(i / np) * nel + e) * np + i % np] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  z[((size_t)(i / np) * nel + e) * np + i % np] = (double)((acc[0] + acc[1]) + (acc[2] + acc[3]));
 }
 
 // ---------------------------------------------------------------- Krylov helpers
@@ -392,7 +396,7 @@ int colour_count(const fr3d_disc* d) {
 // data: only that colour's elements are re-evaluated, their traces from the perturbed
 // state, their residuals against the neighbours' face data at U (one full evaluation at U
 // first, copied to every copy; each copy's colour data restored after the colour).
-fr_status assemble(const fr3d_disc* d, const double* U, const double* R0, double shift, double* B, W3& W,
+fr_status assemble(const fr3d_disc* d, const double* U, const double* R0, double shift, void* B, int prec, W3& W,
                    hipStream_t s) {
   const int nb = 5 * d->np, nc = colour_count(d);
   const size_t n = d->ndof, tb = al(fr3d_trace_bytes(d));
@@ -424,8 +428,12 @@ fr_status assemble(const fr3d_disc* d, const double* U, const double* R0, double
                          d->nx, d->ny, nc, col, n);
       FR_HIP(hipGetLastError());
       FR_HIP(launch_fr3d_residual_subset(d, W.Up, W.Rp, W.Tc, el, cnt, k, tb, false, s));
-      hipLaunchKernelGGL(k3a_column, dim3(gc, k), dim3(256), 0, s, B, W.Rp, R0, W.dl, d->nel, d->np, j0, shift,
-                         d->nx, d->ny, nc, col, n);
+      if (prec == FR_F32)
+        hipLaunchKernelGGL(k3a_column<float>, dim3(gc, k), dim3(256), 0, s, (float*)B, W.Rp, R0, W.dl, d->nel,
+                           d->np, j0, shift, d->nx, d->ny, nc, col, n);
+      else
+        hipLaunchKernelGGL(k3a_column<double>, dim3(gc, k), dim3(256), 0, s, (double*)B, W.Rp, R0, W.dl, d->nel,
+                           d->np, j0, shift, d->nx, d->ny, nc, col, n);
       FR_HIP(hipGetLastError());
       last = j0;
     }
@@ -438,32 +446,43 @@ fr_status assemble(const fr3d_disc* d, const double* U, const double* R0, double
   return FR_OK;
 }
 
-fr_status invert(const fr3d_disc* d, double* B, double* inv, hipStream_t s) {
+template <typename T>
+fr_status invert_t(const fr3d_disc* d, T* B, T* inv, hipStream_t s) {
   switch (d->p) {
     // panel widths that divide N: every panel is full and the pivot loop unrolls into
     // registers (a ragged last panel kept the panel row in scratch memory)
-    case 2: hipLaunchKernelGGL((k3_gj<135, 27>), dim3(d->nel), dim3(192), 0, s, B, inv); break;
-    case 3: hipLaunchKernelGGL((k3_gj<320, 32>), dim3(d->nel), dim3(320), 0, s, B, inv); break;
+    case 2: hipLaunchKernelGGL((k3_gj<135, 27, T>), dim3(d->nel), dim3(192), 0, s, B, inv); break;
+    case 3: hipLaunchKernelGGL((k3_gj<320, 32, T>), dim3(d->nel), dim3(320), 0, s, B, inv); break;
     default: return set_error(FR_EINVAL, "3D element-Jacobi: p must be 2 or 3");
   }
   FR_HIP(hipGetLastError());
   return FR_OK;
 }
 
-fr_status apply(const fr3d_disc* d, const double* inv, const double* r, double* z, hipStream_t s) {
+fr_status invert(const fr3d_disc* d, void* B, void* inv, int prec, hipStream_t s) {
+  return prec == FR_F32 ? invert_t(d, (float*)B, (float*)inv, s) : invert_t(d, (double*)B, (double*)inv, s);
+}
+
+template <typename T>
+fr_status apply_t(const fr3d_disc* d, const T* inv, const double* r, double* z, hipStream_t s) {
   switch (d->p) {
-    case 2: hipLaunchKernelGGL((k3_ej_apply<135>), dim3(d->nel), dim3(192), 0, s, inv, r, z, d->nel, d->np); break;
-    case 3: hipLaunchKernelGGL((k3_ej_apply<320>), dim3(d->nel), dim3(320), 0, s, inv, r, z, d->nel, d->np); break;
+    case 2: hipLaunchKernelGGL((k3_ej_apply<135, T>), dim3(d->nel), dim3(192), 0, s, inv, r, z, d->nel, d->np); break;
+    case 3: hipLaunchKernelGGL((k3_ej_apply<320, T>), dim3(d->nel), dim3(320), 0, s, inv, r, z, d->nel, d->np); break;
     default: return set_error(FR_EINVAL, "3D element-Jacobi: p must be 2 or 3");
   }
   FR_HIP(hipGetLastError());
   return FR_OK;
+}
+
+fr_status apply(const fr3d_disc* d, const void* inv, int prec, const double* r, double* z, hipStream_t s) {
+  return prec == FR_F32 ? apply_t(d, (const float*)inv, r, z, s) : apply_t(d, (const double*)inv, r, z, s);
 }
 
 // The step drivers' preconditioner at (U, R0 = R(U), shift) into W.inv.
-fr_status factor(const fr3d_disc* d, const double* U, const double* R0, double shift, W3& W, hipStream_t s) {
-  FR3_TRY(assemble(d, U, R0, shift, W.blocks, W, s));
-  return invert(d, W.blocks, W.inv, s);
+fr_status factor(const fr3d_disc* d, const double* U, const double* R0, double shift, int prec, W3& W,
+                 hipStream_t s) {
+  FR3_TRY(assemble(d, U, R0, shift, W.blocks, prec, W, s));
+  return invert(d, W.blocks, W.inv, prec, s);
 }
 
 // ---------------------------------------------------------------- FGMRES(m)
@@ -501,7 +520,7 @@ fr_status cgs_pass(const fr3d_disc* d, int nv, W3& W, int off, hipStream_t s) {
   return FR_OK;
 }
 
-fr_status gmres(const fr3d_disc* d, const double* inv, const JfArgs& a, const double* b, double* x, bool x_zero,
+fr_status gmres(const fr3d_disc* d, const void* inv, int prec, const JfArgs& a, const double* b, double* x, bool x_zero,
                 const fr_gmres_opts& o, fr_gmres_stats* out, W3& W, hipStream_t s) {
   const size_t n = d->ndof;
   const int m = o.m;
@@ -536,7 +555,7 @@ fr_status gmres(const fr3d_disc* d, const double* inv, const JfArgs& a, const do
     for (int j = 0; j < m; ++j) {
       double* vj = W.V + (size_t)j * n;
       double* zj = W.Z + (size_t)j * n;
-      FR3_TRY(apply(d, inv, vj, zj, s));
+      FR3_TRY(apply(d, inv, prec, vj, zj, s));
       FR3_TRY(jf(d, a, zj, W.w, W, &evals, s));
       FR_HIP(launch_norm2(W.w, n, W.partials, W.hd + 2 * (kMaxM + 1), nullptr, s));      // ||w||^2 before
       FR3_TRY(cgs_pass(d, j + 1, W, 0, s));
@@ -637,11 +656,11 @@ fr_status ptc(const fr3d_disc* d, const double* cst, double omega_dt, double dt,
     if (k >= max_ptc) return FR_NOTCONV;
     if (rejects > max_rej) return FR_REJECTED;
     const double shift = 1.0 / dtau + iw;
-    FR3_TRY(factor(d, q, Rq, shift, W, s));
+    FR3_TRY(factor(d, q, Rq, shift, o.precond_precision, W, s));
     FR3_TRY(lin(dq, {}, n, s));
     fr_gmres_stats gs{};
     const JfArgs a{q, Rq, shift, o.lin.eps > 0 ? o.lin.eps : 1e-8, o.lin.eps_mode};
-    fr_status g = gmres(d, W.inv, a, negF, dq, true, o.lin, &gs, W, s);
+    fr_status g = gmres(d, W.inv, o.precond_precision, a, negF, dq, true, o.lin, &gs, W, s);
     if (g < 0) return g;
     st->gmres_iters += gs.iters;
     st->linear_solves++;
@@ -672,8 +691,8 @@ fr_status ptc(const fr3d_disc* d, const double* cst, double omega_dt, double dt,
 fr_status check_opts(const fr3d_disc* d, const fr_solver_opts& o) {
   if (d->p != 2 && d->p != 3) return set_error(FR_EINVAL, "3D implicit steps: p must be 2 or 3");
   if (o.lin.m < 1 || o.lin.m > kMaxM) return set_error(FR_EINVAL, "3D implicit steps: m must be 1 .. 64");
-  if (o.lin.precond != FR_PC_EJACOBI || o.precond_precision != FR_F64)
-    return set_error(FR_EINVAL, "3D implicit steps: FP64 element-Jacobi only");
+  if (o.lin.precond != FR_PC_EJACOBI || (o.precond_precision != FR_F64 && o.precond_precision != FR_F32))
+    return set_error(FR_EINVAL, "3D implicit steps: element-Jacobi (FR_F64 or FR_F32) only");
   if (o.warm != nullptr || o.log != nullptr || o.d_yhist != nullptr)
     return set_error(FR_EINVAL, "3D implicit steps: no learned starts");
   if (o.lin.eps_mode != FR_EPS_RMS && o.lin.eps_mode != FR_EPS_ABS)
@@ -691,7 +710,7 @@ fr_status fr3d_assemble_impl(const fr3d_disc* d, const double* U, double shift, 
   if (d->p != 2 && d->p != 3) return set_error(FR_EINVAL, "3D element-Jacobi: p must be 2 or 3");
   W3 W = carve(d, work, 1);
   FR3_TRY(residual(d, U, W.vec[0], W, s));
-  return assemble(d, U, W.vec[0], shift, blocks, W, s);
+  return assemble(d, U, W.vec[0], shift, blocks, FR_F64, W, s);
 }
 
 fr_status fr3d_factor_impl(const fr3d_disc* d, const double* U, double shift, double* inv, void* work,
@@ -699,12 +718,12 @@ fr_status fr3d_factor_impl(const fr3d_disc* d, const double* U, double shift, do
   if (d->p != 2 && d->p != 3) return set_error(FR_EINVAL, "3D element-Jacobi: p must be 2 or 3");
   W3 W = carve(d, work, 1);
   FR3_TRY(residual(d, U, W.vec[0], W, s));
-  FR3_TRY(assemble(d, U, W.vec[0], shift, W.blocks, W, s));
-  return invert(d, W.blocks, inv, s);
+  FR3_TRY(assemble(d, U, W.vec[0], shift, W.blocks, FR_F64, W, s));
+  return invert(d, W.blocks, inv, FR_F64, s);
 }
 
 fr_status fr3d_apply_impl(const fr3d_disc* d, const double* inv, const double* r, double* z, hipStream_t s) {
-  return apply(d, inv, r, z, s);
+  return apply(d, inv, FR_F64, r, z, s);
 }
 
 fr_status fr3d_gmres_impl(const fr3d_disc* d, const double* inv, const double* U, const double* R0, double shift,
@@ -715,7 +734,7 @@ fr_status fr3d_gmres_impl(const fr3d_disc* d, const double* inv, const double* U
   if (o.eps_mode != FR_EPS_RMS && o.eps_mode != FR_EPS_ABS) return set_error(FR_EINVAL, "fr3d_gmres_solve: bad eps_mode");
   W3 W = carve(d, work, o.m);
   const JfArgs a{U, R0, shift, o.eps > 0 ? o.eps : 1e-8, o.eps_mode};
-  fr_status g = gmres(d, inv, a, b, x, false, o, st, W, s);
+  fr_status g = gmres(d, inv, FR_F64, a, b, x, false, o, st, W, s);
   FR_HIP(hipStreamSynchronize(s));
   return g;
 }
@@ -735,7 +754,7 @@ fr_status fr3d_row_impl(const fr3d_disc* d, int scheme, double dt, double* U, co
   FR3_TRY(residual(d, U, R0, W, s));
   st->residual_evals++;
   const double shift = 1.0 / (T->gamma * dt);
-  FR3_TRY(factor(d, U, R0, shift, W, s));
+  FR3_TRY(factor(d, U, R0, shift, o.precond_precision, W, s));
   st->residual_evals += (long)colour_count(d) * 5 * d->np;
   const JfArgs a{U, R0, shift, o.lin.eps > 0 ? o.lin.eps : 1e-8, o.lin.eps_mode};
   fr_status worst = FR_OK;
@@ -774,7 +793,7 @@ fr_status fr3d_row_impl(const fr3d_disc* d, int scheme, double dt, double* U, co
     }
     FR3_TRY(lin(Y[i], {}, n, s));
     fr_gmres_stats gs{};
-    fr_status g = gmres(d, W.inv, a, rhs, Y[i], true, o.lin, &gs, W, s);
+    fr_status g = gmres(d, W.inv, o.precond_precision, a, rhs, Y[i], true, o.lin, &gs, W, s);
     if (g < 0) return g;
     st->gmres_iters += gs.iters;
     st->linear_solves++;

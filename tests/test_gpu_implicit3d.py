@@ -119,14 +119,14 @@ def test_esdirk3_and_bdf2_parity():
 
 
 def test_nan_state_and_invalid_calls():
-    from paper_1904_04825_amd import F32, Disc3D, FrError, GmresOpts, SolverOpts
+    from paper_1904_04825_amd import Disc3D, FrError, GmresOpts, SolverOpts
     box, op, disc, U = _pair(2, 2, 2, 2)
     Un = U.copy()
     Un[1, 3, 5] = np.nan
     st = disc.esdirk_step(to_gpu(Un), 3, 0.1, SolverOpts(lin=GmresOpts(m=10, rtol=1e-1), tol_nl=1e-6))
     assert st["status"] == 3                        # FR_ENAN
     with pytest.raises(FrError):
-        disc.row_step(to_gpu(U), 3, 0.1, SolverOpts(lin=GmresOpts(m=10), precond_precision=F32))
+        disc.row_step(to_gpu(U), 3, 0.1, SolverOpts(lin=GmresOpts(m=10), precond_precision=7))
     with pytest.raises(ValueError):
         disc.step_workspace(65)
     d4 = Disc3D(2, 2, 2, 4, (0.0,) * 3, (1.0,) * 3, mu=0.01)
@@ -215,3 +215,26 @@ def test_runs_of_several_steps():
     err = rel(to_np(cur_g), cur_o)
     print(f"3 BDF2 steps: {err:.2e}", flush=True)
     assert err <= 1e-8
+
+
+def test_fp32_preconditioner_steps():
+    """The FP32 element-Jacobi (blocks rounded to FP32, inverted and applied in FP32) only
+    preconditions: ROW3 and ESDIRK3 steps with stage solves to 1e-10 end where the FP64
+    oracle's do, P2 and P3."""
+    from paper_1904_04825_amd import F32, GmresOpts, SolverOpts
+    for P in (2, 3):
+        box, op, disc, U = _pair(2, 2, 2, P)
+        dt = 0.05
+        Uo, so = I.row_step(op, ROW["ROW3"], dt, U, I.LinOpts(m=20, rtol=1e-10))
+        Ug = to_gpu(U)
+        st = disc.row_step(Ug, 3, dt, SolverOpts(lin=GmresOpts(m=20, rtol=1e-10), precond_precision=F32))
+        print(f"P{P} ROW3 FP32 pc: gpu {st['gmres_iters']} GMRES iterations, oracle (FP64 pc) {so.gmres_iters}",
+              flush=True)
+        assert st["status"] == 0 and so.converged
+        assert rel(to_np(Ug), Uo) <= 1e-8
+    box, op, disc, U = _pair(2, 2, 2, 2)
+    Uo, so = I.esdirk_step(op, ESDIRK["ESDIRK3"], 0.1, U, I.LinOpts(m=20, rtol=1e-1), I.NlOpts(tol_nl=1e-10))
+    Ug = to_gpu(U)
+    st = disc.esdirk_step(Ug, 3, 0.1, SolverOpts(lin=GmresOpts(m=20, rtol=1e-1), tol_nl=1e-10, precond_precision=F32))
+    assert st["status"] == 0 and so.converged
+    assert rel(to_np(Ug), Uo) <= 1e-8
