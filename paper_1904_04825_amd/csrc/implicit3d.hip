@@ -3,13 +3,14 @@
 // discretisation (the Taylor-Green comparison of Section 5.3).
 //
 //   Element-Jacobi: blocks shift I - dR_e/dq_e of Nb = 5 (P+1)^3 rows (135 at P2, 320 at
-//   P3).  Columns come from one-sided differences of the full residual with every
-//   element of one colour perturbed at once (colours chosen so that face neighbours
-//   differ, so each such element sees unperturbed neighbours).  A 320 x 320 FP64 block
-//   fits neither a workgroup's registers nor its LDS, so the inversion is a panel
-//   Gauss-Jordan, one thread per row, that keeps the panel's columns in registers and
-//   streams the rest of the block through global memory once per panel.  Blocks and
-//   inverses are column-major per element.
+//   P3).  Columns come from one-sided differences of the residual with every element of
+//   one colour perturbed at once (colours chosen so that face neighbours differ, so each
+//   such element sees unperturbed neighbours); only that colour's elements are
+//   re-evaluated, eight columns per launch in separate copies of the state.  A 320 x 320
+//   FP64 block fits neither a workgroup's registers nor its LDS, so the inversion is a
+//   panel Gauss-Jordan, one thread per row, that keeps the panel's columns in registers
+//   and streams the rest of the block through global memory once per panel.  Blocks and
+//   inverses are column-major per element, FP64 or FP32 (the preconditioner's precision).
 //   FGMRES(m): classical Gram-Schmidt applied twice; the Hessenberg column, the Givens
 //   rotations and the stopping tests run on the host, one synchronisation per Arnoldi
 //   step (a 3D residual costs far more than that round trip).
