@@ -99,16 +99,19 @@ __global__ void k3a_column(T* __restrict__ B, const double* __restrict__ Rp, con
 // Jordan exchanges: no rows move; step k takes as pivot the row p_k with the largest
 // |a| in column k among the rows not pivoted yet (ties to the lower row, NaN never
 // wins; if every candidate is NaN, the lowest candidate row).  One thread per row.
-// Panels of W columns: the panel is factored in registers (each thread its row's W
-// entries, the pivot row broadcast through LDS); every other column j then becomes
-// (column j with the panel's pivot rows zeroed) + Panel * (column j's old entries at
-// those rows), JB columns per barrier: each thread loads its row's entries, the pivot
-// rows' threads publish theirs in LDS, and each thread forms its new entries from its
-// panel row in registers.  The block streams through global memory once per panel.
-// After all panels A^{-1}[k][p_j] = M[p_k][j]; the inverse goes column-major to out.
-// T = double, or float for the FP32 preconditioner (arithmetic in T).
+// Panels of W columns (W divides N): each thread holds its row of the panel in
+// registers, rotated so that the step's column is always the first (one rotation per
+// step, W per panel, so the panel ends in its own order; the step loop then stays rolled:
+// 2.5k instructions against 14.8k unrolled, at the same speed), the pivot row broadcast through
+// LDS; every other column j then becomes (column j with the panel's pivot rows zeroed)
+// + Panel * (column j's old entries at those rows), JB columns per barrier: each thread
+// loads its row's entries, the pivot rows' threads publish theirs in LDS, and each thread
+// forms its new entries from its panel row.  The block streams through global memory once
+// per panel.  After all panels A^{-1}[k][p_j] = M[p_k][j]; the inverse goes column-major
+// to out.  T = double, or float for the FP32 preconditioner (arithmetic in T).
 template <int N, int W, typename T>
 __global__ void __launch_bounds__((N + 63) / 64 * 64, 1) k3_gj(T* __restrict__ A, T* __restrict__ out) {
+  static_assert(N % W == 0, "whole panels");
   constexpr int NT = (N + 63) / 64 * 64, NW = NT / 64, JB = 16;
   __shared__ T rowp[W];
   __shared__ T ap[W][JB];
@@ -120,15 +123,14 @@ __global__ void __launch_bounds__((N + 63) / 64 * 64, 1) k3_gj(T* __restrict__ A
   T* a = A + (size_t)blockIdx.x * N * N;
   int kst = own ? -1 : N;  // step that pivoted this row; -1 while a candidate
   for (int c0 = 0; c0 < N; c0 += W) {
-    const int w = min(W, N - c0);
     T pr[W];
 #pragma unroll
-    for (int cc = 0; cc < W; ++cc) pr[cc] = (own && cc < w) ? a[(size_t)(c0 + cc) * N + i] : T(0);
-#pragma unroll
+    for (int cc = 0; cc < W; ++cc) pr[cc] = own ? a[(size_t)(c0 + cc) * N + i] : T(0);
+#pragma unroll 1
     for (int c = 0; c < W; ++c) {
-      if (c >= w) continue;  // uniform: the last panel may be narrower
+      // the step's column is pr[0]
       const bool cand = own && kst < 0;
-      const double v = fabs((double)pr[c]);
+      const double v = fabs((double)pr[0]);
       double best = -1.0;
       int bi = N, mc = cand ? i : N;
       if (cand && v > best) {
@@ -165,37 +167,39 @@ __global__ void __launch_bounds__((N + 63) / 64 * 64, 1) k3_gj(T* __restrict__ A
         kst = c0 + c;
         pv[c0 + c] = p;
 #pragma unroll
-        for (int cc = 0; cc < W; ++cc)
-          if (cc < w) rowp[cc] = pr[cc];
+        for (int cc = 0; cc < W; ++cc) rowp[cc] = pr[cc];
       }
       __syncthreads();
-      const T ipiv = T(1) / rowp[c];
+      const T ipiv = T(1) / rowp[0];
       if (own) {
         if (i == p) {
+          pr[0] = ipiv;
 #pragma unroll
-          for (int cc = 0; cc < W; ++cc)
-            if (cc < w) pr[cc] = (cc == c) ? ipiv : pr[cc] * ipiv;
+          for (int cc = 1; cc < W; ++cc) pr[cc] = rowp[cc] * ipiv;
         } else {
-          const T f = pr[c] * ipiv;
+          const T f = pr[0] * ipiv;
+          pr[0] = -f;
 #pragma unroll
-          for (int cc = 0; cc < W; ++cc)
-            if (cc < w) pr[cc] = (cc == c) ? -f : fma(-f, rowp[cc], pr[cc]);
+          for (int cc = 1; cc < W; ++cc) pr[cc] = fma(-f, rowp[cc], pr[cc]);
         }
       }
+      const T t0 = pr[0];  // rotate: the next step's column to the front
+#pragma unroll
+      for (int cc = 0; cc + 1 < W; ++cc) pr[cc] = pr[cc + 1];
+      pr[W - 1] = t0;
     }
     if (own) {
 #pragma unroll
-      for (int cc = 0; cc < W; ++cc)
-        if (cc < w) a[(size_t)(c0 + cc) * N + i] = pr[cc];
+      for (int cc = 0; cc < W; ++cc) a[(size_t)(c0 + cc) * N + i] = pr[cc];
     }
     // this panel's pivot slot of the row (-1: not one of its pivots)
-    const int slot = (kst >= c0 && kst < c0 + w) ? kst - c0 : -1;
+    const int slot = (kst >= c0 && kst < c0 + W) ? kst - c0 : -1;
     for (int j0 = 0; j0 < N; j0 += JB) {
       T x[JB];
 #pragma unroll
       for (int t = 0; t < JB; ++t) {
         const int j = j0 + t;
-        const bool live = own && j < N && (j < c0 || j >= c0 + w);
+        const bool live = own && j < N && (j < c0 || j >= c0 + W);
         x[t] = live ? a[(size_t)j * N + i] : T(0);
       }
       if (slot >= 0) {
@@ -207,11 +211,10 @@ __global__ void __launch_bounds__((N + 63) / 64 * 64, 1) k3_gj(T* __restrict__ A
 #pragma unroll
         for (int t = 0; t < JB; ++t) {
           const int j = j0 + t;
-          if (j >= N || (j >= c0 && j < c0 + w)) continue;
+          if (j >= N || (j >= c0 && j < c0 + W)) continue;
           T v = slot >= 0 ? T(0) : x[t];
 #pragma unroll
-          for (int cc = 0; cc < W; ++cc)
-            if (cc < w) v = fma(pr[cc], ap[cc][t], v);
+          for (int cc = 0; cc < W; ++cc) v = fma(pr[cc], ap[cc][t], v);
           a[(size_t)j * N + i] = v;
         }
       }
@@ -450,8 +453,7 @@ fr_status assemble(const fr3d_disc* d, const double* U, const double* R0, double
 template <typename T>
 fr_status invert_t(const fr3d_disc* d, T* B, T* inv, hipStream_t s) {
   switch (d->p) {
-    // panel widths that divide N: every panel is full and the pivot loop unrolls into
-    // registers (a ragged last panel kept the panel row in scratch memory)
+    // panel widths that divide N (whole panels keep the panel row in registers)
     case 2: hipLaunchKernelGGL((k3_gj<135, 27, T>), dim3(d->nel), dim3(192), 0, s, B, inv); break;
     case 3: hipLaunchKernelGGL((k3_gj<320, 32, T>), dim3(d->nel), dim3(320), 0, s, B, inv); break;
     default: return set_error(FR_EINVAL, "3D element-Jacobi: p must be 2 or 3");
