@@ -637,20 +637,23 @@ def tgv_study(n_el, P, steps, dt_tc, sample_every, verbose=True):
             "history": hist}
 
 
-def tgv_implicit_study(n_el, P, schemes, per_tc, t0, t1, dt_ref_tc, ref_save=None, ref_load=None, verbose=True):
+def tgv_implicit_study(n_el, P, schemes, per_tc, t0, t1, dt_ref_tc, ref_save=None, ref_load=None, pc_prec="f64",
+                       verbose=True):
     """The implicit schemes on the Taylor-Green vortex (Section 5.3) on n_el^3 P hexahedra:
     the reference is SSPRK3 at dt_ref_tc t_c from t = 0 (the paper's 2e-4 t_c), which also
     gives the state at t0; each scheme then runs from t0 to t1 at dt = t_c / k and
     Error(eps) is the paper's root mean square over its steps of eps - eps_ref, eps = eps1 +
     eps3 (eps2 = 0).  Tolerances as the paper's: ROW linear 1e-6; ESDIRK and BDF2 nonlinear
-    1e-6 with linear 1e-1, dtau_init = dt, dtau_max = 1e20; GMRES(30), FP64 element-Jacobi."""
+    1e-6 with linear 1e-1, dtau_init = dt, dtau_max = 1e20; GMRES(30), element-Jacobi in
+    pc_prec ("f64", or "f32": blocks rounded to FP32, inverted and applied in FP32)."""
     import math
 
     import numpy as np
     import torch
 
     import fr_inputs as fi
-    from paper_1904_04825_amd import Disc3D, GmresOpts, SolverOpts
+    from paper_1904_04825_amd import F32, F64, Disc3D, GmresOpts, SolverOpts
+    pp = F32 if pc_prec == "f32" else F64
     tg = fi.TaylorGreen()
     L = tg.L
     tc = L / tg.V0
@@ -699,8 +702,9 @@ def tgv_implicit_study(n_el, P, schemes, per_tc, t0, t1, dt_ref_tc, ref_save=Non
         for k in per_tc:
             dt = tc / k
             n = int(round((t1 - t0) * k))
-            o = SolverOpts(lin=GmresOpts(m=30, rtol=1e-6)) if sch.startswith("ROW") else \
-                SolverOpts(lin=GmresOpts(m=30, rtol=1e-1), tol_nl=1e-6, dtau_init=0.0, dtau_max=1e20)
+            o = SolverOpts(lin=GmresOpts(m=30, rtol=1e-6), precond_precision=pp) if sch.startswith("ROW") else \
+                SolverOpts(lin=GmresOpts(m=30, rtol=1e-1), tol_nl=1e-6, dtau_init=0.0, dtau_max=1e20,
+                           precond_precision=pp)
             U = U0.clone()
             Um1 = None
             tot = {"gmres_iters": 0, "ptc_iters": 0, "rejections": 0, "residual_evals": 0}
@@ -740,6 +744,7 @@ def tgv_implicit_study(n_el, P, schemes, per_tc, t0, t1, dt_ref_tc, ref_save=Non
                       f"GMRES/step {row['gmres_iters']:.1f}, PTC/step {row['ptc_iters']:.1f}, "
                       f"rejections {tot['rejections']}{'' if failed is None else f' FAILED ({failed})'}", flush=True)
     return {"mode": "tgv-implicit", "mesh": f"{n_el}^3 hexahedra, P{P}", "ndof": disc.ndof, "reynolds": 1600,
+            "precond_precision": pc_prec,
             "mach": 0.1, "window_tc": [t0, t1], "reference": {"scheme": "SSPRK3", "dt_tc": dt_ref_tc, "wall_s": ref_s,
                                                                "loaded_from": ref_load,
                                                                "eps_t0": float(ref_eps[0]),
@@ -813,7 +818,8 @@ def main():
     if args.tgv_implicit:
         print(json.dumps(tgv_implicit_study(args.tgvi_n, args.tgv_p, args.tgvi_schemes.split(","),
                                             [int(k) for k in args.tgvi_steps_per_tc.split(",")], args.tgvi_t0,
-                                            args.tgvi_t1, args.tgv_dt, args.tgvi_ref_save, args.tgvi_ref_load)),
+                                            args.tgvi_t1, args.tgv_dt, args.tgvi_ref_save, args.tgvi_ref_load,
+                                            args.study_precond)),
               flush=True)
         return
     if args.cylinder:
