@@ -830,7 +830,7 @@ def main():
                                         args.cyl_ref_load, args.cyl_settle)), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU: --gpus must be 1 (the sharding over several GPUs is a design, not a run)"}))
         sys.exit(2)
     import numpy as np
     import torch
